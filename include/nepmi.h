@@ -1,0 +1,190 @@
+/*
+ * nepmi.h -- C ABI of the MI355X (gfx950) NEP evaluation library.
+ *
+ * The library evaluates a neuroevolution potential (NEP) as stated in the
+ * AI2Pot paper, Sec. 2: the total energy is a sum of site energies (Eq. 1),
+ * each the output of a per-element one-hidden-layer network (Sec. 2.3) on
+ * radial descriptors (Eq. 11-15) and angular descriptors (Eq. 16-17, plus
+ * 4-body and 5-body invariants); forces follow Eq. 3 and the virial Eq. 4.
+ * A loss of the form of Eq. 18-21 and its gradient with respect to every
+ * parameter serve training (Sec. 3.2: one operator backend for training and
+ * inference; Sec. 3.4: neighbour lists rebuilt on every training step).
+ *
+ * Conventions (every entry point):
+ *   - Units: Angstrom, eV, eV/Angstrom, atomic mass units, femtoseconds.
+ *   - Species are 0..n_species-1.  Periodic in all three directions; the
+ *     cell's rows are its lattice vectors a, b, c (row-major double[9]).
+ *     Every cell width must be at least 2 * (rc_radial + skin); the pair
+ *     vectors use the cell rounded to float32.
+ *   - Positions and forces are float32, array-of-structs (N x 3, row-major),
+ *     in the caller's atom order; configuration c owns atoms
+ *     [atom_off[c], atom_off[c+1]).
+ *   - The virial is V_ab = - sum_i sum_j dE_i/dr_ij,a r_ij,b in eV (Eq. 4),
+ *     not divided by the volume.
+ *   - Arithmetic: float32 for descriptors, network and pair forces; float64
+ *     for energy, virial and loss sums.
+ *   - Pointers named dev_* are device pointers the caller owns (for example
+ *     torch tensors) and that stay valid for the duration of the call, which
+ *     is asynchronous on `stream` (a hipStream_t; NULL = default stream) unless
+ *     stated.  Host pointers (atom_off, cells, masses, weights) are read
+ *     before the call returns.  The library keeps no caller pointer past a
+ *     call; handles own their workspace, which grows on demand.
+ *   - Every call returns NEPMI_OK (0) or a negative code; nepmi_last_error()
+ *     gives a message for the calling thread.  No C++ exception crosses the
+ *     ABI.  A handle must not be used from two threads or streams at once.
+ */
+#ifndef NEPMI_H
+#define NEPMI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  NEPMI_OK = 0,
+  NEPMI_INVALID_ARG = -1,       /* bad size, pointer, species or hyper-parameter  */
+  NEPMI_CELL_TOO_SMALL = -2,    /* a cell width below 2 * (rc_radial + skin)      */
+  NEPMI_NEIGHBOR_OVERFLOW = -3, /* neighbour capacity exceeded (MD only; compute
+                                   calls grow the capacity and retry)            */
+  NEPMI_HIP_ERROR = -4,         /* a HIP runtime call failed                      */
+  NEPMI_NAN_DETECTED = -5,      /* a non-finite position was given               */
+  NEPMI_UNSUPPORTED = -6        /* hyper-parameters with no compiled kernel set   */
+};
+
+/* Hyper-parameters, named as in Sec. 2.3: n_radial = n_max^radial and
+ * n_angular = n_max^angular (counts of functions, n = 0..n-1); basis_* =
+ * N_basis (Chebyshev orders 0..N_basis-1); l_max: the three-body term uses
+ * l = 1..l_max; use_4body / use_5body add n_angular invariants each;
+ * n_hidden = N_neurons; rc_* = r_max of the radial and angular terms
+ * (rc_angular <= rc_radial). */
+typedef struct {
+  int32_t n_species, n_radial, n_angular, basis_radial, basis_angular;
+  int32_t l_max, use_4body, use_5body, n_hidden, reserved;
+  double rc_radial, rc_angular;
+} nepmi_hparams;
+
+typedef struct nepmi_model nepmi_model;
+typedef struct nepmi_md nepmi_md;
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *nepmi_last_error(void);
+
+/* Number of trainable parameters (7899 for the model of Table 2). */
+int nepmi_param_count(const nepmi_hparams *hp, int64_t *out);
+
+/* Descriptor length D = n_radial + l_max n_angular (+ n_angular for each of
+ * the 4-body and 5-body terms). */
+int nepmi_descriptor_dim(const nepmi_hparams *hp, int32_t *out);
+
+/* Create a model handle on the current HIP device.  NEPMI_UNSUPPORTED if the
+ * hyper-parameters have no compiled kernel set (see nepmi_supported). */
+int nepmi_model_create(const nepmi_hparams *hp, nepmi_model **out);
+
+/* 1 if kernels for these hyper-parameters are compiled in, else 0. */
+int nepmi_supported(const nepmi_hparams *hp);
+
+/* Copy the flat float32 parameter vector (device memory, param_count values)
+ * into the model.  Layout: [c_R: T*T*n_radial*basis_radial, order (Z_i, Z_j,
+ * n, k)] [c_A: T*T*n_angular*basis_angular] then for each species s:
+ * [W0: n_hidden x D row-major] [b0: n_hidden] [w1: n_hidden] [b1: 1].
+ * The site energy is E_i = w1 . tanh(W0 q_i + b0) + b1 (Sec. 2.3). */
+int nepmi_model_set_params(nepmi_model *m, const float *dev_params, void *stream);
+
+void nepmi_model_destroy(nepmi_model *m);
+
+/* Energy, forces and virial of n_cfg periodic configurations (Eq. 1, 3, 4).
+ *   atom_off: host int64[n_cfg+1]; cells: host double[9*n_cfg];
+ *   dev_pos: float[N*3]; dev_species: int32[N];
+ *   dev_energy: double[n_cfg]; dev_forces: float[N*3]; dev_virial:
+ *   double[9*n_cfg]; dev_atom_energy: float[N] or NULL; dev_atom_virial:
+ *   float[N*9] or NULL (row-major 3x3 per atom, -sum_j dE_i/dr_ij (x) r_ij).
+ * Synchronises `stream` once to check the neighbour capacity. */
+int nepmi_compute(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, const double *cells,
+                  const float *dev_pos, const int32_t *dev_species, double *dev_energy, float *dev_forces,
+                  double *dev_virial, float *dev_atom_energy, float *dev_atom_virial, void *stream);
+
+/* Descriptors q_i (float[N*D], caller's atom order) of the same batch: the
+ * radial q_n (Eq. 11), three-body q_nl (Eq. 17, l = 1..l_max, index
+ * n_radial + (l-1) n_angular + n), then the 4-body and 5-body values. */
+int nepmi_descriptors(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, const double *cells,
+                      const float *dev_pos, const int32_t *dev_species, float *dev_q, void *stream);
+
+/* Neighbour lists of the same batch, for inspection and tests.  which = 0:
+ * radial list (pairs closer than rc_radial), 1: angular list (rc_angular).
+ * For caller atom i, dev_count[i] (int32[N]) neighbours are written to
+ * dev_nbr[i*cap + k] (int32, caller index of the neighbour) and
+ * dev_rvec[(i*cap + k)*3 + a] (float32, r_ij = r_j - r_i + image shift);
+ * entries beyond cap are dropped (dev_count still reports the full length).
+ * The list order is the library's evaluation order. */
+int nepmi_neighbors(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, const double *cells,
+                    const float *dev_pos, const int32_t *dev_species, int32_t which, int32_t cap,
+                    int32_t *dev_count, int32_t *dev_nbr, float *dev_rvec, void *stream);
+
+/* Vector-Jacobian product of (E, F, V) with respect to the parameters:
+ *   dev_grad[p] = sum_c ebar_c dE_c/dtheta_p + sum_i lambda_i . dF_i/dtheta_p
+ *               + sum_c mu_c : dV_c/dtheta_p
+ * with dev_ebar double[n_cfg], dev_lambda float[N*3], dev_mu double[9*n_cfg];
+ * dev_grad float[param_count] is overwritten.  Uses the neighbour lists and
+ * forward state of the last nepmi_compute on the same batch (call that
+ * first); descriptors are recomputed, no per-pair state is cached. */
+int nepmi_backward_params(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, const double *cells,
+                          const float *dev_pos, const int32_t *dev_species, const double *dev_ebar,
+                          const float *dev_lambda, const double *dev_mu, float *dev_grad, void *stream);
+
+/* Loss of Eq. 18-21 and its parameter gradient in one call (forward, loss,
+ * adjoint seeds, backward).  weights = host double[3] (w_E, w_F, w_V).
+ * loss_form 0: L = w_E/B sum_c ((E_c - Eref_c)/N_c)^2
+ *                + w_F/(3 sum_c N_c) sum_{c,i,a} (F - Fref)^2
+ *                + w_V/(9B) sum_c sum_ab ((V_c - Vref_c)/N_c)^2;
+ * loss_form 1: L = 1/B sum_c [w_E/N_c dE^2 + w_F/(3N_c) sum dF^2 + w_V/(9N_c) sum dV^2]
+ * (Eq. 19-21 per configuration, averaged over the batch).
+ * dev_E_ref double[n_cfg], dev_F_ref float[N*3], dev_V_ref double[9*n_cfg];
+ * dev_loss double[4] = (total, energy, force, virial); dev_grad float[P] or
+ * NULL (loss only). */
+int nepmi_loss_grad(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, const double *cells,
+                    const float *dev_pos, const int32_t *dev_species, const double *dev_E_ref,
+                    const float *dev_F_ref, const double *dev_V_ref, const double *weights, int32_t loss_form,
+                    double *dev_loss, float *dev_grad, void *stream);
+
+/* Velocity-Verlet NVE molecular dynamics of n_cfg independent cells stepped
+ * together (one time step for all).  The handle copies positions, velocities
+ * (float[N*3], Angstrom/fs) and species; masses: host double[n_species] (u);
+ * dt_fs: time step; skin: Verlet-list skin in Angstrom (lists are rebuilt
+ * when an atom has moved more than skin/2 since the last build).  Positions
+ * are wrapped into the cell at each rebuild.  The step (half kick, drift,
+ * displacement check, conditional rebuild, forces, half kick, float64
+ * energy/virial/kinetic sums) is captured once in a HIP graph and replayed. */
+int nepmi_md_create(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, const double *cells,
+                    const float *dev_pos, const float *dev_vel, const int32_t *dev_species, const double *masses,
+                    double dt_fs, double skin, nepmi_md **out, void *stream);
+
+/* Advance n_steps time steps (graph replays) on `stream`.  Synchronises
+ * `stream` at the end to check the neighbour capacity and returns
+ * NEPMI_NEIGHBOR_OVERFLOW if it was exceeded (results are then invalid). */
+int nepmi_md_step(nepmi_md *md, int32_t n_steps, void *stream);
+
+/* Copy the current state out (any pointer may be NULL): positions and
+ * velocities float[N*3] and forces float[N*3] in the caller's atom order;
+ * potential energy, kinetic energy double[n_cfg] and virial double[9*n_cfg]
+ * of the last step. */
+int nepmi_md_get(nepmi_md *md, float *dev_pos, float *dev_vel, float *dev_forces, double *dev_epot,
+                 double *dev_ekin, double *dev_virial, void *stream);
+
+/* Host counters: steps taken and neighbour-list builds (including the first). */
+int nepmi_md_stats(nepmi_md *md, int64_t *steps, int64_t *rebuilds);
+
+void nepmi_md_destroy(nepmi_md *md);
+
+/* Average duration of each hot kernel, measured with HIP events recorded on
+ * `stream` around `reps` standalone launches of the force evaluation on the
+ * current MD state (the same kernels and launch shapes the graph replays).
+ * ms_per_launch: host double[4] = descriptors + network, pair forces +
+ * virial, force gather, neighbour-list build.  Synchronises `stream`. */
+int nepmi_md_time_kernels(nepmi_md *md, int32_t reps, double *ms_per_launch, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NEPMI_H */

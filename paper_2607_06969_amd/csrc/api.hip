@@ -1,0 +1,266 @@
+// api.hip -- extern "C" entry points: model handle, compute, descriptors.
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "model.hpp"
+
+namespace nepmi {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int hip_fail(hipError_t e, const char* what) {
+  set_error(std::string("HIP error '") + hipGetErrorString(e) + "' in " + what);
+  return NEPMI_HIP_ERROR;
+}
+
+template <class S>
+static const Ops* ops_of() {
+  static const Ops o = {&Launch<S>::desc, &Launch<S>::force, &Launch<S>::gather, S::T, S::NR, S::NA, S::BR, S::BA,
+                        S::L, S::D, S::NANG, S::P};
+  return &o;
+}
+
+template <class S>
+static bool matches(const nepmi_hparams& h) {
+  return h.n_species == S::T && h.n_radial == S::NR && h.n_angular == S::NA && h.basis_radial == S::BR &&
+         h.basis_angular == S::BA && h.l_max == S::L && (h.use_4body != 0) == S::F4 && (h.use_5body != 0) == S::F5 &&
+         h.n_hidden == S::H;
+}
+
+const Ops* find_ops(const nepmi_hparams& h) {
+  if (matches<ShapeSmall>(h)) return ops_of<ShapeSmall>();
+  if (matches<ShapeGST>(h)) return ops_of<ShapeGST>();
+  if (matches<ShapeTable2>(h)) return ops_of<ShapeTable2>();
+  return nullptr;
+}
+
+static int check_hp(const nepmi_hparams* hp) {
+  if (!hp) {
+    set_error("null hyper-parameters");
+    return NEPMI_INVALID_ARG;
+  }
+  const nepmi_hparams& h = *hp;
+  if (h.n_species < 1 || h.n_radial < 1 || h.n_angular < 0 || h.basis_radial < 1 || h.basis_angular < 0 ||
+      h.l_max < 0 || h.l_max > 4 || h.n_hidden < 1 || !(h.rc_radial > 0) || !(h.rc_angular > 0) ||
+      h.rc_angular > h.rc_radial || (h.use_4body && h.l_max < 2) || (h.use_5body && h.l_max < 1)) {
+    set_error("invalid hyper-parameters");
+    return NEPMI_INVALID_ARG;
+  }
+  return NEPMI_OK;
+}
+
+static int64_t param_count(const nepmi_hparams& h) {
+  const int64_t D = h.n_radial + (int64_t)h.l_max * h.n_angular + (h.use_4body ? h.n_angular : 0) +
+                    (h.use_5body ? h.n_angular : 0);
+  const int64_t T = h.n_species;
+  return T * T * ((int64_t)h.n_radial * h.basis_radial + (int64_t)h.n_angular * h.basis_angular) +
+         T * (h.n_hidden * D + 2 * h.n_hidden + 1);
+}
+
+}  // namespace nepmi
+
+using namespace nepmi;
+
+int nepmi_model::prepare(int n_cfg, const int64_t* atom_off, const double* cells, const float* pos,
+                         const int32_t* species, hipStream_t st) {
+  int rc;
+  if ((rc = nbr.setup(n_cfg, atom_off, cells, ops->T, hp.rc_radial, hp.rc_angular, 0.0, st))) return rc;
+  if ((rc = nbr.build(st, pos, species))) return rc;
+  if ((rc = red.setup(n_cfg, atom_off, st))) return rc;
+  const size_t ns = (size_t)nbr.n_slots, N = (size_t)(nbr.N > 0 ? nbr.N : 1);
+  if ((rc = fp.ensure(4 * ns * (size_t)ops->NANG)) || (rc = aR.ensure(4 * ns * (size_t)(ops->T * ops->BR))) ||
+      (rc = Ei.ensure(4 * N)) || (rc = frad.ensure(16 * ns)) || (rc = fA.ensure(16 * ns * (size_t)nbr.capA)) ||
+      (rc = Wi.ensure(36 * N)) || (rc = Eproc.ensure(4 * ns)))
+    return rc;
+  return NEPMI_OK;
+}
+
+NepIO nepmi_model::io(float* Fuser, float4* Fproc, float* qout) {
+  NepIO o;
+  o.n_slots = nbr.n_slots;
+  o.pos4 = nbr.pos4.ptr<float4>();
+  o.cfg_of = nbr.cfg_of.ptr<int>();
+  o.orig = nbr.orig.ptr<int>();
+  o.cfgs = nbr.cfgs.ptr<CfgDev>();
+  o.nbrR = nbr.nbrR.ptr<uint32_t>();
+  o.cntR = nbr.cntR.ptr<int>();
+  o.nbrA = nbr.nbrA.ptr<uint32_t>();
+  o.cntA = nbr.cntA.ptr<int>();
+  o.revA = nbr.revA.ptr<int>();
+  const float rcR = (float)hp.rc_radial, rcA = (float)hp.rc_angular;
+  o.cut.rcR = rcR;
+  o.cut.rcA = rcA;
+  o.cut.rcR2 = rcR * rcR;
+  o.cut.rcA2 = rcA * rcA;
+  o.cut.rclR2 = nbr.rclR2;
+  o.cut.rclA2 = nbr.rclA2;
+  o.fp = fp.ptr<float>();
+  o.aR = aR.ptr<float>();
+  o.Ei = Ei.ptr<float>();
+  o.qout = qout;
+  o.frad = frad.ptr<float4>();
+  o.fA = fA.ptr<float4>();
+  o.Wi = Wi.ptr<float>();
+  o.Fuser = Fuser;
+  o.Fproc = Fproc;
+  o.Eproc = Eproc.ptr<float>();
+  return o;
+}
+
+extern "C" {
+
+const char* nepmi_last_error(void) { return g_last_error.c_str(); }
+
+int nepmi_param_count(const nepmi_hparams* hp, int64_t* out) {
+  int rc = check_hp(hp);
+  if (rc) return rc;
+  if (!out) return NEPMI_INVALID_ARG;
+  *out = param_count(*hp);
+  return NEPMI_OK;
+}
+
+int nepmi_descriptor_dim(const nepmi_hparams* hp, int32_t* out) {
+  int rc = check_hp(hp);
+  if (rc) return rc;
+  if (!out) return NEPMI_INVALID_ARG;
+  *out = hp->n_radial + hp->l_max * hp->n_angular + (hp->use_4body ? hp->n_angular : 0) +
+         (hp->use_5body ? hp->n_angular : 0);
+  return NEPMI_OK;
+}
+
+int nepmi_supported(const nepmi_hparams* hp) { return (hp && check_hp(hp) == 0 && find_ops(*hp)) ? 1 : 0; }
+
+int nepmi_model_create(const nepmi_hparams* hp, nepmi_model** out) {
+  int rc = check_hp(hp);
+  if (rc) return rc;
+  if (!out) {
+    set_error("null output handle");
+    return NEPMI_INVALID_ARG;
+  }
+  const Ops* ops = find_ops(*hp);
+  if (!ops) {
+    set_error("no compiled kernel set for these hyper-parameters");
+    return NEPMI_UNSUPPORTED;
+  }
+  nepmi_model* m = new (std::nothrow) nepmi_model();
+  if (!m) return NEPMI_INVALID_ARG;
+  m->hp = *hp;
+  m->ops = ops;
+  if (hipGetDevice(&m->device) != hipSuccess || (rc = m->params.ensure(4 * (size_t)ops->P))) {
+    delete m;
+    return rc ? rc : NEPMI_HIP_ERROR;
+  }
+  *out = m;
+  return NEPMI_OK;
+}
+
+int nepmi_model_set_params(nepmi_model* m, const float* dev_params, void* stream) {
+  if (!m || !dev_params) {
+    set_error("null model or parameters");
+    return NEPMI_INVALID_ARG;
+  }
+  NEPMI_HIP(hipMemcpyAsync(m->params.p, dev_params, 4 * (size_t)m->ops->P, hipMemcpyDeviceToDevice,
+                           (hipStream_t)stream));
+  return NEPMI_OK;
+}
+
+void nepmi_model_destroy(nepmi_model* m) { delete m; }
+
+int nepmi_compute(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, const double* cells, const float* dev_pos,
+                  const int32_t* dev_species, double* dev_energy, float* dev_forces, double* dev_virial,
+                  float* dev_atom_energy, float* dev_atom_virial, void* stream) {
+  if (!m || !dev_pos || !dev_species) {
+    set_error("null argument");
+    return NEPMI_INVALID_ARG;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  int rc = m->prepare(n_cfg, atom_off, cells, dev_pos, dev_species, st);
+  if (rc) return rc;
+  NepIO io = m->io(dev_forces, nullptr, nullptr);
+  const float* P = m->params.ptr<float>();
+  if ((rc = m->ops->desc(st, io, P, true)) || (rc = m->ops->force(st, io, P)) || (rc = m->ops->gather(st, io)))
+    return rc;
+  if ((rc = m->red.run(st, io.Ei, io.Wi, nullptr, dev_energy, dev_virial, nullptr))) return rc;
+  const size_t N = (size_t)m->nbr.N;
+  if (dev_atom_energy && N)
+    NEPMI_HIP(hipMemcpyAsync(dev_atom_energy, io.Ei, 4 * N, hipMemcpyDeviceToDevice, st));
+  if (dev_atom_virial && N)
+    NEPMI_HIP(hipMemcpyAsync(dev_atom_virial, io.Wi, 36 * N, hipMemcpyDeviceToDevice, st));
+  return NEPMI_OK;
+}
+
+int nepmi_descriptors(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, const double* cells,
+                      const float* dev_pos, const int32_t* dev_species, float* dev_q, void* stream) {
+  if (!m || !dev_pos || !dev_species || !dev_q) {
+    set_error("null argument");
+    return NEPMI_INVALID_ARG;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  int rc = m->prepare(n_cfg, atom_off, cells, dev_pos, dev_species, st);
+  if (rc) return rc;
+  NepIO io = m->io(nullptr, nullptr, dev_q);
+  return m->ops->desc(st, io, m->params.ptr<float>(), false);
+}
+
+}  // extern "C"
+
+namespace nepmi {
+// Export the neighbour list of every atom in caller order (pairs within the
+// potential's cutoff only).
+__global__ void k_export_lists(int64_t n_slots, const float4* __restrict__ pos4, const int* __restrict__ cfg_of,
+                               const int* __restrict__ orig, const CfgDev* __restrict__ cfgs,
+                               const uint32_t* __restrict__ nbr, const int* __restrict__ cnt, float rc2, int cap,
+                               int* __restrict__ out_cnt, int* __restrict__ out_nbr, float* __restrict__ out_r) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_slots) return;
+  const int c = cfg_of[p];
+  if (c < 0) return;
+  const int i = orig[p];
+  const float4 xi = pos4[p];
+  float H[9];
+  for (int x = 0; x < 9; ++x) H[x] = cfgs[c].H[x];
+  int n = 0;
+  for (int k = 0; k < cnt[p]; ++k) {
+    const uint32_t e = nbr[(int64_t)k * n_slots + p];
+    const int q = (int)(e & kNbrMask);
+    const float4 xq = pos4[q];
+    float sx, sy, sz;
+    image_shift(H, e >> kNbrShift, sx, sy, sz);
+    const float rx = (xq.x - xi.x) + sx, ry = (xq.y - xi.y) + sy, rz = (xq.z - xi.z) + sz;
+    if (rx * rx + ry * ry + rz * rz < rc2) {
+      if (n < cap) {
+        out_nbr[(int64_t)i * cap + n] = orig[q];
+        out_r[((int64_t)i * cap + n) * 3 + 0] = rx;
+        out_r[((int64_t)i * cap + n) * 3 + 1] = ry;
+        out_r[((int64_t)i * cap + n) * 3 + 2] = rz;
+      }
+      ++n;
+    }
+  }
+  out_cnt[i] = n;
+}
+}  // namespace nepmi
+
+extern "C" int nepmi_neighbors(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, const double* cells,
+                               const float* dev_pos, const int32_t* dev_species, int32_t which, int32_t cap,
+                               int32_t* dev_count, int32_t* dev_nbr, float* dev_rvec, void* stream) {
+  if (!m || !dev_pos || !dev_species || !dev_count || !dev_nbr || !dev_rvec || cap < 0 || (which != 0 && which != 1)) {
+    set_error("invalid argument");
+    return NEPMI_INVALID_ARG;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  int rc = m->prepare(n_cfg, atom_off, cells, dev_pos, dev_species, st);
+  if (rc) return rc;
+  const float rc1 = (float)(which ? m->hp.rc_angular : m->hp.rc_radial);
+  const int64_t ns = m->nbr.n_slots;
+  hipLaunchKernelGGL(k_export_lists, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, ns,
+                     m->nbr.pos4.ptr<float4>(), m->nbr.cfg_of.ptr<int>(), m->nbr.orig.ptr<int>(),
+                     m->nbr.cfgs.ptr<CfgDev>(), which ? m->nbr.nbrA.ptr<uint32_t>() : m->nbr.nbrR.ptr<uint32_t>(),
+                     which ? m->nbr.cntA.ptr<int>() : m->nbr.cntR.ptr<int>(), rc1 * rc1, cap, dev_count, dev_nbr,
+                     dev_rvec);
+  NEPMI_HIP(hipGetLastError());
+  return NEPMI_OK;
+}

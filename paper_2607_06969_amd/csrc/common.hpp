@@ -1,0 +1,280 @@
+// common.hpp -- shared definitions of the HIP NEP library (gfx950).
+//
+// Compile-time model shapes, the per-configuration table, device math for the
+// Chebyshev radial basis (Eq. 12-15) and the real spherical harmonics (Eq. 16),
+// and host-side error plumbing.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/nepmi.h"
+
+namespace nepmi {
+
+// ---------------------------------------------------------------- model shape
+
+// Compile-time NEP shape.  Kernels keep per-atom accumulators in registers, so
+// every array length is a template constant.
+template <int T_, int NR_, int NA_, int BR_, int BA_, int L_, int F4_, int F5_, int H_>
+struct Shape {
+  static constexpr int T = T_;    // species
+  static constexpr int NR = NR_;  // radial functions
+  static constexpr int NA = NA_;  // angular functions
+  static constexpr int BR = BR_;  // Chebyshev basis size, radial
+  static constexpr int BA = BA_;  // Chebyshev basis size, angular
+  static constexpr int L = L_;    // l_max of the three-body term
+  static constexpr bool F4 = F4_ != 0;
+  static constexpr bool F5 = F5_ != 0;
+  static constexpr int H = H_;    // hidden neurons
+  static constexpr int K = L * L + 2 * L;  // real (l, m) components, l = 1..L
+  static constexpr int OFF4 = NR + L * NA;
+  static constexpr int OFF5 = OFF4 + (F4 ? NA : 0);
+  static constexpr int D = OFF5 + (F5 ? NA : 0);
+  static constexpr int NANG = D - NR;  // descriptors that depend on S
+  static constexpr int64_t PCR = (int64_t)T * T * NR * BR;
+  static constexpr int64_t PCA = (int64_t)T * T * NA * BA;
+  static constexpr int64_t PMLP = (int64_t)H * D + 2 * H + 1;
+  static constexpr int64_t P = PCR + PCA + T * PMLP;
+};
+
+// Shapes compiled into the library: the 64-atom single-element test model,
+// the three-species Ge-Sb-Te model with 4- and 5-body terms, and the model of
+// the paper's Table 2.
+using ShapeSmall = Shape<1, 4, 4, 8, 8, 4, 0, 0, 30>;
+using ShapeGST = Shape<3, 8, 8, 12, 12, 4, 1, 1, 50>;
+using ShapeTable2 = Shape<3, 10, 8, 8, 8, 4, 0, 0, 50>;
+
+constexpr int kWave = 64;
+constexpr int kNbrShift = 27;  // neighbour entry: index (27 bits) | image code (5 bits)
+constexpr uint32_t kNbrMask = (1u << kNbrShift) - 1u;
+constexpr int kMaxAtoms = (1 << kNbrShift) - 1;
+
+// One periodic configuration as the kernels see it.
+struct CfgDev {
+  float H[9];       // lattice vectors as rows, float32
+  double Hd[9];     // same, float64
+  double Hinv[9];   // inverse, float64 (fractional = x . Hinv)
+  int nb[3];        // bins per direction
+  int bin_off;      // first global bin of this configuration
+  int64_t atom_off; // first atom (caller's order)
+  int n_atoms;
+  int pad;
+};
+
+// Runtime (non-shape) parameters of a launch.
+struct Cutoffs {
+  float rcR, rcA;        // cutoffs of the potential
+  float rcR2, rcA2;      // squared
+  float rclR2, rclA2;    // squared list cutoffs (cutoff + skin)
+};
+
+// ------------------------------------------------------------ device helpers
+
+__device__ __forceinline__ void image_shift(const float* __restrict__ H, uint32_t code, float& sx, float& sy,
+                                            float& sz) {
+  const float w0 = (float)((int)(code / 9u) - 1);
+  const float w1 = (float)((int)((code / 3u) % 3u) - 1);
+  const float w2 = (float)((int)(code % 3u) - 1);
+  sx = w0 * H[0] + w1 * H[3] + w2 * H[6];
+  sy = w0 * H[1] + w1 * H[4] + w2 * H[7];
+  sz = w0 * H[2] + w1 * H[5] + w2 * H[8];
+}
+
+// Chebyshev radial basis of Eq. 12-15:
+//   x = 2 (d/rc - 1)^2 - 1,  f_c = (1 + cos(pi d/rc)) / 2,  Q_k = (T_k(x) + 1)/2 f_c.
+// Valid for d < rc (the caller tests the cutoff).
+template <int B>
+__device__ __forceinline__ void cheb_basis(float d, float rc_inv, float (&Q)[B]) {
+  const float t = d * rc_inv;
+  const float y = t - 1.0f;
+  const float x = 2.0f * y * y - 1.0f;
+  const float fc = 0.5f * (1.0f + cospif(t));
+  const float hf = 0.5f * fc;
+  float tm = 1.0f, tk = x;
+  Q[0] = fc;
+  if (B > 1) Q[1] = hf * (x + 1.0f);
+#pragma unroll
+  for (int k = 2; k < B; ++k) {
+    const float tn = 2.0f * x * tk - tm;
+    tm = tk;
+    tk = tn;
+    Q[k] = hf * (tn + 1.0f);
+  }
+}
+
+// Basis and its radial derivative dQ_k/dd.
+template <int B>
+__device__ __forceinline__ void cheb_basis_d(float d, float rc_inv, float (&Q)[B], float (&dQ)[B]) {
+  const float t = d * rc_inv;
+  const float y = t - 1.0f;
+  const float x = 2.0f * y * y - 1.0f;
+  const float dx = 4.0f * y * rc_inv;
+  float sn, cs;
+  sincospif(t, &sn, &cs);
+  const float fc = 0.5f * (1.0f + cs);
+  const float dfc = -0.5f * 3.14159265358979323846f * rc_inv * sn;
+  float tm = 1.0f, tk = x, dtm = 0.0f, dtk = 1.0f;
+  Q[0] = fc;
+  dQ[0] = dfc;
+  if (B > 1) {
+    Q[1] = 0.5f * (x + 1.0f) * fc;
+    dQ[1] = 0.5f * (dx * fc + (x + 1.0f) * dfc);
+  }
+#pragma unroll
+  for (int k = 2; k < B; ++k) {
+    const float tn = 2.0f * x * tk - tm;
+    const float dtn = 2.0f * tk + 2.0f * x * dtk - dtm;
+    tm = tk;
+    tk = tn;
+    dtm = dtk;
+    dtk = dtn;
+    Q[k] = 0.5f * (tn + 1.0f) * fc;
+    dQ[k] = 0.5f * (dtn * dx * fc + (tn + 1.0f) * dfc);
+  }
+}
+
+// Real orthonormal spherical harmonics Y_lm(u) of a unit vector u for
+// l = 1..L, ordered per l as m = 0, then (cos m, sin m) for m = 1..l.
+// Written as polynomials in the components of u (normalisation
+// sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!), times sqrt(2) for m > 0).
+namespace sh {
+constexpr float c1 = 0.488602511902919921f;     // sqrt(3/(4pi))
+constexpr float k20 = 0.315391565252520051f;    // sqrt(5/(16pi))
+constexpr float k21 = 1.092548430592079070f;    // sqrt(15/(4pi))
+constexpr float k22 = 0.546274215296039535f;    // sqrt(15/(16pi))
+constexpr float k30 = 0.373176332590115391f;    // sqrt(7/(16pi))
+constexpr float k31 = 0.457045799464465736f;    // sqrt(21/(32pi))
+constexpr float k32 = 1.445305721320277027f;    // sqrt(105/(16pi))
+constexpr float k32s = 2.890611442640554055f;   // sqrt(105/(4pi))
+constexpr float k33 = 0.590043589926643510f;    // sqrt(35/(32pi))
+constexpr float k40 = 0.105785546915204322f;    // (3/16) sqrt(1/pi)
+constexpr float k41 = 0.669046543557289168f;    // (3/4) sqrt(5/(2pi))
+constexpr float k42 = 0.473087347878780009f;    // (3/8) sqrt(5/pi)
+constexpr float k42s = 0.946174695757560018f;   // (3/4) sqrt(5/pi)
+constexpr float k43 = 1.770130769779930531f;    // (3/4) sqrt(35/(2pi))
+constexpr float k44 = 0.625835735449176135f;    // (3/16) sqrt(35/pi)
+constexpr float k44s = 2.503342941796704538f;   // (3/4) sqrt(35/pi)
+}  // namespace sh
+
+template <int L>
+__device__ __forceinline__ void real_sph(float x, float y, float z, float (&Y)[L * L + 2 * L]) {
+  using namespace sh;
+  Y[0] = c1 * z;
+  Y[1] = c1 * x;
+  Y[2] = c1 * y;
+  if constexpr (L >= 2) {
+    const float z2 = z * z;
+    Y[3] = k20 * (3.0f * z2 - 1.0f);
+    Y[4] = k21 * x * z;
+    Y[5] = k21 * y * z;
+    Y[6] = k22 * (x * x - y * y);
+    Y[7] = k21 * x * y;
+    if constexpr (L >= 3) {
+      const float x2my2 = x * x - y * y;
+      const float p = 5.0f * z2 - 1.0f;
+      Y[8] = k30 * z * (5.0f * z2 - 3.0f);
+      Y[9] = k31 * x * p;
+      Y[10] = k31 * y * p;
+      Y[11] = k32 * z * x2my2;
+      Y[12] = k32s * x * y * z;
+      Y[13] = k33 * x * (x * x - 3.0f * y * y);
+      Y[14] = k33 * y * (3.0f * x * x - y * y);
+      if constexpr (L >= 4) {
+        const float q = 7.0f * z2 - 3.0f;
+        const float r = 7.0f * z2 - 1.0f;
+        Y[15] = k40 * (35.0f * z2 * z2 - 30.0f * z2 + 3.0f);
+        Y[16] = k41 * x * z * q;
+        Y[17] = k41 * y * z * q;
+        Y[18] = k42 * x2my2 * r;
+        Y[19] = k42s * x * y * r;
+        Y[20] = k43 * x * z * (x * x - 3.0f * y * y);
+        Y[21] = k43 * y * z * (3.0f * x * x - y * y);
+        Y[22] = k44 * (x2my2 * x2my2 - 4.0f * x * x * y * y);
+        Y[23] = k44s * x * y * x2my2;
+      }
+    }
+  }
+}
+
+// g = sum_lm G_lm grad_u P_lm(u), where P_lm is the polynomial of real_sph
+// (extended off the unit sphere).  The gradient of Y_lm(r/|r|) with respect to
+// r is (I - u u^T) grad_u P_lm / |r|; the caller applies that projection.
+template <int L>
+__device__ __forceinline__ void real_sph_grad_dot(float x, float y, float z, const float (&G)[L * L + 2 * L],
+                                                  float& gx, float& gy, float& gz) {
+  using namespace sh;
+  gx = c1 * G[1];
+  gy = c1 * G[2];
+  gz = c1 * G[0];
+  if constexpr (L >= 2) {
+    gz += 6.0f * k20 * z * G[3];
+    gx += k21 * z * G[4];
+    gz += k21 * x * G[4];
+    gy += k21 * z * G[5];
+    gz += k21 * y * G[5];
+    gx += 2.0f * k22 * x * G[6];
+    gy -= 2.0f * k22 * y * G[6];
+    gx += k21 * y * G[7];
+    gy += k21 * x * G[7];
+    if constexpr (L >= 3) {
+      const float z2 = z * z, x2 = x * x, y2 = y * y;
+      const float p = 5.0f * z2 - 1.0f;
+      gz += k30 * (15.0f * z2 - 3.0f) * G[8];
+      gx += k31 * p * G[9];
+      gz += 10.0f * k31 * x * z * G[9];
+      gy += k31 * p * G[10];
+      gz += 10.0f * k31 * y * z * G[10];
+      gx += 2.0f * k32 * x * z * G[11];
+      gy -= 2.0f * k32 * y * z * G[11];
+      gz += k32 * (x2 - y2) * G[11];
+      gx += k32s * y * z * G[12];
+      gy += k32s * x * z * G[12];
+      gz += k32s * x * y * G[12];
+      gx += 3.0f * k33 * (x2 - y2) * G[13];
+      gy -= 6.0f * k33 * x * y * G[13];
+      gx += 6.0f * k33 * x * y * G[14];
+      gy += 3.0f * k33 * (x2 - y2) * G[14];
+      if constexpr (L >= 4) {
+        const float q = 7.0f * z2 - 3.0f;
+        const float r = 7.0f * z2 - 1.0f;
+        gz += k40 * (140.0f * z2 * z - 60.0f * z) * G[15];
+        gx += k41 * z * q * G[16];
+        gz += k41 * x * (21.0f * z2 - 3.0f) * G[16];
+        gy += k41 * z * q * G[17];
+        gz += k41 * y * (21.0f * z2 - 3.0f) * G[17];
+        gx += 2.0f * k42 * x * r * G[18];
+        gy -= 2.0f * k42 * y * r * G[18];
+        gz += 14.0f * k42 * z * (x2 - y2) * G[18];
+        gx += k42s * y * r * G[19];
+        gy += k42s * x * r * G[19];
+        gz += 14.0f * k42s * x * y * z * G[19];
+        gx += 3.0f * k43 * z * (x2 - y2) * G[20];
+        gy -= 6.0f * k43 * x * y * z * G[20];
+        gz += k43 * x * (x2 - 3.0f * y2) * G[20];
+        gx += 6.0f * k43 * x * y * z * G[21];
+        gy += 3.0f * k43 * z * (x2 - y2) * G[21];
+        gz += k43 * y * (3.0f * x2 - y2) * G[21];
+        gx += 4.0f * k44 * x * (x2 - 3.0f * y2) * G[22];
+        gy += 4.0f * k44 * y * (y2 - 3.0f * x2) * G[22];
+        gx += k44s * y * (3.0f * x2 - y2) * G[23];
+        gy += k44s * x * (x2 - 3.0f * y2) * G[23];
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------- host helpers
+
+void set_error(const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+}  // namespace nepmi
+
+#define NEPMI_HIP(call)                                             \
+  do {                                                              \
+    hipError_t _e = (call);                                         \
+    if (_e != hipSuccess) return ::nepmi::hip_fail(_e, #call);      \
+  } while (0)

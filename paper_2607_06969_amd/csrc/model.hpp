@@ -1,0 +1,42 @@
+// model.hpp -- the model handle and per-shape kernel dispatch.
+#pragma once
+
+#include "nep_kernels.hpp"
+#include "reduce.hpp"
+
+namespace nepmi {
+
+// Kernel set of one compiled shape.
+struct Ops {
+  int (*desc)(hipStream_t, const NepIO&, const float*, bool);
+  int (*force)(hipStream_t, const NepIO&, const float*);
+  int (*gather)(hipStream_t, const NepIO&);
+  int T, NR, NA, BR, BA, L, D, NANG;
+  int64_t P;
+};
+
+const Ops* find_ops(const nepmi_hparams& hp);
+
+// Training-only buffers (see train.hip).
+struct TrainBufs {
+  DevBuf seeds_e, seeds_mu, lam_proc, tan_fp, ebar_proc, gpart, grad64, loss64;
+  DevBuf qdot, qbar, atom_w, atom_z;
+  DevBuf Fuser, Euser, Vuser, Wuser;
+};
+
+}  // namespace nepmi
+
+struct nepmi_model {
+  nepmi_hparams hp{};
+  const nepmi::Ops* ops = nullptr;
+  nepmi::DevBuf params;
+  nepmi::NbrPipeline nbr;
+  nepmi::Reducer red;
+  nepmi::DevBuf fp, aR, Ei, frad, fA, Wi, Eproc;
+  nepmi::TrainBufs tr;
+  int device = 0;
+  // Prepare the batch: neighbour lists, work buffers and reduction plan.
+  int prepare(int n_cfg, const int64_t* atom_off, const double* cells, const float* pos, const int32_t* species,
+              hipStream_t st);
+  nepmi::NepIO io(float* Fuser, float4* Fproc, float* qout);
+};

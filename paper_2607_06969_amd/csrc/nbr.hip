@@ -1,0 +1,572 @@
+// nbr.hip -- cell-list binning, processing order and Verlet neighbour lists.
+//
+// The paper builds neighbour lists on the fly with linear complexity before
+// every evaluation (Sec. 3.4, Sec. 3.5).  Here that is a counting sort of the
+// atoms into cell bins, done on the GPU, followed by a 27-bin stencil search.
+//
+// Processing order.  Atoms are renumbered into "slots" sorted by
+// (species, global bin, caller index).  Each species group starts at a
+// multiple of the wavefront size, so every wavefront of the evaluation
+// kernels holds atoms of a single species and reads that species'
+// coefficients and network weights through the scalar unit.  Padding slots
+// carry orig = -1.
+//
+// Neighbour entries are 32-bit: slot index (27 bits) | image code (5 bits),
+// code = (w0+1)*9 + (w1+1)*3 + (w2+1) for the lattice shift w in {-1,0,1}^3.
+// Lists are column-major, entry k of slot p at [k * n_slots + p].
+#include "nbr.hpp"
+
+namespace nepmi {
+
+// ------------------------------------------------------------------ staging
+
+// Per caller-order atom: validate, wrap into the cell, find its bin and sort key.
+__global__ void k_stage(int64_t N, int n_cfg, const int64_t* __restrict__ atom_off, const CfgDev* __restrict__ cfgs,
+                        const float* __restrict__ pos, int pos_stride, const int32_t* __restrict__ species,
+                        int n_species, int total_bins, float4* __restrict__ pos_tmp, int* __restrict__ cfg_tmp,
+                        int* __restrict__ key, int* __restrict__ cnt, int* __restrict__ flags,
+                        const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  // configuration of atom i: binary search in atom_off
+  int lo = 0, hi = n_cfg;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (atom_off[mid] <= i) lo = mid; else hi = mid;
+  }
+  const CfgDev& C = cfgs[lo];
+  const int z = species[i];
+  if (z < 0 || z >= n_species) {
+    atomicOr(&flags[kFlagBadSpecies], 1);
+    key[i] = -1;
+    return;
+  }
+  const float x = pos[i * pos_stride + 0], y = pos[i * pos_stride + 1], w = pos[i * pos_stride + 2];
+  if (!(isfinite(x) && isfinite(y) && isfinite(w))) {
+    atomicOr(&flags[kFlagNaN], 1);
+    key[i] = -1;
+    return;
+  }
+  int b[3];
+  double m[3];
+  for (int a = 0; a < 3; ++a) {
+    const double s = (double)x * C.Hinv[a] + (double)y * C.Hinv[3 + a] + (double)w * C.Hinv[6 + a];
+    m[a] = floor(s);
+    int bb = (int)floor((s - m[a]) * C.nb[a]);
+    b[a] = bb < 0 ? 0 : (bb >= C.nb[a] ? C.nb[a] - 1 : bb);
+  }
+  float o[3] = {x, y, w};
+  if (m[0] != 0.0 || m[1] != 0.0 || m[2] != 0.0) {
+    // wrap by whole lattice vectors (float64, then rounded once)
+    for (int a = 0; a < 3; ++a)
+      o[a] = (float)((double)o[a] - m[0] * C.Hd[a] - m[1] * C.Hd[3 + a] - m[2] * C.Hd[6 + a]);
+  }
+  const int gbin = C.bin_off + (b[0] * C.nb[1] + b[1]) * C.nb[2] + b[2];
+  const int k = z * total_bins + gbin;
+  key[i] = k;
+  pos_tmp[i] = make_float4(o[0], o[1], o[2], __int_as_float(z));
+  cfg_tmp[i] = lo;
+  atomicAdd(&cnt[k], 1);
+}
+
+// ------------------------------------------------------------ exclusive scan
+
+constexpr int kScanBlock = 1024;
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kScanBlock * kScanItems;
+
+__device__ int block_exclusive_scan(int v, int* sh, int& total) {
+  // Hillis-Steele within a block of kScanBlock threads (deterministic).
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = 1; off < kScanBlock; off <<= 1) {
+    const int add = t >= off ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += add;
+    __syncthreads();
+  }
+  total = sh[kScanBlock - 1];
+  const int incl = sh[t];
+  __syncthreads();
+  return incl - v;
+}
+
+// out[0..M] = exclusive prefix sum of in[0..M-1] (out[M] = total), tile level.
+__global__ __launch_bounds__(kScanBlock) void k_scan_tiles(const int* __restrict__ in, int M, int* __restrict__ out,
+                                                           int* __restrict__ tile_sums, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  __shared__ int sh[kScanBlock];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  int v[kScanItems], s = 0;
+  for (int j = 0; j < kScanItems; ++j) {
+    v[j] = (base + j < M) ? in[base + j] : 0;
+    s += v[j];
+  }
+  int total;
+  int ex = block_exclusive_scan(s, sh, total);
+  for (int j = 0; j < kScanItems; ++j) {
+    if (base + j < M) out[base + j] = ex;
+    ex += v[j];
+  }
+  if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
+}
+
+// Scan of the tile sums (one block; n_tiles <= kScanTile) and the final total.
+__global__ __launch_bounds__(kScanBlock) void k_scan_sums(int* __restrict__ tile_sums, int n_tiles,
+                                                          int* __restrict__ out, int M,
+                                                          const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  __shared__ int sh[kScanBlock];
+  const int base = threadIdx.x * kScanItems;
+  int v[kScanItems], s = 0;
+  for (int j = 0; j < kScanItems; ++j) {
+    v[j] = (base + j < n_tiles) ? tile_sums[base + j] : 0;
+    s += v[j];
+  }
+  int total;
+  int ex = block_exclusive_scan(s, sh, total);
+  for (int j = 0; j < kScanItems; ++j) {
+    if (base + j < n_tiles) tile_sums[base + j] = ex;
+    ex += v[j];
+  }
+  if (threadIdx.x == 0) out[M] = total;
+}
+
+__global__ void k_scan_add(int* __restrict__ out, int M, const int* __restrict__ tile_sums,
+                           const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < M) out[i] += tile_sums[i / kScanTile];
+}
+
+// ------------------------------------------------------- processing order
+
+// base[z] = first slot of species z; groups are padded to the wavefront size.
+__global__ void k_species_base(const int* __restrict__ start, int total_bins, int n_species, int* __restrict__ base,
+                               const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int acc = 0;
+  for (int z = 0; z < n_species; ++z) {
+    base[z] = acc;
+    const int c = start[(z + 1) * total_bins] - start[z * total_bins];
+    acc += (c + kWave - 1) / kWave * kWave;
+  }
+  base[n_species] = acc;
+}
+
+// Slot of every atom (order inside a key decided by an atomic; made
+// deterministic by k_sort_keys).
+__global__ void k_scatter(int64_t N, const int* __restrict__ key, const int* __restrict__ start,
+                          int* __restrict__ cursor, const int* __restrict__ base, int total_bins,
+                          int* __restrict__ perm, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int k = key[i];
+  if (k < 0) return;
+  const int z = k / total_bins;
+  // cursor[k] starts at start[k]: the returned value is start[k] + rank in key
+  const int r = atomicAdd(&cursor[k], 1);
+  const int p = base[z] + (r - start[z * total_bins]);
+  perm[p] = (int)i;
+}
+
+// Sort the slots of each key by caller index (insertion sort; keys hold few atoms).
+__global__ void k_sort_keys(int M, const int* __restrict__ start, const int* __restrict__ base, int total_bins,
+                            int* __restrict__ perm, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= M) return;
+  const int z = k / total_bins;
+  const int n = start[k + 1] - start[k];
+  if (n < 2) return;
+  int* s = perm + base[z] + (start[k] - start[z * total_bins]);
+  for (int a = 1; a < n; ++a) {
+    const int v = s[a];
+    int b = a - 1;
+    while (b >= 0 && s[b] > v) {
+      s[b + 1] = s[b];
+      --b;
+    }
+    s[b + 1] = v;
+  }
+}
+
+// Fill the slot arrays.  Padding slots get orig = -1 and their group's species.
+__global__ void k_fill_slots(int64_t n_slots, const int* __restrict__ base, const int* __restrict__ start,
+                             int total_bins, int n_species, const int* __restrict__ perm,
+                             const float4* __restrict__ pos_tmp, const int* __restrict__ cfg_tmp,
+                             const int* __restrict__ key, float4* __restrict__ pos4, int* __restrict__ cfg_of,
+                             int* __restrict__ orig, int* __restrict__ bin_of, int* __restrict__ slot_of,
+                             const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_slots) return;
+  int z = -1;
+  for (int t = 0; t < n_species; ++t)
+    if (p >= base[t] && p < base[t + 1]) z = t;
+  if (z >= 0) {
+    const int r = (int)(p - base[z]);
+    const int c = start[(z + 1) * total_bins] - start[z * total_bins];
+    if (r < c) {
+      const int i = perm[p];
+      pos4[p] = pos_tmp[i];
+      cfg_of[p] = cfg_tmp[i];
+      orig[p] = i;
+      bin_of[p] = key[i] - z * total_bins;
+      if (slot_of) slot_of[i] = (int)p;
+      return;
+    }
+  } else {
+    z = 0;
+  }
+  pos4[p] = make_float4(0.f, 0.f, 0.f, __int_as_float(z));
+  cfg_of[p] = -1;
+  orig[p] = -1;
+  bin_of[p] = -1;
+}
+
+// --------------------------------------------------------- Verlet lists
+
+// For every active slot, scan the 27 stencil bins (with periodic images) and
+// keep neighbours within the radial and angular list cutoffs.
+__global__ __launch_bounds__(256) void k_build_lists(int64_t n_slots, int n_species, int total_bins,
+                                                     const CfgDev* __restrict__ cfgs,
+                                                     const float4* __restrict__ pos4, const int* __restrict__ cfg_of,
+                                                     const int* __restrict__ bin_of, const int* __restrict__ start,
+                                                     const int* __restrict__ base, float rclR2, float rclA2, int capR,
+                                                     int capA, uint32_t* __restrict__ nbrR, int* __restrict__ cntR,
+                                                     uint32_t* __restrict__ nbrA, int* __restrict__ cntA,
+                                                     int* __restrict__ flags, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_slots) return;
+  const int c = cfg_of[p];
+  if (c < 0) {
+    cntR[p] = 0;
+    cntA[p] = 0;
+    return;
+  }
+  const CfgDev& C = cfgs[c];
+  const float4 xi = pos4[p];
+  const int lb = bin_of[p] - C.bin_off;
+  const int b0 = lb / (C.nb[1] * C.nb[2]), b1 = (lb / C.nb[2]) % C.nb[1], b2 = lb % C.nb[2];
+  int kR = 0, kA = 0;
+  for (int o = 0; o < 27; ++o) {
+    int t0 = b0 + o / 9 - 1, t1 = b1 + (o / 3) % 3 - 1, t2 = b2 + o % 3 - 1;
+    const int w0 = t0 < 0 ? -1 : (t0 >= C.nb[0] ? 1 : 0);
+    const int w1 = t1 < 0 ? -1 : (t1 >= C.nb[1] ? 1 : 0);
+    const int w2 = t2 < 0 ? -1 : (t2 >= C.nb[2] ? 1 : 0);
+    t0 -= w0 * C.nb[0];
+    t1 -= w1 * C.nb[1];
+    t2 -= w2 * C.nb[2];
+    const uint32_t code = (uint32_t)((w0 + 1) * 9 + (w1 + 1) * 3 + (w2 + 1));
+    float sx, sy, sz;
+    image_shift(C.H, code, sx, sy, sz);
+    const int tb = C.bin_off + (t0 * C.nb[1] + t1) * C.nb[2] + t2;
+    for (int z = 0; z < n_species; ++z) {
+      const int k = z * total_bins + tb;
+      const int q0 = base[z] + start[k] - start[z * total_bins];
+      const int q1 = q0 + start[k + 1] - start[k];
+      for (int q = q0; q < q1; ++q) {
+        if (q == (int)p && code == 13u) continue;
+        const float4 xq = pos4[q];
+        const float rx = (xq.x - xi.x) + sx, ry = (xq.y - xi.y) + sy, rz = (xq.z - xi.z) + sz;
+        const float d2 = rx * rx + ry * ry + rz * rz;
+        if (d2 < rclR2) {
+          const uint32_t e = (uint32_t)q | (code << kNbrShift);
+          if (kR < capR) nbrR[(int64_t)kR * n_slots + p] = e;
+          ++kR;
+          if (d2 < rclA2) {
+            if (kA < capA) nbrA[(int64_t)kA * n_slots + p] = e;
+            ++kA;
+          }
+        }
+      }
+    }
+  }
+  cntR[p] = kR < capR ? kR : capR;
+  cntA[p] = kA < capA ? kA : capA;
+  if (kR > capR || kA > capA) atomicOr(&flags[kFlagOverflow], 1);
+  atomicMax(&flags[kFlagMaxR], kR);
+  atomicMax(&flags[kFlagMaxA], kA);
+}
+
+// revA[k][p] = flat index of the entry (q -> p) in q's angular list, where
+// entry k of p is (p -> q).  Every pair is listed from both sides because the
+// pair vector is computed with the same rounding in both directions.
+__global__ __launch_bounds__(256) void k_build_rev(int64_t n_slots, const uint32_t* __restrict__ nbrA,
+                                                   const int* __restrict__ cntA, int* __restrict__ revA,
+                                                   int* __restrict__ flags, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_slots) return;
+  const int n = cntA[p];
+  for (int k = 0; k < n; ++k) {
+    const uint32_t e = nbrA[(int64_t)k * n_slots + p];
+    const int q = (int)(e & kNbrMask);
+    const uint32_t want = (uint32_t)p | ((26u - (e >> kNbrShift)) << kNbrShift);
+    const int nq = cntA[q];
+    int found = -1;
+    for (int j = 0; j < nq; ++j)
+      if (nbrA[(int64_t)j * n_slots + q] == want) {
+        found = j;
+        break;
+      }
+    if (found < 0) {
+      atomicOr(&flags[kFlagAsym], 1);
+      found = 0;
+    }
+    revA[(int64_t)k * n_slots + p] = (int)((int64_t)found * n_slots + q);
+  }
+}
+
+// ---------------------------------------------------------------- host side
+
+static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+__global__ void k_fill_int(int* __restrict__ p, int64_t n, int v, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_copy_int(int* __restrict__ dst, const int* __restrict__ src, int64_t n,
+                           const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+void fill_int(hipStream_t st, int* p, int64_t n, int v, const int* gate) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_int, dim3(nblk(n, 256)), dim3(256), 0, st, p, n, v, gate);
+}
+
+int DevBuf::ensure(size_t n) {
+  if (n <= bytes && p) return NEPMI_OK;
+  release();
+  const size_t want = n < 256 ? 256 : n;
+  NEPMI_HIP(hipMalloc(&p, want));
+  bytes = want;
+  return NEPMI_OK;
+}
+
+void DevBuf::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+static void cell_geometry(const double* H, double w[3], double Hi[9], double& det) {
+  const double *a = H, *b = H + 3, *c = H + 6;
+  const double bc[3] = {b[1] * c[2] - b[2] * c[1], b[2] * c[0] - b[0] * c[2], b[0] * c[1] - b[1] * c[0]};
+  const double ca[3] = {c[1] * a[2] - c[2] * a[1], c[2] * a[0] - c[0] * a[2], c[0] * a[1] - c[1] * a[0]};
+  const double ab[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+  det = a[0] * bc[0] + a[1] * bc[1] + a[2] * bc[2];
+  const double V = fabs(det);
+  w[0] = V / sqrt(bc[0] * bc[0] + bc[1] * bc[1] + bc[2] * bc[2]);
+  w[1] = V / sqrt(ca[0] * ca[0] + ca[1] * ca[1] + ca[2] * ca[2]);
+  w[2] = V / sqrt(ab[0] * ab[0] + ab[1] * ab[1] + ab[2] * ab[2]);
+  // rows of Hinv^T are bc, ca, ab divided by det: fractional s_a = x . (col a of Hinv)
+  for (int x = 0; x < 3; ++x) {
+    Hi[3 * x + 0] = bc[x] / det;
+    Hi[3 * x + 1] = ca[x] / det;
+    Hi[3 * x + 2] = ab[x] / det;
+  }
+}
+
+int NbrPipeline::setup(int n_cfg_, const int64_t* atom_off, const double* cells, int n_species_, double rcR,
+                       double rcA, double skin_, hipStream_t st) {
+  if (n_cfg_ < 1 || !atom_off || !cells) {
+    set_error("n_cfg must be >= 1 and atom_off, cells non-null");
+    return NEPMI_INVALID_ARG;
+  }
+  if (atom_off[0] != 0) {
+    set_error("atom_off[0] must be 0");
+    return NEPMI_INVALID_ARG;
+  }
+  for (int c = 0; c < n_cfg_; ++c)
+    if (atom_off[c + 1] < atom_off[c]) {
+      set_error("atom_off must be non-decreasing");
+      return NEPMI_INVALID_ARG;
+    }
+  const int64_t N_ = atom_off[n_cfg_];
+  if (N_ > (int64_t)kMaxAtoms - 64 * n_species_) {
+    set_error("too many atoms for 27-bit neighbour indices");
+    return NEPMI_INVALID_ARG;
+  }
+  const double rcl = rcR + skin_;
+  std::vector<CfgDev> hc((size_t)n_cfg_);
+  int64_t bins = 0;
+  for (int c = 0; c < n_cfg_; ++c) {
+    CfgDev& C = hc[(size_t)c];
+    const double* H = cells + 9 * (size_t)c;
+    double w[3], det;
+    cell_geometry(H, w, C.Hinv, det);
+    if (!(fabs(det) > 0.0) || !std::isfinite(det)) {
+      set_error("singular or non-finite cell");
+      return NEPMI_INVALID_ARG;
+    }
+    for (int a = 0; a < 3; ++a) {
+      if (w[a] < 2.0 * rcl) {
+        set_error("cell width " + std::to_string(w[a]) + " of configuration " + std::to_string(c) +
+                  " is below 2 * (rc_radial + skin) = " + std::to_string(2.0 * rcl));
+        return NEPMI_CELL_TOO_SMALL;
+      }
+      int nb = (int)floor(w[a] / (rcl * (1.0 + 1e-6)));
+      C.nb[a] = nb < 1 ? 1 : (nb > 1024 ? 1024 : nb);
+    }
+    for (int x = 0; x < 9; ++x) {
+      C.Hd[x] = H[x];
+      C.H[x] = (float)H[x];
+    }
+    C.bin_off = (int)bins;
+    C.atom_off = atom_off[c];
+    C.n_atoms = (int)(atom_off[c + 1] - atom_off[c]);
+    C.pad = 0;
+    bins += (int64_t)C.nb[0] * C.nb[1] * C.nb[2];
+  }
+  if (bins * n_species_ > (int64_t)1 << 30) {
+    set_error("too many cell bins");
+    return NEPMI_INVALID_ARG;
+  }
+  N = N_;
+  n_cfg = n_cfg_;
+  n_species = n_species_;
+  n_slots = N + (int64_t)kWave * n_species_;
+  total_bins = (int)bins;
+  skin = skin_;
+  const float rlR = (float)(rcR + skin_), rlA = (float)(rcA + skin_);
+  rclR2 = rlR * rlR;
+  rclA2 = rlA * rlA;
+  host_cfgs = hc;
+  host_off.assign(atom_off, atom_off + n_cfg_ + 1);
+  const int64_t M = (int64_t)n_species_ * bins;
+  const int64_t n_tiles = (M + kScanTile - 1) / kScanTile;
+  if (n_tiles > kScanTile) {
+    set_error("too many sort keys");
+    return NEPMI_INVALID_ARG;
+  }
+  int rc;
+  const size_t Na = (size_t)(N > 0 ? N : 1);
+  if ((rc = cfgs.ensure(sizeof(CfgDev) * (size_t)n_cfg_)) || (rc = atom_off_dev.ensure(8 * (size_t)(n_cfg_ + 1))) ||
+      (rc = key.ensure(4 * Na)) || (rc = cnt.ensure(4 * (size_t)(M + 1))) || (rc = start.ensure(4 * (size_t)(M + 1))) ||
+      (rc = cursor.ensure(4 * (size_t)(M + 1))) || (rc = tile_sums.ensure(4 * (size_t)(n_tiles + 1))) ||
+      (rc = base.ensure(4 * (size_t)(n_species_ + 1))) || (rc = perm.ensure(4 * (size_t)n_slots)) ||
+      (rc = pos_tmp.ensure(16 * Na)) || (rc = cfg_tmp.ensure(4 * Na)) || (rc = pos4.ensure(16 * (size_t)n_slots)) ||
+      (rc = cfg_of.ensure(4 * (size_t)n_slots)) || (rc = orig.ensure(4 * (size_t)n_slots)) ||
+      (rc = bin_of.ensure(4 * (size_t)n_slots)) || (rc = slot_of.ensure(4 * Na)) ||
+      (rc = cntR.ensure(4 * (size_t)n_slots)) || (rc = cntA.ensure(4 * (size_t)n_slots)) ||
+      (rc = flags.ensure(4 * kFlagCount)))
+    return rc;
+  NEPMI_HIP(hipMemcpyAsync(cfgs.p, hc.data(), sizeof(CfgDev) * (size_t)n_cfg_, hipMemcpyHostToDevice, st));
+  NEPMI_HIP(hipMemcpyAsync(atom_off_dev.p, atom_off, 8 * (size_t)(n_cfg_ + 1), hipMemcpyHostToDevice, st));
+  if (capR == 0) {
+    // initial capacity from the densest configuration
+    double dmax = 0.0;
+    for (int c = 0; c < n_cfg_; ++c) {
+      const double* H = cells + 9 * (size_t)c;
+      double w[3], Hi[9], det;
+      cell_geometry(H, w, Hi, det);
+      const double dens = (double)hc[(size_t)c].n_atoms / fabs(det);
+      dmax = dens > dmax ? dens : dmax;
+    }
+    const double vR = 4.18879020478639 * rlR * rlR * rlR, vA = 4.18879020478639 * rlA * rlA * rlA;
+    capR = (int)(1.5 * dmax * vR) + 16;
+    capA = (int)(1.5 * dmax * vA) + 16;
+  }
+  return ensure_lists(capR, capA);
+}
+
+int NbrPipeline::ensure_lists(int capR_, int capA_) {
+  capR = capR_;
+  capA = capA_;
+  int rc;
+  if ((rc = nbrR.ensure(4 * (size_t)capR * (size_t)n_slots)) || (rc = nbrA.ensure(4 * (size_t)capA * (size_t)n_slots)) ||
+      (rc = revA.ensure(4 * (size_t)capA * (size_t)n_slots)))
+    return rc;
+  return NEPMI_OK;
+}
+
+int NbrPipeline::check_flags(hipStream_t st, int* hf) {
+  NEPMI_HIP(hipMemcpyAsync(hf, flags.p, sizeof(int) * kFlagCount, hipMemcpyDeviceToHost, st));
+  NEPMI_HIP(hipStreamSynchronize(st));
+  if (hf[kFlagNaN]) {
+    set_error("non-finite position");
+    return NEPMI_NAN_DETECTED;
+  }
+  if (hf[kFlagBadSpecies]) {
+    set_error("species index out of range");
+    return NEPMI_INVALID_ARG;
+  }
+  return NEPMI_OK;
+}
+
+int NbrPipeline::build(hipStream_t st, const float* pos, const int32_t* species) {
+  fill_int(st, flags.ptr<int>(), kFlagCount, 0, nullptr);
+  int rc = launch_sort(st, pos, 3, species, n_species, nullptr);
+  if (rc) return rc;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    if ((rc = launch_lists(st, n_species, nullptr))) return rc;
+    int hf[kFlagCount];
+    if ((rc = check_flags(st, hf))) return rc;
+    if (!hf[kFlagOverflow]) {
+      asym = hf[kFlagAsym];
+      return NEPMI_OK;
+    }
+    // grow to the largest list seen plus a margin and rebuild the lists
+    if ((rc = ensure_lists(hf[kFlagMaxR] + 8, hf[kFlagMaxA] + 8))) return rc;
+    fill_int(st, flags.ptr<int>(), kFlagCount, 0, nullptr);
+  }
+  set_error("neighbour capacity overflow after regrow");
+  return NEPMI_NEIGHBOR_OVERFLOW;
+}
+
+int NbrPipeline::launch_sort(hipStream_t st, const float* pos, int pos_stride, const int32_t* species, int n_species,
+                             const int* gate) {
+  const int M = n_species * total_bins;
+  fill_int(st, cnt.ptr<int>(), M + 1, 0, gate);
+  if (N > 0)
+  hipLaunchKernelGGL(k_stage, dim3(nblk(N, 256)), dim3(256), 0, st, N, n_cfg, atom_off_dev.ptr<int64_t>(),
+                     cfgs.ptr<CfgDev>(), pos, pos_stride, species, n_species, total_bins, pos_tmp.ptr<float4>(),
+                     cfg_tmp.ptr<int>(), key.ptr<int>(), cnt.ptr<int>(), flags.ptr<int>(), gate);
+  const int n_tiles = (M + kScanTile - 1) / kScanTile;
+  hipLaunchKernelGGL(k_scan_tiles, dim3(n_tiles), dim3(kScanBlock), 0, st, cnt.ptr<int>(), M, start.ptr<int>(),
+                     tile_sums.ptr<int>(), gate);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, st, tile_sums.ptr<int>(), n_tiles, start.ptr<int>(),
+                     M, gate);
+  hipLaunchKernelGGL(k_scan_add, dim3(nblk(M, 256)), dim3(256), 0, st, start.ptr<int>(), M, tile_sums.ptr<int>(),
+                     gate);
+  hipLaunchKernelGGL(k_species_base, dim3(1), dim3(64), 0, st, start.ptr<int>(), total_bins, n_species,
+                     base.ptr<int>(), gate);
+  hipLaunchKernelGGL(k_copy_int, dim3(nblk(M, 256)), dim3(256), 0, st, cursor.ptr<int>(), start.ptr<int>(), (int64_t)M,
+                     gate);
+  if (N > 0)
+  hipLaunchKernelGGL(k_scatter, dim3(nblk(N, 256)), dim3(256), 0, st, N, key.ptr<int>(), start.ptr<int>(),
+                     cursor.ptr<int>(), base.ptr<int>(), total_bins, perm.ptr<int>(), gate);
+  hipLaunchKernelGGL(k_sort_keys, dim3(nblk(M, 256)), dim3(256), 0, st, M, start.ptr<int>(), base.ptr<int>(),
+                     total_bins, perm.ptr<int>(), gate);
+  hipLaunchKernelGGL(k_fill_slots, dim3(nblk(n_slots, 256)), dim3(256), 0, st, n_slots, base.ptr<int>(),
+                     start.ptr<int>(), total_bins, n_species, perm.ptr<int>(), pos_tmp.ptr<float4>(),
+                     cfg_tmp.ptr<int>(), key.ptr<int>(), pos4.ptr<float4>(), cfg_of.ptr<int>(), orig.ptr<int>(),
+                     bin_of.ptr<int>(), slot_of.ptr<int>(), gate);
+  NEPMI_HIP(hipGetLastError());
+  return NEPMI_OK;
+}
+
+int NbrPipeline::launch_lists(hipStream_t st, int n_species, const int* gate) {
+  hipLaunchKernelGGL(k_build_lists, dim3(nblk(n_slots, 256)), dim3(256), 0, st, n_slots, n_species, total_bins,
+                     cfgs.ptr<CfgDev>(), pos4.ptr<float4>(), cfg_of.ptr<int>(), bin_of.ptr<int>(), start.ptr<int>(),
+                     base.ptr<int>(), rclR2, rclA2, capR, capA, nbrR.ptr<uint32_t>(), cntR.ptr<int>(),
+                     nbrA.ptr<uint32_t>(), cntA.ptr<int>(), flags.ptr<int>(), gate);
+  hipLaunchKernelGGL(k_build_rev, dim3(nblk(n_slots, 256)), dim3(256), 0, st, n_slots, nbrA.ptr<uint32_t>(),
+                     cntA.ptr<int>(), revA.ptr<int>(), flags.ptr<int>(), gate);
+  NEPMI_HIP(hipGetLastError());
+  return NEPMI_OK;
+}
+
+}  // namespace nepmi

@@ -1,0 +1,77 @@
+// nbr.hpp -- device buffers and the neighbour-list pipeline (host side).
+#pragma once
+
+#include <vector>
+
+#include "common.hpp"
+
+namespace nepmi {
+
+// Slots of the device flag word array.
+enum {
+  kFlagOverflow = 0,   // a list exceeded its capacity
+  kFlagMaxR = 1,       // largest radial list length seen
+  kFlagMaxA = 2,       // largest angular list length seen
+  kFlagNaN = 3,        // non-finite input position
+  kFlagBadSpecies = 4, // species out of range
+  kFlagAsym = 5,       // an angular pair listed from one side only
+  kFlagRebuild = 6,    // MD: rebuild the lists in this step
+  kFlagCount = 16
+};
+
+// Device allocation that grows on demand (contents are not preserved).
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  template <class T>
+  T* ptr() const {
+    return static_cast<T*>(p);
+  }
+  int ensure(size_t n);
+  void release();
+  ~DevBuf() { release(); }
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+};
+
+// Neighbour lists of one batch of configurations, in processing order.
+struct NbrPipeline {
+  int64_t N = 0;        // atoms
+  int n_cfg = 0;
+  int n_species = 0;
+  int64_t n_slots = 0;  // N + n_species * wavefront (upper bound of used slots)
+  int total_bins = 0;
+  int capR = 0, capA = 0;
+  float rclR2 = 0.f, rclA2 = 0.f;
+  double skin = 0.0;
+  int asym = 0;  // last build found a one-sided angular pair
+  std::vector<CfgDev> host_cfgs;
+  std::vector<int64_t> host_off;
+
+  DevBuf cfgs, atom_off_dev;
+  DevBuf key, cnt, start, cursor, tile_sums, base, perm, pos_tmp, cfg_tmp;
+  DevBuf pos4, cfg_of, orig, bin_of, slot_of;
+  DevBuf nbrR, cntR, nbrA, cntA, revA;
+  DevBuf flags;
+
+  // Host-side setup of a batch: validates the cells, computes bins, sizes
+  // buffers and uploads the configuration table.  Returns NEPMI_* codes.
+  int setup(int n_cfg, const int64_t* atom_off, const double* cells, int n_species, double rcR, double rcA,
+            double skin, hipStream_t st);
+  // Sizes the lists for capR x capA entries per slot.
+  int ensure_lists(int capR_, int capA_);
+  // Stage, bin and sort (pos: N x pos_stride floats).  gate: optional device
+  // flag; every kernel returns at once when *gate == 0.
+  int launch_sort(hipStream_t st, const float* pos, int pos_stride, const int32_t* species, int n_species,
+                  const int* gate);
+  int launch_lists(hipStream_t st, int n_species, const int* gate);
+  // Full build with capacity check and regrow (synchronises st once or twice).
+  int build(hipStream_t st, const float* pos, const int32_t* species);
+  int check_flags(hipStream_t st, int* host_flags);
+};
+
+// Fill an int array with a value on the stream (graph-safe, no memset node).
+void fill_int(hipStream_t st, int* p, int64_t n, int v, const int* gate);
+
+}  // namespace nepmi

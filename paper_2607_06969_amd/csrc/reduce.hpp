@@ -1,0 +1,27 @@
+// reduce.hpp -- deterministic float64 per-configuration reductions.
+#pragma once
+
+#include <vector>
+
+#include "nbr.hpp"
+
+namespace nepmi {
+
+constexpr int kRedValues = 11;    // energy, 9 virial components, kinetic energy
+constexpr int64_t kRedChunk = 16384;
+
+struct RedItem {
+  int cfg;
+  int pad;
+  int64_t a0, a1;  // caller-order atom range
+};
+
+struct Reducer {
+  int n_cfg = 0, n_items = 0;
+  DevBuf items_dev, start_dev, part;
+  int setup(int n_cfg, const int64_t* atom_off, hipStream_t st);
+  // Any input or output may be null.
+  int run(hipStream_t st, const float* Ei, const float* Wi, const float* Ki, double* E, double* V, double* Kout);
+};
+
+}  // namespace nepmi

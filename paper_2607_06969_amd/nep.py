@@ -1,0 +1,216 @@
+"""Python face of the HIP NEP library: model handle, batch evaluation,
+training gradient, molecular dynamics and a torch.autograd.Function.
+
+Tensors live on the GPU (torch is used for device memory and streams only);
+per-batch metadata (atom offsets, cells) are host arrays.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import HParams, _host_f64, _host_i64, _ptr, _stream, check, load
+
+
+def _dev(t, dtype):
+    if t is None:
+        return None
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"expected a contiguous {dtype} CUDA tensor")
+    return t
+
+
+class Batch:
+    """A batch of periodic configurations resident on the GPU.
+
+    pos: (N, 3) float32 CUDA tensor; species: (N,) int32 CUDA tensor;
+    atom_off: host int64 (n_cfg + 1); cells: host float64 (n_cfg, 3, 3)."""
+
+    def __init__(self, pos, species, atom_off, cells):
+        self.pos = _dev(pos, torch.float32)
+        self.species = _dev(species, torch.int32)
+        self.atom_off = np.ascontiguousarray(np.asarray(atom_off, dtype=np.int64))
+        self.cells = np.ascontiguousarray(np.asarray(cells, dtype=np.float64).reshape(-1, 9))
+        self.n_cfg = len(self.atom_off) - 1
+        self.n_atoms = int(self.atom_off[-1])
+
+    @classmethod
+    def from_system(cls, system, device="cuda"):
+        return cls(torch.as_tensor(system.pos, dtype=torch.float32, device=device).contiguous(),
+                   torch.as_tensor(system.species, dtype=torch.int32, device=device).contiguous(),
+                   system.atom_off, system.cells)
+
+    def _meta(self):
+        off, poff = _host_i64(self.atom_off)
+        cel, pcel = _host_f64(self.cells)
+        return (off, cel), poff, pcel
+
+
+class NepModel:
+    """NEP model handle on the current GPU."""
+
+    def __init__(self, hp, params=None):
+        self.hp = hp
+        self._hp = HParams.from_any(hp)
+        h = C.c_void_p()
+        check(load().nepmi_model_create(C.byref(self._hp), C.byref(h)))
+        self._h = h
+        self.n_params = _lib.param_count(hp)
+        self.dim = _lib.descriptor_dim(hp)
+        if params is not None:
+            self.set_params(params)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                load().nepmi_model_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    def set_params(self, params):
+        p = torch.as_tensor(params, dtype=torch.float32, device="cuda").contiguous()
+        if p.numel() != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters, got {p.numel()}")
+        self._params = p
+        check(load().nepmi_model_set_params(self._h, _ptr(p), _stream()))
+
+    def compute(self, batch: Batch, atom_energy=False, atom_virial=False):
+        """Energy (n_cfg,) float64, forces (N, 3) float32, virial (n_cfg, 3, 3) float64."""
+        dev = batch.pos.device
+        E = torch.empty(batch.n_cfg, dtype=torch.float64, device=dev)
+        F = torch.empty(batch.n_atoms, 3, dtype=torch.float32, device=dev)
+        V = torch.empty(batch.n_cfg, 9, dtype=torch.float64, device=dev)
+        Ea = torch.empty(batch.n_atoms, dtype=torch.float32, device=dev) if atom_energy else None
+        Wa = torch.empty(batch.n_atoms, 9, dtype=torch.float32, device=dev) if atom_virial else None
+        keep, poff, pcel = batch._meta()
+        check(load().nepmi_compute(self._h, batch.n_cfg, poff, pcel, _ptr(batch.pos), _ptr(batch.species),
+                                   _ptr(E), _ptr(F), _ptr(V), _ptr(Ea), _ptr(Wa), _stream()))
+        out = {"E": E, "F": F, "V": V.view(-1, 3, 3)}
+        if atom_energy:
+            out["Ei"] = Ea
+        if atom_virial:
+            out["Wi"] = Wa.view(-1, 3, 3)
+        return out
+
+    def descriptors(self, batch: Batch):
+        q = torch.empty(batch.n_atoms, self.dim, dtype=torch.float32, device=batch.pos.device)
+        keep, poff, pcel = batch._meta()
+        check(load().nepmi_descriptors(self._h, batch.n_cfg, poff, pcel, _ptr(batch.pos), _ptr(batch.species),
+                                       _ptr(q), _stream()))
+        return q
+
+    def neighbors(self, batch: Batch, which=0, cap=128):
+        """(count (N,), nbr (N, cap) caller indices, rvec (N, cap, 3)) of the radial (0) or angular (1) list."""
+        dev = batch.pos.device
+        cnt = torch.empty(batch.n_atoms, dtype=torch.int32, device=dev)
+        nb = torch.full((batch.n_atoms, cap), -1, dtype=torch.int32, device=dev)
+        rv = torch.zeros(batch.n_atoms, cap, 3, dtype=torch.float32, device=dev)
+        keep, poff, pcel = batch._meta()
+        check(load().nepmi_neighbors(self._h, batch.n_cfg, poff, pcel, _ptr(batch.pos), _ptr(batch.species),
+                                     int(which), int(cap), _ptr(cnt), _ptr(nb), _ptr(rv), _stream()))
+        return cnt, nb, rv
+
+    def backward_params(self, batch: Batch, ebar, lam, mu):
+        """sum_c ebar_c dE_c/dtheta + sum_i lam_i.dF_i/dtheta + sum_c mu_c:dV_c/dtheta (float32, P).
+        Needs a preceding compute() on the same batch."""
+        g = torch.empty(self.n_params, dtype=torch.float32, device=batch.pos.device)
+        keep, poff, pcel = batch._meta()
+        check(load().nepmi_backward_params(
+            self._h, batch.n_cfg, poff, pcel, _ptr(batch.pos), _ptr(batch.species),
+            _ptr(_dev(ebar.contiguous(), torch.float64)), _ptr(_dev(lam.contiguous(), torch.float32)),
+            _ptr(_dev(mu.reshape(-1, 9).contiguous(), torch.float64)), _ptr(g), _stream()))
+        return g
+
+    def loss_grad(self, batch: Batch, E_ref, F_ref, V_ref, weights=(1.0, 1.0, 0.1), loss_form=0, grad=True):
+        """Loss parts (4,) float64 on the GPU and the gradient (P,) float32 (or None)."""
+        dev = batch.pos.device
+        loss = torch.empty(4, dtype=torch.float64, device=dev)
+        g = torch.empty(self.n_params, dtype=torch.float32, device=dev) if grad else None
+        keep, poff, pcel = batch._meta()
+        w, pw = _host_f64(weights)
+        check(load().nepmi_loss_grad(
+            self._h, batch.n_cfg, poff, pcel, _ptr(batch.pos), _ptr(batch.species),
+            _ptr(_dev(E_ref, torch.float64)), _ptr(_dev(F_ref, torch.float32)),
+            _ptr(_dev(V_ref.reshape(-1, 9).contiguous(), torch.float64)), pw, int(loss_form), _ptr(loss), _ptr(g),
+            _stream()))
+        return loss, g
+
+
+class NepFunction(torch.autograd.Function):
+    """(params, batch) -> (E, F, V) with a hand-written parameter backward.
+
+    Gradients flow to the parameter vector only; asking for gradients with
+    respect to positions raises."""
+
+    @staticmethod
+    def forward(ctx, params, model: NepModel, batch: Batch):
+        model.set_params(params.detach())
+        out = model.compute(batch)
+        ctx.model, ctx.batch = model, batch
+        ctx.mark_non_differentiable()
+        return out["E"], out["F"], out["V"]
+
+    @staticmethod
+    def backward(ctx, gE, gF, gV):
+        model, batch = ctx.model, ctx.batch
+        if batch.pos.requires_grad:
+            raise RuntimeError("position gradients of forces are not provided")
+        dev = batch.pos.device
+        gE = torch.zeros(batch.n_cfg, dtype=torch.float64, device=dev) if gE is None else gE.to(torch.float64)
+        gF = torch.zeros(batch.n_atoms, 3, dtype=torch.float32, device=dev) if gF is None else gF.to(torch.float32)
+        gV = torch.zeros(batch.n_cfg, 3, 3, dtype=torch.float64, device=dev) if gV is None else gV.to(torch.float64)
+        g = model.backward_params(batch, gE.contiguous(), gF.contiguous(), gV.contiguous())
+        return g, None, None
+
+
+class NepMD:
+    """Velocity-Verlet NVE of a batch of cells, replayed as a HIP graph."""
+
+    def __init__(self, model: NepModel, batch: Batch, vel, masses, dt_fs=1.0, skin=1.0):
+        self.model, self.batch = model, batch
+        vel = _dev(vel, torch.float32)
+        keep, poff, pcel = batch._meta()
+        m, pm = _host_f64(masses)
+        h = C.c_void_p()
+        check(load().nepmi_md_create(model._h, batch.n_cfg, poff, pcel, _ptr(batch.pos), _ptr(vel),
+                                     _ptr(batch.species), pm, float(dt_fs), float(skin), C.byref(h), _stream()))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                load().nepmi_md_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    def step(self, n=1):
+        check(load().nepmi_md_step(self._h, int(n), _stream()))
+
+    def state(self):
+        b = self.batch
+        dev = b.pos.device
+        x = torch.empty(b.n_atoms, 3, dtype=torch.float32, device=dev)
+        v = torch.empty_like(x)
+        f = torch.empty_like(x)
+        ep = torch.empty(b.n_cfg, dtype=torch.float64, device=dev)
+        ek = torch.empty_like(ep)
+        vir = torch.empty(b.n_cfg, 9, dtype=torch.float64, device=dev)
+        check(load().nepmi_md_get(self._h, _ptr(x), _ptr(v), _ptr(f), _ptr(ep), _ptr(ek), _ptr(vir), _stream()))
+        return {"pos": x, "vel": v, "F": f, "Epot": ep, "Ekin": ek, "V": vir.view(-1, 3, 3)}
+
+    def stats(self):
+        s, r = C.c_int64(), C.c_int64()
+        check(load().nepmi_md_stats(self._h, C.byref(s), C.byref(r)))
+        return {"steps": s.value, "rebuilds": r.value}
+
+    def time_kernels(self, reps=10):
+        ms = (C.c_double * 4)()
+        check(load().nepmi_md_time_kernels(self._h, int(reps), ms, _stream()))
+        return {"desc": ms[0], "force": ms[1], "gather": ms[2], "lists": ms[3]}
