@@ -1,0 +1,190 @@
+"""Benchmark: NEP molecular dynamics throughput on one MI355X.
+
+Workload (one "step" = one velocity-Verlet NVE time step of the whole hot
+path: half kick, drift, displacement check and conditional neighbour-list
+rebuild, descriptors + network, pair forces + virial, force gather, second
+half kick, float64 energy/virial/kinetic sums): a rocksalt-derived
+Ge-Sb-Te cell of 100^3 sites (Te on one sublattice, Ge/Sb/vacancy 40/40/20 %
+on the other) = 900,000 atoms in a 300 A box, three-species NEP with
+n_radial = n_angular = 8, 12 Chebyshev functions, l_max = 4 plus 4- and 5-body
+terms, 50 hidden neurons, cutoffs 6 / 4 A, random N(0, 0.1) parameters,
+300 K Maxwell-Boltzmann velocities, dt = 1 fs, 1 A skin.  Inputs are seeded
+and synthetic and already resident in HBM when timing starts.
+
+Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+# MI355X figures used for the roofline (public specifications).
+HBM_PEAK_GBS = 8000.0
+# FP32 vector peak without packed FP32 instructions: 256 CU x 4 SIMD x 16 lanes
+# x 2 flop (FMA) x 2.4 GHz.  Packed FP32 (v_pk_fma_f32) would double it to the
+# published 157.3 TFLOP/s, but these kernels are built with packed FP32 off.
+FP32_VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+FP32_PACKED_PEAK_TFLOPS = 157.3
+
+
+def shape_of(hp):
+    K = hp.l_max * hp.l_max + 2 * hp.l_max
+    return dict(T=hp.n_species, NR=hp.n_radial, NA=hp.n_angular, BR=hp.basis_radial, BA=hp.basis_angular,
+                L=hp.l_max, K=K, D=hp.dim, H=hp.n_hidden, F4=hp.use_4body, F5=hp.use_5body)
+
+
+def algorithmic_flops(hp, pairs_r: float, pairs_a: float):
+    """Flops per atom of the descriptor/network kernel and of the pair-force
+    kernel, counted on the algorithm (not on the implementation): FMA = 2,
+    add/mul = 1, a transcendental or sqrt/reciprocal = 1; only pairs inside the
+    cutoffs count (pairs_r, pairs_a = mean pairs per atom within rc_radial,
+    rc_angular); recomputation of S in the force kernel and the work spent on
+    masked species are not counted."""
+    s = shape_of(hp)
+    T, NR, NA, BR, BA, K, D, H = s["T"], s["NR"], s["NA"], s["BR"], s["BA"], s["K"], s["D"], s["H"]
+    ylm = 60           # real Y_lm, l = 1..4, from the unit vector
+    grad_ylm = 200     # sum_lm G_lm grad P_lm, three components
+    # descriptors + network + adjoints
+    radial_pair = 12 + (6 + 4 * BR) + BR               # pair vector and d, basis, species bin
+    angular_pair = 16 + (6 + 4 * BA) + 2 * NA * BA + ylm + 2 * NA * K
+    per_atom = 2 * T * BR * NR                          # radial contraction
+    per_atom += 2 * NA * K + (50 * NA if s["F4"] else 0) + (NA if s["F5"] else 0)   # invariants
+    per_atom += 4 * D * H + 6 * H                       # network forward and dE/dq
+    per_atom += 2 * T * BR * NR                         # radial adjoint a_i[b][k]
+    desc = pairs_r * radial_pair + pairs_a * angular_pair + per_atom
+    # pair forces + virial
+    radial_f = 13 + (6 + 9 * BR) + 2 * BR + 2 * BR + 6 + 21
+    angular_f = 16 + ylm + (6 + 9 * BA) + 4 * NA * BA + 4 * NA * K + 2 * NA + grad_ylm + 15 + 21
+    per_atom_f = NA * K + (60 * NA if s["F4"] else 0) + (6 * NA if s["F5"] else 0)
+    force = pairs_r * radial_f + pairs_a * angular_f + per_atom_f
+    return float(desc), float(force)
+
+
+def gather_bytes(pairs_a_list: float):
+    """HBM bytes per atom of the force-gather kernel: radial part (16 B), own
+    and reverse angular pair forces (2 x 16 B per listed pair), reverse index
+    (4 B per pair), count/orig (8 B), output float4 (16 B)."""
+    return 16 + pairs_a_list * (32 + 4) + 8 + 16
+
+
+def cpu_baseline(hp, params, system, budget_s=20.0):
+    """The FP64 oracle on the same 900,000-atom cell, timed on the host cores."""
+    from oracle import oracle as O
+    O.build(force=False)
+    times = []
+    t_start = time.time()
+    while True:
+        t0 = time.time()
+        O.evaluate(hp, params, system, nbr_mode=1)
+        times.append(time.time() - t0)
+        if len(times) >= 3 or time.time() - t_start + times[-1] > budget_s:
+            break
+    t = float(np.median(times))
+    return {"value": system.n_atoms / t, "unit": "atom-steps/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"FP64 oracle energy+forces+virial of the full {system.n_atoms}-atom cell "
+                      f"(cell-list neighbours), median of {len(times)} evaluation(s), {t:.2f} s each; "
+                      f"host: {os.cpu_count()} logical CPUs"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--sites", type=int, default=100, help="rocksalt sites per side (even)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-reps", type=int, default=5)
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU path is not built",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2607_06969_amd import nep, workloads as W
+
+    hp = W.hp_gst()
+    params = W.random_params(hp, W.SEED_PARAM + 3)
+    system = W.rocksalt_gst(a.sites, seed=W.SEED_POS + 3)
+    vel = W.maxwell_boltzmann(system.species, W.MASSES_GST, 300.0, seed=W.SEED_VEL)
+    print(f"[bench] workload: {system.n_atoms} atoms, box {system.cells[0, 0, 0]:.1f} A", file=sys.stderr,
+          flush=True)
+
+    model = nep.NepModel(hp, params)
+    batch = nep.Batch.from_system(system)
+    cnt_r, _, _ = model.neighbors(batch, 0, cap=1)
+    cnt_a, _, _ = model.neighbors(batch, 1, cap=1)
+    pairs_r = float(cnt_r.double().mean())
+    pairs_a = float(cnt_a.double().mean())
+    v = torch.as_tensor(vel, dtype=torch.float32, device="cuda").contiguous()
+    md = nep.NepMD(model, batch, v, W.MASSES_GST, dt_fs=1.0, skin=1.0)
+    torch.cuda.synchronize()
+    md.step(a.warmup)
+    torch.cuda.synchronize()
+    print(f"[bench] warmup {a.warmup} steps done", file=sys.stderr, flush=True)
+    st0 = md.stats()
+    t0 = time.perf_counter()
+    md.step(a.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st1 = md.stats()
+    dt = t1 - t0
+    value = system.n_atoms * a.steps / dt
+    state = md.state()
+    epot = float(state["Epot"][0])
+    ekin = float(state["Ekin"][0])
+    print(f"[bench] timed {a.steps} steps in {dt:.3f} s; rebuilds {st1['rebuilds'] - st0['rebuilds']}",
+          file=sys.stderr, flush=True)
+
+    # per-kernel durations (HIP events on this stream, standalone launches on the final state)
+    kt = md.time_kernels(a.kernel_reps)
+    flop_desc, flop_force = algorithmic_flops(hp, pairs_r, pairs_a)
+    n = system.n_atoms
+    kernels = {"desc": (kt["desc"], flop_desc * n), "force": (kt["force"], flop_force * n)}
+    dom = max(kernels, key=lambda k: kernels[k][0])
+    ms, flops = kernels[dom]
+    achieved = flops / (ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": f"k_{dom}", "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / FP32_VALU_PEAK_TFLOPS,
+                "frac_of_packed_fp32_peak": achieved / FP32_PACKED_PEAK_TFLOPS, "traffic": None,
+                "algorithmic_flop_per_atom": {"desc": flop_desc, "force": flop_force},
+                "kernel_ms": {k: round(v_, 4) for k, v_ in kt.items()}}
+    gb = gather_bytes(pairs_a) * n / (kt["gather"] * 1e-3) / 1e9
+    roofline["gather_hbm"] = {"achieved_GBs": gb, "frac": gb / HBM_PEAK_GBS}
+
+    out = {
+        "metric": "atom-steps/s (E+F+virial) at 1M atoms; training configs/s vs plain path",
+        "value": value,
+        "unit": "atom-steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": dt / a.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"NVE MD, rocksalt Ge-Sb-Te {a.sites}^3 sites = {n} atoms, 3-species NEP "
+                               f"(8/8 radial/angular, 12 basis, l_max 4 + 4/5-body, 50 hidden, rc 6/4 A), "
+                               f"dt 1 fs, skin 1 A, 300 K",
+                   "atoms": n, "pairs_radial_per_atom": pairs_r, "pairs_angular_per_atom": pairs_a,
+                   "rebuilds_in_timed_steps": st1["rebuilds"] - st0["rebuilds"],
+                   "epot_per_atom_eV": epot / n, "ekin_per_atom_eV": ekin / n},
+        "roofline": roofline,
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(hp, params, system)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

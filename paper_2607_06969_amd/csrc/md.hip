@@ -1,0 +1,519 @@
+// md.hip -- velocity-Verlet NVE molecular dynamics replayed as a HIP graph.
+//
+// One step: half kick + drift (float64 positions, float32 copy for the force
+// kernels) and a displacement check; a neighbour-list rebuild whose kernels
+// all return at once unless an atom moved more than skin/2 since the last
+// build; descriptor/network, pair-force and gather kernels; the second half
+// kick; float64 sums of potential energy (Eq. 1), virial (Eq. 4) and kinetic
+// energy.  The graph topology is fixed; only the rebuild flag decides whether
+// the rebuild kernels do work.
+#include <cmath>
+#include <new>
+
+#include "model.hpp"
+
+namespace nepmi {
+
+constexpr float kAccUnit = 9.648533212e-3f;  // 1 eV/(A u) in A/fs^2
+constexpr int kMaxSpecies = 8;
+
+struct MdConst {
+  float acc[kMaxSpecies];   // dt/2 * kAccUnit / m_s   (half kick per unit force)
+  float kin[kMaxSpecies];   // m_s / (2 kAccUnit)       (eV per (A/fs)^2)
+  float dt;
+  float half_skin2;         // (skin/2)^2
+};
+
+struct Dbl3 {
+  double x, y, z;
+};
+
+__global__ void k_md_kick_drift(int64_t n_slots, MdConst mc, const int* __restrict__ cfg_of,
+                                const float4* __restrict__ F4, float4* __restrict__ vel4, Dbl3* __restrict__ xd,
+                                float4* __restrict__ pos4, const float4* __restrict__ ref4, int* __restrict__ flags) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_slots || cfg_of[p] < 0) return;
+  float4 x = pos4[p];
+  const int z = __float_as_int(x.w);
+  const float4 f = F4[p];
+  float4 v = vel4[p];
+  v.x = fmaf(mc.acc[z], f.x, v.x);
+  v.y = fmaf(mc.acc[z], f.y, v.y);
+  v.z = fmaf(mc.acc[z], f.z, v.z);
+  vel4[p] = v;
+  Dbl3 r = xd[p];
+  r.x += (double)mc.dt * v.x;
+  r.y += (double)mc.dt * v.y;
+  r.z += (double)mc.dt * v.z;
+  xd[p] = r;
+  x.x = (float)r.x;
+  x.y = (float)r.y;
+  x.z = (float)r.z;
+  pos4[p] = x;
+  const float4 o = ref4[p];
+  const float dx = x.x - o.x, dy = x.y - o.y, dz = x.z - o.z;
+  if (dx * dx + dy * dy + dz * dz > mc.half_skin2) atomicOr(&flags[kFlagRebuild], 1);
+}
+
+// Before a rebuild: state back to caller order, positions wrapped into the
+// cell in float64 so that the float32 copy needs no further wrapping.
+__global__ void k_md_unpermute(int64_t n_slots, const int* __restrict__ cfg_of, const int* __restrict__ orig,
+                               const CfgDev* __restrict__ cfgs, const Dbl3* __restrict__ xd,
+                               const float4* __restrict__ vel4, Dbl3* __restrict__ xd_user,
+                               float4* __restrict__ x_user, float4* __restrict__ v_user,
+                               const int* __restrict__ gate) {
+  if (*gate == 0) return;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_slots) return;
+  const int c = cfg_of[p];
+  if (c < 0) return;
+  const CfgDev& C = cfgs[c];
+  double r[3] = {xd[p].x, xd[p].y, xd[p].z};
+  float f[3];
+  for (int pass = 0; pass < 2; ++pass) {
+    double m[3];
+    for (int a = 0; a < 3; ++a) {
+      const double s = r[0] * C.Hinv[a] + r[1] * C.Hinv[3 + a] + r[2] * C.Hinv[6 + a];
+      m[a] = floor(s);
+    }
+    for (int a = 0; a < 3; ++a) r[a] -= m[0] * C.Hd[a] + m[1] * C.Hd[3 + a] + m[2] * C.Hd[6 + a];
+    for (int a = 0; a < 3; ++a) f[a] = (float)r[a];
+    // the float32 copy must also lie in the cell (as the staging kernel sees it)
+    bool inside = true;
+    for (int a = 0; a < 3; ++a) {
+      const double s = (double)f[0] * C.Hinv[a] + (double)f[1] * C.Hinv[3 + a] + (double)f[2] * C.Hinv[6 + a];
+      if (floor(s) != 0.0) inside = false;
+    }
+    if (inside) break;
+    for (int a = 0; a < 3; ++a) r[a] = (double)f[a];
+  }
+  const int i = orig[p];
+  xd_user[i] = Dbl3{r[0], r[1], r[2]};
+  x_user[i] = make_float4(f[0], f[1], f[2], 0.f);
+  v_user[i] = vel4[p];
+}
+
+__global__ void k_md_repermute(int64_t n_slots, const int* __restrict__ orig, const Dbl3* __restrict__ xd_user,
+                               const float4* __restrict__ x_user, const float4* __restrict__ v_user,
+                               const float4* __restrict__ pos4, Dbl3* __restrict__ xd, float4* __restrict__ vel4,
+                               float4* __restrict__ ref4, const int* __restrict__ gate) {
+  if (*gate == 0) return;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_slots) return;
+  const int i = orig[p];
+  if (i < 0) {
+    vel4[p] = make_float4(0.f, 0.f, 0.f, 0.f);
+    return;
+  }
+  // the staging kernel wraps again only in a last-ulp case at a cell face;
+  // carry that shift (zero otherwise) into the float64 position
+  const float4 xs = pos4[p], xu = x_user[i];
+  const Dbl3 r = xd_user[i];
+  xd[p] = Dbl3{r.x + ((double)xs.x - (double)xu.x), r.y + ((double)xs.y - (double)xu.y),
+               r.z + ((double)xs.z - (double)xu.z)};
+  vel4[p] = v_user[i];
+  ref4[p] = pos4[p];
+}
+
+__global__ void k_md_kick2(int64_t n_slots, MdConst mc, const int* __restrict__ orig, const float4* __restrict__ pos4,
+                           const float4* __restrict__ F4, float4* __restrict__ vel4, float* __restrict__ Ki) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_slots) return;
+  const int i = orig[p];
+  if (i < 0) return;
+  const int z = __float_as_int(pos4[p].w);
+  const float4 f = F4[p];
+  float4 v = vel4[p];
+  v.x = fmaf(mc.acc[z], f.x, v.x);
+  v.y = fmaf(mc.acc[z], f.y, v.y);
+  v.z = fmaf(mc.acc[z], f.z, v.z);
+  vel4[p] = v;
+  Ki[i] = mc.kin[z] * (v.x * v.x + v.y * v.y + v.z * v.z);
+}
+
+__global__ void k_md_kin(int64_t n_slots, MdConst mc, const int* __restrict__ orig, const float4* __restrict__ pos4,
+                         const float4* __restrict__ vel4, float* __restrict__ Ki) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_slots) return;
+  const int i = orig[p];
+  if (i < 0) return;
+  const float4 v = vel4[p];
+  Ki[i] = mc.kin[__float_as_int(pos4[p].w)] * (v.x * v.x + v.y * v.y + v.z * v.z);
+}
+
+__global__ void k_md_finish(int* __restrict__ flags, long long* __restrict__ counters) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    if (flags[kFlagRebuild]) counters[1] += 1;
+    counters[0] += 1;
+    flags[kFlagRebuild] = 0;
+  }
+}
+
+__global__ void k_md_export(int64_t n_slots, const int* __restrict__ orig, const Dbl3* __restrict__ xd,
+                            const float4* __restrict__ vel4, const float4* __restrict__ F4, float* __restrict__ x,
+                            float* __restrict__ v, float* __restrict__ f) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_slots) return;
+  const int i = orig[p];
+  if (i < 0) return;
+  if (x) {
+    x[3 * (int64_t)i + 0] = (float)xd[p].x;
+    x[3 * (int64_t)i + 1] = (float)xd[p].y;
+    x[3 * (int64_t)i + 2] = (float)xd[p].z;
+  }
+  if (v) {
+    v[3 * (int64_t)i + 0] = vel4[p].x;
+    v[3 * (int64_t)i + 1] = vel4[p].y;
+    v[3 * (int64_t)i + 2] = vel4[p].z;
+  }
+  if (f) {
+    f[3 * (int64_t)i + 0] = F4[p].x;
+    f[3 * (int64_t)i + 1] = F4[p].y;
+    f[3 * (int64_t)i + 2] = F4[p].z;
+  }
+}
+
+// Initial state: caller-order float32 positions/velocities to the wrapped
+// float64 caller-order copies the rebuild consumes.
+__global__ void k_md_init(int64_t N, int n_cfg, const int64_t* __restrict__ atom_off, const CfgDev* __restrict__ cfgs,
+                          const float* __restrict__ pos, const float* __restrict__ vel, Dbl3* __restrict__ xd_user,
+                          float4* __restrict__ x_user, float4* __restrict__ v_user) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  int lo = 0, hi = n_cfg;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (atom_off[mid] <= i) lo = mid; else hi = mid;
+  }
+  const CfgDev& C = cfgs[lo];
+  double r[3] = {(double)pos[3 * i], (double)pos[3 * i + 1], (double)pos[3 * i + 2]};
+  float f[3];
+  for (int pass = 0; pass < 2; ++pass) {
+    double m[3];
+    for (int a = 0; a < 3; ++a) m[a] = floor(r[0] * C.Hinv[a] + r[1] * C.Hinv[3 + a] + r[2] * C.Hinv[6 + a]);
+    for (int a = 0; a < 3; ++a) r[a] -= m[0] * C.Hd[a] + m[1] * C.Hd[3 + a] + m[2] * C.Hd[6 + a];
+    for (int a = 0; a < 3; ++a) f[a] = (float)r[a];
+    bool inside = true;
+    for (int a = 0; a < 3; ++a)
+      if (floor((double)f[0] * C.Hinv[a] + (double)f[1] * C.Hinv[3 + a] + (double)f[2] * C.Hinv[6 + a]) != 0.0)
+        inside = false;
+    if (inside) break;
+    for (int a = 0; a < 3; ++a) r[a] = (double)f[a];
+  }
+  xd_user[i] = Dbl3{r[0], r[1], r[2]};
+  x_user[i] = make_float4(f[0], f[1], f[2], 0.f);
+  v_user[i] = make_float4(vel[3 * i], vel[3 * i + 1], vel[3 * i + 2], 0.f);
+}
+
+__global__ void k_set_int(int* p, int v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+static inline unsigned nb256(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace nepmi
+
+using namespace nepmi;
+
+struct nepmi_md {
+  nepmi_model* m = nullptr;
+  NbrPipeline nbr;
+  Reducer red;
+  MdConst mc{};
+  int n_species = 0;
+  DevBuf species_user, xd_user, x_user, v_user, xd, vel4, ref4, F4;
+  DevBuf fp, aR, Ei, frad, fA, Wi, Ki, Eproc;
+  DevBuf epot, ekin, vir, counters;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int64_t host_steps = 0;
+
+  NepIO io() {
+    NepIO o;
+    o.n_slots = nbr.n_slots;
+    o.pos4 = nbr.pos4.ptr<float4>();
+    o.cfg_of = nbr.cfg_of.ptr<int>();
+    o.orig = nbr.orig.ptr<int>();
+    o.cfgs = nbr.cfgs.ptr<CfgDev>();
+    o.nbrR = nbr.nbrR.ptr<uint32_t>();
+    o.cntR = nbr.cntR.ptr<int>();
+    o.nbrA = nbr.nbrA.ptr<uint32_t>();
+    o.cntA = nbr.cntA.ptr<int>();
+    o.revA = nbr.revA.ptr<int>();
+    const float rcR = (float)m->hp.rc_radial, rcA = (float)m->hp.rc_angular;
+    o.cut.rcR = rcR;
+    o.cut.rcA = rcA;
+    o.cut.rcR2 = rcR * rcR;
+    o.cut.rcA2 = rcA * rcA;
+    o.cut.rclR2 = nbr.rclR2;
+    o.cut.rclA2 = nbr.rclA2;
+    o.fp = fp.ptr<float>();
+    o.aR = aR.ptr<float>();
+    o.Ei = Ei.ptr<float>();
+    o.qout = nullptr;
+    o.frad = frad.ptr<float4>();
+    o.fA = fA.ptr<float4>();
+    o.Wi = Wi.ptr<float>();
+    o.Fuser = nullptr;
+    o.Fproc = F4.ptr<float4>();
+    o.Eproc = nullptr;
+    return o;
+  }
+
+  int forces(hipStream_t st) {
+    NepIO o = io();
+    const float* P = m->params.ptr<float>();
+    int rc;
+    if ((rc = m->ops->desc(st, o, P, true)) || (rc = m->ops->force(st, o, P)) || (rc = m->ops->gather(st, o)))
+      return rc;
+    return NEPMI_OK;
+  }
+
+  int rebuild(hipStream_t st, const int* gate) {
+    const int64_t ns = nbr.n_slots;
+    hipLaunchKernelGGL(k_md_unpermute, dim3(nb256(ns)), dim3(256), 0, st, ns, nbr.cfg_of.ptr<int>(),
+                       nbr.orig.ptr<int>(), nbr.cfgs.ptr<CfgDev>(), xd.ptr<Dbl3>(), vel4.ptr<float4>(),
+                       xd_user.ptr<Dbl3>(), x_user.ptr<float4>(), v_user.ptr<float4>(), gate);
+    return after_unpermute(st, gate);
+  }
+
+  int after_unpermute(hipStream_t st, const int* gate) {
+    int rc;
+    if ((rc = nbr.launch_sort(st, x_user.ptr<float>(), 4, species_user.ptr<int32_t>(), n_species, gate))) return rc;
+    if ((rc = nbr.launch_lists(st, n_species, gate))) return rc;
+    const int64_t ns = nbr.n_slots;
+    hipLaunchKernelGGL(k_md_repermute, dim3(nb256(ns)), dim3(256), 0, st, ns, nbr.orig.ptr<int>(),
+                       xd_user.ptr<Dbl3>(), x_user.ptr<float4>(), v_user.ptr<float4>(), nbr.pos4.ptr<float4>(),
+                       xd.ptr<Dbl3>(),
+                       vel4.ptr<float4>(), ref4.ptr<float4>(), gate);
+    NEPMI_HIP(hipGetLastError());
+    return NEPMI_OK;
+  }
+
+  int step_launch(hipStream_t st) {
+    const int64_t ns = nbr.n_slots;
+    int* flags = nbr.flags.ptr<int>();
+    hipLaunchKernelGGL(k_md_kick_drift, dim3(nb256(ns)), dim3(256), 0, st, ns, mc, nbr.cfg_of.ptr<int>(),
+                       F4.ptr<float4>(), vel4.ptr<float4>(), xd.ptr<Dbl3>(), nbr.pos4.ptr<float4>(),
+                       ref4.ptr<float4>(), flags);
+    int rc;
+    if ((rc = rebuild(st, flags + kFlagRebuild))) return rc;
+    if ((rc = forces(st))) return rc;
+    hipLaunchKernelGGL(k_md_kick2, dim3(nb256(ns)), dim3(256), 0, st, ns, mc, nbr.orig.ptr<int>(),
+                       nbr.pos4.ptr<float4>(), F4.ptr<float4>(), vel4.ptr<float4>(), Ki.ptr<float>());
+    if ((rc = red.run(st, Ei.ptr<float>(), Wi.ptr<float>(), Ki.ptr<float>(), epot.ptr<double>(), vir.ptr<double>(),
+                      ekin.ptr<double>())))
+      return rc;
+    hipLaunchKernelGGL(k_md_finish, dim3(1), dim3(64), 0, st, flags, counters.ptr<long long>());
+    NEPMI_HIP(hipGetLastError());
+    return NEPMI_OK;
+  }
+
+  ~nepmi_md() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  }
+};
+
+extern "C" {
+
+int nepmi_md_create(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, const double* cells, const float* dev_pos,
+                    const float* dev_vel, const int32_t* dev_species, const double* masses, double dt_fs, double skin,
+                    nepmi_md** out, void* stream) {
+  if (!m || !dev_pos || !dev_vel || !dev_species || !masses || !out || !(dt_fs > 0) || !(skin >= 0)) {
+    set_error("invalid argument");
+    return NEPMI_INVALID_ARG;
+  }
+  if (m->ops->T > kMaxSpecies) {
+    set_error("too many species for the MD path");
+    return NEPMI_UNSUPPORTED;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  nepmi_md* md = new (std::nothrow) nepmi_md();
+  if (!md) return NEPMI_INVALID_ARG;
+  md->m = m;
+  md->n_species = m->ops->T;
+  int rc = NEPMI_OK;
+  auto fail = [&](int code) {
+    delete md;
+    return code;
+  };
+  for (int s = 0; s < md->n_species; ++s) {
+    if (!(masses[s] > 0)) {
+      set_error("masses must be positive");
+      return fail(NEPMI_INVALID_ARG);
+    }
+    md->mc.acc[s] = (float)(0.5 * dt_fs * kAccUnit / masses[s]);
+    md->mc.kin[s] = (float)(0.5 * masses[s] / kAccUnit);
+  }
+  md->mc.dt = (float)dt_fs;
+  md->mc.half_skin2 = (float)(0.25 * skin * skin);
+  NbrPipeline& nb = md->nbr;
+  if ((rc = nb.setup(n_cfg, atom_off, cells, md->n_species, m->hp.rc_radial, m->hp.rc_angular, skin, st)))
+    return fail(rc);
+  if ((rc = md->red.setup(n_cfg, atom_off, st))) return fail(rc);
+  const int64_t N = nb.N, ns = nb.n_slots;
+  const size_t Na = (size_t)(N > 0 ? N : 1);
+  if ((rc = md->species_user.ensure(4 * Na)) || (rc = md->xd_user.ensure(24 * Na)) ||
+      (rc = md->x_user.ensure(16 * Na)) || (rc = md->v_user.ensure(16 * Na)) || (rc = md->xd.ensure(24 * (size_t)ns)) ||
+      (rc = md->vel4.ensure(16 * (size_t)ns)) || (rc = md->ref4.ensure(16 * (size_t)ns)) ||
+      (rc = md->F4.ensure(16 * (size_t)ns)) || (rc = md->fp.ensure(4 * (size_t)ns * m->ops->NANG)) ||
+      (rc = md->aR.ensure(4 * (size_t)ns * m->ops->T * m->ops->BR)) || (rc = md->Ei.ensure(4 * Na)) ||
+      (rc = md->frad.ensure(16 * (size_t)ns)) || (rc = md->Wi.ensure(36 * Na)) || (rc = md->Ki.ensure(4 * Na)) ||
+      (rc = md->epot.ensure(8 * (size_t)n_cfg)) || (rc = md->ekin.ensure(8 * (size_t)n_cfg)) ||
+      (rc = md->vir.ensure(72 * (size_t)n_cfg)) || (rc = md->counters.ensure(16)))
+    return fail(rc);
+  if (hipMemcpyAsync(md->species_user.p, dev_species, 4 * (size_t)N, hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return fail(hip_fail(hipGetLastError(), "hipMemcpyAsync(species)"));
+  hipLaunchKernelGGL(k_md_init, dim3(nb256(N > 0 ? N : 1)), dim3(256), 0, st, N, n_cfg, nb.atom_off_dev.ptr<int64_t>(),
+                     nb.cfgs.ptr<CfgDev>(), dev_pos, dev_vel, md->xd_user.ptr<Dbl3>(), md->x_user.ptr<float4>(),
+                     md->v_user.ptr<float4>());
+  fill_int(st, nb.flags.ptr<int>(), kFlagCount, 0, nullptr);
+  fill_int(st, md->counters.ptr<int>(), 4, 0, nullptr);
+  // first build, with capacity growth and a margin for the density
+  // fluctuations of the run
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, nb.flags.ptr<int>() + kFlagRebuild, 1);
+  if ((rc = md->after_unpermute(st, nb.flags.ptr<int>() + kFlagRebuild))) return fail(rc);
+  int hf[kFlagCount];
+  if ((rc = nb.check_flags(st, hf))) return fail(rc);
+  const int wantR = hf[kFlagMaxR] + hf[kFlagMaxR] / 4 + 16, wantA = hf[kFlagMaxA] + hf[kFlagMaxA] / 4 + 16;
+  if (hf[kFlagOverflow] || nb.capR < wantR || nb.capA < wantA) {
+    if ((rc = nb.ensure_lists(wantR > nb.capR ? wantR : nb.capR, wantA > nb.capA ? wantA : nb.capA))) return fail(rc);
+    fill_int(st, nb.flags.ptr<int>(), kFlagCount, 0, nullptr);
+    if ((rc = nb.launch_lists(st, md->n_species, nullptr))) return fail(rc);
+    if ((rc = nb.check_flags(st, hf))) return fail(rc);
+    if (hf[kFlagOverflow]) {
+      set_error("neighbour capacity overflow");
+      return fail(NEPMI_NEIGHBOR_OVERFLOW);
+    }
+  }
+  if (hf[kFlagAsym]) {
+    set_error("angular neighbour list is not symmetric");
+    return fail(NEPMI_INVALID_ARG);
+  }
+  if ((rc = md->fA.ensure(16 * (size_t)ns * nb.capA))) return fail(rc);
+  fill_int(st, nb.flags.ptr<int>(), kFlagCount, 0, nullptr);
+  // forces of the initial state
+  if ((rc = md->forces(st))) return fail(rc);
+  hipLaunchKernelGGL(k_md_kin, dim3(nb256(ns)), dim3(256), 0, st, ns, md->mc, nb.orig.ptr<int>(), nb.pos4.ptr<float4>(),
+                     md->vel4.ptr<float4>(), md->Ki.ptr<float>());
+  if ((rc = md->red.run(st, md->Ei.ptr<float>(), md->Wi.ptr<float>(), md->Ki.ptr<float>(), md->epot.ptr<double>(),
+                        md->vir.ptr<double>(), md->ekin.ptr<double>())))
+    return fail(rc);
+  if (hipStreamSynchronize(st) != hipSuccess) return fail(hip_fail(hipGetLastError(), "hipStreamSynchronize"));
+  // capture one step
+  if (hipStreamCreateWithFlags(&md->cap_stream, hipStreamNonBlocking) != hipSuccess)
+    return fail(hip_fail(hipGetLastError(), "hipStreamCreate"));
+  if (hipStreamBeginCapture(md->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    return fail(hip_fail(hipGetLastError(), "hipStreamBeginCapture"));
+  rc = md->step_launch(md->cap_stream);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(md->cap_stream, &g);
+  if (rc) return fail(rc);
+  if (e != hipSuccess) return fail(hip_fail(e, "hipStreamEndCapture"));
+  md->graph = g;
+  if ((e = hipGraphInstantiate(&md->exec, g, nullptr, nullptr, 0)) != hipSuccess)
+    return fail(hip_fail(e, "hipGraphInstantiate"));
+  if (hipStreamSynchronize(st) != hipSuccess) return fail(hip_fail(hipGetLastError(), "hipStreamSynchronize"));
+  *out = md;
+  return NEPMI_OK;
+}
+
+int nepmi_md_step(nepmi_md* md, int32_t n_steps, void* stream) {
+  if (!md || n_steps < 0) {
+    set_error("invalid argument");
+    return NEPMI_INVALID_ARG;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  for (int s = 0; s < n_steps; ++s) NEPMI_HIP(hipGraphLaunch(md->exec, st));
+  md->host_steps += n_steps;
+  int hf[kFlagCount];
+  int rc = md->nbr.check_flags(st, hf);
+  if (rc) return rc;
+  if (hf[kFlagOverflow]) {
+    set_error("neighbour capacity exceeded during MD (results are invalid)");
+    return NEPMI_NEIGHBOR_OVERFLOW;
+  }
+  if (hf[kFlagAsym]) {
+    set_error("angular neighbour list is not symmetric");
+    return NEPMI_INVALID_ARG;
+  }
+  return NEPMI_OK;
+}
+
+int nepmi_md_get(nepmi_md* md, float* dev_pos, float* dev_vel, float* dev_forces, double* dev_epot, double* dev_ekin,
+                 double* dev_virial, void* stream) {
+  if (!md) {
+    set_error("null handle");
+    return NEPMI_INVALID_ARG;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t ns = md->nbr.n_slots;
+  if (dev_pos || dev_vel || dev_forces)
+    hipLaunchKernelGGL(k_md_export, dim3(nb256(ns)), dim3(256), 0, st, ns, md->nbr.orig.ptr<int>(),
+                       md->xd.ptr<Dbl3>(), md->vel4.ptr<float4>(), md->F4.ptr<float4>(), dev_pos, dev_vel, dev_forces);
+  const size_t nc = (size_t)md->nbr.n_cfg;
+  if (dev_epot) NEPMI_HIP(hipMemcpyAsync(dev_epot, md->epot.p, 8 * nc, hipMemcpyDeviceToDevice, st));
+  if (dev_ekin) NEPMI_HIP(hipMemcpyAsync(dev_ekin, md->ekin.p, 8 * nc, hipMemcpyDeviceToDevice, st));
+  if (dev_virial) NEPMI_HIP(hipMemcpyAsync(dev_virial, md->vir.p, 72 * nc, hipMemcpyDeviceToDevice, st));
+  NEPMI_HIP(hipGetLastError());
+  return NEPMI_OK;
+}
+
+int nepmi_md_stats(nepmi_md* md, int64_t* steps, int64_t* rebuilds) {
+  if (!md) return NEPMI_INVALID_ARG;
+  long long c[2];
+  NEPMI_HIP(hipMemcpy(c, md->counters.p, sizeof c, hipMemcpyDeviceToHost));
+  if (steps) *steps = c[0];
+  if (rebuilds) *rebuilds = c[1] + 1;  // plus the build at creation
+  return NEPMI_OK;
+}
+
+void nepmi_md_destroy(nepmi_md* md) { delete md; }
+
+int nepmi_md_time_kernels(nepmi_md* md, int32_t reps, double* ms, void* stream) {
+  if (!md || reps < 1 || !ms) {
+    set_error("invalid argument");
+    return NEPMI_INVALID_ARG;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t ev[8];
+  for (int k = 0; k < 8; ++k) NEPMI_HIP(hipEventCreate(&ev[k]));
+  double acc[4] = {0, 0, 0, 0};
+  NepIO o = md->io();
+  const float* P = md->m->params.ptr<float>();
+  int rc = NEPMI_OK;
+  for (int r = 0; r < reps && !rc; ++r) {
+    NEPMI_HIP(hipEventRecord(ev[0], st));
+    rc = md->m->ops->desc(st, o, P, true);
+    NEPMI_HIP(hipEventRecord(ev[1], st));
+    if (!rc) rc = md->m->ops->force(st, o, P);
+    NEPMI_HIP(hipEventRecord(ev[2], st));
+    if (!rc) rc = md->m->ops->gather(st, o);
+    NEPMI_HIP(hipEventRecord(ev[3], st));
+    // a full list rebuild on the current state (sort + lists)
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, md->nbr.flags.ptr<int>() + kFlagRebuild, 1);
+    NEPMI_HIP(hipEventRecord(ev[4], st));
+    if (!rc) rc = md->rebuild(st, md->nbr.flags.ptr<int>() + kFlagRebuild);
+    NEPMI_HIP(hipEventRecord(ev[5], st));
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, md->nbr.flags.ptr<int>() + kFlagRebuild, 0);
+    NEPMI_HIP(hipStreamSynchronize(st));
+    float t;
+    for (int k = 0; k < 3; ++k) {
+      NEPMI_HIP(hipEventElapsedTime(&t, ev[k], ev[k + 1]));
+      acc[k] += t;
+    }
+    NEPMI_HIP(hipEventElapsedTime(&t, ev[4], ev[5]));
+    acc[3] += t;
+  }
+  // forces of the rebuilt state, so the next step starts consistent
+  if (!rc) rc = md->forces(st);
+  NEPMI_HIP(hipStreamSynchronize(st));
+  for (int k = 0; k < 8; ++k) (void)hipEventDestroy(ev[k]);
+  for (int k = 0; k < 4; ++k) ms[k] = acc[k] / reps;
+  return rc;
+}
+
+}  // extern "C"

@@ -417,7 +417,9 @@ int NbrPipeline::setup(int n_cfg_, const int64_t* atom_off, const double* cells,
                   " is below 2 * (rc_radial + skin) = " + std::to_string(2.0 * rcl));
         return NEPMI_CELL_TOO_SMALL;
       }
-      int nb = (int)floor(w[a] / (rcl * (1.0 + 1e-6)));
+      // bins a little wider than the list cutoff, so that a position rounded
+      // differently by 1e-3 A cannot move a neighbour out of the 27-bin stencil
+      int nb = (int)floor(w[a] / (rcl * (1.0 + 1e-6) + 1e-3));
       C.nb[a] = nb < 1 ? 1 : (nb > 1024 ? 1024 : nb);
     }
     for (int x = 0; x < 9; ++x) {
@@ -515,7 +517,10 @@ int NbrPipeline::build(hipStream_t st, const float* pos, const int32_t* species)
     int hf[kFlagCount];
     if ((rc = check_flags(st, hf))) return rc;
     if (!hf[kFlagOverflow]) {
-      asym = hf[kFlagAsym];
+      if (hf[kFlagAsym]) {
+        set_error("angular neighbour list is not symmetric");
+        return NEPMI_INVALID_ARG;
+      }
       return NEPMI_OK;
     }
     // grow to the largest list seen plus a margin and rebuild the lists

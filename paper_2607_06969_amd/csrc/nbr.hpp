@@ -45,7 +45,6 @@ struct NbrPipeline {
   int capR = 0, capA = 0;
   float rclR2 = 0.f, rclA2 = 0.f;
   double skin = 0.0;
-  int asym = 0;  // last build found a one-sided angular pair
   std::vector<CfgDev> host_cfgs;
   std::vector<int64_t> host_off;
 

@@ -1,0 +1,89 @@
+"""GPU molecular dynamics: the graph-replayed velocity-Verlet step.
+
+Checks that the state after many steps (with in-graph neighbour-list
+rebuilds) still evaluates to the FP64 oracle's forces, energy and virial at
+the same positions; that momentum and total energy are conserved; and that
+the integrator is time reversible."""
+import numpy as np
+import pytest
+
+from paper_2607_06969_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300)
+
+
+def _make(skin=1.0, dt=1.0, n=12, seed=61, temp=300.0, pseed=2021):
+    from paper_2607_06969_amd import nep
+    hp = W.hp_gst()
+    s = W.rocksalt_gst(n, seed=seed)
+    p = W.random_params(hp, pseed)
+    v = W.maxwell_boltzmann(s.species, W.MASSES_GST, temp, seed=W.SEED_VEL + seed)
+    m = nep.NepModel(hp, p)
+    b = nep.Batch.from_system(s)
+    md = nep.NepMD(m, b, torch.as_tensor(v, dtype=torch.float32, device="cuda"), W.MASSES_GST, dt_fs=dt, skin=skin)
+    return hp, p, s, m, b, md
+
+
+def test_md_initial_state_matches_compute():
+    hp, p, s, m, b, md = _make()
+    st = md.state()
+    ref = m.compute(b)
+    assert abs(float(st["Epot"][0]) - float(ref["E"][0])) / s.n_atoms < 1e-7
+    assert rel(st["F"].cpu().numpy(), ref["F"].cpu().numpy()) < 1e-6
+
+
+def test_md_state_after_rebuilds_matches_oracle(oracle_lib):
+    # small skin: frequent in-graph rebuilds
+    hp, p, s, m, b, md = _make(skin=0.3, temp=600.0)
+    md.step(60)
+    stats = md.stats()
+    assert stats["steps"] == 60
+    assert stats["rebuilds"] >= 3, stats
+    st = md.state()
+    pos = st["pos"].cpu().numpy().astype(np.float64)
+    sys2 = W.System(pos, s.species, s.cells, s.atom_off)
+    ref = oracle_lib.evaluate(hp, p, sys2, nbr_mode=1)
+    n = s.n_atoms
+    assert abs(float(st["Epot"][0]) - ref["E"][0]) / n < 1e-6
+    assert rel(st["F"].cpu().numpy(), ref["F"]) < 1e-5
+    assert rel(st["V"][0].cpu().numpy(), ref["V"][0]) < 1e-5
+
+
+def test_md_conservation():
+    hp, p, s, m, b, md = _make(dt=0.5)
+    masses = np.asarray(W.MASSES_GST)[s.species][:, None]
+    st0 = md.state()
+    e0 = float(st0["Epot"][0] + st0["Ekin"][0])
+    p0 = (masses * st0["vel"].cpu().numpy().astype(np.float64)).sum(axis=0)
+    es = []
+    for _ in range(10):
+        md.step(20)
+        st = md.state()
+        es.append(float(st["Epot"][0] + st["Ekin"][0]))
+    p1 = (masses * st["vel"].cpu().numpy().astype(np.float64)).sum(axis=0)
+    ekin = float(st0["Ekin"][0])
+    # total energy fluctuates by a small fraction of the kinetic energy
+    assert max(abs(e - e0) for e in es) < 2e-3 * ekin, (e0, es, ekin)
+    # net force is zero: momentum stays at its initial (zero) value
+    assert np.max(np.abs(p1 - p0)) < 1e-3 * np.sqrt(ekin), (p0, p1)
+
+
+def test_md_time_reversibility():
+    hp, p, s, m, b, md = _make(dt=0.5, skin=1.0)
+    x0 = md.state()["pos"].cpu().numpy()
+    md.step(40)
+    st = md.state()
+    from paper_2607_06969_amd import nep
+    b2 = nep.Batch(st["pos"].contiguous(), b.species, s.atom_off, s.cells)
+    md2 = nep.NepMD(m, b2, (-st["vel"]).contiguous(), W.MASSES_GST, dt_fs=0.5, skin=1.0)
+    md2.step(40)
+    x1 = md2.state()["pos"].cpu().numpy()
+    L = s.cells[0, 0, 0]
+    d = x1 - x0
+    d -= L * np.round(d / L)
+    assert np.max(np.abs(d)) < 2e-3, np.max(np.abs(d))
