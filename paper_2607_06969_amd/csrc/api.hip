@@ -18,8 +18,9 @@ int hip_fail(hipError_t e, const char* what) {
 
 template <class S>
 static const Ops* ops_of() {
-  static const Ops o = {&Launch<S>::desc, &Launch<S>::force, &Launch<S>::gather, S::T, S::NR, S::NA, S::BR, S::BA,
-                        S::L, S::D, S::NANG, S::P};
+  static const Ops o = {&Launch<S>::desc, &Launch<S>::force, &Launch<S>::gather, &TrainLaunch<S>::seeds,
+                        &TrainLaunch<S>::backward, S::T, S::NR, S::NA, S::BR, S::BA, S::L, S::D, S::NANG, S::H,
+                        S::K, S::P};
   return &o;
 }
 

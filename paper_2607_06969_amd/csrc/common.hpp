@@ -266,6 +266,47 @@ __device__ __forceinline__ void real_sph_grad_dot(float x, float y, float z, con
   }
 }
 
+// Dl[lm] = w . grad_u P_lm(u) for every component (P_lm as in real_sph).
+template <int L>
+__device__ __forceinline__ void real_sph_dir(float x, float y, float z, float wx, float wy, float wz,
+                                             float (&Dl)[L * L + 2 * L]) {
+  using namespace sh;
+  Dl[0] = c1 * wz;
+  Dl[1] = c1 * wx;
+  Dl[2] = c1 * wy;
+  if constexpr (L >= 2) {
+    Dl[3] = 6.0f * k20 * z * wz;
+    Dl[4] = k21 * (z * wx + x * wz);
+    Dl[5] = k21 * (z * wy + y * wz);
+    Dl[6] = 2.0f * k22 * (x * wx - y * wy);
+    Dl[7] = k21 * (y * wx + x * wy);
+    if constexpr (L >= 3) {
+      const float z2 = z * z, x2 = x * x, y2 = y * y;
+      const float p = 5.0f * z2 - 1.0f;
+      Dl[8] = k30 * (15.0f * z2 - 3.0f) * wz;
+      Dl[9] = k31 * (p * wx + 10.0f * x * z * wz);
+      Dl[10] = k31 * (p * wy + 10.0f * y * z * wz);
+      Dl[11] = k32 * (2.0f * x * z * wx - 2.0f * y * z * wy + (x2 - y2) * wz);
+      Dl[12] = k32s * (y * z * wx + x * z * wy + x * y * wz);
+      Dl[13] = k33 * (3.0f * (x2 - y2) * wx - 6.0f * x * y * wy);
+      Dl[14] = k33 * (6.0f * x * y * wx + 3.0f * (x2 - y2) * wy);
+      if constexpr (L >= 4) {
+        const float q = 7.0f * z2 - 3.0f;
+        const float r = 7.0f * z2 - 1.0f;
+        Dl[15] = k40 * (140.0f * z2 * z - 60.0f * z) * wz;
+        Dl[16] = k41 * (z * q * wx + x * (21.0f * z2 - 3.0f) * wz);
+        Dl[17] = k41 * (z * q * wy + y * (21.0f * z2 - 3.0f) * wz);
+        Dl[18] = k42 * (2.0f * x * r * wx - 2.0f * y * r * wy + 14.0f * z * (x2 - y2) * wz);
+        Dl[19] = k42s * (y * r * wx + x * r * wy + 14.0f * x * y * z * wz);
+        Dl[20] = k43 * (3.0f * z * (x2 - y2) * wx - 6.0f * x * y * z * wy + x * (x2 - 3.0f * y2) * wz);
+        Dl[21] = k43 * (6.0f * x * y * z * wx + 3.0f * z * (x2 - y2) * wy + y * (3.0f * x2 - y2) * wz);
+        Dl[22] = k44 * (4.0f * x * (x2 - 3.0f * y2) * wx + 4.0f * y * (y2 - 3.0f * x2) * wy);
+        Dl[23] = k44s * (y * (3.0f * x2 - y2) * wx + x * (x2 - 3.0f * y2) * wy);
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------- host helpers
 
 void set_error(const std::string& msg);

@@ -3,6 +3,7 @@
 
 #include "nep_kernels.hpp"
 #include "reduce.hpp"
+#include "train.hpp"
 
 namespace nepmi {
 
@@ -11,7 +12,10 @@ struct Ops {
   int (*desc)(hipStream_t, const NepIO&, const float*, bool);
   int (*force)(hipStream_t, const NepIO&, const float*);
   int (*gather)(hipStream_t, const NepIO&);
-  int T, NR, NA, BR, BA, L, D, NANG;
+  int (*seeds)(hipStream_t, const TrainSeedArgs&);
+  int (*backward)(hipStream_t, TrainIO, const Cutoffs&, const float*, const float*, const int*, double*, double*,
+                  float*);
+  int T, NR, NA, BR, BA, L, D, NANG, H, K;
   int64_t P;
 };
 
@@ -19,9 +23,8 @@ const Ops* find_ops(const nepmi_hparams& hp);
 
 // Training-only buffers (see train.hip).
 struct TrainBufs {
-  DevBuf seeds_e, seeds_mu, lam_proc, tan_fp, ebar_proc, gpart, grad64, loss64;
-  DevBuf qdot, qbar, atom_w, atom_z;
-  DevBuf Fuser, Euser, Vuser, Wuser;
+  DevBuf F, E, V, lam, ebar, mu, partF, lam4;
+  DevBuf Sst, Sdt, q, qd, Pb, Pdn, abar, zneg, gw1, eat, qbR, FpR, GA, part, grad64, gradf;
 };
 
 }  // namespace nepmi
