@@ -94,6 +94,89 @@ def cpu_baseline(hp, params, system, budget_s=20.0):
                       f"host: {os.cpu_count()} logical CPUs"}
 
 
+def bench_training(nep, W, hp, reps=3):
+    """Forward + loss + parameter gradient of 256 uneven configurations
+    (64-512 atoms, amorphous-like, min distance 2.2 A, Ge:Sb:Te = 2:2:5) in one
+    batched call, against the same kernels run one configuration at a time.
+    Labels come from a seeded teacher NEP evaluated on the GPU."""
+    import torch
+    s = W.amorphous_batch()
+    n_cfg = s.n_cfg
+    teacher = nep.NepModel(hp, W.random_params(hp, W.SEED_TEACHER))
+    b = nep.Batch.from_system(s)
+    lab = teacher.compute(b)
+    Er, Fr, Vr = lab["E"], lab["F"].contiguous(), lab["V"].reshape(-1, 9).contiguous()
+    m = nep.NepModel(hp, W.random_params(hp, W.SEED_STUDENT))
+    subs = [nep.Batch.from_system(s.config(c)) for c in range(n_cfg)]
+    off = s.atom_off
+    sub_lab = [(Er[c:c + 1].contiguous(), Fr[off[c]:off[c + 1]].contiguous(), Vr[c:c + 1].contiguous())
+               for c in range(n_cfg)]
+    form = 1  # per-configuration loss averaged over the batch: batch gradient = mean of single gradients
+    m.loss_grad(b, Er, Fr, Vr, loss_form=form)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        loss, g_batch = m.loss_grad(b, Er, Fr, Vr, loss_form=form)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / reps
+    g_sum = torch.zeros_like(g_batch, dtype=torch.float64)
+    for c in range(n_cfg):
+        m.loss_grad(subs[c], *sub_lab[c], loss_form=form)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c in range(n_cfg):
+        _, gc = m.loss_grad(subs[c], *sub_lab[c], loss_form=form)
+        g_sum += gc.double()
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    g_mean = g_sum / n_cfg
+    diff = float((g_batch.double() - g_mean).norm() / g_mean.norm())
+    return {"workload": f"{n_cfg} amorphous Ge-Sb-Te cells, {s.n_atoms} atoms (64-512 each)",
+            "metric": "configs/s (forward + loss + parameter gradient)",
+            "batched_configs_per_s": n_cfg / t_batch, "plain_configs_per_s": n_cfg / t_plain,
+            "speedup": t_plain / t_batch, "batched_ms": t_batch * 1e3, "plain_ms": t_plain * 1e3,
+            "grad_rel_diff_batched_vs_plain": diff, "loss": float(loss[0])}
+
+
+def bench_serving(nep, W, hp, params, steps=20):
+    """64 independent rocksalt cells of 1e3-2e5 atoms (log-uniform) stepped
+    together in one MD handle, against one handle per cell stepped in turn."""
+    import torch
+    s = W.mixed_size_cells()
+    vel = W.maxwell_boltzmann(s.species, W.MASSES_GST, 300.0, seed=W.SEED_VEL + 5)
+    m = nep.NepModel(hp, params)
+    b = nep.Batch.from_system(s)
+    v = torch.as_tensor(vel, dtype=torch.float32, device="cuda").contiguous()
+    md = nep.NepMD(m, b, v, W.MASSES_GST)
+    md.step(3)
+    lat = []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        md.step(1)
+        lat.append(time.perf_counter() - t0)
+    del md
+    mds = []
+    for c in range(s.n_cfg):
+        a0, a1 = s.atom_off[c], s.atom_off[c + 1]
+        bc = nep.Batch.from_system(s.config(c))
+        mds.append(nep.NepMD(m, bc, v[a0:a1].contiguous(), W.MASSES_GST))
+    for mc in mds:
+        mc.step(3)
+    lat1 = []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        for mc in mds:
+            mc.step(1)
+        lat1.append(time.perf_counter() - t0)
+    n = s.n_atoms
+    return {"workload": f"{s.n_cfg} rocksalt Ge-Sb-Te cells, {n} atoms (900-175,600 each)",
+            "batched_atom_steps_per_s": n * steps / sum(lat), "one_at_a_time_atom_steps_per_s": n * steps / sum(lat1),
+            "batched_step_ms_p50": 1e3 * float(np.percentile(lat, 50)),
+            "batched_step_ms_p99": 1e3 * float(np.percentile(lat, 99)),
+            "one_at_a_time_step_ms_p50": 1e3 * float(np.percentile(lat1, 50)),
+            "one_at_a_time_step_ms_p99": 1e3 * float(np.percentile(lat1, 99))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +185,8 @@ def main():
     ap.add_argument("--sites", type=int, default=100, help="rocksalt sites per side (even)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=5)
+    ap.add_argument("--no-train", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU path is not built",
@@ -181,7 +266,14 @@ def main():
                    "epot_per_atom_eV": epot / n, "ekin_per_atom_eV": ekin / n},
         "roofline": roofline,
     }
+    if not a.no_train:
+        print("[bench] training leg", file=sys.stderr, flush=True)
+        out["training"] = bench_training(nep, W, hp)
+    if not a.no_serve:
+        print("[bench] serving leg", file=sys.stderr, flush=True)
+        out["serving"] = bench_serving(nep, W, hp, params)
     if not a.no_cpu_baseline:
+        print("[bench] cpu baseline leg", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(hp, params, system)
     print(json.dumps(out))
 
