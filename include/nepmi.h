@@ -122,13 +122,26 @@ int nepmi_neighbors(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, cons
                     const float *dev_pos, const int32_t *dev_species, int32_t which, int32_t cap,
                     int32_t *dev_count, int32_t *dev_nbr, float *dev_rvec, void *stream);
 
+/* Kernel variants.  The descriptor and pair-force kernels are compiled in
+ * several variants (angular functions handled per pass over the pairs, and
+ * the register budget they keep to); all compute the same result (descriptor
+ * variants bitwise, force variants up to float32 summation order).
+ * nepmi_autotune times every variant on the given batch and keeps the
+ * fastest in the model; chosen = host int32[2] (descriptor, force) or NULL.
+ * Synchronises `stream`.  nepmi_set_variants pins a choice (0..3 each);
+ * nepmi_md_create autotunes on its initial state. */
+int nepmi_autotune(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, const double *cells,
+                   const float *dev_pos, const int32_t *dev_species, int32_t *chosen, void *stream);
+int nepmi_set_variants(nepmi_model *m, int32_t desc_variant, int32_t force_variant);
+int nepmi_get_variants(nepmi_model *m, int32_t *desc_variant, int32_t *force_variant);
+
 /* Vector-Jacobian product of (E, F, V) with respect to the parameters:
  *   dev_grad[p] = sum_c ebar_c dE_c/dtheta_p + sum_i lambda_i . dF_i/dtheta_p
  *               + sum_c mu_c : dV_c/dtheta_p
  * with dev_ebar double[n_cfg], dev_lambda float[N*3], dev_mu double[9*n_cfg];
- * dev_grad float[param_count] is overwritten.  Uses the neighbour lists and
- * forward state of the last nepmi_compute on the same batch (call that
- * first); descriptors are recomputed, no per-pair state is cached. */
+ * dev_grad float[param_count] is overwritten.  The neighbour lists and
+ * forward state are rebuilt for the batch given; descriptors are recomputed,
+ * no per-pair state is cached. */
 int nepmi_backward_params(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, const double *cells,
                           const float *dev_pos, const int32_t *dev_species, const double *dev_ebar,
                           const float *dev_lambda, const double *dev_mu, float *dev_grad, void *stream);

@@ -88,9 +88,11 @@ NepIO nepmi_model::io(float* Fuser, float4* Fproc, float* qout) {
   o.cfgs = nbr.cfgs.ptr<CfgDev>();
   o.nbrR = nbr.nbrR.ptr<uint32_t>();
   o.cntR = nbr.cntR.ptr<int>();
-  o.nbrA = nbr.nbrA.ptr<uint32_t>();
-  o.cntA = nbr.cntA.ptr<int>();
-  o.revA = nbr.revA.ptr<int>();
+  o.cnR = nbr.cnbrR.ptr<uint32_t>();
+  o.ccR = nbr.ccntR.ptr<int>();
+  o.cnA = nbr.cnbrA.ptr<uint32_t>();
+  o.ccA = nbr.ccntA.ptr<int>();
+  o.flags = nbr.flags.ptr<int>();
   const float rcR = (float)hp.rc_radial, rcA = (float)hp.rc_angular;
   o.cut.rcR = rcR;
   o.cut.rcA = rcA;
@@ -182,7 +184,7 @@ int nepmi_compute(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, const 
   if (rc) return rc;
   NepIO io = m->io(dev_forces, nullptr, nullptr);
   const float* P = m->params.ptr<float>();
-  if ((rc = m->ops->desc(st, io, P, true)) || (rc = m->ops->force(st, io, P)) || (rc = m->ops->gather(st, io)))
+  if ((rc = m->ops->desc(st, io, P, true, m->vdesc)) || (rc = m->ops->force(st, io, P, m->vforce)) || (rc = m->ops->gather(st, io)))
     return rc;
   if ((rc = m->red.run(st, io.Ei, io.Wi, nullptr, dev_energy, dev_virial, nullptr))) return rc;
   const size_t N = (size_t)m->nbr.N;
@@ -203,7 +205,7 @@ int nepmi_descriptors(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, co
   int rc = m->prepare(n_cfg, atom_off, cells, dev_pos, dev_species, st);
   if (rc) return rc;
   NepIO io = m->io(nullptr, nullptr, dev_q);
-  return m->ops->desc(st, io, m->params.ptr<float>(), false);
+  return m->ops->desc(st, io, m->params.ptr<float>(), false, m->vdesc);
 }
 
 }  // extern "C"
@@ -259,8 +261,8 @@ extern "C" int nepmi_neighbors(nepmi_model* m, int32_t n_cfg, const int64_t* ato
   const int64_t ns = m->nbr.n_slots;
   hipLaunchKernelGGL(k_export_lists, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, ns,
                      m->nbr.pos4.ptr<float4>(), m->nbr.cfg_of.ptr<int>(), m->nbr.orig.ptr<int>(),
-                     m->nbr.cfgs.ptr<CfgDev>(), which ? m->nbr.nbrA.ptr<uint32_t>() : m->nbr.nbrR.ptr<uint32_t>(),
-                     which ? m->nbr.cntA.ptr<int>() : m->nbr.cntR.ptr<int>(), rc1 * rc1, cap, dev_count, dev_nbr,
+                     m->nbr.cfgs.ptr<CfgDev>(), m->nbr.nbrR.ptr<uint32_t>(),
+                     m->nbr.cntR.ptr<int>(), rc1 * rc1, cap, dev_count, dev_nbr,
                      dev_rvec);
   NEPMI_HIP(hipGetLastError());
   return NEPMI_OK;

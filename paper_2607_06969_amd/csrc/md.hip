@@ -238,9 +238,11 @@ struct nepmi_md {
     o.cfgs = nbr.cfgs.ptr<CfgDev>();
     o.nbrR = nbr.nbrR.ptr<uint32_t>();
     o.cntR = nbr.cntR.ptr<int>();
-    o.nbrA = nbr.nbrA.ptr<uint32_t>();
-    o.cntA = nbr.cntA.ptr<int>();
-    o.revA = nbr.revA.ptr<int>();
+    o.cnR = nbr.cnbrR.ptr<uint32_t>();
+    o.ccR = nbr.ccntR.ptr<int>();
+    o.cnA = nbr.cnbrA.ptr<uint32_t>();
+    o.ccA = nbr.ccntA.ptr<int>();
+    o.flags = nbr.flags.ptr<int>();
     const float rcR = (float)m->hp.rc_radial, rcA = (float)m->hp.rc_angular;
     o.cut.rcR = rcR;
     o.cut.rcA = rcA;
@@ -265,7 +267,7 @@ struct nepmi_md {
     NepIO o = io();
     const float* P = m->params.ptr<float>();
     int rc;
-    if ((rc = m->ops->desc(st, o, P, true)) || (rc = m->ops->force(st, o, P)) || (rc = m->ops->gather(st, o)))
+    if ((rc = m->ops->desc(st, o, P, true, m->vdesc)) || (rc = m->ops->force(st, o, P, m->vforce)) || (rc = m->ops->gather(st, o)))
       return rc;
     return NEPMI_OK;
   }
@@ -395,7 +397,8 @@ int nepmi_md_create(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, cons
   }
   if ((rc = md->fA.ensure(16 * (size_t)ns * nb.capA))) return fail(rc);
   fill_int(st, nb.flags.ptr<int>(), kFlagCount, 0, nullptr);
-  // forces of the initial state
+  // kernel variants timed on this state, then the forces of the initial state
+  if ((rc = autotune_io(m, md->io(), st, 2))) return fail(rc);
   if ((rc = md->forces(st))) return fail(rc);
   hipLaunchKernelGGL(k_md_kin, dim3(nb256(ns)), dim3(256), 0, st, ns, md->mc, nb.orig.ptr<int>(), nb.pos4.ptr<float4>(),
                      md->vel4.ptr<float4>(), md->Ki.ptr<float>());
@@ -487,9 +490,9 @@ int nepmi_md_time_kernels(nepmi_md* md, int32_t reps, double* ms, void* stream) 
   int rc = NEPMI_OK;
   for (int r = 0; r < reps && !rc; ++r) {
     NEPMI_HIP(hipEventRecord(ev[0], st));
-    rc = md->m->ops->desc(st, o, P, true);
+    rc = md->m->ops->desc(st, o, P, true, md->m->vdesc);
     NEPMI_HIP(hipEventRecord(ev[1], st));
-    if (!rc) rc = md->m->ops->force(st, o, P);
+    if (!rc) rc = md->m->ops->force(st, o, P, md->m->vforce);
     NEPMI_HIP(hipEventRecord(ev[2], st));
     if (!rc) rc = md->m->ops->gather(st, o);
     NEPMI_HIP(hipEventRecord(ev[3], st));

@@ -9,8 +9,8 @@ namespace nepmi {
 
 // Kernel set of one compiled shape.
 struct Ops {
-  int (*desc)(hipStream_t, const NepIO&, const float*, bool);
-  int (*force)(hipStream_t, const NepIO&, const float*);
+  int (*desc)(hipStream_t, const NepIO&, const float*, bool, int);
+  int (*force)(hipStream_t, const NepIO&, const float*, int);
   int (*gather)(hipStream_t, const NepIO&);
   int (*seeds)(hipStream_t, const TrainSeedArgs&);
   int (*backward)(hipStream_t, TrainIO, const Cutoffs&, const float*, const float*, const int*, double*, double*,
@@ -38,8 +38,15 @@ struct nepmi_model {
   nepmi::DevBuf fp, aR, Ei, frad, fA, Wi, Eproc;
   nepmi::TrainBufs tr;
   int device = 0;
+  int vdesc = 0, vforce = 0;  // kernel variants in use (see nepmi_autotune)
   // Prepare the batch: neighbour lists, work buffers and reduction plan.
   int prepare(int n_cfg, const int64_t* atom_off, const double* cells, const float* pos, const int32_t* species,
               hipStream_t st);
   nepmi::NepIO io(float* Fuser, float4* Fproc, float* qout);
 };
+
+namespace nepmi {
+// Time every compiled variant of k_desc and k_force on `io` and keep the
+// fastest in the model (see tune.hip).
+int autotune_io(nepmi_model* m, const NepIO& io, hipStream_t st, int reps);
+}  // namespace nepmi

@@ -13,7 +13,10 @@
 //
 // Neighbour entries are 32-bit: slot index (27 bits) | image code (5 bits),
 // code = (w0+1)*9 + (w1+1)*3 + (w2+1) for the lattice shift w in {-1,0,1}^3.
-// Lists are column-major, entry k of slot p at [k * n_slots + p].
+// Lists are column-major, entry k of slot p at [k * n_slots + p].  The
+// Verlet list holds pairs within rc_radial + skin; at every evaluation the
+// descriptor kernel filters it into compact lists of the pairs within
+// rc_radial and within rc_angular, which all later kernels iterate.
 #include "nbr.hpp"
 
 namespace nepmi {
@@ -239,7 +242,6 @@ __global__ __launch_bounds__(256) void k_build_lists(int64_t n_slots, int n_spec
                                                      const int* __restrict__ bin_of, const int* __restrict__ start,
                                                      const int* __restrict__ base, float rclR2, float rclA2, int capR,
                                                      int capA, uint32_t* __restrict__ nbrR, int* __restrict__ cntR,
-                                                     uint32_t* __restrict__ nbrA, int* __restrict__ cntA,
                                                      int* __restrict__ flags, const int* __restrict__ gate) {
   if (gate && *gate == 0) return;
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -247,7 +249,6 @@ __global__ __launch_bounds__(256) void k_build_lists(int64_t n_slots, int n_spec
   const int c = cfg_of[p];
   if (c < 0) {
     cntR[p] = 0;
-    cntA[p] = 0;
     return;
   }
   const CfgDev& C = cfgs[c];
@@ -280,48 +281,17 @@ __global__ __launch_bounds__(256) void k_build_lists(int64_t n_slots, int n_spec
           const uint32_t e = (uint32_t)q | (code << kNbrShift);
           if (kR < capR) nbrR[(int64_t)kR * n_slots + p] = e;
           ++kR;
-          if (d2 < rclA2) {
-            if (kA < capA) nbrA[(int64_t)kA * n_slots + p] = e;
-            ++kA;
-          }
+          if (d2 < rclA2) ++kA;
         }
       }
     }
   }
   cntR[p] = kR < capR ? kR : capR;
-  cntA[p] = kA < capA ? kA : capA;
+  // the angular pairs within rc_angular at any step between rebuilds are among
+  // those within rc_angular + skin now, so kA bounds the per-step angular list
   if (kR > capR || kA > capA) atomicOr(&flags[kFlagOverflow], 1);
   atomicMax(&flags[kFlagMaxR], kR);
   atomicMax(&flags[kFlagMaxA], kA);
-}
-
-// revA[k][p] = flat index of the entry (q -> p) in q's angular list, where
-// entry k of p is (p -> q).  Every pair is listed from both sides because the
-// pair vector is computed with the same rounding in both directions.
-__global__ __launch_bounds__(256) void k_build_rev(int64_t n_slots, const uint32_t* __restrict__ nbrA,
-                                                   const int* __restrict__ cntA, int* __restrict__ revA,
-                                                   int* __restrict__ flags, const int* __restrict__ gate) {
-  if (gate && *gate == 0) return;
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n_slots) return;
-  const int n = cntA[p];
-  for (int k = 0; k < n; ++k) {
-    const uint32_t e = nbrA[(int64_t)k * n_slots + p];
-    const int q = (int)(e & kNbrMask);
-    const uint32_t want = (uint32_t)p | ((26u - (e >> kNbrShift)) << kNbrShift);
-    const int nq = cntA[q];
-    int found = -1;
-    for (int j = 0; j < nq; ++j)
-      if (nbrA[(int64_t)j * n_slots + q] == want) {
-        found = j;
-        break;
-      }
-    if (found < 0) {
-      atomicOr(&flags[kFlagAsym], 1);
-      found = 0;
-    }
-    revA[(int64_t)k * n_slots + p] = (int)((int64_t)found * n_slots + q);
-  }
 }
 
 // ---------------------------------------------------------------- host side
@@ -462,7 +432,8 @@ int NbrPipeline::setup(int n_cfg_, const int64_t* atom_off, const double* cells,
       (rc = pos_tmp.ensure(16 * Na)) || (rc = cfg_tmp.ensure(4 * Na)) || (rc = pos4.ensure(16 * (size_t)n_slots)) ||
       (rc = cfg_of.ensure(4 * (size_t)n_slots)) || (rc = orig.ensure(4 * (size_t)n_slots)) ||
       (rc = bin_of.ensure(4 * (size_t)n_slots)) || (rc = slot_of.ensure(4 * Na)) ||
-      (rc = cntR.ensure(4 * (size_t)n_slots)) || (rc = cntA.ensure(4 * (size_t)n_slots)) ||
+      (rc = cntR.ensure(4 * (size_t)n_slots)) || (rc = ccntR.ensure(4 * (size_t)n_slots)) ||
+      (rc = ccntA.ensure(4 * (size_t)n_slots)) ||
       (rc = flags.ensure(4 * kFlagCount)))
     return rc;
   NEPMI_HIP(hipMemcpyAsync(cfgs.p, hc.data(), sizeof(CfgDev) * (size_t)n_cfg_, hipMemcpyHostToDevice, st));
@@ -488,8 +459,8 @@ int NbrPipeline::ensure_lists(int capR_, int capA_) {
   capR = capR_;
   capA = capA_;
   int rc;
-  if ((rc = nbrR.ensure(4 * (size_t)capR * (size_t)n_slots)) || (rc = nbrA.ensure(4 * (size_t)capA * (size_t)n_slots)) ||
-      (rc = revA.ensure(4 * (size_t)capA * (size_t)n_slots)))
+  if ((rc = nbrR.ensure(4 * (size_t)capR * (size_t)n_slots)) || (rc = cnbrR.ensure(4 * (size_t)capR * (size_t)n_slots)) ||
+      (rc = cnbrA.ensure(4 * (size_t)capA * (size_t)n_slots)))
     return rc;
   return NEPMI_OK;
 }
@@ -516,13 +487,7 @@ int NbrPipeline::build(hipStream_t st, const float* pos, const int32_t* species)
     if ((rc = launch_lists(st, n_species, nullptr))) return rc;
     int hf[kFlagCount];
     if ((rc = check_flags(st, hf))) return rc;
-    if (!hf[kFlagOverflow]) {
-      if (hf[kFlagAsym]) {
-        set_error("angular neighbour list is not symmetric");
-        return NEPMI_INVALID_ARG;
-      }
-      return NEPMI_OK;
-    }
+    if (!hf[kFlagOverflow]) return NEPMI_OK;
     // grow to the largest list seen plus a margin and rebuild the lists
     if ((rc = ensure_lists(hf[kFlagMaxR] + 8, hf[kFlagMaxA] + 8))) return rc;
     fill_int(st, flags.ptr<int>(), kFlagCount, 0, nullptr);
@@ -567,9 +532,7 @@ int NbrPipeline::launch_lists(hipStream_t st, int n_species, const int* gate) {
   hipLaunchKernelGGL(k_build_lists, dim3(nblk(n_slots, 256)), dim3(256), 0, st, n_slots, n_species, total_bins,
                      cfgs.ptr<CfgDev>(), pos4.ptr<float4>(), cfg_of.ptr<int>(), bin_of.ptr<int>(), start.ptr<int>(),
                      base.ptr<int>(), rclR2, rclA2, capR, capA, nbrR.ptr<uint32_t>(), cntR.ptr<int>(),
-                     nbrA.ptr<uint32_t>(), cntA.ptr<int>(), flags.ptr<int>(), gate);
-  hipLaunchKernelGGL(k_build_rev, dim3(nblk(n_slots, 256)), dim3(256), 0, st, n_slots, nbrA.ptr<uint32_t>(),
-                     cntA.ptr<int>(), revA.ptr<int>(), flags.ptr<int>(), gate);
+                     flags.ptr<int>(), gate);
   NEPMI_HIP(hipGetLastError());
   return NEPMI_OK;
 }

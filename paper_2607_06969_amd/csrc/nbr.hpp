@@ -14,7 +14,7 @@ enum {
   kFlagMaxA = 2,       // largest angular list length seen
   kFlagNaN = 3,        // non-finite input position
   kFlagBadSpecies = 4, // species out of range
-  kFlagAsym = 5,       // an angular pair listed from one side only
+  kFlagAsym = 5,       // a pair found from one side only
   kFlagRebuild = 6,    // MD: rebuild the lists in this step
   kFlagCount = 16
 };
@@ -51,7 +51,8 @@ struct NbrPipeline {
   DevBuf cfgs, atom_off_dev;
   DevBuf key, cnt, start, cursor, tile_sums, base, perm, pos_tmp, cfg_tmp;
   DevBuf pos4, cfg_of, orig, bin_of, slot_of;
-  DevBuf nbrR, cntR, nbrA, cntA, revA;
+  DevBuf nbrR, cntR;             // Verlet list (rc_radial + skin)
+  DevBuf cnbrR, ccntR, cnbrA, ccntA;  // per-evaluation compact lists (rc_radial, rc_angular)
   DevBuf flags;
 
   // Host-side setup of a batch: validates the cells, computes bins, sizes

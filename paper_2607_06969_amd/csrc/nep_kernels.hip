@@ -1,5 +1,6 @@
 // nep_kernels.hip -- descriptor/network, pair-force and gather kernels.
 #include "nep_kernels.hpp"
+#include "nbr.hpp"
 
 namespace nepmi {
 
@@ -69,13 +70,13 @@ __device__ __forceinline__ float tr_cube(const float (&A)[6]) {
 
 // ------------------------------------------------------------------ k_desc
 
-template <class S, int NSPLIT>
-__global__ __launch_bounds__(kBlock) void k_desc(
+template <class S, int NSPLIT, int WPE>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) void k_desc(
     int64_t n_slots, const float4* __restrict__ pos4, const int* __restrict__ cfg_of, const int* __restrict__ orig,
     const CfgDev* __restrict__ cfgs, const uint32_t* __restrict__ nbrR, const int* __restrict__ cntR,
-    const uint32_t* __restrict__ nbrA, const int* __restrict__ cntA, Cutoffs cut, const float* __restrict__ params,
-    float* __restrict__ fp, float* __restrict__ aR, float* __restrict__ Ei, float* __restrict__ qout,
-    float* __restrict__ Eproc, int want_adjoint) {
+    uint32_t* __restrict__ cnR, int* __restrict__ ccR, uint32_t* __restrict__ cnA, int* __restrict__ ccA,
+    Cutoffs cut, const float* __restrict__ params, float* __restrict__ fp, float* __restrict__ aR,
+    float* __restrict__ Ei, float* __restrict__ qout, float* __restrict__ Eproc, int want_adjoint) {
   constexpr int T = S::T, NR = S::NR, NA = S::NA, BR = S::BR, BA = S::BA, L = S::L, K = S::K, D = S::D, H = S::H;
   constexpr int NH = NA / NSPLIT;
   static_assert(NA % NSPLIT == 0, "NSPLIT must divide n_angular");
@@ -93,6 +94,26 @@ __global__ __launch_bounds__(kBlock) void k_desc(
   load_cell(cfgs, c, Hc);
   const float rcR_inv = 1.0f / cut.rcR, rcA_inv = 1.0f / cut.rcA;
 
+  // ---- filter the Verlet list into the pairs inside the two cutoffs
+  int nR = 0, nA = 0;
+  if (active) {
+    const int n = cntR[p];
+    for (int k = 0; k < n; ++k) {
+      const uint32_t e = nbrR[(int64_t)k * n_slots + p];
+      const PairVec v = pair_vec(pos4, e, xi, Hc);
+      if (v.d2 < cut.rcR2) {
+        cnR[(int64_t)nR * n_slots + p] = e;
+        ++nR;
+        if (v.d2 < cut.rcA2) {
+          cnA[(int64_t)nA * n_slots + p] = e;
+          ++nA;
+        }
+      }
+    }
+  }
+  ccR[p] = nR;
+  ccA[p] = nA;
+
   float q[D];
   // ---- radial descriptors, Eq. 11: q_n = sum_b sum_k c^R[Z_i][b][n][k] P_b[k],
   //      P_b[k] = sum over neighbours j of species b of Q_k(r_ij)
@@ -102,18 +123,15 @@ __global__ __launch_bounds__(kBlock) void k_desc(
     for (int b = 0; b < T; ++b)
 #pragma unroll
       for (int k = 0; k < BR; ++k) P[b][k] = 0.f;
-    const int n = active ? cntR[p] : 0;
-    for (int k = 0; k < n; ++k) {
-      const PairVec v = pair_vec(pos4, nbrR[(int64_t)k * n_slots + p], xi, Hc);
-      if (v.d2 < cut.rcR2) {
-        float Q[BR];
-        cheb_basis<BR>(sqrtf(v.d2), rcR_inv, Q);
+    for (int k = 0; k < nR; ++k) {
+      const PairVec v = pair_vec(pos4, cnR[(int64_t)k * n_slots + p], xi, Hc);
+      float Q[BR];
+      cheb_basis<BR>(sqrtf(v.d2), rcR_inv, Q);
 #pragma unroll
-        for (int b = 0; b < T; ++b) {
-          const float m = (T == 1 || v.zj == b) ? 1.0f : 0.0f;
+      for (int b = 0; b < T; ++b) {
+        const float m = (T == 1 || v.zj == b) ? 1.0f : 0.0f;
 #pragma unroll
-          for (int kk = 0; kk < BR; ++kk) P[b][kk] = fmaf(m, Q[kk], P[b][kk]);
-        }
+        for (int kk = 0; kk < BR; ++kk) P[b][kk] = fmaf(m, Q[kk], P[b][kk]);
       }
     }
     const float* cR = params + (int64_t)Zs * (T * NR * BR);
@@ -129,7 +147,6 @@ __global__ __launch_bounds__(kBlock) void k_desc(
   }
 
   // ---- angular descriptors, Eq. 16-17, in NSPLIT groups of n
-  const int nA = active ? cntA[p] : 0;
 #pragma unroll
   for (int h = 0; h < NSPLIT; ++h) {
     float Sg[NH][K];
@@ -138,8 +155,8 @@ __global__ __launch_bounds__(kBlock) void k_desc(
 #pragma unroll
       for (int lm = 0; lm < K; ++lm) Sg[nn][lm] = 0.f;
     for (int k = 0; k < nA; ++k) {
-      const PairVec v = pair_vec(pos4, nbrA[(int64_t)k * n_slots + p], xi, Hc);
-      if (v.d2 < cut.rcA2) {
+      const PairVec v = pair_vec(pos4, cnA[(int64_t)k * n_slots + p], xi, Hc);
+      {
         const float d = sqrtf(v.d2);
         const float inv = 1.0f / d;
         float Q[BA];
@@ -224,11 +241,11 @@ __global__ __launch_bounds__(kBlock) void k_desc(
 
 // ----------------------------------------------------------------- k_force
 
-template <class S, int NSPLIT>
-__global__ __launch_bounds__(kBlock) void k_force(
+template <class S, int NSPLIT, int WPE>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) void k_force(
     int64_t n_slots, const float4* __restrict__ pos4, const int* __restrict__ cfg_of, const int* __restrict__ orig,
-    const CfgDev* __restrict__ cfgs, const uint32_t* __restrict__ nbrR, const int* __restrict__ cntR,
-    const uint32_t* __restrict__ nbrA, const int* __restrict__ cntA, Cutoffs cut, const float* __restrict__ params,
+    const CfgDev* __restrict__ cfgs, const uint32_t* __restrict__ cnR, const int* __restrict__ ccR,
+    const uint32_t* __restrict__ cnA, const int* __restrict__ ccA, Cutoffs cut, const float* __restrict__ params,
     const float* __restrict__ fp, const float* __restrict__ aR, float4* __restrict__ frad, float4* __restrict__ fA,
     float* __restrict__ Wi) {
   constexpr int T = S::T, NR = S::NR, NA = S::NA, BR = S::BR, BA = S::BA, L = S::L, K = S::K;
@@ -259,10 +276,10 @@ __global__ __launch_bounds__(kBlock) void k_force(
     for (int b = 0; b < T; ++b)
 #pragma unroll
       for (int kk = 0; kk < BR; ++kk) a_own[b][kk] = aR[p * (T * BR) + b * BR + kk];
-    const int n = cntR[p];
+    const int n = ccR[p];
     for (int k = 0; k < n; ++k) {
-      const PairVec v = pair_vec(pos4, nbrR[(int64_t)k * n_slots + p], xi, Hc);
-      if (v.d2 < cut.rcR2) {
+      const PairVec v = pair_vec(pos4, cnR[(int64_t)k * n_slots + p], xi, Hc);
+      {
         const float d = sqrtf(v.d2);
         const float inv = 1.0f / d;
         float Q[BR], dQ[BR];
@@ -293,7 +310,7 @@ __global__ __launch_bounds__(kBlock) void k_force(
   }
 
   // ---- angular pairs, in NSPLIT groups of n
-  const int nA = cntA[p];
+  const int nA = ccA[p];
 #pragma unroll
   for (int h = 0; h < NSPLIT; ++h) {
     // recompute S for this group
@@ -303,8 +320,8 @@ __global__ __launch_bounds__(kBlock) void k_force(
 #pragma unroll
       for (int lm = 0; lm < K; ++lm) Sg[nn][lm] = 0.f;
     for (int k = 0; k < nA; ++k) {
-      const PairVec v = pair_vec(pos4, nbrA[(int64_t)k * n_slots + p], xi, Hc);
-      if (v.d2 < cut.rcA2) {
+      const PairVec v = pair_vec(pos4, cnA[(int64_t)k * n_slots + p], xi, Hc);
+      {
         const float d = sqrtf(v.d2);
         const float inv = 1.0f / d;
         float Q[BA];
@@ -364,9 +381,9 @@ __global__ __launch_bounds__(kBlock) void k_force(
     // pair forces of this group: f = u sum_n g'_n Z_n + (I - u u^T) v / d,
     // Z_n = sum_lm sigma_nlm Y_lm, v = sum_lm G_lm grad P_lm, G_lm = sum_n sigma_nlm g_n
     for (int k = 0; k < nA; ++k) {
-      const PairVec v = pair_vec(pos4, nbrA[(int64_t)k * n_slots + p], xi, Hc);
+      const PairVec v = pair_vec(pos4, cnA[(int64_t)k * n_slots + p], xi, Hc);
       float fx = 0.f, fy = 0.f, fz = 0.f;
-      if (v.d2 < cut.rcA2) {
+      {
         const float d = sqrtf(v.d2);
         const float inv = 1.0f / d;
         const float ux = v.rx * inv, uy = v.ry * inv, uz = v.rz * inv;
@@ -424,9 +441,10 @@ __global__ __launch_bounds__(kBlock) void k_force(
 // ---------------------------------------------------------------- k_gather
 
 __global__ __launch_bounds__(kBlock) void k_gather(int64_t n_slots, const int* __restrict__ orig,
-                                                   const int* __restrict__ cntA, const int* __restrict__ revA,
+                                                   const uint32_t* __restrict__ cnA, const int* __restrict__ ccA,
                                                    const float4* __restrict__ frad, const float4* __restrict__ fA,
-                                                   float* __restrict__ Fuser, float4* __restrict__ Fproc) {
+                                                   float* __restrict__ Fuser, float4* __restrict__ Fproc,
+                                                   int* __restrict__ flags) {
   const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (p >= n_slots) return;
   const int i = orig[p];
@@ -435,13 +453,24 @@ __global__ __launch_bounds__(kBlock) void k_gather(int64_t n_slots, const int* _
     return;
   }
   float4 F = frad[p];
-  const int n = cntA[p];
+  const int n = ccA[p];
   for (int k = 0; k < n; ++k) {
+    const uint32_t e = cnA[(int64_t)k * n_slots + p];
+    const int q = (int)(e & kNbrMask);
+    // the pair seen from q: slot p with the opposite image shift
+    const uint32_t want = (uint32_t)p | ((26u - (e >> kNbrShift)) << kNbrShift);
+    const int nq = ccA[q];
+    int j = 0;
+    while (j < nq && cnA[(int64_t)j * n_slots + q] != want) ++j;
     const float4 a = fA[(int64_t)k * n_slots + p];
-    const float4 b = fA[revA[(int64_t)k * n_slots + p]];
-    F.x += a.x - b.x;
-    F.y += a.y - b.y;
-    F.z += a.z - b.z;
+    if (j < nq) {
+      const float4 b = fA[(int64_t)j * n_slots + q];
+      F.x += a.x - b.x;
+      F.y += a.y - b.y;
+      F.z += a.z - b.z;
+    } else {
+      atomicOr(&flags[kFlagAsym], 1);
+    }
   }
   if (Fuser) {
     Fuser[(int64_t)i * 3 + 0] = F.x;
@@ -453,36 +482,60 @@ __global__ __launch_bounds__(kBlock) void k_gather(int64_t n_slots, const int* _
 
 // ------------------------------------------------------------- launchers
 
-template <class S>
-constexpr int nsplit() {
-  return S::NA >= 8 ? 2 : 1;
+// Kernel variants: (groups of angular functions per pass, waves per SIMD the
+// register allocation must allow).  Every variant computes the same result;
+// descriptor variants are bitwise identical, force variants differ only in
+// the order the per-group pair forces are added.
+template <class S, int NS>
+constexpr int groups() {
+  return NS <= S::NA ? NS : S::NA;
 }
 
-template <class S>
-int Launch<S>::desc(hipStream_t st, const NepIO& io, const float* params, bool want_adjoint) {
+template <class S, int NS, int W>
+static int launch_desc(hipStream_t st, const NepIO& io, const float* params, bool want_adjoint) {
   const unsigned g = (unsigned)((io.n_slots + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL((k_desc<S, nsplit<S>()>), dim3(g), dim3(kBlock), 0, st, io.n_slots, io.pos4, io.cfg_of, io.orig,
-                     io.cfgs, io.nbrR, io.cntR, io.nbrA, io.cntA, io.cut, params, io.fp, io.aR, io.Ei, io.qout,
-                     io.Eproc, want_adjoint ? 1 : 0);
+  hipLaunchKernelGGL((k_desc<S, groups<S, NS>(), W>), dim3(g), dim3(kBlock), 0, st, io.n_slots, io.pos4, io.cfg_of,
+                     io.orig, io.cfgs, io.nbrR, io.cntR, io.cnR, io.ccR, io.cnA, io.ccA, io.cut, params, io.fp, io.aR,
+                     io.Ei, io.qout, io.Eproc, want_adjoint ? 1 : 0);
+  NEPMI_HIP(hipGetLastError());
+  return NEPMI_OK;
+}
+
+template <class S, int NS, int W>
+static int launch_force(hipStream_t st, const NepIO& io, const float* params) {
+  const unsigned g = (unsigned)((io.n_slots + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL((k_force<S, groups<S, NS>(), W>), dim3(g), dim3(kBlock), 0, st, io.n_slots, io.pos4, io.cfg_of,
+                     io.orig, io.cfgs, io.cnR, io.ccR, io.cnA, io.ccA, io.cut, params, io.fp, io.aR, io.frad, io.fA,
+                     io.Wi);
   NEPMI_HIP(hipGetLastError());
   return NEPMI_OK;
 }
 
 template <class S>
-int Launch<S>::force(hipStream_t st, const NepIO& io, const float* params) {
-  const unsigned g = (unsigned)((io.n_slots + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL((k_force<S, nsplit<S>()>), dim3(g), dim3(kBlock), 0, st, io.n_slots, io.pos4, io.cfg_of,
-                     io.orig, io.cfgs, io.nbrR, io.cntR, io.nbrA, io.cntA, io.cut, params, io.fp, io.aR, io.frad,
-                     io.fA, io.Wi);
-  NEPMI_HIP(hipGetLastError());
-  return NEPMI_OK;
+int Launch<S>::desc(hipStream_t st, const NepIO& io, const float* params, bool want_adjoint, int variant) {
+  switch (variant) {
+    case 1: return launch_desc<S, 4, 3>(st, io, params, want_adjoint);
+    case 2: return launch_desc<S, 4, 2>(st, io, params, want_adjoint);
+    case 3: return launch_desc<S, 8, 3>(st, io, params, want_adjoint);
+    default: return launch_desc<S, 2, 2>(st, io, params, want_adjoint);
+  }
+}
+
+template <class S>
+int Launch<S>::force(hipStream_t st, const NepIO& io, const float* params, int variant) {
+  switch (variant) {
+    case 1: return launch_force<S, 4, 2>(st, io, params);
+    case 2: return launch_force<S, 4, 3>(st, io, params);
+    case 3: return launch_force<S, 8, 3>(st, io, params);
+    default: return launch_force<S, 2, 2>(st, io, params);
+  }
 }
 
 template <class S>
 int Launch<S>::gather(hipStream_t st, const NepIO& io) {
   const unsigned g = (unsigned)((io.n_slots + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_gather, dim3(g), dim3(kBlock), 0, st, io.n_slots, io.orig, io.cntA, io.revA, io.frad, io.fA,
-                     io.Fuser, io.Fproc);
+  hipLaunchKernelGGL(k_gather, dim3(g), dim3(kBlock), 0, st, io.n_slots, io.orig, io.cnA, io.ccA, io.frad, io.fA,
+                     io.Fuser, io.Fproc, io.flags);
   NEPMI_HIP(hipGetLastError());
   return NEPMI_OK;
 }

@@ -37,10 +37,10 @@ TrainIO train_io(nepmi_model* m, const double* mu, const double* ebar) {
   io.cfg_of = m->nbr.cfg_of.ptr<int>();
   io.orig = m->nbr.orig.ptr<int>();
   io.cfgs = m->nbr.cfgs.ptr<CfgDev>();
-  io.nbrR = m->nbr.nbrR.ptr<uint32_t>();
-  io.cntR = m->nbr.cntR.ptr<int>();
-  io.nbrA = m->nbr.nbrA.ptr<uint32_t>();
-  io.cntA = m->nbr.cntA.ptr<int>();
+  io.nbrR = m->nbr.cnbrR.ptr<uint32_t>();  // compact lists written by the forward
+  io.cntR = m->nbr.ccntR.ptr<int>();
+  io.nbrA = m->nbr.cnbrA.ptr<uint32_t>();
+  io.cntA = m->nbr.ccntA.ptr<int>();
   io.lam4 = t.lam4.ptr<float4>();
   io.mu = mu;
   io.ebar = ebar;
@@ -83,6 +83,8 @@ int nepmi_backward_params(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off
   hipStream_t st = (hipStream_t)stream;
   int rc;
   if ((rc = m->prepare(n_cfg, atom_off, cells, dev_pos, dev_species, st)) || (rc = ensure_train(m))) return rc;
+  // the descriptor kernel writes the per-evaluation compact pair lists
+  if ((rc = m->ops->desc(st, m->io(nullptr, nullptr, nullptr), m->params.ptr<float>(), false, m->vdesc))) return rc;
   return run_backward(m, st, dev_ebar, dev_lambda, dev_mu, dev_grad);
 }
 
@@ -102,7 +104,7 @@ int nepmi_loss_grad(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, cons
   // forward: E, F, V
   NepIO io = m->io(t.F.ptr<float>(), nullptr, nullptr);
   const float* P = m->params.ptr<float>();
-  if ((rc = m->ops->desc(st, io, P, true)) || (rc = m->ops->force(st, io, P)) || (rc = m->ops->gather(st, io)) ||
+  if ((rc = m->ops->desc(st, io, P, true, m->vdesc)) || (rc = m->ops->force(st, io, P, m->vforce)) || (rc = m->ops->gather(st, io)) ||
       (rc = m->red.run(st, io.Ei, io.Wi, nullptr, t.E.ptr<double>(), t.V.ptr<double>(), nullptr)))
     return rc;
   // loss and seeds

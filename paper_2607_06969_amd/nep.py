@@ -115,6 +115,22 @@ class NepModel:
                                      int(which), int(cap), _ptr(cnt), _ptr(nb), _ptr(rv), _stream()))
         return cnt, nb, rv
 
+    def autotune(self, batch: Batch):
+        """Time every kernel variant on this batch and keep the fastest; returns (desc, force)."""
+        ch = (C.c_int32 * 2)()
+        keep, poff, pcel = batch._meta()
+        check(load().nepmi_autotune(self._h, batch.n_cfg, poff, pcel, _ptr(batch.pos), _ptr(batch.species), ch,
+                                    _stream()))
+        return int(ch[0]), int(ch[1])
+
+    def set_variants(self, desc: int, force: int):
+        check(load().nepmi_set_variants(self._h, int(desc), int(force)))
+
+    def variants(self):
+        d, f = C.c_int32(), C.c_int32()
+        check(load().nepmi_get_variants(self._h, C.byref(d), C.byref(f)))
+        return d.value, f.value
+
     def backward_params(self, batch: Batch, ebar, lam, mu):
         """sum_c ebar_c dE_c/dtheta + sum_i lam_i.dF_i/dtheta + sum_c mu_c:dV_c/dtheta (float32, P).
         Needs a preceding compute() on the same batch."""
