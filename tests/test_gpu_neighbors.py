@@ -1,0 +1,128 @@
+"""GPU neighbour lists against brute force, general (triclinic) cells,
+unwrapped positions, empty configurations, capacity growth and the error
+paths (all forced from the host; no kernel is made to fault)."""
+import numpy as np
+import pytest
+
+from paper_2607_06969_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300)
+
+
+def _nep():
+    from paper_2607_06969_amd import nep
+    return nep
+
+
+@pytest.mark.parametrize("which,rc", [(0, 6.0), (1, 4.0)])
+@pytest.mark.parametrize("sysf", [lambda: W.simple_cubic(), lambda: W.rocksalt_gst(8, seed=81),
+                                  lambda: W.amorphous_batch(n_cfg=3, n_min=64, n_max=200, seed=82)])
+def test_neighbor_sets_match_bruteforce(oracle_lib, sysf, which, rc):
+    nep = _nep()
+    s = sysf()
+    hp = W.hp_gst() if s.species.max() > 0 else W.hp_small_single()
+    m = nep.NepModel(hp, W.random_params(hp, 1))
+    cnt, nb, rv = m.neighbors(nep.Batch.from_system(s), which, cap=160)
+    cnt, nb, rv = cnt.cpu().numpy(), nb.cpu().numpy(), rv.cpu().numpy()
+    for c in range(s.n_cfg):
+        a0, a1 = s.atom_off[c], s.atom_off[c + 1]
+        sub = s.config(c)
+        ij, r = oracle_lib.pairs(sub.pos, sub.cells[0], rc, 0)
+        ref = {(int(i) + a0, int(j) + a0): v for (i, j), v in zip(ij, r)}
+        got = {}
+        for i in range(a0, a1):
+            assert cnt[i] <= 160
+            for k in range(cnt[i]):
+                key = (i, int(nb[i, k]))
+                assert key not in got  # widths >= 2 rc: one image per pair
+                got[key] = rv[i, k].astype(np.float64)
+        # pairs within 1e-4 A of the cutoff may fall on either side in float32
+        edge = {k for k, v in ref.items() if abs(np.linalg.norm(v) - rc) < 1e-4}
+        edge |= {k for k, v in got.items() if abs(np.linalg.norm(v) - rc) < 1e-4}
+        assert set(ref) - edge == set(got) - edge
+        for k in set(ref) - edge:
+            assert np.max(np.abs(ref[k] - got[k])) < 1e-4
+
+
+def test_triclinic_cell_and_unwrapped_positions(oracle_lib):
+    nep = _nep()
+    hp = W.hp_gst()
+    base = W.rocksalt_gst(12, seed=83)
+    M = np.array([[1.0, 0.0, 0.0], [0.23, 1.0, 0.0], [-0.17, 0.11, 1.0]])
+    cell = (base.cells[0] @ M).astype(np.float32).astype(np.float64)
+    frac = base.pos @ np.linalg.inv(base.cells[0])
+    pos = W._wrap_round(frac @ cell, cell)
+    s = W.System(pos, base.species, cell[None], base.atom_off)
+    p = W.random_params(hp, 2041)
+    ref = oracle_lib.evaluate(hp, p, s, nbr_mode=0)
+    m = nep.NepModel(hp, p)
+    got = m.compute(nep.Batch.from_system(s))
+    assert abs(float(got["E"][0]) - ref["E"][0]) / s.n_atoms < 1e-6
+    assert rel(got["F"].cpu().numpy(), ref["F"]) < 1e-5
+    assert rel(got["V"][0].cpu().numpy(), ref["V"][0]) < 1e-5
+    # the same atoms moved by lattice vectors: results unchanged (wrapping on the GPU)
+    rng = np.random.default_rng(3)
+    shift = rng.integers(-2, 3, size=(s.n_atoms, 3)) @ cell
+    s2 = W.System((s.pos + shift).astype(np.float32).astype(np.float64), s.species, s.cells, s.atom_off)
+    ref2 = oracle_lib.evaluate(hp, p, s2, nbr_mode=0)
+    got2 = m.compute(nep.Batch.from_system(s2))
+    assert abs(float(got2["E"][0]) - ref2["E"][0]) / s.n_atoms < 1e-6
+    assert rel(got2["F"].cpu().numpy(), ref2["F"]) < 1e-5
+
+
+def test_empty_configuration_in_batch(oracle_lib):
+    nep = _nep()
+    hp = W.hp_gst()
+    a = W.amorphous_batch(n_cfg=2, n_min=64, n_max=120, seed=84)
+    empty = W.System(np.zeros((0, 3)), np.zeros(0, dtype=np.int32), np.eye(3)[None] * 20.0, np.array([0, 0]))
+    s = W.concat_systems([a.config(0), empty, a.config(1)])
+    p = W.random_params(hp, 2042)
+    m = nep.NepModel(hp, p)
+    got = m.compute(nep.Batch.from_system(s))
+    ref = oracle_lib.evaluate(hp, p, s, nbr_mode=0)
+    E = got["E"].cpu().numpy()
+    assert E[1] == 0.0 and np.all(got["V"][1].cpu().numpy() == 0.0)
+    assert np.max(np.abs(E - ref["E"]) / np.maximum(np.diff(s.atom_off), 1)) < 1e-6
+    assert rel(got["F"].cpu().numpy(), ref["F"]) < 1e-5
+
+
+def test_capacity_grows_for_denser_input(oracle_lib):
+    nep = _nep()
+    hp = W.hp_gst()
+    p = W.random_params(hp, 2043)
+    m = nep.NepModel(hp, p)
+    sparse = W.amorphous_batch(n_cfg=1, n_min=100, n_max=100, density=0.02, rmin=2.5, seed=85)
+    m.compute(nep.Batch.from_system(sparse))
+    dense = W.amorphous_batch(n_cfg=1, n_min=300, n_max=300, density=0.06, rmin=1.9, seed=86)
+    got = m.compute(nep.Batch.from_system(dense))
+    ref = oracle_lib.evaluate(hp, p, dense, nbr_mode=0)
+    assert rel(got["F"].cpu().numpy(), ref["F"]) < 1e-5
+
+
+def test_error_paths_and_recovery():
+    nep = _nep()
+    from paper_2607_06969_amd._lib import NepmiError, CELL_TOO_SMALL, NAN_DETECTED, INVALID_ARG
+    hp = W.hp_gst()
+    m = nep.NepModel(hp, W.random_params(hp, 2044))
+    small = W.rocksalt_gst(2, seed=87)  # 6 A box < 2 rc
+    with pytest.raises(NepmiError) as e:
+        m.compute(nep.Batch.from_system(small))
+    assert e.value.code == CELL_TOO_SMALL
+    s = W.rocksalt_gst(8, seed=88)
+    bad = s.pos.copy()
+    bad[5, 1] = np.nan
+    with pytest.raises(NepmiError) as e:
+        m.compute(nep.Batch.from_system(W.System(bad, s.species, s.cells, s.atom_off)))
+    assert e.value.code == NAN_DETECTED
+    spc = s.species.copy()
+    spc[7] = 3
+    with pytest.raises(NepmiError) as e:
+        m.compute(nep.Batch.from_system(W.System(s.pos, spc, s.cells, s.atom_off)))
+    assert e.value.code == INVALID_ARG
+    ok = m.compute(nep.Batch.from_system(s))
+    assert torch.isfinite(ok["F"]).all()
