@@ -185,6 +185,8 @@ def main():
     ap.add_argument("--sites", type=int, default=100, help="rocksalt sites per side (even)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=5)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="run a plain fill and elementwise add of this many MiB first (counter calibration)")
     ap.add_argument("--no-train", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     a = ap.parse_args()
@@ -196,6 +198,14 @@ def main():
     import torch
     from paper_2607_06969_amd import nep, workloads as W
 
+    if a.copy_mib > 0:
+        # plain elementwise kernels of known size: a fill writing copy_mib MiB,
+        # then an add reading and writing copy_mib MiB each
+        src = torch.ones(a.copy_mib * 262144, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.add(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     hp = W.hp_gst()
     params = W.random_params(hp, W.SEED_PARAM + 3)
     system = W.rocksalt_gst(a.sites, seed=W.SEED_POS + 3)

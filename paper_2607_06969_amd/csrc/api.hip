@@ -18,9 +18,9 @@ int hip_fail(hipError_t e, const char* what) {
 
 template <class S>
 static const Ops* ops_of() {
-  static const Ops o = {&Launch<S>::desc, &Launch<S>::force, &Launch<S>::gather, &TrainLaunch<S>::seeds,
-                        &TrainLaunch<S>::backward, S::T, S::NR, S::NA, S::BR, S::BA, S::L, S::D, S::NANG, S::H,
-                        S::K, S::P};
+  static const Ops o = {&Launch<S>::desc, &Launch<S>::force, &Launch<S>::gather, &Launch<S>::derive,
+                        &TrainLaunch<S>::seeds, &TrainLaunch<S>::backward, S::T, S::NR, S::NA, S::BR, S::BA, S::L,
+                        S::D, S::NANG, S::H, S::K, S::P, S::P + S::PCR + S::PCA};
   return &o;
 }
 
@@ -73,7 +73,7 @@ int nepmi_model::prepare(int n_cfg, const int64_t* atom_off, const double* cells
   if ((rc = red.setup(n_cfg, atom_off, st))) return rc;
   const size_t ns = (size_t)nbr.n_slots, N = (size_t)(nbr.N > 0 ? nbr.N : 1);
   if ((rc = fp.ensure(4 * ns * (size_t)ops->NANG)) || (rc = aR.ensure(4 * ns * (size_t)(ops->T * ops->BR))) ||
-      (rc = Ei.ensure(4 * N)) || (rc = frad.ensure(16 * ns)) || (rc = fA.ensure(16 * ns * (size_t)nbr.capA)) ||
+      (rc = Ei.ensure(4 * N)) || (rc = frad.ensure(16 * ns)) || (rc = fT.ensure(16 * ns * (size_t)nbr.capR)) || (rc = fA.ensure(16 * ns * (size_t)nbr.capA)) ||
       (rc = Wi.ensure(36 * N)) || (rc = Eproc.ensure(4 * ns)))
     return rc;
   return NEPMI_OK;
@@ -82,15 +82,19 @@ int nepmi_model::prepare(int n_cfg, const int64_t* atom_off, const double* cells
 NepIO nepmi_model::io(float* Fuser, float4* Fproc, float* qout) {
   NepIO o;
   o.n_slots = nbr.n_slots;
+  o.capR = nbr.capR;
+  o.capA = nbr.capA;
   o.pos4 = nbr.pos4.ptr<float4>();
   o.cfg_of = nbr.cfg_of.ptr<int>();
   o.orig = nbr.orig.ptr<int>();
   o.cfgs = nbr.cfgs.ptr<CfgDev>();
   o.nbrR = nbr.nbrR.ptr<uint32_t>();
   o.cntR = nbr.cntR.ptr<int>();
+  o.vrev = nbr.vrev.ptr<uint32_t>();
   o.cnR = nbr.cnbrR.ptr<uint32_t>();
   o.ccR = nbr.ccntR.ptr<int>();
   o.cnA = nbr.cnbrA.ptr<uint32_t>();
+  o.cpA = nbr.cposA.ptr<uint32_t>();
   o.ccA = nbr.ccntA.ptr<int>();
   o.flags = nbr.flags.ptr<int>();
   const float rcR = (float)hp.rc_radial, rcA = (float)hp.rc_angular;
@@ -106,6 +110,7 @@ NepIO nepmi_model::io(float* Fuser, float4* Fproc, float* qout) {
   o.qout = qout;
   o.frad = frad.ptr<float4>();
   o.fA = fA.ptr<float4>();
+  o.fT = fT.ptr<float4>();
   o.Wi = Wi.ptr<float>();
   o.Fuser = Fuser;
   o.Fproc = Fproc;
@@ -152,7 +157,7 @@ int nepmi_model_create(const nepmi_hparams* hp, nepmi_model** out) {
   if (!m) return NEPMI_INVALID_ARG;
   m->hp = *hp;
   m->ops = ops;
-  if (hipGetDevice(&m->device) != hipSuccess || (rc = m->params.ensure(4 * (size_t)ops->P))) {
+  if (hipGetDevice(&m->device) != hipSuccess || (rc = m->params.ensure(4 * (size_t)ops->P_alloc))) {
     delete m;
     return rc ? rc : NEPMI_HIP_ERROR;
   }
@@ -167,7 +172,7 @@ int nepmi_model_set_params(nepmi_model* m, const float* dev_params, void* stream
   }
   NEPMI_HIP(hipMemcpyAsync(m->params.p, dev_params, 4 * (size_t)m->ops->P, hipMemcpyDeviceToDevice,
                            (hipStream_t)stream));
-  return NEPMI_OK;
+  return m->ops->derive((hipStream_t)stream, m->params.ptr<float>());
 }
 
 void nepmi_model_destroy(nepmi_model* m) { delete m; }
@@ -233,7 +238,7 @@ __global__ void k_export_lists(int64_t n_slots, const float4* __restrict__ pos4,
     float sx, sy, sz;
     image_shift(H, e >> kNbrShift, sx, sy, sz);
     const float rx = (xq.x - xi.x) + sx, ry = (xq.y - xi.y) + sy, rz = (xq.z - xi.z) + sz;
-    if (rx * rx + ry * ry + rz * rz < rc2) {
+    if (pair_d2(rx, ry, rz) < rc2) {
       if (n < cap) {
         out_nbr[(int64_t)i * cap + n] = orig[q];
         out_r[((int64_t)i * cap + n) * 3 + 0] = rx;

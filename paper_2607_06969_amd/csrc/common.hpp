@@ -73,11 +73,20 @@ struct Cutoffs {
 
 // ------------------------------------------------------------ device helpers
 
+// Image code = 9 (w0 + 1) + 3 (w1 + 1) + (w2 + 1), w in {-1, 0, 1}; the shift is
+// w0 a + w1 b + w2 c for lattice rows a, b, c.  Digits by multiply-shift
+// (exact for code < 27: floor(57 c / 512) = floor(c / 9), floor(11 r / 32) =
+// floor(r / 3) for r < 9).  Every w_a is -1, 0 or 1, so the shift of code
+// 26 - code is the exact negative of the shift of code.
 __device__ __forceinline__ void image_shift(const float* __restrict__ H, uint32_t code, float& sx, float& sy,
                                             float& sz) {
-  const float w0 = (float)((int)(code / 9u) - 1);
-  const float w1 = (float)((int)((code / 3u) % 3u) - 1);
-  const float w2 = (float)((int)(code % 3u) - 1);
+  const uint32_t d0 = (code * 57u) >> 9;
+  const uint32_t r = code - 9u * d0;
+  const uint32_t d1 = (r * 11u) >> 5;
+  const uint32_t d2 = r - 3u * d1;
+  const float w0 = (float)((int)d0 - 1);
+  const float w1 = (float)((int)d1 - 1);
+  const float w2 = (float)((int)d2 - 1);
   sx = w0 * H[0] + w1 * H[3] + w2 * H[6];
   sy = w0 * H[1] + w1 * H[4] + w2 * H[7];
   sz = w0 * H[2] + w1 * H[5] + w2 * H[8];
@@ -133,6 +142,121 @@ __device__ __forceinline__ void cheb_basis_d(float d, float rc_inv, float (&Q)[B
     dtk = dtn;
     Q[k] = 0.5f * (tn + 1.0f) * fc;
     dQ[k] = 0.5f * (dtn * dx * fc + (tn + 1.0f) * dfc);
+  }
+}
+
+// Workgroups of a launch are dispatched round-robin over the XCDs, each with
+// its own L2: block b runs on XCD b % kXcds.  Per-atom kernels take their
+// tile from this remapping instead of blockIdx.x, so that every XCD walks one
+// contiguous range of slots (spatially close atoms, whose neighbours' data
+// then stay in that XCD's L2).  It is a bijection on [0, gridDim.x).
+constexpr unsigned kXcds = 8;
+__device__ __forceinline__ int64_t xcd_tile() {
+  const unsigned b = blockIdx.x, nb = gridDim.x;
+  const unsigned x = b % kXcds, i = b / kXcds, per = nb / kXcds, rem = nb % kXcds;
+  return (int64_t)(x * per + (x < rem ? x : rem) + i);
+}
+
+// |r|^2 with a fixed operation order (fused), shared by every kernel that
+// compares pair distances so that all of them agree on which pairs are in.
+__device__ __forceinline__ float pair_d2(float rx, float ry, float rz) {
+  return fmaf(rz, rz, fmaf(ry, ry, rx * rx));
+}
+
+// 1/sqrt(x) with the hardware reciprocal square root (1 ulp).
+__device__ __forceinline__ float rsqrt_hw(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// sin(pi u) and cos(pi u) for |u| <= 1/2 by their Taylor series to degree 13
+// and 12: coefficients (-1)^k pi^(2k+1)/(2k+1)! and (-1)^k pi^(2k)/(2k)!; the
+// truncation error is below (pi/2)^15/15! < 7e-10 and (pi/2)^14/14! < 7e-9.
+namespace taylor {
+constexpr double kPi = 3.14159265358979323846;
+constexpr double fact(int n) { return n <= 1 ? 1.0 : n * fact(n - 1); }
+constexpr double ipow(double x, int n) { return n == 0 ? 1.0 : x * ipow(x, n - 1); }
+constexpr float sin_c(int k) { return (float)((k % 2 ? -1.0 : 1.0) * ipow(kPi, 2 * k + 1) / fact(2 * k + 1)); }
+constexpr float cos_c(int k) { return (float)((k % 2 ? -1.0 : 1.0) * ipow(kPi, 2 * k) / fact(2 * k)); }
+}  // namespace taylor
+
+__device__ __forceinline__ float sinpi_small(float u, float w /* u*u */) {
+  constexpr float a0 = taylor::sin_c(0), a1 = taylor::sin_c(1), a2 = taylor::sin_c(2), a3 = taylor::sin_c(3);
+  constexpr float a4 = taylor::sin_c(4), a5 = taylor::sin_c(5), a6 = taylor::sin_c(6);
+  float p = fmaf(a6, w, a5);
+  p = fmaf(p, w, a4);
+  p = fmaf(p, w, a3);
+  p = fmaf(p, w, a2);
+  p = fmaf(p, w, a1);
+  p = fmaf(p, w, a0);
+  return p * u;
+}
+
+__device__ __forceinline__ float cospi_small(float w /* u*u */) {
+  constexpr float b0 = taylor::cos_c(0), b1 = taylor::cos_c(1), b2 = taylor::cos_c(2), b3 = taylor::cos_c(3);
+  constexpr float b4 = taylor::cos_c(4), b5 = taylor::cos_c(5), b6 = taylor::cos_c(6);
+  float p = fmaf(b6, w, b5);
+  p = fmaf(p, w, b4);
+  p = fmaf(p, w, b3);
+  p = fmaf(p, w, b2);
+  p = fmaf(p, w, b1);
+  return fmaf(p, w, b0);
+}
+
+// Radial factors of Eq. 12-15 for t = d / rc in [0, 1):
+//   x = 2 (t - 1)^2 - 1,  hf = f_c / 2 = (1 + cos(pi t)) / 4.
+// With cos(pi t) = -sin(pi (t - 1/2)) the argument stays in [-1/2, 1/2].
+struct RadialF {
+  float x, hf;
+};
+__device__ __forceinline__ RadialF radial_f(float t) {
+  const float y = t - 1.0f;
+  const float u = t - 0.5f;
+  RadialF r;
+  r.x = fmaf(2.0f * y, y, -1.0f);
+  r.hf = fmaf(-0.25f, sinpi_small(u, u * u), 0.25f);
+  return r;
+}
+
+// The same with the derivatives needed by the pair forces:
+//   dxhf = (dx/dd) hf = 4 (t - 1) / rc * hf,  dfc2 = (df_c/dd) / 2 = -pi sin(pi t) / (4 rc),
+// so that dQ_k/dd = dxhf T'_k(x) + dfc2 (T_k(x) + 1).
+struct RadialFD {
+  float x, hf, dxhf, dfc2;
+};
+__device__ __forceinline__ RadialFD radial_fd(float t, float rc_inv) {
+  const float y = t - 1.0f;
+  const float u = t - 0.5f;
+  const float w = u * u;
+  RadialFD r;
+  r.x = fmaf(2.0f * y, y, -1.0f);
+  r.hf = fmaf(-0.25f, sinpi_small(u, w), 0.25f);
+  r.dxhf = (4.0f * rc_inv) * y * r.hf;
+  r.dfc2 = (-0.25f * 3.14159265358979323846f) * rc_inv * cospi_small(w);
+  return r;
+}
+
+// Chebyshev polynomials T_0..T_{B-1} at x (three-term recurrence).
+template <int B>
+__device__ __forceinline__ void cheb_t(float x, float (&Tk)[B]) {
+  Tk[0] = 1.0f;
+  if (B > 1) Tk[1] = x;
+  const float x2 = 2.0f * x;
+#pragma unroll
+  for (int k = 2; k < B; ++k) Tk[k] = fmaf(x2, Tk[k - 1], -Tk[k - 2]);
+}
+
+// T_k and T'_k = dT_k/dx (T'_0 = 0, T'_1 = 1, T'_{k+1} = 2 T_k + 2x T'_k - T'_{k-1}).
+template <int B>
+__device__ __forceinline__ void cheb_tt(float x, float (&Tk)[B], float (&Dk)[B]) {
+  Tk[0] = 1.0f;
+  Dk[0] = 0.0f;
+  if (B > 1) {
+    Tk[1] = x;
+    Dk[1] = 1.0f;
+  }
+  const float x2 = 2.0f * x;
+#pragma unroll
+  for (int k = 2; k < B; ++k) {
+    Tk[k] = fmaf(x2, Tk[k - 1], -Tk[k - 2]);
+    Dk[k] = fmaf(2.0f, Tk[k - 1], fmaf(x2, Dk[k - 1], -Dk[k - 2]));
   }
 }
 
@@ -302,6 +426,115 @@ __device__ __forceinline__ void real_sph_dir(float x, float y, float z, float wx
         Dl[21] = k43 * (6.0f * x * y * z * wx + 3.0f * z * (x2 - y2) * wy + y * (3.0f * x2 - y2) * wz);
         Dl[22] = k44 * (4.0f * x * (x2 - 3.0f * y2) * wx + 4.0f * y * (y2 - 3.0f * x2) * wy);
         Dl[23] = k44s * (y * (3.0f * x2 - y2) * wx + x * (x2 - 3.0f * y2) * wy);
+      }
+    }
+  }
+}
+
+// Unnormalised harmonics: Y_lm(u) = kappa_lm Praw_lm(u), where Praw_lm is
+// the polynomial of real_sph without its constant (same order).  The kernels
+// accumulate sums of Praw and apply kappa once per atom.
+template <int L>
+struct Kappa {
+  static constexpr int K = L * L + 2 * L;
+  float v[K > 0 ? K : 1];
+  constexpr Kappa() : v() {
+    using namespace sh;
+    const float all[24] = {c1,  c1,  c1,  k20, k21,  k21, k22, k21, k30, k31, k31, k32,
+                           k32s, k33, k33, k40, k41, k41, k42, k42s, k43, k43, k44, k44s};
+    for (int i = 0; i < K; ++i) v[i] = all[i];
+  }
+};
+
+template <int L>
+__device__ __forceinline__ void raw_sph(float x, float y, float z, float (&P)[L * L + 2 * L]) {
+  P[0] = z;
+  P[1] = x;
+  P[2] = y;
+  if constexpr (L >= 2) {
+    const float z2 = z * z, xy = x * y;
+    const float dxy = (x - y) * (x + y);  // x^2 - y^2
+    P[3] = fmaf(3.0f, z2, -1.0f);
+    P[4] = x * z;
+    P[5] = y * z;
+    P[6] = dxy;
+    P[7] = xy;
+    if constexpr (L >= 3) {
+      const float p5 = fmaf(5.0f, z2, -1.0f);
+      const float x3 = x * (dxy - 2.0f * y * y);  // x (x^2 - 3 y^2)
+      const float y3 = y * (dxy + 2.0f * x * x);  // y (3 x^2 - y^2)
+      P[8] = z * (p5 - 2.0f);                     // z (5 z^2 - 3)
+      P[9] = x * p5;
+      P[10] = y * p5;
+      P[11] = z * dxy;
+      P[12] = xy * z;
+      P[13] = x3;
+      P[14] = y3;
+      if constexpr (L >= 4) {
+        const float q7 = fmaf(7.0f, z2, -3.0f);
+        const float r7 = q7 + 2.0f;  // 7 z^2 - 1
+        P[15] = fmaf(z2, fmaf(35.0f, z2, -30.0f), 3.0f);
+        P[16] = P[4] * q7;
+        P[17] = P[5] * q7;
+        P[18] = dxy * r7;
+        P[19] = xy * r7;
+        P[20] = z * x3;
+        P[21] = z * y3;
+        P[22] = fmaf(dxy, dxy, -4.0f * xy * xy);
+        P[23] = xy * dxy;
+      }
+    }
+  }
+}
+
+// v = sum_lm G_lm grad_u Praw_lm(u) (Praw extended off the unit sphere as
+// polynomials); the caller projects out the radial component.
+template <int L>
+__device__ __forceinline__ void raw_sph_grad_dot(float x, float y, float z, const float (&G)[L * L + 2 * L], float& gx,
+                                                 float& gy, float& gz) {
+  gx = G[1];
+  gy = G[2];
+  gz = G[0];
+  if constexpr (L >= 2) {
+    // 3z^2-1: (0,0,6z)  xz: (z,0,x)  yz: (0,z,y)  x^2-y^2: (2x,-2y,0)  xy: (y,x,0)
+    const float g6 = 2.0f * G[6];
+    gx = fmaf(z, G[4], fmaf(x, g6, fmaf(y, G[7], gx)));
+    gy = fmaf(z, G[5], fmaf(-y, g6, fmaf(x, G[7], gy)));
+    gz = fmaf(6.0f * z, G[3], fmaf(x, G[4], fmaf(y, G[5], gz)));
+    if constexpr (L >= 3) {
+      const float z2 = z * z, xy = x * y, xz = x * z, yz = y * z;
+      const float dxy = (x - y) * (x + y);
+      const float p5 = fmaf(5.0f, z2, -1.0f);
+      // z(5z^2-3): (0,0,15z^2-3)  x(5z^2-1): (p5,0,10xz)  y(5z^2-1): (0,p5,10yz)
+      // z(x^2-y^2): (2xz,-2yz,dxy)  xyz: (yz,xz,xy)
+      // x(x^2-3y^2): (3dxy,-6xy,0)  y(3x^2-y^2): (6xy,3dxy,0)
+      const float g11 = 2.0f * G[11];
+      const float a13 = 3.0f * G[13], a14 = 3.0f * G[14];
+      gx = fmaf(p5, G[9], fmaf(xz, g11, fmaf(yz, G[12], fmaf(dxy, a13, fmaf(2.0f * xy, a14, gx)))));
+      gy = fmaf(p5, G[10], fmaf(-yz, g11, fmaf(xz, G[12], fmaf(-2.0f * xy, a13, fmaf(dxy, a14, gy)))));
+      gz = fmaf(fmaf(15.0f, z2, -3.0f), G[8],
+                fmaf(10.0f * xz, G[9], fmaf(10.0f * yz, G[10], fmaf(dxy, G[11], fmaf(xy, G[12], gz)))));
+      if constexpr (L >= 4) {
+        const float q7 = fmaf(7.0f, z2, -3.0f), r7 = q7 + 2.0f;
+        const float x3 = x * (dxy - 2.0f * y * y), y3 = y * (dxy + 2.0f * x * x);
+        const float zq = z * q7;                       // 7z^3 - 3z
+        const float w21 = fmaf(21.0f, z2, -3.0f);      // 21 z^2 - 3
+        const float xyz = xy * z;
+        // 35z^4-30z^2+3: (0,0,z(140z^2-60))
+        // xz(7z^2-3): (zq,0,x w21)     yz(7z^2-3): (0,zq,y w21)
+        // dxy r7: (2x r7,-2y r7,14 z dxy)   xy r7: (y r7, x r7, 14 xyz)
+        // z x3: (3 z dxy, -6 xyz, x3)   z y3: (6 xyz, 3 z dxy, y3)
+        // dxy^2-4x^2y^2: (4 x3, -4 y3, 0)   xy dxy: (y3, x3, 0)
+        const float g18 = 2.0f * r7 * G[18];
+        const float zd3 = 3.0f * z * dxy, xyz6 = 6.0f * xyz;
+        const float g22 = 4.0f * G[22];
+        gx = fmaf(zq, G[16], fmaf(x, g18, fmaf(y * r7, G[19], fmaf(zd3, G[20], fmaf(xyz6, G[21],
+             fmaf(x3, g22, fmaf(y3, G[23], gx)))))));
+        gy = fmaf(zq, G[17], fmaf(-y, g18, fmaf(x * r7, G[19], fmaf(-xyz6, G[20], fmaf(zd3, G[21],
+             fmaf(-y3, g22, fmaf(x3, G[23], gy)))))));
+        gz = fmaf(z * fmaf(140.0f, z2, -60.0f), G[15],
+                  fmaf(x * w21, G[16], fmaf(y * w21, G[17], fmaf(14.0f * z * dxy, G[18], fmaf(14.0f * xyz, G[19],
+                  fmaf(x3, G[20], fmaf(y3, G[21], gz)))))));
       }
     }
   }

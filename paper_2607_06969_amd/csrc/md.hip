@@ -222,7 +222,7 @@ struct nepmi_md {
   MdConst mc{};
   int n_species = 0;
   DevBuf species_user, xd_user, x_user, v_user, xd, vel4, ref4, F4;
-  DevBuf fp, aR, Ei, frad, fA, Wi, Ki, Eproc;
+  DevBuf fp, aR, Ei, frad, fA, fT, Wi, Ki, Eproc;
   DevBuf epot, ekin, vir, counters;
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -232,15 +232,19 @@ struct nepmi_md {
   NepIO io() {
     NepIO o;
     o.n_slots = nbr.n_slots;
+    o.capR = nbr.capR;
+    o.capA = nbr.capA;
     o.pos4 = nbr.pos4.ptr<float4>();
     o.cfg_of = nbr.cfg_of.ptr<int>();
     o.orig = nbr.orig.ptr<int>();
     o.cfgs = nbr.cfgs.ptr<CfgDev>();
     o.nbrR = nbr.nbrR.ptr<uint32_t>();
     o.cntR = nbr.cntR.ptr<int>();
+    o.vrev = nbr.vrev.ptr<uint32_t>();
     o.cnR = nbr.cnbrR.ptr<uint32_t>();
     o.ccR = nbr.ccntR.ptr<int>();
     o.cnA = nbr.cnbrA.ptr<uint32_t>();
+    o.cpA = nbr.cposA.ptr<uint32_t>();
     o.ccA = nbr.ccntA.ptr<int>();
     o.flags = nbr.flags.ptr<int>();
     const float rcR = (float)m->hp.rc_radial, rcA = (float)m->hp.rc_angular;
@@ -256,6 +260,7 @@ struct nepmi_md {
     o.qout = nullptr;
     o.frad = frad.ptr<float4>();
     o.fA = fA.ptr<float4>();
+    o.fT = fT.ptr<float4>();
     o.Wi = Wi.ptr<float>();
     o.Fuser = nullptr;
     o.Fproc = F4.ptr<float4>();
@@ -395,7 +400,7 @@ int nepmi_md_create(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, cons
     set_error("angular neighbour list is not symmetric");
     return fail(NEPMI_INVALID_ARG);
   }
-  if ((rc = md->fA.ensure(16 * (size_t)ns * nb.capA))) return fail(rc);
+  if ((rc = md->fT.ensure(16 * (size_t)ns * nb.capR)) || (rc = md->fA.ensure(16 * (size_t)ns * nb.capA))) return fail(rc);
   fill_int(st, nb.flags.ptr<int>(), kFlagCount, 0, nullptr);
   // kernel variants timed on this state, then the forces of the initial state
   if ((rc = autotune_io(m, md->io(), st, 2))) return fail(rc);

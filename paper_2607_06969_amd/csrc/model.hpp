@@ -12,11 +12,13 @@ struct Ops {
   int (*desc)(hipStream_t, const NepIO&, const float*, bool, int);
   int (*force)(hipStream_t, const NepIO&, const float*, int);
   int (*gather)(hipStream_t, const NepIO&);
+  int (*derive)(hipStream_t, float*);
   int (*seeds)(hipStream_t, const TrainSeedArgs&);
   int (*backward)(hipStream_t, TrainIO, const Cutoffs&, const float*, const float*, const int*, double*, double*,
                   float*);
   int T, NR, NA, BR, BA, L, D, NANG, H, K;
   int64_t P;
+  int64_t P_alloc;  // P parameters + the derived coefficient table
 };
 
 const Ops* find_ops(const nepmi_hparams& hp);
@@ -35,7 +37,7 @@ struct nepmi_model {
   nepmi::DevBuf params;
   nepmi::NbrPipeline nbr;
   nepmi::Reducer red;
-  nepmi::DevBuf fp, aR, Ei, frad, fA, Wi, Eproc;
+  nepmi::DevBuf fp, aR, Ei, frad, fA, fT, Wi, Eproc;
   nepmi::TrainBufs tr;
   int device = 0;
   int vdesc = 0, vforce = 0;  // kernel variants in use (see nepmi_autotune)

@@ -241,10 +241,11 @@ __global__ __launch_bounds__(256) void k_build_lists(int64_t n_slots, int n_spec
                                                      const float4* __restrict__ pos4, const int* __restrict__ cfg_of,
                                                      const int* __restrict__ bin_of, const int* __restrict__ start,
                                                      const int* __restrict__ base, float rclR2, float rclA2, int capR,
-                                                     int capA, uint32_t* __restrict__ nbrR, int* __restrict__ cntR,
+                                                     int capA, int rowT, uint32_t* __restrict__ nbrR,
+                                                     uint32_t* __restrict__ nbrT, int* __restrict__ cntR,
                                                      int* __restrict__ flags, const int* __restrict__ gate) {
   if (gate && *gate == 0) return;
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t p = xcd_tile() * blockDim.x + threadIdx.x;
   if (p >= n_slots) return;
   const int c = cfg_of[p];
   if (c < 0) {
@@ -276,10 +277,13 @@ __global__ __launch_bounds__(256) void k_build_lists(int64_t n_slots, int n_spec
         if (q == (int)p && code == 13u) continue;
         const float4 xq = pos4[q];
         const float rx = (xq.x - xi.x) + sx, ry = (xq.y - xi.y) + sy, rz = (xq.z - xi.z) + sz;
-        const float d2 = rx * rx + ry * ry + rz * rz;
+        const float d2 = pair_d2(rx, ry, rz);
         if (d2 < rclR2) {
           const uint32_t e = (uint32_t)q | (code << kNbrShift);
-          if (kR < capR) nbrR[(int64_t)kR * n_slots + p] = e;
+          if (kR < capR) {
+            nbrR[(int64_t)kR * n_slots + p] = e;
+            nbrT[p * rowT + kR] = e;
+          }
           ++kR;
           if (d2 < rclA2) ++kA;
         }
@@ -292,6 +296,66 @@ __global__ __launch_bounds__(256) void k_build_lists(int64_t n_slots, int n_spec
   if (kR > capR || kA > capA) atomicOr(&flags[kFlagOverflow], 1);
   atomicMax(&flags[kFlagMaxR], kR);
   atomicMax(&flags[kFlagMaxA], kA);
+}
+
+// Reverse index: for every entry k of i's Verlet list whose pair is within
+// rc_angular + skin, the position of i in the list of the neighbour j (the
+// entry with i's slot and the opposite image code), else 0xFFFFFFFF.  The
+// pair-force buffer is indexed by these positions, so that each step's gather
+// reads without searching.  A pair found from one side only raises the
+// asymmetry flag.
+__global__ __launch_bounds__(256) void k_reverse(int64_t n_slots, const CfgDev* __restrict__ cfgs,
+                                                 const float4* __restrict__ pos4, const int* __restrict__ cfg_of,
+                                                 const uint32_t* __restrict__ nbrR, const uint32_t* __restrict__ nbrT,
+                                                 int rowT, const int* __restrict__ cntR, float rclA2,
+                                                 uint32_t* __restrict__ vrev, int* __restrict__ flags,
+                                                 const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  const int64_t p = xcd_tile() * blockDim.x + threadIdx.x;
+  if (p >= n_slots) return;
+  const int c = cfg_of[p];
+  if (c < 0) return;
+  float H[9];
+#pragma unroll
+  for (int x = 0; x < 9; ++x) H[x] = cfgs[c].H[x];
+  const float4 xi = pos4[p];
+  const int n = cntR[p];
+  bool missing = false;
+  for (int k = 0; k < n; ++k) {
+    const uint32_t e = nbrR[(int64_t)k * n_slots + p];
+    const int q = (int)(e & kNbrMask);
+    const uint32_t code = e >> kNbrShift;
+    float sx, sy, sz;
+    image_shift(H, code, sx, sy, sz);
+    const float4 xq = pos4[q];
+    const float rx = (xq.x - xi.x) + sx, ry = (xq.y - xi.y) + sy, rz = (xq.z - xi.z) + sz;
+    uint32_t res = 0xFFFFFFFFu;
+    if (pair_d2(rx, ry, rz) < rclA2) {
+      const uint32_t want = (uint32_t)p | ((26u - code) << kNbrShift);
+      // q's list, row-major: rows are padded to a multiple of 4 entries, so
+      // the 16-byte reads stay inside the row.  Up to 64 entries are read at
+      // once (one memory latency per search); entries at or past nq are ignored.
+      const int nq = cntR[q];
+      const uint4* row = reinterpret_cast<const uint4*>(nbrT + (int64_t)q * rowT);
+      for (int j0 = 0; j0 < nq && res == 0xFFFFFFFFu; j0 += 64) {
+        uint4 w[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t)
+          w[t] = j0 + 4 * t < nq ? row[(j0 >> 2) + t] : make_uint4(~0u, ~0u, ~0u, ~0u);
+#pragma unroll
+        for (int t = 15; t >= 0; --t) {
+          const int j = j0 + 4 * t;
+          if (w[t].w == want && j + 3 < nq) res = (uint32_t)(j + 3);
+          if (w[t].z == want && j + 2 < nq) res = (uint32_t)(j + 2);
+          if (w[t].y == want && j + 1 < nq) res = (uint32_t)(j + 1);
+          if (w[t].x == want && j < nq) res = (uint32_t)j;
+        }
+      }
+      missing |= res == 0xFFFFFFFFu;
+    }
+    vrev[(int64_t)k * n_slots + p] = res;
+  }
+  if (missing) atomicOr(&flags[kFlagAsym], 1);
 }
 
 // ---------------------------------------------------------------- host side
@@ -456,11 +520,20 @@ int NbrPipeline::setup(int n_cfg_, const int64_t* atom_off, const double* cells,
 }
 
 int NbrPipeline::ensure_lists(int capR_, int capA_) {
+  if (capR_ > kMaxListRows) {
+    // list positions are stored in 16 bits (reverse index, pair buffer rows)
+    set_error("more than " + std::to_string(kMaxListRows) + " neighbours within rc_radial + skin");
+    return NEPMI_NEIGHBOR_OVERFLOW;
+  }
   capR = capR_;
   capA = capA_;
   int rc;
-  if ((rc = nbrR.ensure(4 * (size_t)capR * (size_t)n_slots)) || (rc = cnbrR.ensure(4 * (size_t)capR * (size_t)n_slots)) ||
-      (rc = cnbrA.ensure(4 * (size_t)capA * (size_t)n_slots)))
+  const size_t ns = (size_t)n_slots;
+  rowT = (capR + 3) / 4 * 4;
+  if ((rc = nbrR.ensure(4 * (size_t)capR * ns)) || (rc = nbrT.ensure(4 * (size_t)rowT * ns)) ||
+      (rc = vrev.ensure(4 * (size_t)capR * ns)) ||
+      (rc = cnbrR.ensure(4 * (size_t)capR * ns)) || (rc = cnbrA.ensure(4 * (size_t)capA * ns)) ||
+      (rc = cposA.ensure(4 * (size_t)capA * ns)))
     return rc;
   return NEPMI_OK;
 }
@@ -487,7 +560,13 @@ int NbrPipeline::build(hipStream_t st, const float* pos, const int32_t* species)
     if ((rc = launch_lists(st, n_species, nullptr))) return rc;
     int hf[kFlagCount];
     if ((rc = check_flags(st, hf))) return rc;
-    if (!hf[kFlagOverflow]) return NEPMI_OK;
+    if (!hf[kFlagOverflow]) {
+      if (hf[kFlagAsym]) {
+        set_error("neighbour list is not symmetric");
+        return NEPMI_INVALID_ARG;
+      }
+      return NEPMI_OK;
+    }
     // grow to the largest list seen plus a margin and rebuild the lists
     if ((rc = ensure_lists(hf[kFlagMaxR] + 8, hf[kFlagMaxA] + 8))) return rc;
     fill_int(st, flags.ptr<int>(), kFlagCount, 0, nullptr);
@@ -531,8 +610,11 @@ int NbrPipeline::launch_sort(hipStream_t st, const float* pos, int pos_stride, c
 int NbrPipeline::launch_lists(hipStream_t st, int n_species, const int* gate) {
   hipLaunchKernelGGL(k_build_lists, dim3(nblk(n_slots, 256)), dim3(256), 0, st, n_slots, n_species, total_bins,
                      cfgs.ptr<CfgDev>(), pos4.ptr<float4>(), cfg_of.ptr<int>(), bin_of.ptr<int>(), start.ptr<int>(),
-                     base.ptr<int>(), rclR2, rclA2, capR, capA, nbrR.ptr<uint32_t>(), cntR.ptr<int>(),
-                     flags.ptr<int>(), gate);
+                     base.ptr<int>(), rclR2, rclA2, capR, capA, rowT, nbrR.ptr<uint32_t>(), nbrT.ptr<uint32_t>(),
+                     cntR.ptr<int>(), flags.ptr<int>(), gate);
+  hipLaunchKernelGGL(k_reverse, dim3(nblk(n_slots, 256)), dim3(256), 0, st, n_slots, cfgs.ptr<CfgDev>(),
+                     pos4.ptr<float4>(), cfg_of.ptr<int>(), nbrR.ptr<uint32_t>(), nbrT.ptr<uint32_t>(), rowT,
+                     cntR.ptr<int>(), rclA2, vrev.ptr<uint32_t>(), flags.ptr<int>(), gate);
   NEPMI_HIP(hipGetLastError());
   return NEPMI_OK;
 }

@@ -19,6 +19,9 @@ enum {
   kFlagCount = 16
 };
 
+// Largest Verlet list length: positions are kept in 16 bits.
+constexpr int kMaxListRows = 65535;
+
 // Device allocation that grows on demand (contents are not preserved).
 struct DevBuf {
   void* p = nullptr;
@@ -52,7 +55,10 @@ struct NbrPipeline {
   DevBuf key, cnt, start, cursor, tile_sums, base, perm, pos_tmp, cfg_tmp;
   DevBuf pos4, cfg_of, orig, bin_of, slot_of;
   DevBuf nbrR, cntR;             // Verlet list (rc_radial + skin)
-  DevBuf cnbrR, ccntR, cnbrA, ccntA;  // per-evaluation compact lists (rc_radial, rc_angular)
+  DevBuf nbrT;                   // the same list row-major, rows of rowT entries (reverse search)
+  int rowT = 0;
+  DevBuf vrev;                   // reverse index of the Verlet list (see k_reverse)
+  DevBuf cnbrR, ccntR, cnbrA, ccntA, cposA;  // per-evaluation compact lists (rc_radial, rc_angular)
   DevBuf flags;
 
   // Host-side setup of a batch: validates the cells, computes bins, sizes

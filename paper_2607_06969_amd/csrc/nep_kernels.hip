@@ -13,19 +13,69 @@ struct PairVec {
   int q, zj;
 };
 
-__device__ __forceinline__ PairVec pair_vec(const float4* __restrict__ pos4, uint32_t e, float4 xi, const float (&H)[9]) {
+__device__ __forceinline__ PairVec pair_vec(uint32_t e, float4 xq, float4 xi, const float (&H)[9]) {
   PairVec v;
   v.q = (int)(e & kNbrMask);
-  const float4 xq = pos4[v.q];
   float sx, sy, sz;
   image_shift(H, e >> kNbrShift, sx, sy, sz);
   v.rx = (xq.x - xi.x) + sx;
   v.ry = (xq.y - xi.y) + sy;
   v.rz = (xq.z - xi.z) + sz;
-  v.d2 = v.rx * v.rx + v.ry * v.ry + v.rz * v.rz;
+  v.d2 = pair_d2(v.rx, v.ry, v.rz);
   v.zj = __float_as_int(xq.w);
   return v;
 }
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// Network dimensions padded to the 4-wide groups of the matrix instructions.
+template <class S>
+struct MlpPad {
+  static constexpr int HP = (S::H + 3) / 4 * 4;
+  static constexpr int DP = (S::D + 3) / 4 * 4;
+};
+
+// tanh(x) = 1 - 2 / (1 + e^{2x}) with the hardware exp2 and reciprocal
+// (absolute error a few 1e-7; saturates to +-1 for large |x|).
+__device__ __forceinline__ float tanh_fast(float x) {
+  const float e = __builtin_amdgcn_exp2f(x * 2.8853900817779268f);  // 2 log2(e)
+  return fmaf(-2.0f, __builtin_amdgcn_rcpf(1.0f + e), 1.0f);
+}
+
+// Software-pipelined walk over one atom's column of a pair list.  A pair
+// needs two dependent loads (the list entry, then the neighbour's position);
+// the walker keeps the entry two pairs ahead and the position one pair ahead
+// in flight while the current pair is processed.  Usage, in iteration k:
+//   prefetch(k, ...) first, then use (e, x), then advance(...).
+struct PairWalk {
+  const uint32_t* __restrict__ list;
+  int64_t ns, p;
+  int n;
+  uint32_t e, e1;  // entries of pairs k and k + 1
+  float4 x;        // position (and species) of the neighbour of pair k
+  // Inside the loop the loads are unconditional, with the row clamped to the
+  // last valid one (n >= 1 there), so no branch splits the wavefront.
+  __device__ __forceinline__ PairWalk(const uint32_t* __restrict__ l, int64_t ns_, int64_t p_, int n_,
+                                      const float4* __restrict__ pos4)
+      : list(l), ns(ns_), p(p_), n(n_) {
+    e = 0u;
+    x = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (n > 0) {
+      e = list[p];
+      x = pos4[e & kNbrMask];
+    }
+    e1 = n > 1 ? list[ns + p] : e;
+  }
+  __device__ __forceinline__ void prefetch(int k, const float4* __restrict__ pos4, uint32_t& e2, float4& x1) const {
+    e2 = list[(int64_t)(k + 2 < n ? k + 2 : n - 1) * ns + p];
+    x1 = pos4[e1 & kNbrMask];
+  }
+  __device__ __forceinline__ void advance(uint32_t e2, float4 x1) {
+    e = e1;
+    e1 = e2;
+    x = x1;
+  }
+};
 
 __device__ __forceinline__ void load_cell(const CfgDev* __restrict__ cfgs, int c, float (&H)[9]) {
   if (c >= 0) {
@@ -68,80 +118,178 @@ __device__ __forceinline__ float tr_cube(const float (&A)[6]) {
   return B[0] * A[0] + B[1] * A[1] + B[2] * A[2] + 2.0f * (B[3] * A[3] + B[4] * A[4] + B[5] * A[5]);
 }
 
+// S_nlm (l = 1..L) of one group of NH angular functions, summed over the
+// angular pairs of the atom (Eq. 16): S = sum_j g_n(r_ij) Y_lm(u_ij) with
+// g_n = sum_k c[Z_i][Z_j][n][k] Q_k = hf sum_k ctil_nk T_k (derived table).
+template <class S, int NH>
+__device__ __forceinline__ void angular_sums(const float4* __restrict__ pos4, const uint32_t* __restrict__ cnA,
+                                             int64_t n_slots, int64_t p, int nA, float4 xi, const float (&Hc)[9],
+                                             const float* cl0, float rcA_inv, float (&Sg)[NH][S::K]) {
+  constexpr int T = S::T, NA = S::NA, BA = S::BA, L = S::L, K = S::K;
+#pragma unroll
+  for (int nn = 0; nn < NH; ++nn)
+#pragma unroll
+    for (int lm = 0; lm < K; ++lm) Sg[nn][lm] = 0.f;
+  PairWalk w(cnA, n_slots, p, nA, pos4);
+  for (int k = 0; k < nA; ++k) {
+    uint32_t e2;
+    float4 x1;
+    w.prefetch(k, pos4, e2, x1);
+    const PairVec v = pair_vec(w.e, w.x, xi, Hc);
+    w.advance(e2, x1);
+    const float inv = rsqrt_hw(v.d2);
+    const RadialF f = radial_f(v.d2 * inv * rcA_inv);
+    float Tk[BA];
+    cheb_t<BA>(f.x, Tk);
+    const float* cl = cl0 + v.zj * (NA * BA);
+    float g[NH];
+#pragma unroll
+    for (int nn = 0; nn < NH; ++nn) {
+      float acc = 0.f;
+#pragma unroll
+      for (int kk = 0; kk < BA; ++kk) acc = fmaf(cl[nn * BA + kk], Tk[kk], acc);
+      g[nn] = f.hf * acc;
+    }
+    float P[K];
+    raw_sph<L>(v.rx * inv, v.ry * inv, v.rz * inv, P);
+#pragma unroll
+    for (int nn = 0; nn < NH; ++nn)
+#pragma unroll
+      for (int lm = 0; lm < K; ++lm) Sg[nn][lm] = fmaf(g[nn], P[lm], Sg[nn][lm]);
+  }
+  constexpr Kappa<L> kap;
+#pragma unroll
+  for (int nn = 0; nn < NH; ++nn)
+#pragma unroll
+    for (int lm = 0; lm < K; ++lm) Sg[nn][lm] *= kap.v[lm];
+  (void)T;
+}
+
 // ------------------------------------------------------------------ k_desc
 
 template <class S, int NSPLIT, int WPE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) void k_desc(
-    int64_t n_slots, const float4* __restrict__ pos4, const int* __restrict__ cfg_of, const int* __restrict__ orig,
-    const CfgDev* __restrict__ cfgs, const uint32_t* __restrict__ nbrR, const int* __restrict__ cntR,
-    uint32_t* __restrict__ cnR, int* __restrict__ ccR, uint32_t* __restrict__ cnA, int* __restrict__ ccA,
-    Cutoffs cut, const float* __restrict__ params, float* __restrict__ fp, float* __restrict__ aR,
-    float* __restrict__ Ei, float* __restrict__ qout, float* __restrict__ Eproc, int want_adjoint) {
+    int64_t n_slots, int capA, const float4* __restrict__ pos4, const int* __restrict__ cfg_of,
+    const int* __restrict__ orig, const CfgDev* __restrict__ cfgs, const uint32_t* __restrict__ nbrR,
+    const int* __restrict__ cntR, const uint32_t* __restrict__ vrev, uint32_t* __restrict__ cnR, int* __restrict__ ccR,
+    uint32_t* __restrict__ cnA, uint32_t* __restrict__ cpA, int* __restrict__ ccA, int* __restrict__ flags, Cutoffs cut,
+    const float* __restrict__ params, float* __restrict__ fp, float* __restrict__ aR, float* __restrict__ Ei,
+    float* __restrict__ qout, float* __restrict__ Eproc, int want_adjoint) {
   constexpr int T = S::T, NR = S::NR, NA = S::NA, BR = S::BR, BA = S::BA, L = S::L, K = S::K, D = S::D, H = S::H;
   constexpr int NH = NA / NSPLIT;
   static_assert(NA % NSPLIT == 0, "NSPLIT must divide n_angular");
+  constexpr int HP = MlpPad<S>::HP, DP = MlpPad<S>::DP;
+  const float* __restrict__ dco = params + S::P;  // derived coefficients: radial, then angular
   __shared__ float cA_s[T * T * NA * BA];
-  for (int t = threadIdx.x; t < T * T * NA * BA; t += kBlock) cA_s[t] = params[S::PCR + t];
+  __shared__ float W0s[T * HP * DP];   // [Z][h][d] network weights, zero padded
+  __shared__ float W0Ts[T * DP * HP];  // [Z][d][h] the same, transposed
+
+  // Every lane of a wavefront takes part in the matrix instructions of the
+  // network, so lanes past the last slot stay alive as inactive atoms.
+  const int64_t p = xcd_tile() * kBlock + threadIdx.x;
+  const bool in_range = p < n_slots;
+  const int64_t pc = in_range ? p : n_slots - 1;
+  const float4 xi = pos4[pc];
+  const int Zs = __builtin_amdgcn_readfirstlane(__float_as_int(xi.w));
+  {
+    // weights of the species of this block's wavefronts (each is uniform)
+    const int64_t b0 = p - threadIdx.x;
+    unsigned need = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / kWave; ++w) {
+      const int64_t s0 = b0 + w * kWave;
+      need |= 1u << __float_as_int(pos4[s0 < n_slots ? s0 : n_slots - 1].w);
+    }
+    for (int t = threadIdx.x; t < T * T * NA * BA; t += kBlock) cA_s[t] = dco[S::PCR + t];
+    for (int z = 0; z < T; ++z) {
+      if (!(need >> z & 1u)) continue;
+      const float* W0g = params + S::PCR + S::PCA + (int64_t)z * S::PMLP;
+      for (int t = threadIdx.x; t < HP * DP; t += kBlock) {
+        const int h = t / DP, d = t % DP;
+        const float w = (h < H && d < D) ? W0g[h * D + d] : 0.0f;
+        W0s[(z * HP + h) * DP + d] = w;
+        W0Ts[(z * DP + d) * HP + h] = w;
+      }
+    }
+  }
   __syncthreads();
 
-  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (p >= n_slots) return;
-  const float4 xi = pos4[p];
-  const int Zs = __builtin_amdgcn_readfirstlane(__float_as_int(xi.w));
-  const int c = cfg_of[p];
+  const int c = in_range ? cfg_of[p] : -1;
   const bool active = c >= 0;
   float Hc[9];
   load_cell(cfgs, c, Hc);
   const float rcR_inv = 1.0f / cut.rcR, rcA_inv = 1.0f / cut.rcA;
 
-  // ---- filter the Verlet list into the pairs inside the two cutoffs
+  // ---- filter the Verlet list into the pairs inside the two cutoffs, and
+  //      accumulate PT_b[k] = sum over radial neighbours j of species b of
+  //      hf_j T_k(x_j) on the way (Eq. 11-15)
+  float PT[T][BR];
+#pragma unroll
+  for (int b = 0; b < T; ++b)
+#pragma unroll
+    for (int k = 0; k < BR; ++k) PT[b][k] = 0.f;
   int nR = 0, nA = 0;
   if (active) {
     const int n = cntR[p];
+    bool bad = false;
+    PairWalk w(nbrR, n_slots, p, n, pos4);
+    uint32_t rv = n > 0 ? vrev[p] : 0u;
     for (int k = 0; k < n; ++k) {
-      const uint32_t e = nbrR[(int64_t)k * n_slots + p];
-      const PairVec v = pair_vec(pos4, e, xi, Hc);
+      uint32_t e2;
+      float4 x1;
+      w.prefetch(k, pos4, e2, x1);
+      const uint32_t rv1 = vrev[(int64_t)(k + 1 < n ? k + 1 : n - 1) * n_slots + p];
+      const uint32_t e = w.e;
+      const PairVec v = pair_vec(e, w.x, xi, Hc);
+      w.advance(e2, x1);
+      const uint32_t rvk = rv;
+      rv = rv1;
       if (v.d2 < cut.rcR2) {
         cnR[(int64_t)nR * n_slots + p] = e;
         ++nR;
         if (v.d2 < cut.rcA2) {
-          cnA[(int64_t)nA * n_slots + p] = e;
-          ++nA;
+          // within rc_angular now implies within rc_angular + skin at the
+          // last build, so nA stays below capA and the reverse row exists
+          if (rvk <= 0xFFFFu && nA < capA) {
+            cnA[(int64_t)nA * n_slots + p] = e;
+            cpA[(int64_t)nA * n_slots + p] = (uint32_t)k | (rvk << 16);
+            ++nA;
+          } else {
+            bad = true;
+          }
+        }
+        const float inv = rsqrt_hw(v.d2);
+        const RadialF f = radial_f(v.d2 * inv * rcR_inv);
+        float Tk[BR];
+        cheb_t<BR>(f.x, Tk);
+#pragma unroll
+        for (int b = 0; b < T; ++b) {
+          const float m = (T == 1 || v.zj == b) ? f.hf : 0.0f;
+#pragma unroll
+          for (int kk = 0; kk < BR; ++kk) PT[b][kk] = fmaf(m, Tk[kk], PT[b][kk]);
         }
       }
     }
+    if (bad) atomicOr(&flags[kFlagAsym], 1);
   }
-  ccR[p] = nR;
-  ccA[p] = nA;
+  if (in_range) {
+    ccR[p] = nR;
+    ccA[p] = nA;
+  }
 
-  float q[D];
-  // ---- radial descriptors, Eq. 11: q_n = sum_b sum_k c^R[Z_i][b][n][k] P_b[k],
-  //      P_b[k] = sum over neighbours j of species b of Q_k(r_ij)
+  float q[DP];
+#pragma unroll
+  for (int d = D; d < DP; ++d) q[d] = 0.f;
+  // ---- radial descriptors, Eq. 11: q_n = sum_b sum_k ctil[Z_i][b][n][k] PT_b[k]
   {
-    float P[T][BR];
-#pragma unroll
-    for (int b = 0; b < T; ++b)
-#pragma unroll
-      for (int k = 0; k < BR; ++k) P[b][k] = 0.f;
-    for (int k = 0; k < nR; ++k) {
-      const PairVec v = pair_vec(pos4, cnR[(int64_t)k * n_slots + p], xi, Hc);
-      float Q[BR];
-      cheb_basis<BR>(sqrtf(v.d2), rcR_inv, Q);
-#pragma unroll
-      for (int b = 0; b < T; ++b) {
-        const float m = (T == 1 || v.zj == b) ? 1.0f : 0.0f;
-#pragma unroll
-        for (int kk = 0; kk < BR; ++kk) P[b][kk] = fmaf(m, Q[kk], P[b][kk]);
-      }
-    }
-    const float* cR = params + (int64_t)Zs * (T * NR * BR);
+    const float* cR = dco + (int64_t)Zs * (T * NR * BR);
 #pragma unroll
     for (int nn = 0; nn < NR; ++nn) {
       float acc = 0.f;
 #pragma unroll
       for (int b = 0; b < T; ++b)
 #pragma unroll
-        for (int kk = 0; kk < BR; ++kk) acc = fmaf(cR[(b * NR + nn) * BR + kk], P[b][kk], acc);
+        for (int kk = 0; kk < BR; ++kk) acc = fmaf(cR[(b * NR + nn) * BR + kk], PT[b][kk], acc);
       q[nn] = acc;
     }
   }
@@ -150,34 +298,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
 #pragma unroll
   for (int h = 0; h < NSPLIT; ++h) {
     float Sg[NH][K];
-#pragma unroll
-    for (int nn = 0; nn < NH; ++nn)
-#pragma unroll
-      for (int lm = 0; lm < K; ++lm) Sg[nn][lm] = 0.f;
-    for (int k = 0; k < nA; ++k) {
-      const PairVec v = pair_vec(pos4, cnA[(int64_t)k * n_slots + p], xi, Hc);
-      {
-        const float d = sqrtf(v.d2);
-        const float inv = 1.0f / d;
-        float Q[BA];
-        cheb_basis<BA>(d, rcA_inv, Q);
-        const float* cl = cA_s + ((Zs * T + v.zj) * NA + h * NH) * BA;
-        float g[NH];
-#pragma unroll
-        for (int nn = 0; nn < NH; ++nn) {
-          float acc = 0.f;
-#pragma unroll
-          for (int kk = 0; kk < BA; ++kk) acc = fmaf(cl[nn * BA + kk], Q[kk], acc);
-          g[nn] = acc;
-        }
-        float Y[K];
-        real_sph<L>(v.rx * inv, v.ry * inv, v.rz * inv, Y);
-#pragma unroll
-        for (int nn = 0; nn < NH; ++nn)
-#pragma unroll
-          for (int lm = 0; lm < K; ++lm) Sg[nn][lm] = fmaf(g[nn], Y[lm], Sg[nn][lm]);
-      }
-    }
+    angular_sums<S, NH>(pos4, cnA, n_slots, p, nA, xi, Hc, cA_s + (Zs * T * NA + h * NH) * BA, rcA_inv, Sg);
     // invariants of this group
 #pragma unroll
     for (int nn = 0; nn < NH; ++nn) {
@@ -198,36 +319,88 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
     }
   }
 
-  // ---- network of Sec. 2.3 (weights of species Z_i through the scalar unit)
-  const float* W0 = params + S::PCR + S::PCA + (int64_t)Zs * S::PMLP;
-  const float* b0 = W0 + H * D;
-  const float* w1 = b0 + H;
-  float E = w1[H];
-  float Fp[D];
+  // ---- network of Sec. 2.3 on the matrix cores.  With the 16-block 4x4x1
+  //      fp32 MFMA, block b (lanes 4b..4b+3) forms C[i][j] += A[i] B[j] with
+  //      A[i] from lane 4b+i and B[j] from lane 4b+j, and lane 4b+j keeps
+  //      column j.  Every lane supplies its own atom's value as B and a weight
+  //      row selected by lane % 4 as A, so each lane accumulates four entries
+  //      of its own atom: no data moves between lanes.
+  const int lq = threadIdx.x & 3;
+  const float* b0g = params + S::PCR + S::PCA + (int64_t)Zs * S::PMLP + H * D;
+  const float* w1g = b0g + H;
+  //  forward: a_h = b0_h + sum_d W0[h][d] q_d, four hidden units per group
+  floatx4 acc[HP / 4];
 #pragma unroll
-  for (int d = 0; d < D; ++d) Fp[d] = 0.f;
-  for (int hh = 0; hh < H; ++hh) {
-    float a = b0[hh];
+  for (int hg = 0; hg < HP / 4; ++hg)
 #pragma unroll
-    for (int d = 0; d < D; ++d) a = fmaf(W0[hh * D + d], q[d], a);
-    const float t = tanhf(a);
-    E = fmaf(w1[hh], t, E);
-    const float z = w1[hh] * (1.0f - t * t);
+    for (int r = 0; r < 4; ++r) acc[hg][r] = (4 * hg + r < H) ? b0g[4 * hg + r] : 0.f;
+  {
+    const float* Wz = W0s + (Zs * HP + lq) * DP;
 #pragma unroll
-    for (int d = 0; d < D; ++d) Fp[d] = fmaf(z, W0[hh * D + d], Fp[d]);
+    for (int dg = 0; dg < DP / 4; ++dg) {
+#pragma unroll
+      for (int hg = 0; hg < HP / 4; ++hg) {
+        const float4 w = *reinterpret_cast<const float4*>(Wz + 4 * hg * DP + 4 * dg);
+        acc[hg] = __builtin_amdgcn_mfma_f32_4x4x1f32(w.x, q[4 * dg + 0], acc[hg], 0, 0, 0);
+        acc[hg] = __builtin_amdgcn_mfma_f32_4x4x1f32(w.y, q[4 * dg + 1], acc[hg], 0, 0, 0);
+        acc[hg] = __builtin_amdgcn_mfma_f32_4x4x1f32(w.z, q[4 * dg + 2], acc[hg], 0, 0, 0);
+        acc[hg] = __builtin_amdgcn_mfma_f32_4x4x1f32(w.w, q[4 * dg + 3], acc[hg], 0, 0, 0);
+      }
+    }
   }
+  if (active && qout) {
+    const int i = orig[p];
+#pragma unroll
+    for (int d = 0; d < D; ++d) qout[(int64_t)i * D + d] = q[d];
+  }
+  //  E = b1 + sum_h w1_h tanh(a_h);  z_h = dE/da_h = w1_h (1 - tanh^2)
+  float E = w1g[H];
+  float zt[HP];
+#pragma unroll
+  for (int hg = 0; hg < HP / 4; ++hg)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int h = 4 * hg + r;
+      if (h < H) {
+        const float t = tanh_fast(acc[hg][r]);
+        E = fmaf(w1g[h], t, E);
+        zt[h] = w1g[h] * fmaf(-t, t, 1.0f);
+      } else {
+        zt[h] = 0.f;
+      }
+    }
+  //  backward: dE/dq_d = sum_h z_h W0[h][d], four descriptors per group
+  floatx4 fpa[DP / 4];
+#pragma unroll
+  for (int dg = 0; dg < DP / 4; ++dg) fpa[dg] = floatx4{0.f, 0.f, 0.f, 0.f};
+  {
+    const float* WzT = W0Ts + (Zs * DP + lq) * HP;
+#pragma unroll
+    for (int hg = 0; hg < HP / 4; ++hg) {
+#pragma unroll
+      for (int dg = 0; dg < DP / 4; ++dg) {
+        const float4 w = *reinterpret_cast<const float4*>(WzT + 4 * dg * HP + 4 * hg);
+        fpa[dg] = __builtin_amdgcn_mfma_f32_4x4x1f32(w.x, zt[4 * hg + 0], fpa[dg], 0, 0, 0);
+        fpa[dg] = __builtin_amdgcn_mfma_f32_4x4x1f32(w.y, zt[4 * hg + 1], fpa[dg], 0, 0, 0);
+        fpa[dg] = __builtin_amdgcn_mfma_f32_4x4x1f32(w.z, zt[4 * hg + 2], fpa[dg], 0, 0, 0);
+        fpa[dg] = __builtin_amdgcn_mfma_f32_4x4x1f32(w.w, zt[4 * hg + 3], fpa[dg], 0, 0, 0);
+      }
+    }
+  }
+  float Fp[DP];
+#pragma unroll
+  for (int dg = 0; dg < DP / 4; ++dg)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Fp[4 * dg + r] = fpa[dg][r];
   if (!active) return;
   const int i = orig[p];
   Ei[i] = E;
   if (Eproc) Eproc[p] = E;
-  if (qout) {
-#pragma unroll
-    for (int d = 0; d < D; ++d) qout[(int64_t)i * D + d] = q[d];
-  }
   if (!want_adjoint) return;
 #pragma unroll
   for (int d = NR; d < D; ++d) fp[(int64_t)(d - NR) * n_slots + p] = Fp[d];
-  const float* cR = params + (int64_t)Zs * (T * NR * BR);
+  // radial adjoint atil[b][k] = sum_n dE/dq_n ctil[Z_i][b][n][k]
+  const float* cR = dco + (int64_t)Zs * (T * NR * BR);
 #pragma unroll
   for (int b = 0; b < T; ++b)
 #pragma unroll
@@ -241,20 +414,32 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
 
 // ----------------------------------------------------------------- k_force
 
+// Row stride (floats) of the per-thread radial adjoint rows in LDS: a multiple
+// of 4 with an odd quotient, so that 128-bit reads of consecutive lanes fall
+// on distinct banks.
+template <int W>
+constexpr int lds_row() {
+  return ((W + 3) / 4) % 2 ? ((W + 3) / 4) * 4 : ((W + 3) / 4 + 1) * 4;
+}
+
 template <class S, int NSPLIT, int WPE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) void k_force(
-    int64_t n_slots, const float4* __restrict__ pos4, const int* __restrict__ cfg_of, const int* __restrict__ orig,
-    const CfgDev* __restrict__ cfgs, const uint32_t* __restrict__ cnR, const int* __restrict__ ccR,
-    const uint32_t* __restrict__ cnA, const int* __restrict__ ccA, Cutoffs cut, const float* __restrict__ params,
-    const float* __restrict__ fp, const float* __restrict__ aR, float4* __restrict__ frad, float4* __restrict__ fA,
+    int64_t n_slots, int capR, const float4* __restrict__ pos4, const int* __restrict__ cfg_of,
+    const int* __restrict__ orig, const CfgDev* __restrict__ cfgs, const uint32_t* __restrict__ cnR,
+    const int* __restrict__ ccR, const uint32_t* __restrict__ cnA, const uint32_t* __restrict__ cpA,
+    const int* __restrict__ ccA, Cutoffs cut, const float* __restrict__ params, const float* __restrict__ fp,
+    const float* __restrict__ aR, float4* __restrict__ frad, float4* __restrict__ fA, float4* __restrict__ fT,
     float* __restrict__ Wi) {
   constexpr int T = S::T, NR = S::NR, NA = S::NA, BR = S::BR, BA = S::BA, L = S::L, K = S::K;
   constexpr int NH = NA / NSPLIT;
+  constexpr int RW = lds_row<T * BR>();
+  const float* __restrict__ dco = params + S::P;
   __shared__ float cA_s[T * T * NA * BA];
-  for (int t = threadIdx.x; t < T * T * NA * BA; t += kBlock) cA_s[t] = params[S::PCR + t];
+  __shared__ float aown_s[T > 1 ? kBlock * RW : 1];
+  for (int t = threadIdx.x; t < T * T * NA * BA; t += kBlock) cA_s[t] = dco[S::PCR + t];
   __syncthreads();
 
-  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t p = xcd_tile() * kBlock + threadIdx.x;
   if (p >= n_slots) return;
   const float4 xi = pos4[p];
   const int Zs = __builtin_amdgcn_readfirstlane(__float_as_int(xi.w));
@@ -265,85 +450,86 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
   const float rcR_inv = 1.0f / cut.rcR, rcA_inv = 1.0f / cut.rcA;
 
   float Fx = 0.f, Fy = 0.f, Fz = 0.f;
-  float W[9];
+  // radial virial is symmetric (f_ij parallel to r_ij): xx, yy, zz, xy, xz, yz
+  float Wr[6];
 #pragma unroll
-  for (int x = 0; x < 9; ++x) W[x] = 0.f;
+  for (int x = 0; x < 6; ++x) Wr[x] = 0.f;
 
-  // ---- radial pairs: f_ij - f_ji = (s_own + s_rev) u_ij
+  // ---- radial pairs: f_ij - f_ji = (s_own + s_rev) u_ij with
+  //      s = dE/dd = dxhf sum_k atil_k T'_k + dfc2 sum_k atil_k T_k
   {
-    float a_own[T][BR];
+    const float* arow = aR + p * (T * BR);
+    float a1[T == 1 ? BR : 1];
+    float* mine = aown_s + (T > 1 ? threadIdx.x * RW : 0);
+    if constexpr (T == 1) {
 #pragma unroll
-    for (int b = 0; b < T; ++b)
+      for (int kk = 0; kk < BR; ++kk) a1[kk] = arow[kk];
+    } else {
 #pragma unroll
-      for (int kk = 0; kk < BR; ++kk) a_own[b][kk] = aR[p * (T * BR) + b * BR + kk];
+      for (int kk = 0; kk < T * BR; ++kk) mine[kk] = arow[kk];
+    }
     const int n = ccR[p];
+    PairWalk w(cnR, n_slots, p, n, pos4);
     for (int k = 0; k < n; ++k) {
-      const PairVec v = pair_vec(pos4, cnR[(int64_t)k * n_slots + p], xi, Hc);
-      {
-        const float d = sqrtf(v.d2);
-        const float inv = 1.0f / d;
-        float Q[BR], dQ[BR];
-        cheb_basis_d<BR>(d, rcR_inv, Q, dQ);
-        float s_own = 0.f;
+      uint32_t e2;
+      float4 x1;
+      w.prefetch(k, pos4, e2, x1);
+      const PairVec v = pair_vec(w.e, w.x, xi, Hc);
+      // the neighbour's adjoint row atil_j[Z_i]
+      const float* ar = aR + (int64_t)v.q * (T * BR) + Zs * BR;
+      w.advance(e2, x1);
+      const float inv = rsqrt_hw(v.d2);
+      const RadialFD f = radial_fd(v.d2 * inv * rcR_inv, rcR_inv);
+      float Tk[BR], Dk[BR];
+      cheb_tt<BR>(f.x, Tk, Dk);
+      float ao[BR];
+      if constexpr (T == 1) {
 #pragma unroll
-        for (int b = 0; b < T; ++b) {
-          float sb = 0.f;
+        for (int kk = 0; kk < BR; ++kk) ao[kk] = a1[kk];
+      } else {
+        const float* src = mine + v.zj * BR;
 #pragma unroll
-          for (int kk = 0; kk < BR; ++kk) sb = fmaf(a_own[b][kk], dQ[kk], sb);
-          s_own = (T == 1 || v.zj == b) ? sb : s_own;
-        }
-        const float* ar = aR + (int64_t)v.q * (T * BR) + Zs * BR;
-        float s_rev = 0.f;
-#pragma unroll
-        for (int kk = 0; kk < BR; ++kk) s_rev = fmaf(ar[kk], dQ[kk], s_rev);
-        const float ux = v.rx * inv, uy = v.ry * inv, uz = v.rz * inv;
-        const float st = s_own + s_rev;
-        Fx = fmaf(st, ux, Fx);
-        Fy = fmaf(st, uy, Fy);
-        Fz = fmaf(st, uz, Fz);
-        const float fx = s_own * ux, fy = s_own * uy, fz = s_own * uz;
-        W[0] -= fx * v.rx; W[1] -= fx * v.ry; W[2] -= fx * v.rz;
-        W[3] -= fy * v.rx; W[4] -= fy * v.ry; W[5] -= fy * v.rz;
-        W[6] -= fz * v.rx; W[7] -= fz * v.ry; W[8] -= fz * v.rz;
+        for (int kk = 0; kk < BR; ++kk) ao[kk] = src[kk];
       }
+      float to = ao[0], dn = 0.f, tr = ar[0], dr = 0.f;
+#pragma unroll
+      for (int kk = 1; kk < BR; ++kk) {
+        to = fmaf(ao[kk], Tk[kk], to);
+        dn = fmaf(ao[kk], Dk[kk], dn);
+        tr = fmaf(ar[kk], Tk[kk], tr);
+        dr = fmaf(ar[kk], Dk[kk], dr);
+      }
+      const float s_own = fmaf(f.dxhf, dn, f.dfc2 * to);
+      const float s_rev = fmaf(f.dxhf, dr, f.dfc2 * tr);
+      const float st = (s_own + s_rev) * inv;
+      Fx = fmaf(st, v.rx, Fx);
+      Fy = fmaf(st, v.ry, Fy);
+      Fz = fmaf(st, v.rz, Fz);
+      const float so = s_own * inv;
+      const float ax = so * v.rx, ay = so * v.ry, az = so * v.rz;
+      Wr[0] = fmaf(-ax, v.rx, Wr[0]);
+      Wr[1] = fmaf(-ay, v.ry, Wr[1]);
+      Wr[2] = fmaf(-az, v.rz, Wr[2]);
+      Wr[3] = fmaf(-ax, v.ry, Wr[3]);
+      Wr[4] = fmaf(-ax, v.rz, Wr[4]);
+      Wr[5] = fmaf(-ay, v.rz, Wr[5]);
     }
   }
 
   // ---- angular pairs, in NSPLIT groups of n
+  float W[9];
+#pragma unroll
+  for (int x = 0; x < 9; ++x) W[x] = 0.f;
   const int nA = ccA[p];
+  constexpr Kappa<L> kap;
 #pragma unroll
   for (int h = 0; h < NSPLIT; ++h) {
+    const float* cl0 = cA_s + (Zs * T * NA + h * NH) * BA;
     // recompute S for this group
     float Sg[NH][K];
-#pragma unroll
-    for (int nn = 0; nn < NH; ++nn)
-#pragma unroll
-      for (int lm = 0; lm < K; ++lm) Sg[nn][lm] = 0.f;
-    for (int k = 0; k < nA; ++k) {
-      const PairVec v = pair_vec(pos4, cnA[(int64_t)k * n_slots + p], xi, Hc);
-      {
-        const float d = sqrtf(v.d2);
-        const float inv = 1.0f / d;
-        float Q[BA];
-        cheb_basis<BA>(d, rcA_inv, Q);
-        const float* cl = cA_s + ((Zs * T + v.zj) * NA + h * NH) * BA;
-        float g[NH];
-#pragma unroll
-        for (int nn = 0; nn < NH; ++nn) {
-          float acc = 0.f;
-#pragma unroll
-          for (int kk = 0; kk < BA; ++kk) acc = fmaf(cl[nn * BA + kk], Q[kk], acc);
-          g[nn] = acc;
-        }
-        float Y[K];
-        real_sph<L>(v.rx * inv, v.ry * inv, v.rz * inv, Y);
-#pragma unroll
-        for (int nn = 0; nn < NH; ++nn)
-#pragma unroll
-          for (int lm = 0; lm < K; ++lm) Sg[nn][lm] = fmaf(g[nn], Y[lm], Sg[nn][lm]);
-      }
-    }
-    // sigma = dE_i/dS for this group (in place)
+    angular_sums<S, NH>(pos4, cnA, n_slots, p, nA, xi, Hc, cl0, rcA_inv, Sg);
+    // sigma = dE_i/dS for this group (in place), then scaled by kappa so that
+    // the pair loop works with the unnormalised polynomials
 #pragma unroll
     for (int nn = 0; nn < NH; ++nn) {
       const int n = h * NH + nn;
@@ -377,75 +563,110 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
 #pragma unroll
         for (int m = 0; m < 5; ++m) Sg[nn][3 + m] += s4[m];
       }
+#pragma unroll
+      for (int lm = 0; lm < K; ++lm) Sg[nn][lm] *= kap.v[lm];
     }
     // pair forces of this group: f = u sum_n g'_n Z_n + (I - u u^T) v / d,
-    // Z_n = sum_lm sigma_nlm Y_lm, v = sum_lm G_lm grad P_lm, G_lm = sum_n sigma_nlm g_n
+    // Z_n = sum_lm sigma_nlm P_lm, v = sum_lm G_lm grad P_lm, G_lm = sum_n sigma_nlm g_n
+    PairWalk w(cnA, n_slots, p, nA, pos4);
+    uint32_t pk = nA > 0 ? cpA[p] : 0u;
     for (int k = 0; k < nA; ++k) {
-      const PairVec v = pair_vec(pos4, cnA[(int64_t)k * n_slots + p], xi, Hc);
-      float fx = 0.f, fy = 0.f, fz = 0.f;
-      {
-        const float d = sqrtf(v.d2);
-        const float inv = 1.0f / d;
-        const float ux = v.rx * inv, uy = v.ry * inv, uz = v.rz * inv;
-        float Y[K];
-        real_sph<L>(ux, uy, uz, Y);
-        float Q[BA], dQ[BA];
-        cheb_basis_d<BA>(d, rcA_inv, Q, dQ);
-        const float* cl = cA_s + ((Zs * T + v.zj) * NA + h * NH) * BA;
-        float G[K];
+      uint32_t e2;
+      float4 x1;
+      w.prefetch(k, pos4, e2, x1);
+      const uint32_t pk1 = cpA[(int64_t)(k + 1 < nA ? k + 1 : nA - 1) * n_slots + p];
+      const PairVec v = pair_vec(w.e, w.x, xi, Hc);
+      w.advance(e2, x1);
+      const uint32_t pkk = pk;
+      pk = pk1;
+      const float inv = rsqrt_hw(v.d2);
+      const float ux = v.rx * inv, uy = v.ry * inv, uz = v.rz * inv;
+      const RadialFD f = radial_fd(v.d2 * inv * rcA_inv, rcA_inv);
+      float P[K];
+      raw_sph<L>(ux, uy, uz, P);
+      float Tk[BA], Dk[BA];
+      cheb_tt<BA>(f.x, Tk, Dk);
+      const float* cl = cl0 + v.zj * (NA * BA);
+      float G[K];
 #pragma unroll
-        for (int lm = 0; lm < K; ++lm) G[lm] = 0.f;
-        float s = 0.f;
+      for (int lm = 0; lm < K; ++lm) G[lm] = 0.f;
+      float s = 0.f;
 #pragma unroll
-        for (int nn = 0; nn < NH; ++nn) {
-          float g = 0.f, gp = 0.f;
+      for (int nn = 0; nn < NH; ++nn) {
+        float ct = cl[nn * BA], cd = 0.f;
 #pragma unroll
-          for (int kk = 0; kk < BA; ++kk) {
-            const float cc = cl[nn * BA + kk];
-            g = fmaf(cc, Q[kk], g);
-            gp = fmaf(cc, dQ[kk], gp);
-          }
-          float zn = 0.f;
-#pragma unroll
-          for (int lm = 0; lm < K; ++lm) {
-            zn = fmaf(Sg[nn][lm], Y[lm], zn);
-            G[lm] = fmaf(Sg[nn][lm], g, G[lm]);
-          }
-          s = fmaf(gp, zn, s);
+        for (int kk = 1; kk < BA; ++kk) {
+          const float cc = cl[nn * BA + kk];
+          ct = fmaf(cc, Tk[kk], ct);
+          cd = fmaf(cc, Dk[kk], cd);
         }
-        float vx, vy, vz;
-        real_sph_grad_dot<L>(ux, uy, uz, G, vx, vy, vz);
-        const float uv = ux * vx + uy * vy + uz * vz;
-        fx = s * ux + (vx - uv * ux) * inv;
-        fy = s * uy + (vy - uv * uy) * inv;
-        fz = s * uz + (vz - uv * uz) * inv;
-        W[0] -= fx * v.rx; W[1] -= fx * v.ry; W[2] -= fx * v.rz;
-        W[3] -= fy * v.rx; W[4] -= fy * v.ry; W[5] -= fy * v.rz;
-        W[6] -= fz * v.rx; W[7] -= fz * v.ry; W[8] -= fz * v.rz;
+        const float g = f.hf * ct;
+        const float gp = fmaf(f.dxhf, cd, f.dfc2 * ct);
+        float zn = 0.f;
+#pragma unroll
+        for (int lm = 0; lm < K; ++lm) {
+          zn = fmaf(Sg[nn][lm], P[lm], zn);
+          G[lm] = fmaf(Sg[nn][lm], g, G[lm]);
+        }
+        s = fmaf(gp, zn, s);
       }
-      float4* dst = fA + (int64_t)k * n_slots + p;
-      if (h == 0) {
-        *dst = make_float4(fx, fy, fz, 0.f);
+      float vx, vy, vz;
+      raw_sph_grad_dot<L>(ux, uy, uz, G, vx, vy, vz);
+      const float uv = fmaf(ux, vx, fmaf(uy, vy, uz * vz));
+      const float fx = fmaf(s, ux, (vx - uv * ux) * inv);
+      const float fy = fmaf(s, uy, (vy - uv * uy) * inv);
+      const float fz = fmaf(s, uz, (vz - uv * uz) * inv);
+      Fx += fx;
+      Fy += fy;
+      Fz += fz;
+      W[0] = fmaf(-fx, v.rx, W[0]); W[1] = fmaf(-fx, v.ry, W[1]); W[2] = fmaf(-fx, v.rz, W[2]);
+      W[3] = fmaf(-fy, v.rx, W[3]); W[4] = fmaf(-fy, v.ry, W[4]); W[5] = fmaf(-fy, v.rz, W[5]);
+      W[6] = fmaf(-fz, v.rx, W[6]); W[7] = fmaf(-fz, v.ry, W[7]); W[8] = fmaf(-fz, v.rz, W[8]);
+      // partial pair forces of the groups collect in i's own (coalesced)
+      // slot; the total goes to the row of j's list that holds i, for j's gather
+      float4* own = fA + (int64_t)k * n_slots + p;
+      if (h + 1 < NSPLIT) {
+        if (h == 0) {
+          *own = make_float4(fx, fy, fz, 0.f);
+        } else {
+          const float4 o = *own;
+          *own = make_float4(o.x + fx, o.y + fy, o.z + fz, 0.f);
+        }
       } else {
-        const float4 o = *dst;
-        *dst = make_float4(o.x + fx, o.y + fy, o.z + fz, 0.f);
+        float4 tot = make_float4(fx, fy, fz, 0.f);
+        if (NSPLIT > 1) {
+          const float4 o = *own;
+          tot = make_float4(o.x + fx, o.y + fy, o.z + fz, 0.f);
+        }
+        const int rev = (int)(pkk >> 16);
+        if (rev < capR) fT[(int64_t)rev * n_slots + v.q] = tot;
       }
     }
   }
   frad[p] = make_float4(Fx, Fy, Fz, 0.f);
   const int i = orig[p];
-#pragma unroll
-  for (int x = 0; x < 9; ++x) Wi[(int64_t)i * 9 + x] = W[x];
+  float* w = Wi + (int64_t)i * 9;
+  w[0] = W[0] + Wr[0];
+  w[1] = W[1] + Wr[3];
+  w[2] = W[2] + Wr[4];
+  w[3] = W[3] + Wr[3];
+  w[4] = W[4] + Wr[1];
+  w[5] = W[5] + Wr[5];
+  w[6] = W[6] + Wr[4];
+  w[7] = W[7] + Wr[5];
+  w[8] = W[8] + Wr[2];
 }
 
 // ---------------------------------------------------------------- k_gather
 
+// F_i = (radial part + sum_j f_ij) - sum_j f_ji: the own part was summed by
+// k_force; f_ji sits in row (position of j in i's Verlet list) of the pair
+// buffer, written there by j.
 __global__ __launch_bounds__(kBlock) void k_gather(int64_t n_slots, const int* __restrict__ orig,
-                                                   const uint32_t* __restrict__ cnA, const int* __restrict__ ccA,
-                                                   const float4* __restrict__ frad, const float4* __restrict__ fA,
-                                                   float* __restrict__ Fuser, float4* __restrict__ Fproc,
-                                                   int* __restrict__ flags) {
-  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+                                                   const uint32_t* __restrict__ cpA, const int* __restrict__ ccA,
+                                                   const float4* __restrict__ frad, const float4* __restrict__ fT,
+                                                   float* __restrict__ Fuser, float4* __restrict__ Fproc) {
+  const int64_t p = xcd_tile() * kBlock + threadIdx.x;
   if (p >= n_slots) return;
   const int i = orig[p];
   if (i < 0) {
@@ -455,22 +676,11 @@ __global__ __launch_bounds__(kBlock) void k_gather(int64_t n_slots, const int* _
   float4 F = frad[p];
   const int n = ccA[p];
   for (int k = 0; k < n; ++k) {
-    const uint32_t e = cnA[(int64_t)k * n_slots + p];
-    const int q = (int)(e & kNbrMask);
-    // the pair seen from q: slot p with the opposite image shift
-    const uint32_t want = (uint32_t)p | ((26u - (e >> kNbrShift)) << kNbrShift);
-    const int nq = ccA[q];
-    int j = 0;
-    while (j < nq && cnA[(int64_t)j * n_slots + q] != want) ++j;
-    const float4 a = fA[(int64_t)k * n_slots + p];
-    if (j < nq) {
-      const float4 b = fA[(int64_t)j * n_slots + q];
-      F.x += a.x - b.x;
-      F.y += a.y - b.y;
-      F.z += a.z - b.z;
-    } else {
-      atomicOr(&flags[kFlagAsym], 1);
-    }
+    const uint32_t own = cpA[(int64_t)k * n_slots + p] & 0xFFFFu;
+    const float4 b = fT[(int64_t)own * n_slots + p];
+    F.x -= b.x;
+    F.y -= b.y;
+    F.z -= b.z;
   }
   if (Fuser) {
     Fuser[(int64_t)i * 3 + 0] = F.x;
@@ -478,6 +688,23 @@ __global__ __launch_bounds__(kBlock) void k_gather(int64_t n_slots, const int* _
     Fuser[(int64_t)i * 3 + 2] = F.z;
   }
   if (Fproc) Fproc[p] = F;
+}
+
+// Derived coefficient table: ctil[..][n][0] = c[..][n][0] + sum_k c[..][n][k],
+// ctil[..][n][k] = c[..][n][k] for k >= 1, for every radial row (length BR)
+// and angular row (length BA).  With Q_k = hf (T_k + 1) this gives
+// sum_k c_nk Q_k = hf sum_k ctil_nk T_k.
+template <class S>
+__global__ void k_derive(const float* __restrict__ params, float* __restrict__ out) {
+  constexpr int rowsR = S::T * S::T * S::NR, rowsA = S::T * S::T * S::NA;
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rowsR + rowsA) return;
+  const int B = r < rowsR ? S::BR : S::BA;
+  const int64_t o = r < rowsR ? (int64_t)r * S::BR : S::PCR + (int64_t)(r - rowsR) * S::BA;
+  double sum = 0.0;
+  for (int k = 0; k < B; ++k) sum += (double)params[o + k];
+  out[o] = (float)((double)params[o] + sum);
+  for (int k = 1; k < B; ++k) out[o + k] = params[o + k];
 }
 
 // ------------------------------------------------------------- launchers
@@ -494,9 +721,9 @@ constexpr int groups() {
 template <class S, int NS, int W>
 static int launch_desc(hipStream_t st, const NepIO& io, const float* params, bool want_adjoint) {
   const unsigned g = (unsigned)((io.n_slots + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL((k_desc<S, groups<S, NS>(), W>), dim3(g), dim3(kBlock), 0, st, io.n_slots, io.pos4, io.cfg_of,
-                     io.orig, io.cfgs, io.nbrR, io.cntR, io.cnR, io.ccR, io.cnA, io.ccA, io.cut, params, io.fp, io.aR,
-                     io.Ei, io.qout, io.Eproc, want_adjoint ? 1 : 0);
+  hipLaunchKernelGGL((k_desc<S, groups<S, NS>(), W>), dim3(g), dim3(kBlock), 0, st, io.n_slots, io.capA, io.pos4,
+                     io.cfg_of, io.orig, io.cfgs, io.nbrR, io.cntR, io.vrev, io.cnR, io.ccR, io.cnA, io.cpA, io.ccA, io.flags,
+                     io.cut, params, io.fp, io.aR, io.Ei, io.qout, io.Eproc, want_adjoint ? 1 : 0);
   NEPMI_HIP(hipGetLastError());
   return NEPMI_OK;
 }
@@ -504,9 +731,9 @@ static int launch_desc(hipStream_t st, const NepIO& io, const float* params, boo
 template <class S, int NS, int W>
 static int launch_force(hipStream_t st, const NepIO& io, const float* params) {
   const unsigned g = (unsigned)((io.n_slots + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL((k_force<S, groups<S, NS>(), W>), dim3(g), dim3(kBlock), 0, st, io.n_slots, io.pos4, io.cfg_of,
-                     io.orig, io.cfgs, io.cnR, io.ccR, io.cnA, io.ccA, io.cut, params, io.fp, io.aR, io.frad, io.fA,
-                     io.Wi);
+  hipLaunchKernelGGL((k_force<S, groups<S, NS>(), W>), dim3(g), dim3(kBlock), 0, st, io.n_slots, io.capR, io.pos4,
+                     io.cfg_of, io.orig, io.cfgs, io.cnR, io.ccR, io.cnA, io.cpA, io.ccA, io.cut, params, io.fp, io.aR,
+                     io.frad, io.fA, io.fT, io.Wi);
   NEPMI_HIP(hipGetLastError());
   return NEPMI_OK;
 }
@@ -516,7 +743,7 @@ int Launch<S>::desc(hipStream_t st, const NepIO& io, const float* params, bool w
   switch (variant) {
     case 1: return launch_desc<S, 4, 3>(st, io, params, want_adjoint);
     case 2: return launch_desc<S, 4, 2>(st, io, params, want_adjoint);
-    case 3: return launch_desc<S, 8, 3>(st, io, params, want_adjoint);
+    case 3: return launch_desc<S, 1, 1>(st, io, params, want_adjoint);
     default: return launch_desc<S, 2, 2>(st, io, params, want_adjoint);
   }
 }
@@ -526,7 +753,7 @@ int Launch<S>::force(hipStream_t st, const NepIO& io, const float* params, int v
   switch (variant) {
     case 1: return launch_force<S, 4, 2>(st, io, params);
     case 2: return launch_force<S, 4, 3>(st, io, params);
-    case 3: return launch_force<S, 8, 3>(st, io, params);
+    case 3: return launch_force<S, 1, 1>(st, io, params);
     default: return launch_force<S, 2, 2>(st, io, params);
   }
 }
@@ -534,8 +761,16 @@ int Launch<S>::force(hipStream_t st, const NepIO& io, const float* params, int v
 template <class S>
 int Launch<S>::gather(hipStream_t st, const NepIO& io) {
   const unsigned g = (unsigned)((io.n_slots + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_gather, dim3(g), dim3(kBlock), 0, st, io.n_slots, io.orig, io.cnA, io.ccA, io.frad, io.fA,
-                     io.Fuser, io.Fproc, io.flags);
+  hipLaunchKernelGGL(k_gather, dim3(g), dim3(kBlock), 0, st, io.n_slots, io.orig, io.cpA, io.ccA, io.frad, io.fT,
+                     io.Fuser, io.Fproc);
+  NEPMI_HIP(hipGetLastError());
+  return NEPMI_OK;
+}
+
+template <class S>
+int Launch<S>::derive(hipStream_t st, float* params) {
+  constexpr int rows = S::T * S::T * (S::NR + S::NA);
+  hipLaunchKernelGGL(k_derive<S>, dim3((rows + 127) / 128), dim3(128), 0, st, params, params + S::P);
   NEPMI_HIP(hipGetLastError());
   return NEPMI_OK;
 }

@@ -3,20 +3,25 @@
 // One thread evaluates one atom slot; every wavefront holds one species (see
 // nbr.hip), so species-pair coefficients c[Z_i][.] and the network weights of
 // Z_i are read through the scalar unit.  Coefficients that depend on the
-// neighbour's species are read from LDS.
+// neighbour's species are read from LDS.  The kernels use a derived copy of
+// the Chebyshev coefficients stored after the parameters (k_derive), in which
+// the "+1" of Q_k = (T_k + 1) f_c / 2 is folded into column 0.
 //
 //   k_desc   filters the Verlet list into compact lists of the pairs inside
-//            the radial and angular cutoffs, then computes the
-//            descriptors (Eq. 11, 16, 17 and the 4-/5-body invariants), the
-//            network (Sec. 2.3), site energy E_i, and the adjoints the force
-//            kernel needs: dE_i/dq for the angular descriptors, and
-//            a_i[b][k] = sum_n dE_i/dq_n c^R[Z_i][b][n][k] for the radial ones.
+//            the radial and angular cutoffs (accumulating the radial sums on
+//            the way), then computes the descriptors (Eq. 11, 16, 17 and the
+//            4-/5-body invariants), the network (Sec. 2.3), site energy E_i,
+//            and the adjoints the force kernel needs: dE_i/dq for the angular
+//            descriptors, and atil_i[b][k] = sum_n dE_i/dq_n ctil[Z_i][b][n][k]
+//            for the radial ones.
 //   k_force  pair forces dE_i/dr_ij and the per-atom virial (Eq. 3, Eq. 4).
-//            Radial pairs gather the neighbour's a_j[Z_i] and add both
-//            directions at once; angular pairs write dE_i/dr_ij to a pair
-//            buffer (no atomics), and S_i is recomputed rather than stored.
-//   k_gather F_i = radial part + sum_j (f_ij - f_ji) over the angular pair
-//            buffer; f_ji is found in j's compact list (Eq. 3).
+//            Radial pairs gather the neighbour's atil_j[Z_i] and add both
+//            directions at once; for angular pairs, dE_i/dr_ij is added to
+//            i's own force and written (no atomics) to the row of the pair
+//            buffer that j's gather reads: the row of i in j's Verlet list,
+//            known from the reverse index built with the lists.  S_i is
+//            recomputed rather than stored.
+//   k_gather F_i = own part - sum_j dE_j/dr_ji over i's angular pairs (Eq. 3).
 #pragma once
 
 #include "common.hpp"
@@ -25,15 +30,19 @@ namespace nepmi {
 
 struct NepIO {
   int64_t n_slots;
+  int capR;              // rows of the Verlet list and of the pair buffer
+  int capA;              // rows of the compact angular list
   const float4* pos4;
   const int* cfg_of;
   const int* orig;
   const CfgDev* cfgs;
   const uint32_t* nbrR;  // Verlet list (rc_radial + skin)
   const int* cntR;
+  const uint32_t* vrev;  // [capR][n_slots] row of i in j's Verlet list (pairs within rc_angular + skin)
   uint32_t* cnR;         // compact list: pairs within rc_radial (written by k_desc)
   int* ccR;
   uint32_t* cnA;         // compact list: pairs within rc_angular (written by k_desc)
+  uint32_t* cpA;         // [capA][n_slots] own Verlet row | reverse Verlet row << 16
   int* ccA;
   int* flags;
   Cutoffs cut;
@@ -41,8 +50,9 @@ struct NepIO {
   float* aR;     // [n_slots][T*BR]  radial adjoint
   float* Ei;     // [N] caller order (site energies)
   float* qout;   // [N][D] caller order, optional
-  float4* frad;  // [n_slots] radial force part
-  float4* fA;    // [capA][n_slots] angular pair forces dE_i/dr_ij
+  float4* frad;  // [n_slots] own force part (radial pairs both ways, angular dE_i/dr_ij)
+  float4* fA;    // [capA][n_slots] partial angular pair forces (own slots, between groups)
+  float4* fT;    // [capR][n_slots] angular pair forces dE_j/dr_ji, row = position of j in i's Verlet list
   float* Wi;     // [N][9] caller order, per-atom virial
   float* Fuser;  // [N][3] caller order, optional
   float4* Fproc; // [n_slots], optional
@@ -56,6 +66,9 @@ struct Launch {
   static int desc(hipStream_t st, const NepIO& io, const float* params, bool want_adjoint, int variant);
   static int force(hipStream_t st, const NepIO& io, const float* params, int variant);
   static int gather(hipStream_t st, const NepIO& io);
+  // Writes the derived coefficient table after the P parameters (the
+  // parameter buffer holds P + PCR + PCA floats).
+  static int derive(hipStream_t st, float* params);
 };
 
 }  // namespace nepmi

@@ -86,7 +86,7 @@ __device__ __forceinline__ PV pvec(const float4* __restrict__ pos4, uint32_t e, 
   v.rx = (xq.x - xi.x) + sx;
   v.ry = (xq.y - xi.y) + sy;
   v.rz = (xq.z - xi.z) + sz;
-  v.d2 = v.rx * v.rx + v.ry * v.ry + v.rz * v.rz;
+  v.d2 = pair_d2(v.rx, v.ry, v.rz);
   v.zj = __float_as_int(xq.w);
   return v;
 }
