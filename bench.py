@@ -69,10 +69,35 @@ def algorithmic_flops(hp, pairs_r: float, pairs_a: float):
 
 
 def gather_bytes(pairs_a_list: float):
-    """HBM bytes per atom of the force-gather kernel: radial part (16 B), own
-    and reverse angular pair forces (2 x 16 B per listed pair), reverse index
-    (4 B per pair), count/orig (8 B), output float4 (16 B)."""
-    return 16 + pairs_a_list * (32 + 4) + 8 + 16
+    """HBM bytes per atom of the force-gather kernel: own part (16 B), per
+    angular pair the neighbour's pair force (16 B) and the row pair (4 B),
+    count/orig (8 B), output float4 (16 B)."""
+    return 16 + pairs_a_list * (16 + 4) + 8 + 16
+
+
+TRAFFIC_PROFILE = os.path.join(HERE, "profiles", "k_force_md900k_hbm_traffic.md")
+KERNEL_SOURCES = ("common.hpp", "nep_kernels.hpp", "nep_kernels.hip")
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary, or None if there is none for this kernel or the kernel
+    sources changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    rec = {}
+    for line in text.splitlines():
+        k, sep, v = line.strip().partition(": ")
+        if sep and k in ("traffic_kernel", "traffic_bytes_per_launch", "source_sha256"):
+            rec[k] = v.strip()
+    csrc = os.path.join(HERE, "paper_2607_06969_amd", "csrc")
+    h = hashlib.sha256(b"".join(open(os.path.join(csrc, n), "rb").read() for n in KERNEL_SOURCES)).hexdigest()
+    if rec.get("traffic_kernel") != kernel or rec.get("source_sha256") != h:
+        return None
+    return float(rec["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(hp, params, system, budget_s=20.0):
@@ -226,8 +251,17 @@ def main():
     torch.cuda.synchronize()
     print(f"[bench] warmup {a.warmup} steps done", file=sys.stderr, flush=True)
     st0 = md.stats()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    md.step(a.steps)
+    # the timed steps; HIP events inside the step graph time each hot kernel
+    # of every one of these steps
+    from paper_2607_06969_amd._lib import NepmiError
+    try:
+        kt_live = md.step_timed(a.steps)
+    except NepmiError as e:
+        print(f"[bench] timed replay unavailable ({e}); plain replay", file=sys.stderr, flush=True)
+        md.step(a.steps)
+        kt_live = None
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     st1 = md.stats()
@@ -239,8 +273,15 @@ def main():
     print(f"[bench] timed {a.steps} steps in {dt:.3f} s; rebuilds {st1['rebuilds'] - st0['rebuilds']}",
           file=sys.stderr, flush=True)
 
-    # per-kernel durations (HIP events on this stream, standalone launches on the final state)
-    kt = md.time_kernels(a.kernel_reps)
+    # a neighbour-list rebuild is timed separately (standalone launches on the final state)
+    standalone = md.time_kernels(a.kernel_reps)
+    if kt_live is not None:
+        kt = dict(kt_live)
+        timing_source = f"HIP events inside the step graph, averaged over the {a.steps} timed steps"
+    else:
+        kt = {k: standalone[k] for k in ("desc", "force", "gather")}
+        timing_source = f"HIP events around {a.kernel_reps} standalone launches after the timed steps"
+    kt["lists"] = standalone["lists"]
     flop_desc, flop_force = algorithmic_flops(hp, pairs_r, pairs_a)
     n = system.n_atoms
     kernels = {"desc": (kt["desc"], flop_desc * n), "force": (kt["force"], flop_force * n)}
@@ -249,9 +290,10 @@ def main():
     achieved = flops / (ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": f"k_{dom}", "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / FP32_VALU_PEAK_TFLOPS,
-                "frac_of_packed_fp32_peak": achieved / FP32_PACKED_PEAK_TFLOPS, "traffic": None,
+                "frac_of_packed_fp32_peak": achieved / FP32_PACKED_PEAK_TFLOPS,
+                "traffic": measured_traffic(f"k_{dom}"), "traffic_unit": "bytes per launch",
                 "algorithmic_flop_per_atom": {"desc": flop_desc, "force": flop_force},
-                "kernel_ms": {k: round(v_, 4) for k, v_ in kt.items()}}
+                "kernel_ms": {k: round(v_, 4) for k, v_ in kt.items()}, "kernel_timing": timing_source}
     gb = gather_bytes(pairs_a) * n / (kt["gather"] * 1e-3) / 1e9
     roofline["gather_hbm"] = {"achieved_GBs": gb, "frac": gb / HBM_PEAK_GBS}
 

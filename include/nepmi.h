@@ -129,7 +129,7 @@ int nepmi_neighbors(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, cons
  * nepmi_autotune times every variant on the given batch and keeps the
  * fastest in the model; chosen = host int32[2] (descriptor, force) or NULL.
  * Synchronises `stream`.  nepmi_set_variants pins a choice (0..3 each);
- * nepmi_md_create autotunes on its initial state. */
+ * nepmi_md_create autotunes on its initial state unless a choice is pinned. */
 int nepmi_autotune(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, const double *cells,
                    const float *dev_pos, const int32_t *dev_species, int32_t *chosen, void *stream);
 int nepmi_set_variants(nepmi_model *m, int32_t desc_variant, int32_t force_variant);
@@ -189,6 +189,15 @@ int nepmi_md_get(nepmi_md *md, float *dev_pos, float *dev_vel, float *dev_forces
 int nepmi_md_stats(nepmi_md *md, int64_t *steps, int64_t *rebuilds);
 
 void nepmi_md_destroy(nepmi_md *md);
+
+/* Advance n_steps (>= 1) like nepmi_md_step and time the hot kernels of
+ * exactly these steps: the step graph records HIP events before k_desc,
+ * k_force and k_gather and after k_gather, each step into its own events.
+ * ms_per_launch: host double[3] = average duration (ms) of descriptors +
+ * network, pair forces + virial, force gather over the n_steps replays.
+ * Synchronises `stream` once at the end.  Errors as nepmi_md_step, and
+ * NEPMI_UNSUPPORTED if the graph could not be built with timing nodes. */
+int nepmi_md_step_timed(nepmi_md *md, int32_t n_steps, double *ms_per_launch, void *stream);
 
 /* Average duration of each hot kernel, measured with HIP events recorded on
  * `stream` around `reps` standalone launches of the force evaluation on the

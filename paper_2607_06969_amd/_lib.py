@@ -60,6 +60,7 @@ SIGNATURES = [
     ("nepmi_loss_grad", C.c_int, [_vp, _i32, _i64p, _dp, _vp, _vp, _vp, _vp, _vp, _dp, _i32, _vp, _vp, _vp]),
     ("nepmi_md_create", C.c_int, [_vp, _i32, _i64p, _dp, _vp, _vp, _vp, _dp, _d, _d, C.POINTER(_vp), _vp]),
     ("nepmi_md_step", C.c_int, [_vp, _i32, _vp]),
+    ("nepmi_md_step_timed", C.c_int, [_vp, _i32, _dp, _vp]),
     ("nepmi_md_get", C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     ("nepmi_md_stats", C.c_int, [_vp, _i64p, _i64p]),
     ("nepmi_md_destroy", None, [_vp]),

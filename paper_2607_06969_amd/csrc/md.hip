@@ -9,6 +9,7 @@
 // the rebuild kernels do work.
 #include <cmath>
 #include <new>
+#include <vector>
 
 #include "model.hpp"
 
@@ -228,6 +229,12 @@ struct nepmi_md {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int64_t host_steps = 0;
+  // timing: events recorded before k_desc, k_force, k_gather and after
+  // k_gather in every replay; their graph nodes; a pool of per-step events
+  hipEvent_t tev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipGraphNode_t tnode[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool timing = false, mark_failed = false;
+  std::vector<hipEvent_t> tpool;
 
   NepIO io() {
     NepIO o;
@@ -268,12 +275,40 @@ struct nepmi_md {
     return o;
   }
 
-  int forces(hipStream_t st) {
+  // mark: while the step is being captured, put an event-record node for
+  // tev[0..3] before k_desc, k_force, k_gather and after k_gather.  The nodes
+  // are added to the capture by hand (current dependencies -> node -> new
+  // dependency).  Best effort: if the runtime refuses, the step is captured
+  // without them and timed replays are unavailable.
+  void mark(int i, hipStream_t st) {
+    if (mark_failed) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    unsigned long long id = 0;
+    hipGraph_t g = nullptr;
+    const hipGraphNode_t* deps = nullptr;
+    size_t nd = 0;
+    hipGraphNode_t node = nullptr;
+    if (hipStreamGetCaptureInfo_v2(st, &cs, &id, &g, &deps, &nd) != hipSuccess || cs != hipStreamCaptureStatusActive ||
+        hipGraphAddEventRecordNode(&node, g, deps, nd, tev[i]) != hipSuccess ||
+        hipStreamUpdateCaptureDependencies(st, &node, 1, hipStreamSetCaptureDependencies) != hipSuccess) {
+      (void)hipGetLastError();
+      mark_failed = true;
+      return;
+    }
+    tnode[i] = node;
+  }
+
+  int forces(hipStream_t st, bool timed = false) {
     NepIO o = io();
     const float* P = m->params.ptr<float>();
     int rc;
-    if ((rc = m->ops->desc(st, o, P, true, m->vdesc)) || (rc = m->ops->force(st, o, P, m->vforce)) || (rc = m->ops->gather(st, o)))
-      return rc;
+    if (timed) mark(0, st);
+    if ((rc = m->ops->desc(st, o, P, true, m->vdesc))) return rc;
+    if (timed) mark(1, st);
+    if ((rc = m->ops->force(st, o, P, m->vforce))) return rc;
+    if (timed) mark(2, st);
+    if ((rc = m->ops->gather(st, o))) return rc;
+    if (timed) mark(3, st);
     return NEPMI_OK;
   }
 
@@ -306,7 +341,7 @@ struct nepmi_md {
                        ref4.ptr<float4>(), flags);
     int rc;
     if ((rc = rebuild(st, flags + kFlagRebuild))) return rc;
-    if ((rc = forces(st))) return rc;
+    if ((rc = forces(st, true))) return rc;
     hipLaunchKernelGGL(k_md_kick2, dim3(nb256(ns)), dim3(256), 0, st, ns, mc, nbr.orig.ptr<int>(),
                        nbr.pos4.ptr<float4>(), F4.ptr<float4>(), vel4.ptr<float4>(), Ki.ptr<float>());
     if ((rc = red.run(st, Ei.ptr<float>(), Wi.ptr<float>(), Ki.ptr<float>(), epot.ptr<double>(), vir.ptr<double>(),
@@ -321,6 +356,10 @@ struct nepmi_md {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    for (hipEvent_t e : tev)
+      if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : tpool)
+      if (e) (void)hipEventDestroy(e);
   }
 };
 
@@ -403,7 +442,7 @@ int nepmi_md_create(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, cons
   if ((rc = md->fT.ensure(16 * (size_t)ns * nb.capR)) || (rc = md->fA.ensure(16 * (size_t)ns * nb.capA))) return fail(rc);
   fill_int(st, nb.flags.ptr<int>(), kFlagCount, 0, nullptr);
   // kernel variants timed on this state, then the forces of the initial state
-  if ((rc = autotune_io(m, md->io(), st, 2))) return fail(rc);
+  if (!m->pinned && (rc = autotune_io(m, md->io(), st, 2))) return fail(rc);
   if ((rc = md->forces(st))) return fail(rc);
   hipLaunchKernelGGL(k_md_kin, dim3(nb256(ns)), dim3(256), 0, st, ns, md->mc, nb.orig.ptr<int>(), nb.pos4.ptr<float4>(),
                      md->vel4.ptr<float4>(), md->Ki.ptr<float>());
@@ -412,6 +451,8 @@ int nepmi_md_create(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, cons
     return fail(rc);
   if (hipStreamSynchronize(st) != hipSuccess) return fail(hip_fail(hipGetLastError(), "hipStreamSynchronize"));
   // capture one step
+  for (int i = 0; i < 4; ++i)
+    if (hipEventCreate(&md->tev[i]) != hipSuccess) return fail(hip_fail(hipGetLastError(), "hipEventCreate"));
   if (hipStreamCreateWithFlags(&md->cap_stream, hipStreamNonBlocking) != hipSuccess)
     return fail(hip_fail(hipGetLastError(), "hipStreamCreate"));
   if (hipStreamBeginCapture(md->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
@@ -424,19 +465,13 @@ int nepmi_md_create(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, cons
   md->graph = g;
   if ((e = hipGraphInstantiate(&md->exec, g, nullptr, nullptr, 0)) != hipSuccess)
     return fail(hip_fail(e, "hipGraphInstantiate"));
+  md->timing = !md->mark_failed && md->tnode[0] && md->tnode[1] && md->tnode[2] && md->tnode[3];
   if (hipStreamSynchronize(st) != hipSuccess) return fail(hip_fail(hipGetLastError(), "hipStreamSynchronize"));
   *out = md;
   return NEPMI_OK;
 }
 
-int nepmi_md_step(nepmi_md* md, int32_t n_steps, void* stream) {
-  if (!md || n_steps < 0) {
-    set_error("invalid argument");
-    return NEPMI_INVALID_ARG;
-  }
-  hipStream_t st = (hipStream_t)stream;
-  for (int s = 0; s < n_steps; ++s) NEPMI_HIP(hipGraphLaunch(md->exec, st));
-  md->host_steps += n_steps;
+static int md_check_flags(nepmi_md* md, hipStream_t st) {
   int hf[kFlagCount];
   int rc = md->nbr.check_flags(st, hf);
   if (rc) return rc;
@@ -449,6 +484,60 @@ int nepmi_md_step(nepmi_md* md, int32_t n_steps, void* stream) {
     return NEPMI_INVALID_ARG;
   }
   return NEPMI_OK;
+}
+
+int nepmi_md_step_timed(nepmi_md* md, int32_t n_steps, double* ms, void* stream) {
+  if (!md || n_steps < 1 || !ms) {
+    set_error("invalid argument");
+    return NEPMI_INVALID_ARG;
+  }
+  if (!md->timing) {
+    set_error("the step graph has no timing nodes");
+    return NEPMI_UNSUPPORTED;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const size_t need = 4 * (size_t)n_steps;
+  while (md->tpool.size() < need) {
+    hipEvent_t e;
+    NEPMI_HIP(hipEventCreate(&e));
+    md->tpool.push_back(e);
+  }
+  // every launch is enqueued before the next change of its event nodes, so
+  // each step records into its own four events
+  int rc = NEPMI_OK;
+  for (int s = 0; s < n_steps && !rc; ++s) {
+    for (int i = 0; i < 4 && !rc; ++i)
+      if (hipGraphExecEventRecordNodeSetEvent(md->exec, md->tnode[i], md->tpool[4 * (size_t)s + i]) != hipSuccess)
+        rc = hip_fail(hipGetLastError(), "hipGraphExecEventRecordNodeSetEvent");
+    if (!rc && hipGraphLaunch(md->exec, st) != hipSuccess) rc = hip_fail(hipGetLastError(), "hipGraphLaunch");
+  }
+  if (hipStreamSynchronize(st) != hipSuccess && !rc) rc = hip_fail(hipGetLastError(), "hipStreamSynchronize");
+  double acc[3] = {0, 0, 0};
+  for (int s = 0; s < n_steps && !rc; ++s)
+    for (int i = 0; i < 3; ++i) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, md->tpool[4 * (size_t)s + i], md->tpool[4 * (size_t)s + i + 1]) != hipSuccess) {
+        rc = hip_fail(hipGetLastError(), "hipEventElapsedTime");
+        break;
+      }
+      acc[i] += t;
+    }
+  for (int i = 0; i < 4; ++i) (void)hipGraphExecEventRecordNodeSetEvent(md->exec, md->tnode[i], md->tev[i]);
+  if (rc) return rc;
+  md->host_steps += n_steps;
+  for (int i = 0; i < 3; ++i) ms[i] = acc[i] / n_steps;
+  return md_check_flags(md, st);
+}
+
+int nepmi_md_step(nepmi_md* md, int32_t n_steps, void* stream) {
+  if (!md || n_steps < 0) {
+    set_error("invalid argument");
+    return NEPMI_INVALID_ARG;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  for (int s = 0; s < n_steps; ++s) NEPMI_HIP(hipGraphLaunch(md->exec, st));
+  md->host_steps += n_steps;
+  return md_check_flags(md, st);
 }
 
 int nepmi_md_get(nepmi_md* md, float* dev_pos, float* dev_vel, float* dev_forces, double* dev_epot, double* dev_ekin,

@@ -41,6 +41,7 @@ struct nepmi_model {
   nepmi::TrainBufs tr;
   int device = 0;
   int vdesc = 0, vforce = 0;  // kernel variants in use (see nepmi_autotune)
+  bool pinned = false;        // variants chosen by nepmi_set_variants: MD creation keeps them
   // Prepare the batch: neighbour lists, work buffers and reduction plan.
   int prepare(int n_cfg, const int64_t* atom_off, const double* cells, const float* pos, const int32_t* species,
               hipStream_t st);

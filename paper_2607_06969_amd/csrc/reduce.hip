@@ -3,8 +3,8 @@
 // E_c = sum_i E_i (Eq. 1) and V_c = sum_i W_i (Eq. 4), plus optional
 // kinetic energies, are summed in float64 in a fixed order: every
 // configuration's caller-order atom range is cut into chunks, one block sums
-// a chunk with a fixed-shape tree, and one thread per configuration adds its
-// chunk sums in order.  Results are bitwise reproducible run to run.
+// a chunk with a fixed-shape tree, and one block per configuration sums its
+// chunk sums the same way.  Results are bitwise reproducible run to run.
 #include "reduce.hpp"
 
 namespace nepmi {
@@ -43,18 +43,36 @@ __global__ __launch_bounds__(kRedBlock) void k_reduce_chunks(const RedItem* __re
   if (threadIdx.x < NV) part[(int64_t)blockIdx.x * NV + threadIdx.x] = sh[threadIdx.x][0];
 }
 
-__global__ void k_reduce_final(int n_cfg, const int* __restrict__ item_start, const double* __restrict__ part,
-                               double* __restrict__ E, double* __restrict__ V, double* __restrict__ Kout) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n_cfg) return;
-  double acc[kRedValues];
-  for (int v = 0; v < kRedValues; ++v) acc[v] = 0.0;
-  for (int w = item_start[c]; w < item_start[c + 1]; ++w)
-    for (int v = 0; v < kRedValues; ++v) acc[v] += part[(int64_t)w * kRedValues + v];
-  if (E) E[c] = acc[0];
-  if (V)
-    for (int x = 0; x < 9; ++x) V[(int64_t)c * 9 + x] = acc[1 + x];
-  if (Kout) Kout[c] = acc[10];
+// One block per configuration: its chunk sums in a fixed assignment to
+// threads, then the same fixed-shape tree.
+__global__ __launch_bounds__(kRedBlock) void k_reduce_final(int n_cfg, const int* __restrict__ item_start,
+                                                            const double* __restrict__ part, double* __restrict__ E,
+                                                            double* __restrict__ V, double* __restrict__ Kout) {
+  constexpr int NV = kRedValues;
+  __shared__ double sh[NV][kRedBlock];
+  const int c = blockIdx.x;
+  double acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  for (int w = item_start[c] + (int)threadIdx.x; w < item_start[c + 1]; w += kRedBlock)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] += part[(int64_t)w * NV + v];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) sh[v][threadIdx.x] = acc[v];
+  __syncthreads();
+  for (int s = kRedBlock / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) sh[v][threadIdx.x] += sh[v][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (E) E[c] = sh[0][0];
+    if (V)
+      for (int x = 0; x < 9; ++x) V[(int64_t)c * 9 + x] = sh[1 + x][0];
+    if (Kout) Kout[c] = sh[10][0];
+  }
 }
 
 int Reducer::setup(int n_cfg_, const int64_t* atom_off, hipStream_t st) {
@@ -90,7 +108,7 @@ int Reducer::run(hipStream_t st, const float* Ei, const float* Wi, const float* 
                  double* Kout) {
   hipLaunchKernelGGL(k_reduce_chunks, dim3(n_items), dim3(kRedBlock), 0, st, items_dev.ptr<RedItem>(), Ei, Wi, Ki,
                      part.ptr<double>());
-  hipLaunchKernelGGL(k_reduce_final, dim3((n_cfg + 63) / 64), dim3(64), 0, st, n_cfg, start_dev.ptr<int>(),
+  hipLaunchKernelGGL(k_reduce_final, dim3(n_cfg), dim3(kRedBlock), 0, st, n_cfg, start_dev.ptr<int>(),
                      part.ptr<double>(), E, V, Kout);
   NEPMI_HIP(hipGetLastError());
   return NEPMI_OK;

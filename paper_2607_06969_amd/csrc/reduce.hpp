@@ -8,7 +8,7 @@
 namespace nepmi {
 
 constexpr int kRedValues = 11;    // energy, 9 virial components, kinetic energy
-constexpr int64_t kRedChunk = 16384;
+constexpr int64_t kRedChunk = 2048;  // atoms per block of the first pass
 
 struct RedItem {
   int cfg;

@@ -94,6 +94,7 @@ int nepmi_set_variants(nepmi_model* m, int32_t desc_variant, int32_t force_varia
   }
   m->vdesc = desc_variant;
   m->vforce = force_variant;
+  m->pinned = true;
   return NEPMI_OK;
 }
 

@@ -209,6 +209,14 @@ class NepMD:
     def step(self, n=1):
         check(load().nepmi_md_step(self._h, int(n), _stream()))
 
+    def step_timed(self, n):
+        """Advance n steps; returns the average duration (ms) of the descriptor,
+        pair-force and gather kernels over exactly these steps (HIP events
+        recorded inside the step graph)."""
+        ms = (C.c_double * 3)()
+        check(load().nepmi_md_step_timed(self._h, int(n), ms, _stream()))
+        return {"desc": ms[0], "force": ms[1], "gather": ms[2]}
+
     def state(self):
         b = self.batch
         dev = b.pos.device
