@@ -76,7 +76,8 @@ def gather_bytes(pairs_a_list: float):
 
 
 TRAFFIC_PROFILE = os.path.join(HERE, "profiles", "k_force_md900k_hbm_traffic.md")
-KERNEL_SOURCES = ("common.hpp", "nep_kernels.hpp", "nep_kernels.hip")
+# the kernel and the data order it sees (slot order, list layout)
+KERNEL_SOURCES = ("common.hpp", "nep_kernels.hpp", "nep_kernels.hip", "nbr.hpp", "nbr.hip")
 
 
 def measured_traffic(kernel: str):

@@ -24,10 +24,24 @@ namespace nepmi {
 // ------------------------------------------------------------------ staging
 
 // Per caller-order atom: validate, wrap into the cell, find its bin and sort key.
+// Global sort key of a cell bin.  Bins are numbered in 4 x 4 x 4 tiles (tile
+// row-major, then row-major inside the tile), so that a contiguous range of
+// slots covers a compact region of space: the atoms a GPU die processes at
+// the same time, and their neighbours, then fit its L2 better than with
+// row-major slabs.  Each configuration owns ceil(nb/4)^3 * 64 keys.
+__device__ __forceinline__ int bin_key(const CfgDev& C, int b0, int b1, int b2) {
+  const int nt1 = (C.nb[1] + 3) >> 2, nt2 = (C.nb[2] + 3) >> 2;
+  const int t = ((b0 >> 2) * nt1 + (b1 >> 2)) * nt2 + (b2 >> 2);
+  return C.bin_off + (t << 6) + (((b0 & 3) << 4) | ((b1 & 3) << 2) | (b2 & 3));
+}
+
+// Bin coordinates packed into one int (each below 1024).
+__device__ __forceinline__ int pack_bin(int b0, int b1, int b2) { return b0 | (b1 << 10) | (b2 << 20); }
+
 __global__ void k_stage(int64_t N, int n_cfg, const int64_t* __restrict__ atom_off, const CfgDev* __restrict__ cfgs,
                         const float* __restrict__ pos, int pos_stride, const int32_t* __restrict__ species,
                         int n_species, int total_bins, float4* __restrict__ pos_tmp, int* __restrict__ cfg_tmp,
-                        int* __restrict__ key, int* __restrict__ cnt, int* __restrict__ flags,
+                        int* __restrict__ crd_tmp, int* __restrict__ key, int* __restrict__ cnt, int* __restrict__ flags,
                         const int* __restrict__ gate) {
   if (gate && *gate == 0) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -65,11 +79,11 @@ __global__ void k_stage(int64_t N, int n_cfg, const int64_t* __restrict__ atom_o
     for (int a = 0; a < 3; ++a)
       o[a] = (float)((double)o[a] - m[0] * C.Hd[a] - m[1] * C.Hd[3 + a] - m[2] * C.Hd[6 + a]);
   }
-  const int gbin = C.bin_off + (b[0] * C.nb[1] + b[1]) * C.nb[2] + b[2];
-  const int k = z * total_bins + gbin;
+  const int k = z * total_bins + bin_key(C, b[0], b[1], b[2]);
   key[i] = k;
   pos_tmp[i] = make_float4(o[0], o[1], o[2], __int_as_float(z));
   cfg_tmp[i] = lo;
+  crd_tmp[i] = pack_bin(b[0], b[1], b[2]);
   atomicAdd(&cnt[k], 1);
 }
 
@@ -202,6 +216,7 @@ __global__ void k_sort_keys(int M, const int* __restrict__ start, const int* __r
 __global__ void k_fill_slots(int64_t n_slots, const int* __restrict__ base, const int* __restrict__ start,
                              int total_bins, int n_species, const int* __restrict__ perm,
                              const float4* __restrict__ pos_tmp, const int* __restrict__ cfg_tmp,
+                             const int* __restrict__ crd_tmp,
                              const int* __restrict__ key, float4* __restrict__ pos4, int* __restrict__ cfg_of,
                              int* __restrict__ orig, int* __restrict__ bin_of, int* __restrict__ slot_of,
                              const int* __restrict__ gate) {
@@ -219,7 +234,7 @@ __global__ void k_fill_slots(int64_t n_slots, const int* __restrict__ base, cons
       pos4[p] = pos_tmp[i];
       cfg_of[p] = cfg_tmp[i];
       orig[p] = i;
-      bin_of[p] = key[i] - z * total_bins;
+      bin_of[p] = crd_tmp[i];  // packed bin coordinates
       if (slot_of) slot_of[i] = (int)p;
       return;
     }
@@ -254,8 +269,8 @@ __global__ __launch_bounds__(256) void k_build_lists(int64_t n_slots, int n_spec
   }
   const CfgDev& C = cfgs[c];
   const float4 xi = pos4[p];
-  const int lb = bin_of[p] - C.bin_off;
-  const int b0 = lb / (C.nb[1] * C.nb[2]), b1 = (lb / C.nb[2]) % C.nb[1], b2 = lb % C.nb[2];
+  const int pb = bin_of[p];
+  const int b0 = pb & 1023, b1 = (pb >> 10) & 1023, b2 = pb >> 20;
   int kR = 0, kA = 0;
   for (int o = 0; o < 27; ++o) {
     int t0 = b0 + o / 9 - 1, t1 = b1 + (o / 3) % 3 - 1, t2 = b2 + o % 3 - 1;
@@ -268,7 +283,7 @@ __global__ __launch_bounds__(256) void k_build_lists(int64_t n_slots, int n_spec
     const uint32_t code = (uint32_t)((w0 + 1) * 9 + (w1 + 1) * 3 + (w2 + 1));
     float sx, sy, sz;
     image_shift(C.H, code, sx, sy, sz);
-    const int tb = C.bin_off + (t0 * C.nb[1] + t1) * C.nb[2] + t2;
+    const int tb = bin_key(C, t0, t1, t2);
     for (int z = 0; z < n_species; ++z) {
       const int k = z * total_bins + tb;
       const int q0 = base[z] + start[k] - start[z * total_bins];
@@ -464,7 +479,7 @@ int NbrPipeline::setup(int n_cfg_, const int64_t* atom_off, const double* cells,
     C.atom_off = atom_off[c];
     C.n_atoms = (int)(atom_off[c + 1] - atom_off[c]);
     C.pad = 0;
-    bins += (int64_t)C.nb[0] * C.nb[1] * C.nb[2];
+    bins += (int64_t)((C.nb[0] + 3) / 4) * ((C.nb[1] + 3) / 4) * ((C.nb[2] + 3) / 4) * 64;
   }
   if (bins * n_species_ > (int64_t)1 << 30) {
     set_error("too many cell bins");
@@ -493,7 +508,7 @@ int NbrPipeline::setup(int n_cfg_, const int64_t* atom_off, const double* cells,
       (rc = key.ensure(4 * Na)) || (rc = cnt.ensure(4 * (size_t)(M + 1))) || (rc = start.ensure(4 * (size_t)(M + 1))) ||
       (rc = cursor.ensure(4 * (size_t)(M + 1))) || (rc = tile_sums.ensure(4 * (size_t)(n_tiles + 1))) ||
       (rc = base.ensure(4 * (size_t)(n_species_ + 1))) || (rc = perm.ensure(4 * (size_t)n_slots)) ||
-      (rc = pos_tmp.ensure(16 * Na)) || (rc = cfg_tmp.ensure(4 * Na)) || (rc = pos4.ensure(16 * (size_t)n_slots)) ||
+      (rc = pos_tmp.ensure(16 * Na)) || (rc = cfg_tmp.ensure(4 * Na)) || (rc = crd_tmp.ensure(4 * Na)) || (rc = pos4.ensure(16 * (size_t)n_slots)) ||
       (rc = cfg_of.ensure(4 * (size_t)n_slots)) || (rc = orig.ensure(4 * (size_t)n_slots)) ||
       (rc = bin_of.ensure(4 * (size_t)n_slots)) || (rc = slot_of.ensure(4 * Na)) ||
       (rc = cntR.ensure(4 * (size_t)n_slots)) || (rc = ccntR.ensure(4 * (size_t)n_slots)) ||
@@ -582,7 +597,7 @@ int NbrPipeline::launch_sort(hipStream_t st, const float* pos, int pos_stride, c
   if (N > 0)
   hipLaunchKernelGGL(k_stage, dim3(nblk(N, 256)), dim3(256), 0, st, N, n_cfg, atom_off_dev.ptr<int64_t>(),
                      cfgs.ptr<CfgDev>(), pos, pos_stride, species, n_species, total_bins, pos_tmp.ptr<float4>(),
-                     cfg_tmp.ptr<int>(), key.ptr<int>(), cnt.ptr<int>(), flags.ptr<int>(), gate);
+                     cfg_tmp.ptr<int>(), crd_tmp.ptr<int>(), key.ptr<int>(), cnt.ptr<int>(), flags.ptr<int>(), gate);
   const int n_tiles = (M + kScanTile - 1) / kScanTile;
   hipLaunchKernelGGL(k_scan_tiles, dim3(n_tiles), dim3(kScanBlock), 0, st, cnt.ptr<int>(), M, start.ptr<int>(),
                      tile_sums.ptr<int>(), gate);
@@ -601,7 +616,7 @@ int NbrPipeline::launch_sort(hipStream_t st, const float* pos, int pos_stride, c
                      total_bins, perm.ptr<int>(), gate);
   hipLaunchKernelGGL(k_fill_slots, dim3(nblk(n_slots, 256)), dim3(256), 0, st, n_slots, base.ptr<int>(),
                      start.ptr<int>(), total_bins, n_species, perm.ptr<int>(), pos_tmp.ptr<float4>(),
-                     cfg_tmp.ptr<int>(), key.ptr<int>(), pos4.ptr<float4>(), cfg_of.ptr<int>(), orig.ptr<int>(),
+                     cfg_tmp.ptr<int>(), crd_tmp.ptr<int>(), key.ptr<int>(), pos4.ptr<float4>(), cfg_of.ptr<int>(), orig.ptr<int>(),
                      bin_of.ptr<int>(), slot_of.ptr<int>(), gate);
   NEPMI_HIP(hipGetLastError());
   return NEPMI_OK;

@@ -516,10 +516,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
     }
   }
 
-  // ---- angular pairs, in NSPLIT groups of n
-  float W[9];
-#pragma unroll
-  for (int x = 0; x < 9; ++x) W[x] = 0.f;
+  // ---- angular pairs, in NSPLIT groups of n (the virial continues from the
+  //      radial part, rows xx xy xz / yx yy yz / zx zy zz)
+  float W[9] = {Wr[0], Wr[3], Wr[4], Wr[3], Wr[1], Wr[5], Wr[4], Wr[5], Wr[2]};
   const int nA = ccA[p];
   constexpr Kappa<L> kap;
 #pragma unroll
@@ -582,33 +581,40 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
       const float inv = rsqrt_hw(v.d2);
       const float ux = v.rx * inv, uy = v.ry * inv, uz = v.rz * inv;
       const RadialFD f = radial_fd(v.d2 * inv * rcA_inv, rcA_inv);
+      // g_n and g'_n of this group first, so that T and T' die early
+      float g[NH], gp[NH];
+      {
+        float Tk[BA], Dk[BA];
+        cheb_tt<BA>(f.x, Tk, Dk);
+        const float* cl = cl0 + v.zj * (NA * BA);
+#pragma unroll
+        for (int nn = 0; nn < NH; ++nn) {
+          float ct = cl[nn * BA], cd = 0.f;
+#pragma unroll
+          for (int kk = 1; kk < BA; ++kk) {
+            const float cc = cl[nn * BA + kk];
+            ct = fmaf(cc, Tk[kk], ct);
+            cd = fmaf(cc, Dk[kk], cd);
+          }
+          g[nn] = f.hf * ct;
+          gp[nn] = fmaf(f.dxhf, cd, f.dfc2 * ct);
+        }
+      }
       float P[K];
       raw_sph<L>(ux, uy, uz, P);
-      float Tk[BA], Dk[BA];
-      cheb_tt<BA>(f.x, Tk, Dk);
-      const float* cl = cl0 + v.zj * (NA * BA);
       float G[K];
 #pragma unroll
       for (int lm = 0; lm < K; ++lm) G[lm] = 0.f;
       float s = 0.f;
 #pragma unroll
       for (int nn = 0; nn < NH; ++nn) {
-        float ct = cl[nn * BA], cd = 0.f;
-#pragma unroll
-        for (int kk = 1; kk < BA; ++kk) {
-          const float cc = cl[nn * BA + kk];
-          ct = fmaf(cc, Tk[kk], ct);
-          cd = fmaf(cc, Dk[kk], cd);
-        }
-        const float g = f.hf * ct;
-        const float gp = fmaf(f.dxhf, cd, f.dfc2 * ct);
         float zn = 0.f;
 #pragma unroll
         for (int lm = 0; lm < K; ++lm) {
           zn = fmaf(Sg[nn][lm], P[lm], zn);
-          G[lm] = fmaf(Sg[nn][lm], g, G[lm]);
+          G[lm] = fmaf(Sg[nn][lm], g[nn], G[lm]);
         }
-        s = fmaf(gp, zn, s);
+        s = fmaf(gp[nn], zn, s);
       }
       float vx, vy, vz;
       raw_sph_grad_dot<L>(ux, uy, uz, G, vx, vy, vz);
@@ -646,15 +652,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
   frad[p] = make_float4(Fx, Fy, Fz, 0.f);
   const int i = orig[p];
   float* w = Wi + (int64_t)i * 9;
-  w[0] = W[0] + Wr[0];
-  w[1] = W[1] + Wr[3];
-  w[2] = W[2] + Wr[4];
-  w[3] = W[3] + Wr[3];
-  w[4] = W[4] + Wr[1];
-  w[5] = W[5] + Wr[5];
-  w[6] = W[6] + Wr[4];
-  w[7] = W[7] + Wr[5];
-  w[8] = W[8] + Wr[2];
+#pragma unroll
+  for (int x = 0; x < 9; ++x) w[x] = W[x];
 }
 
 // ---------------------------------------------------------------- k_gather
