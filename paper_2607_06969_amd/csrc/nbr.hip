@@ -288,19 +288,27 @@ __global__ __launch_bounds__(256) void k_build_lists(int64_t n_slots, int n_spec
       const int k = z * total_bins + tb;
       const int q0 = base[z] + start[k] - start[z * total_bins];
       const int q1 = q0 + start[k + 1] - start[k];
-      for (int q = q0; q < q1; ++q) {
-        if (q == (int)p && code == 13u) continue;
-        const float4 xq = pos4[q];
-        const float rx = (xq.x - xi.x) + sx, ry = (xq.y - xi.y) + sy, rz = (xq.z - xi.z) + sz;
-        const float d2 = pair_d2(rx, ry, rz);
-        if (d2 < rclR2) {
-          const uint32_t e = (uint32_t)q | (code << kNbrShift);
-          if (kR < capR) {
-            nbrR[(int64_t)kR * n_slots + p] = e;
-            nbrT[p * rowT + kR] = e;
+      // four candidates per round, loaded together (indices clamped into the
+      // bin's range, so every load is in bounds; the extra ones are skipped)
+      for (int q4 = q0; q4 < q1; q4 += 4) {
+        float4 xs[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) xs[u] = pos4[q4 + u < q1 ? q4 + u : q1 - 1];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int q = q4 + u;
+          if (q >= q1 || (q == (int)p && code == 13u)) continue;
+          const float rx = (xs[u].x - xi.x) + sx, ry = (xs[u].y - xi.y) + sy, rz = (xs[u].z - xi.z) + sz;
+          const float d2 = pair_d2(rx, ry, rz);
+          if (d2 < rclR2) {
+            const uint32_t e = (uint32_t)q | (code << kNbrShift);
+            if (kR < capR) {
+              nbrR[(int64_t)kR * n_slots + p] = e;
+              nbrT[p * rowT + kR] = e;
+            }
+            ++kR;
+            if (d2 < rclA2) ++kA;
           }
-          ++kR;
-          if (d2 < rclA2) ++kA;
         }
       }
     }

@@ -408,7 +408,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
       float acc = 0.f;
 #pragma unroll
       for (int nn = 0; nn < NR; ++nn) acc = fmaf(Fp[nn], cR[(b * NR + nn) * BR + kk], acc);
-      aR[p * (T * BR) + b * BR + kk] = acc;
+      aR[((int64_t)b * n_slots + p) * BR + kk] = acc;
     }
 }
 
@@ -458,15 +458,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
   // ---- radial pairs: f_ij - f_ji = (s_own + s_rev) u_ij with
   //      s = dE/dd = dxhf sum_k atil_k T'_k + dfc2 sum_k atil_k T_k
   {
-    const float* arow = aR + p * (T * BR);
     float a1[T == 1 ? BR : 1];
     float* mine = aown_s + (T > 1 ? threadIdx.x * RW : 0);
     if constexpr (T == 1) {
 #pragma unroll
-      for (int kk = 0; kk < BR; ++kk) a1[kk] = arow[kk];
+      for (int kk = 0; kk < BR; ++kk) a1[kk] = aR[p * BR + kk];
     } else {
 #pragma unroll
-      for (int kk = 0; kk < T * BR; ++kk) mine[kk] = arow[kk];
+      for (int b = 0; b < T; ++b)
+#pragma unroll
+        for (int kk = 0; kk < BR; ++kk) mine[b * BR + kk] = aR[((int64_t)b * n_slots + p) * BR + kk];
     }
     const int n = ccR[p];
     PairWalk w(cnR, n_slots, p, n, pos4);
@@ -475,8 +476,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
       float4 x1;
       w.prefetch(k, pos4, e2, x1);
       const PairVec v = pair_vec(w.e, w.x, xi, Hc);
-      // the neighbour's adjoint row atil_j[Z_i]
-      const float* ar = aR + (int64_t)v.q * (T * BR) + Zs * BR;
+      // the neighbour's adjoint row atil_j[Z_i] (part Z_i of the adjoint,
+      // stored part-major so that a wavefront reads one compact array)
+      const float* ar = aR + ((int64_t)Zs * n_slots + v.q) * BR;
       w.advance(e2, x1);
       const float inv = rsqrt_hw(v.d2);
       const RadialFD f = radial_fd(v.d2 * inv * rcR_inv, rcR_inv);

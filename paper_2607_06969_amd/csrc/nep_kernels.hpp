@@ -47,7 +47,7 @@ struct NepIO {
   int* flags;
   Cutoffs cut;
   float* fp;     // [NANG][n_slots]  dE_i/dq (angular descriptors)
-  float* aR;     // [n_slots][T*BR]  radial adjoint
+  float* aR;     // [T][n_slots][BR] radial adjoint, part b = atil_i[b][.]
   float* Ei;     // [N] caller order (site energies)
   float* qout;   // [N][D] caller order, optional
   float4* frad;  // [n_slots] own force part (radial pairs both ways, angular dE_i/dr_ij)
