@@ -73,7 +73,7 @@ int nepmi_model::prepare(int n_cfg, const int64_t* atom_off, const double* cells
   if ((rc = red.setup(n_cfg, atom_off, st))) return rc;
   const size_t ns = (size_t)nbr.n_slots, N = (size_t)(nbr.N > 0 ? nbr.N : 1);
   if ((rc = fp.ensure(4 * ns * (size_t)ops->NANG)) || (rc = aR.ensure(4 * ns * (size_t)(ops->T * ops->BR))) ||
-      (rc = Ei.ensure(4 * N)) || (rc = frad.ensure(16 * ns)) || (rc = fT.ensure(16 * ns * (size_t)nbr.capR)) || (rc = fA.ensure(16 * ns * (size_t)nbr.capA)) ||
+      (rc = Ei.ensure(4 * N)) || (rc = frad.ensure(16 * ns)) || (rc = amask.ensure(8 * ns * (size_t)((nbr.capR + 63) / 64))) || (rc = fA.ensure(16 * ns * (size_t)nbr.capA)) ||
       (rc = Wi.ensure(36 * N)) || (rc = Eproc.ensure(4 * ns)))
     return rc;
   return NEPMI_OK;
@@ -110,7 +110,7 @@ NepIO nepmi_model::io(float* Fuser, float4* Fproc, float* qout) {
   o.qout = qout;
   o.frad = frad.ptr<float4>();
   o.fA = fA.ptr<float4>();
-  o.fT = fT.ptr<float4>();
+  o.amask = amask.ptr<uint64_t>();
   o.Wi = Wi.ptr<float>();
   o.Fuser = Fuser;
   o.Fproc = Fproc;

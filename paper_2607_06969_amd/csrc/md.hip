@@ -223,7 +223,7 @@ struct nepmi_md {
   MdConst mc{};
   int n_species = 0;
   DevBuf species_user, xd_user, x_user, v_user, xd, vel4, ref4, F4;
-  DevBuf fp, aR, Ei, frad, fA, fT, Wi, Ki, Eproc;
+  DevBuf fp, aR, Ei, frad, fA, amask, Wi, Ki, Eproc;
   DevBuf epot, ekin, vir, counters;
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -267,7 +267,7 @@ struct nepmi_md {
     o.qout = nullptr;
     o.frad = frad.ptr<float4>();
     o.fA = fA.ptr<float4>();
-    o.fT = fT.ptr<float4>();
+    o.amask = amask.ptr<uint64_t>();
     o.Wi = Wi.ptr<float>();
     o.Fuser = nullptr;
     o.Fproc = F4.ptr<float4>();
@@ -439,7 +439,8 @@ int nepmi_md_create(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, cons
     set_error("angular neighbour list is not symmetric");
     return fail(NEPMI_INVALID_ARG);
   }
-  if ((rc = md->fT.ensure(16 * (size_t)ns * nb.capR)) || (rc = md->fA.ensure(16 * (size_t)ns * nb.capA))) return fail(rc);
+  if ((rc = md->amask.ensure(8 * (size_t)ns * ((nb.capR + 63) / 64))) || (rc = md->fA.ensure(16 * (size_t)ns * nb.capA)))
+    return fail(rc);
   fill_int(st, nb.flags.ptr<int>(), kFlagCount, 0, nullptr);
   // kernel variants timed on this state, then the forces of the initial state
   if (!m->pinned && (rc = autotune_io(m, md->io(), st, 2))) return fail(rc);

@@ -37,7 +37,7 @@ struct nepmi_model {
   nepmi::DevBuf params;
   nepmi::NbrPipeline nbr;
   nepmi::Reducer red;
-  nepmi::DevBuf fp, aR, Ei, frad, fA, fT, Wi, Eproc;
+  nepmi::DevBuf fp, aR, Ei, frad, fA, amask, Wi, Eproc;
   nepmi::TrainBufs tr;
   int device = 0;
   int vdesc = 0, vforce = 0;  // kernel variants in use (see nepmi_autotune)

@@ -172,7 +172,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
     int64_t n_slots, int capA, const float4* __restrict__ pos4, const int* __restrict__ cfg_of,
     const int* __restrict__ orig, const CfgDev* __restrict__ cfgs, const uint32_t* __restrict__ nbrR,
     const int* __restrict__ cntR, const uint32_t* __restrict__ vrev, uint32_t* __restrict__ cnR, int* __restrict__ ccR,
-    uint32_t* __restrict__ cnA, uint32_t* __restrict__ cpA, int* __restrict__ ccA, int* __restrict__ flags, Cutoffs cut,
+    uint32_t* __restrict__ cnA, uint32_t* __restrict__ cpA, int* __restrict__ ccA, uint64_t* __restrict__ amask,
+    int* __restrict__ flags, Cutoffs cut,
     const float* __restrict__ params, float* __restrict__ fp, float* __restrict__ aR, float* __restrict__ Ei,
     float* __restrict__ qout, float* __restrict__ Eproc, int want_adjoint) {
   constexpr int T = S::T, NR = S::NR, NA = S::NA, BR = S::BR, BA = S::BA, L = S::L, K = S::K, D = S::D, H = S::H;
@@ -234,6 +235,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
     bool bad = false;
     PairWalk w(nbrR, n_slots, p, n, pos4);
     uint32_t rv = n > 0 ? vrev[p] : 0u;
+    uint64_t mword = 0;  // bit k % 64: entry k of the Verlet list is in the compact angular list
     for (int k = 0; k < n; ++k) {
       uint32_t e2;
       float4 x1;
@@ -253,6 +255,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
           if (rvk <= 0xFFFFu && nA < capA) {
             cnA[(int64_t)nA * n_slots + p] = e;
             cpA[(int64_t)nA * n_slots + p] = (uint32_t)k | (rvk << 16);
+            mword |= 1ull << (k & 63);
             ++nA;
           } else {
             bad = true;
@@ -268,6 +271,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
 #pragma unroll
           for (int kk = 0; kk < BR; ++kk) PT[b][kk] = fmaf(m, Tk[kk], PT[b][kk]);
         }
+      }
+      if ((k & 63) == 63 || k == n - 1) {
+        amask[(int64_t)(k >> 6) * n_slots + p] = mword;
+        mword = 0;
       }
     }
     if (bad) atomicOr(&flags[kFlagAsym], 1);
@@ -424,12 +431,10 @@ constexpr int lds_row() {
 
 template <class S, int NSPLIT, int WPE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) void k_force(
-    int64_t n_slots, int capR, const float4* __restrict__ pos4, const int* __restrict__ cfg_of,
+    int64_t n_slots, const float4* __restrict__ pos4, const int* __restrict__ cfg_of,
     const int* __restrict__ orig, const CfgDev* __restrict__ cfgs, const uint32_t* __restrict__ cnR,
-    const int* __restrict__ ccR, const uint32_t* __restrict__ cnA, const uint32_t* __restrict__ cpA,
-    const int* __restrict__ ccA, Cutoffs cut, const float* __restrict__ params, const float* __restrict__ fp,
-    const float* __restrict__ aR, float4* __restrict__ frad, float4* __restrict__ fA, float4* __restrict__ fT,
-    float* __restrict__ Wi) {
+    const int* __restrict__ ccR, const uint32_t* __restrict__ cnA, const int* __restrict__ ccA, Cutoffs cut, const float* __restrict__ params, const float* __restrict__ fp,
+    const float* __restrict__ aR, float4* __restrict__ frad, float4* __restrict__ fA, float* __restrict__ Wi) {
   constexpr int T = S::T, NR = S::NR, NA = S::NA, BR = S::BR, BA = S::BA, L = S::L, K = S::K;
   constexpr int NH = NA / NSPLIT;
   constexpr int RW = lds_row<T * BR>();
@@ -570,16 +575,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
     // pair forces of this group: f = u sum_n g'_n Z_n + (I - u u^T) v / d,
     // Z_n = sum_lm sigma_nlm P_lm, v = sum_lm G_lm grad P_lm, G_lm = sum_n sigma_nlm g_n
     PairWalk w(cnA, n_slots, p, nA, pos4);
-    uint32_t pk = nA > 0 ? cpA[p] : 0u;
     for (int k = 0; k < nA; ++k) {
       uint32_t e2;
       float4 x1;
       w.prefetch(k, pos4, e2, x1);
-      const uint32_t pk1 = cpA[(int64_t)(k + 1 < nA ? k + 1 : nA - 1) * n_slots + p];
       const PairVec v = pair_vec(w.e, w.x, xi, Hc);
       w.advance(e2, x1);
-      const uint32_t pkk = pk;
-      pk = pk1;
       const float inv = rsqrt_hw(v.d2);
       const float ux = v.rx * inv, uy = v.ry * inv, uz = v.rz * inv;
       const RadialFD f = radial_fd(v.d2 * inv * rcA_inv, rcA_inv);
@@ -630,24 +631,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
       W[0] = fmaf(-fx, v.rx, W[0]); W[1] = fmaf(-fx, v.ry, W[1]); W[2] = fmaf(-fx, v.rz, W[2]);
       W[3] = fmaf(-fy, v.rx, W[3]); W[4] = fmaf(-fy, v.ry, W[4]); W[5] = fmaf(-fy, v.rz, W[5]);
       W[6] = fmaf(-fz, v.rx, W[6]); W[7] = fmaf(-fz, v.ry, W[7]); W[8] = fmaf(-fz, v.rz, W[8]);
-      // partial pair forces of the groups collect in i's own (coalesced)
-      // slot; the total goes to the row of j's list that holds i, for j's gather
+      // dE_i/dr_ij (summed over the groups) stays in i's own compact slot,
+      // where j's gather finds it
       float4* own = fA + (int64_t)k * n_slots + p;
-      if (h + 1 < NSPLIT) {
-        if (h == 0) {
-          *own = make_float4(fx, fy, fz, 0.f);
-        } else {
-          const float4 o = *own;
-          *own = make_float4(o.x + fx, o.y + fy, o.z + fz, 0.f);
-        }
+      if (h == 0) {
+        *own = make_float4(fx, fy, fz, 0.f);
       } else {
-        float4 tot = make_float4(fx, fy, fz, 0.f);
-        if (NSPLIT > 1) {
-          const float4 o = *own;
-          tot = make_float4(o.x + fx, o.y + fy, o.z + fz, 0.f);
-        }
-        const int rev = (int)(pkk >> 16);
-        if (rev < capR) fT[(int64_t)rev * n_slots + v.q] = tot;
+        const float4 o = *own;
+        *own = make_float4(o.x + fx, o.y + fy, o.z + fz, 0.f);
       }
     }
   }
@@ -660,12 +651,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
 
 // ---------------------------------------------------------------- k_gather
 
-// F_i = (radial part + sum_j f_ij) - sum_j f_ji: the own part was summed by
-// k_force; f_ji sits in row (position of j in i's Verlet list) of the pair
-// buffer, written there by j.
+// F_i = (radial part + sum_j f_ij) - sum_j f_ji (Eq. 3).  The own part was
+// summed by k_force.  f_ji = dE_j/dr_ji sits in j's compact angular slot of
+// i, whose index is the number of j's Verlet entries before i's that are in
+// j's compact angular list: a popcount of j's entry mask.
 __global__ __launch_bounds__(kBlock) void k_gather(int64_t n_slots, const int* __restrict__ orig,
-                                                   const uint32_t* __restrict__ cpA, const int* __restrict__ ccA,
-                                                   const float4* __restrict__ frad, const float4* __restrict__ fT,
+                                                   const uint32_t* __restrict__ cnA, const uint32_t* __restrict__ cpA,
+                                                   const int* __restrict__ ccA, const uint64_t* __restrict__ amask,
+                                                   const float4* __restrict__ frad, const float4* __restrict__ fA,
                                                    float* __restrict__ Fuser, float4* __restrict__ Fproc) {
   const int64_t p = xcd_tile() * kBlock + threadIdx.x;
   if (p >= n_slots) return;
@@ -677,8 +670,12 @@ __global__ __launch_bounds__(kBlock) void k_gather(int64_t n_slots, const int* _
   float4 F = frad[p];
   const int n = ccA[p];
   for (int k = 0; k < n; ++k) {
-    const uint32_t own = cpA[(int64_t)k * n_slots + p] & 0xFFFFu;
-    const float4 b = fT[(int64_t)own * n_slots + p];
+    const int64_t j = cnA[(int64_t)k * n_slots + p] & kNbrMask;
+    const uint32_t rv = cpA[(int64_t)k * n_slots + p] >> 16;  // position of i in j's Verlet list
+    int jc = 0;
+    for (uint32_t w = 0; w < (rv >> 6); ++w) jc += __popcll(amask[(int64_t)w * n_slots + j]);
+    jc += __popcll(amask[(int64_t)(rv >> 6) * n_slots + j] & ((1ull << (rv & 63)) - 1ull));
+    const float4 b = fA[(int64_t)jc * n_slots + j];
     F.x -= b.x;
     F.y -= b.y;
     F.z -= b.z;
@@ -723,7 +720,7 @@ template <class S, int NS, int W>
 static int launch_desc(hipStream_t st, const NepIO& io, const float* params, bool want_adjoint) {
   const unsigned g = (unsigned)((io.n_slots + kBlock - 1) / kBlock);
   hipLaunchKernelGGL((k_desc<S, groups<S, NS>(), W>), dim3(g), dim3(kBlock), 0, st, io.n_slots, io.capA, io.pos4,
-                     io.cfg_of, io.orig, io.cfgs, io.nbrR, io.cntR, io.vrev, io.cnR, io.ccR, io.cnA, io.cpA, io.ccA, io.flags,
+                     io.cfg_of, io.orig, io.cfgs, io.nbrR, io.cntR, io.vrev, io.cnR, io.ccR, io.cnA, io.cpA, io.ccA, io.amask, io.flags,
                      io.cut, params, io.fp, io.aR, io.Ei, io.qout, io.Eproc, want_adjoint ? 1 : 0);
   NEPMI_HIP(hipGetLastError());
   return NEPMI_OK;
@@ -732,9 +729,9 @@ static int launch_desc(hipStream_t st, const NepIO& io, const float* params, boo
 template <class S, int NS, int W>
 static int launch_force(hipStream_t st, const NepIO& io, const float* params) {
   const unsigned g = (unsigned)((io.n_slots + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL((k_force<S, groups<S, NS>(), W>), dim3(g), dim3(kBlock), 0, st, io.n_slots, io.capR, io.pos4,
-                     io.cfg_of, io.orig, io.cfgs, io.cnR, io.ccR, io.cnA, io.cpA, io.ccA, io.cut, params, io.fp, io.aR,
-                     io.frad, io.fA, io.fT, io.Wi);
+  hipLaunchKernelGGL((k_force<S, groups<S, NS>(), W>), dim3(g), dim3(kBlock), 0, st, io.n_slots, io.pos4,
+                     io.cfg_of, io.orig, io.cfgs, io.cnR, io.ccR, io.cnA, io.ccA, io.cut, params, io.fp, io.aR,
+                     io.frad, io.fA, io.Wi);
   NEPMI_HIP(hipGetLastError());
   return NEPMI_OK;
 }
@@ -762,8 +759,8 @@ int Launch<S>::force(hipStream_t st, const NepIO& io, const float* params, int v
 template <class S>
 int Launch<S>::gather(hipStream_t st, const NepIO& io) {
   const unsigned g = (unsigned)((io.n_slots + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_gather, dim3(g), dim3(kBlock), 0, st, io.n_slots, io.orig, io.cpA, io.ccA, io.frad, io.fT,
-                     io.Fuser, io.Fproc);
+  hipLaunchKernelGGL(k_gather, dim3(g), dim3(kBlock), 0, st, io.n_slots, io.orig, io.cnA, io.cpA, io.ccA, io.amask,
+                     io.frad, io.fA, io.Fuser, io.Fproc);
   NEPMI_HIP(hipGetLastError());
   return NEPMI_OK;
 }

@@ -17,11 +17,11 @@
 //   k_force  pair forces dE_i/dr_ij and the per-atom virial (Eq. 3, Eq. 4).
 //            Radial pairs gather the neighbour's atil_j[Z_i] and add both
 //            directions at once; for angular pairs, dE_i/dr_ij is added to
-//            i's own force and written (no atomics) to the row of the pair
-//            buffer that j's gather reads: the row of i in j's Verlet list,
-//            known from the reverse index built with the lists.  S_i is
+//            i's own force and kept in i's compact slot (no atomics).  S_i is
 //            recomputed rather than stored.
-//   k_gather F_i = own part - sum_j dE_j/dr_ji over i's angular pairs (Eq. 3).
+//   k_gather F_i = own part - sum_j dE_j/dr_ji over i's angular pairs (Eq. 3),
+//            finding i's slot in j's compact list from the reverse index
+//            built with the lists and j's entry mask.
 #pragma once
 
 #include "common.hpp"
@@ -51,8 +51,8 @@ struct NepIO {
   float* Ei;     // [N] caller order (site energies)
   float* qout;   // [N][D] caller order, optional
   float4* frad;  // [n_slots] own force part (radial pairs both ways, angular dE_i/dr_ij)
-  float4* fA;    // [capA][n_slots] partial angular pair forces (own slots, between groups)
-  float4* fT;    // [capR][n_slots] angular pair forces dE_j/dr_ji, row = position of j in i's Verlet list
+  float4* fA;    // [capA][n_slots] angular pair forces dE_i/dr_ij in i's compact slots
+  uint64_t* amask; // [ceil(capR/64)][n_slots] Verlet entries of i in its compact angular list
   float* Wi;     // [N][9] caller order, per-atom virial
   float* Fuser;  // [N][3] caller order, optional
   float4* Fproc; // [n_slots], optional
