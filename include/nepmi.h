@@ -206,6 +206,36 @@ int nepmi_md_step_timed(nepmi_md *md, int32_t n_steps, double *ms_per_launch, vo
  * virial, force gather, neighbour-list build.  Synchronises `stream`. */
 int nepmi_md_time_kernels(nepmi_md *md, int32_t reps, double *ms_per_launch, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Optimisation protocol (Sec. 3.3).
+ * ------------------------------------------------------------------------- */
+
+/* One Adam step (Sec. 3.3.1) over n FP32 parameters on the device, with the
+ * moments kept by the caller (dev_m, dev_v: n floats each, zero before the
+ * first step; updated in place).  With g = dev_grad and t >= 1 the step count:
+ *   m <- beta1 m + (1 - beta1) g,  v <- beta2 v + (1 - beta2) g^2,
+ *   p <- p - lr / (1 - beta1^t) * m / (sqrt(v) / sqrt(1 - beta2^t) + eps).
+ * No weight decay.  The paper's setting is beta1 = 0.9, beta2 = 0.999,
+ * eps = 1e-8.  Asynchronous on `stream`.  NEPMI_INVALID_ARG on bad sizes,
+ * null pointers, t < 1 or coefficients out of range. */
+int nepmi_adam_step(int64_t n, float *dev_params, const float *dev_grad, float *dev_m, float *dev_v, int64_t t,
+                    double lr, double beta1, double beta2, double eps, void *stream);
+
+/* Learning rate of training step `step` (0-based) under the two-stage
+ * schedule of Sec. 3.3.2 (host only): linear warmup of the factor from
+ * start_factor (1e-4 in the paper) to 1 over warmup_steps (one epoch in the
+ * paper), then cosine annealing from lr_start to lr_end over the remaining
+ * total_steps - warmup_steps steps (held at lr_end after them). */
+int nepmi_lr_schedule(int64_t step, int64_t warmup_steps, int64_t total_steps, double lr_start, double lr_end,
+                      double start_factor, double *lr_out);
+
+/* Loss weights of one step (Sec. 3.3.3, host only):
+ *   w_c = w_start[c] x + w_end[c] (1 - x),  c = energy, force, virial,
+ * with x = lr (the formula as printed, normalised = 0) or x = lr / lr_start
+ * (normalised = 1).  w_start, w_end, w_out: host double[3]. */
+int nepmi_loss_weights(double lr, double lr_start, const double *w_start, const double *w_end, int32_t normalised,
+                       double *w_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -157,6 +157,62 @@ class NepModel:
         return loss, g
 
 
+def adam_step(params, grad, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step (Sec. 3.3.1) in place on float32 CUDA tensors; t >= 1."""
+    for x in (params, grad, m, v):
+        if x.dtype != torch.float32 or not x.is_cuda or not x.is_contiguous() or x.numel() != params.numel():
+            raise ValueError("adam_step needs contiguous float32 CUDA tensors of one size")
+    check(load().nepmi_adam_step(params.numel(), _ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(t), float(lr),
+                                 float(beta1), float(beta2), float(eps), _stream()))
+
+
+def lr_schedule(step, warmup_steps, total_steps, lr_start, lr_end, start_factor=1e-4):
+    """Learning rate at 0-based step (Sec. 3.3.2): linear warmup, then cosine annealing."""
+    out = C.c_double()
+    check(load().nepmi_lr_schedule(int(step), int(warmup_steps), int(total_steps), float(lr_start), float(lr_end),
+                                   float(start_factor), C.byref(out)))
+    return out.value
+
+
+def loss_weights(lr, lr_start, w_start, w_end, normalised=True):
+    """Energy, force, virial loss weights at learning rate lr (Sec. 3.3.3)."""
+    a, b, w = (C.c_double * 3)(*w_start), (C.c_double * 3)(*w_end), (C.c_double * 3)()
+    check(load().nepmi_loss_weights(float(lr), float(lr_start), a, b, 1 if normalised else 0, w))
+    return tuple(w)
+
+
+class Trainer:
+    """The training loop of Sec. 3.3 on one batch source: each step computes
+    the loss of Eq. 18-21 with the step's dynamic weights and its parameter
+    gradient, then one Adam step at the scheduled learning rate.  Parameters,
+    moments and gradient stay on the GPU."""
+
+    def __init__(self, model: NepModel, total_steps, warmup_steps, lr_start=1e-3, lr_end=1e-5,
+                 w_start=(1.0, 1.0, 0.1), w_end=(1.0, 1.0, 0.1), normalised=True, loss_form=1,
+                 betas=(0.9, 0.999), eps=1e-8):
+        self.model = model
+        self.params = model._params.clone()
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.t = 0
+        self.total_steps, self.warmup_steps = int(total_steps), int(warmup_steps)
+        self.lr_start, self.lr_end = float(lr_start), float(lr_end)
+        self.w_start, self.w_end, self.normalised = tuple(w_start), tuple(w_end), bool(normalised)
+        self.loss_form, self.betas, self.eps = int(loss_form), tuple(betas), float(eps)
+        self.last_grad = None
+
+    def step(self, batch: Batch, E_ref, F_ref, V_ref):
+        """One optimisation step; returns (loss parts (4,) float64 on the GPU, lr, weights)."""
+        lr = lr_schedule(self.t, self.warmup_steps, self.total_steps, self.lr_start, self.lr_end)
+        w = loss_weights(lr, self.lr_start, self.w_start, self.w_end, self.normalised)
+        loss, g = self.model.loss_grad(batch, E_ref, F_ref, V_ref, weights=w, loss_form=self.loss_form)
+        self.t += 1
+        self.last_grad = g
+        adam_step(self.params, g, self.m, self.v, self.t, lr, self.betas[0], self.betas[1], self.eps)
+        self.model.set_params(self.params)
+        return loss, lr, w
+
+
 class NepFunction(torch.autograd.Function):
     """(params, batch) -> (E, F, V) with a hand-written parameter backward.
 
