@@ -80,10 +80,11 @@ struct Cutoffs {
 // 26 - code is the exact negative of the shift of code.
 __device__ __forceinline__ void image_shift(const float* __restrict__ H, uint32_t code, float& sx, float& sy,
                                             float& sz) {
-  const uint32_t d0 = (code * 57u) >> 9;
-  const uint32_t r = code - 9u * d0;
-  const uint32_t d1 = (r * 11u) >> 5;
-  const uint32_t d2 = r - 3u * d1;
+  // 24-bit products (full-rate multiplies; every operand is below 2^9)
+  const uint32_t d0 = __umul24(code, 57u) >> 9;
+  const uint32_t r = code - __umul24(9u, d0);
+  const uint32_t d1 = __umul24(r, 11u) >> 5;
+  const uint32_t d2 = r - __umul24(3u, d1);
   const float w0 = (float)((int)d0 - 1);
   const float w1 = (float)((int)d1 - 1);
   const float w2 = (float)((int)d2 - 1);

@@ -42,40 +42,62 @@ __device__ __forceinline__ float tanh_fast(float x) {
   return fmaf(-2.0f, __builtin_amdgcn_rcpf(1.0f + e), 1.0f);
 }
 
-// Software-pipelined walk over one atom's column of a pair list.  A pair
-// needs two dependent loads (the list entry, then the neighbour's position);
-// the walker keeps the entry two pairs ahead and the position one pair ahead
-// in flight while the current pair is processed.  Usage, in iteration k:
-//   prefetch(k, ...) first, then use (e, x), then advance(...).
-struct PairWalk {
-  const uint32_t* __restrict__ list;
-  int64_t ns, p;
-  int n;
-  uint32_t e, e1;  // entries of pairs k and k + 1
-  float4 x;        // position (and species) of the neighbour of pair k
-  // Inside the loop the loads are unconditional, with the row clamped to the
-  // last valid one (n >= 1 there), so no branch splits the wavefront.
-  __device__ __forceinline__ PairWalk(const uint32_t* __restrict__ l, int64_t ns_, int64_t p_, int n_,
-                                      const float4* __restrict__ pos4)
-      : list(l), ns(ns_), p(p_), n(n_) {
-    e = 0u;
-    x = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (n > 0) {
-      e = list[p];
-      x = pos4[e & kNbrMask];
+// Software-pipelined walk over one atom's column of a pair list, calling
+// f(k, entry, neighbour position, aux entry) for k = 0 .. n-1 in order.
+// A pair needs two dependent loads: the list entry (a stream from HBM), then
+// the neighbour's position (a gather, mostly from L2).  Entries (and the
+// optional aux column of the same layout) are loaded DE pairs ahead and
+// positions DX pairs ahead.  The loop is unrolled by DE so that every ring
+// slot is a fixed register: no value is copied while its load is in flight,
+// so a load really has DE (or DX) pairs of work to arrive.  Rows are reached
+// by adding the column stride to a pointer, clamped at the last row, so the
+// loads are unconditional and always in bounds.  An empty list loads nothing.
+template <int DE, int DX, bool AUX, class F>
+__device__ __forceinline__ void walk_pairs(const uint32_t* __restrict__ list, const uint32_t* __restrict__ aux,
+                                           int64_t ns, int64_t p, int n, const float4* __restrict__ pos4, F&& f) {
+  static_assert(DX >= 1 && DX < DE && DE % DX == 0, "ring sizes");
+  if (n <= 0) return;
+  uint32_t e[DE], a[AUX ? DE : 1];
+  float4 x[DX];
+  const uint32_t* lp = list + p;
+  const uint32_t* ap = AUX ? aux + p : nullptr;
+#pragma unroll
+  for (int u = 0; u < DE; ++u) {
+    e[u] = *lp;
+    if constexpr (AUX) a[u] = *ap;
+    if (u + 1 < n) {
+      lp += ns;
+      if constexpr (AUX) ap += ns;
     }
-    e1 = n > 1 ? list[ns + p] : e;
   }
-  __device__ __forceinline__ void prefetch(int k, const float4* __restrict__ pos4, uint32_t& e2, float4& x1) const {
-    e2 = list[(int64_t)(k + 2 < n ? k + 2 : n - 1) * ns + p];
-    x1 = pos4[e1 & kNbrMask];
+  // lp (ap) now points at row min(DE, n - 1)
+#pragma unroll
+  for (int u = 0; u < DX; ++u) x[u] = pos4[e[u] & kNbrMask];
+  for (int k0 = 0; k0 < n; k0 += DE) {
+#pragma unroll
+    for (int u = 0; u < DE; ++u) {
+      const int k = k0 + u;
+      const uint32_t ek = e[u];
+      const uint32_t ak = AUX ? a[u] : 0u;
+      const float4 xk = x[u % DX];
+      // entry (and aux) of pair k + DE into the slot just read, then the
+      // position of pair k + DX, whose entry arrived DE - DX pairs ago
+      e[u] = *lp;
+      if constexpr (AUX) a[u] = *ap;
+      if (k + DE < n - 1) {
+        lp += ns;
+        if constexpr (AUX) ap += ns;
+      }
+      x[u % DX] = pos4[e[(u + DX) % DE] & kNbrMask];
+      if (k < n) f(k, ek, xk, ak);
+    }
   }
-  __device__ __forceinline__ void advance(uint32_t e2, float4 x1) {
-    e = e1;
-    e1 = e2;
-    x = x1;
-  }
-};
+}
+
+// Prefetch distances, measured at 900k atoms: entries 4 and positions 2
+// pairs ahead; deeper rings (6/2, 6/3, 8/2, 8/4) are no faster.
+constexpr int kWalkDE = 4;
+constexpr int kWalkDX = 2;
 
 __device__ __forceinline__ void load_cell(const CfgDev* __restrict__ cfgs, int c, float (&H)[9]) {
   if (c >= 0) {
@@ -130,13 +152,8 @@ __device__ __forceinline__ void angular_sums(const float4* __restrict__ pos4, co
   for (int nn = 0; nn < NH; ++nn)
 #pragma unroll
     for (int lm = 0; lm < K; ++lm) Sg[nn][lm] = 0.f;
-  PairWalk w(cnA, n_slots, p, nA, pos4);
-  for (int k = 0; k < nA; ++k) {
-    uint32_t e2;
-    float4 x1;
-    w.prefetch(k, pos4, e2, x1);
-    const PairVec v = pair_vec(w.e, w.x, xi, Hc);
-    w.advance(e2, x1);
+  walk_pairs<kWalkDE, kWalkDX, false>(cnA, nullptr, n_slots, p, nA, pos4, [&](int, uint32_t e, float4 xq, uint32_t) {
+    const PairVec v = pair_vec(e, xq, xi, Hc);
     const float inv = rsqrt_hw(v.d2);
     const RadialF f = radial_f(v.d2 * inv * rcA_inv);
     float Tk[BA];
@@ -156,7 +173,7 @@ __device__ __forceinline__ void angular_sums(const float4* __restrict__ pos4, co
     for (int nn = 0; nn < NH; ++nn)
 #pragma unroll
       for (int lm = 0; lm < K; ++lm) Sg[nn][lm] = fmaf(g[nn], P[lm], Sg[nn][lm]);
-  }
+  });
   constexpr Kappa<L> kap;
 #pragma unroll
   for (int nn = 0; nn < NH; ++nn)
@@ -233,28 +250,25 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
   if (active) {
     const int n = cntR[p];
     bool bad = false;
-    PairWalk w(nbrR, n_slots, p, n, pos4);
-    uint32_t rv = n > 0 ? vrev[p] : 0u;
+    uint32_t* cr = cnR + p;   // next free row of the compact radial list
+    uint32_t* ca = cnA + p;   // ... and of the compact angular list
+    uint32_t* cpa = cpA + p;
+    uint64_t* mw = amask + p;
     uint64_t mword = 0;  // bit k % 64: entry k of the Verlet list is in the compact angular list
-    for (int k = 0; k < n; ++k) {
-      uint32_t e2;
-      float4 x1;
-      w.prefetch(k, pos4, e2, x1);
-      const uint32_t rv1 = vrev[(int64_t)(k + 1 < n ? k + 1 : n - 1) * n_slots + p];
-      const uint32_t e = w.e;
-      const PairVec v = pair_vec(e, w.x, xi, Hc);
-      w.advance(e2, x1);
-      const uint32_t rvk = rv;
-      rv = rv1;
+    walk_pairs<kWalkDE, kWalkDX, true>(nbrR, vrev, n_slots, p, n, pos4, [&](int k, uint32_t e, float4 xq, uint32_t rvk) {
+      const PairVec v = pair_vec(e, xq, xi, Hc);
       if (v.d2 < cut.rcR2) {
-        cnR[(int64_t)nR * n_slots + p] = e;
+        *cr = e;
+        cr += n_slots;
         ++nR;
         if (v.d2 < cut.rcA2) {
           // within rc_angular now implies within rc_angular + skin at the
           // last build, so nA stays below capA and the reverse row exists
           if (rvk <= 0xFFFFu && nA < capA) {
-            cnA[(int64_t)nA * n_slots + p] = e;
-            cpA[(int64_t)nA * n_slots + p] = (uint32_t)k | (rvk << 16);
+            *ca = e;
+            *cpa = (uint32_t)k | (rvk << 16);
+            ca += n_slots;
+            cpa += n_slots;
             mword |= 1ull << (k & 63);
             ++nA;
           } else {
@@ -273,10 +287,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
         }
       }
       if ((k & 63) == 63 || k == n - 1) {
-        amask[(int64_t)(k >> 6) * n_slots + p] = mword;
+        *mw = mword;
+        mw += n_slots;
         mword = 0;
       }
-    }
+    });
     if (bad) atomicOr(&flags[kFlagAsym], 1);
   }
   if (in_range) {
@@ -475,16 +490,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
         for (int kk = 0; kk < BR; ++kk) mine[b * BR + kk] = aR[((int64_t)b * n_slots + p) * BR + kk];
     }
     const int n = ccR[p];
-    PairWalk w(cnR, n_slots, p, n, pos4);
-    for (int k = 0; k < n; ++k) {
-      uint32_t e2;
-      float4 x1;
-      w.prefetch(k, pos4, e2, x1);
-      const PairVec v = pair_vec(w.e, w.x, xi, Hc);
+    const float* aRz = aR + (int64_t)Zs * n_slots * BR;
+    walk_pairs<kWalkDE, kWalkDX, false>(cnR, nullptr, n_slots, p, n, pos4, [&](int, uint32_t e, float4 xq, uint32_t) {
+      const PairVec v = pair_vec(e, xq, xi, Hc);
       // the neighbour's adjoint row atil_j[Z_i] (part Z_i of the adjoint,
       // stored part-major so that a wavefront reads one compact array)
-      const float* ar = aR + ((int64_t)Zs * n_slots + v.q) * BR;
-      w.advance(e2, x1);
+      const float* ar = aRz + (int64_t)v.q * BR;
       const float inv = rsqrt_hw(v.d2);
       const RadialFD f = radial_fd(v.d2 * inv * rcR_inv, rcR_inv);
       float Tk[BR], Dk[BR];
@@ -520,7 +531,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
       Wr[3] = fmaf(-ax, v.ry, Wr[3]);
       Wr[4] = fmaf(-ax, v.rz, Wr[4]);
       Wr[5] = fmaf(-ay, v.rz, Wr[5]);
-    }
+    });
   }
 
   // ---- angular pairs, in NSPLIT groups of n (the virial continues from the
@@ -574,13 +585,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
     }
     // pair forces of this group: f = u sum_n g'_n Z_n + (I - u u^T) v / d,
     // Z_n = sum_lm sigma_nlm P_lm, v = sum_lm G_lm grad P_lm, G_lm = sum_n sigma_nlm g_n
-    PairWalk w(cnA, n_slots, p, nA, pos4);
-    for (int k = 0; k < nA; ++k) {
-      uint32_t e2;
-      float4 x1;
-      w.prefetch(k, pos4, e2, x1);
-      const PairVec v = pair_vec(w.e, w.x, xi, Hc);
-      w.advance(e2, x1);
+    float4* own = fA + p;  // i's compact slot k of the pair-force buffer
+    walk_pairs<kWalkDE, kWalkDX, false>(cnA, nullptr, n_slots, p, nA, pos4, [&](int, uint32_t e, float4 xq, uint32_t) {
+      const PairVec v = pair_vec(e, xq, xi, Hc);
       const float inv = rsqrt_hw(v.d2);
       const float ux = v.rx * inv, uy = v.ry * inv, uz = v.rz * inv;
       const RadialFD f = radial_fd(v.d2 * inv * rcA_inv, rcA_inv);
@@ -633,14 +640,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
       W[6] = fmaf(-fz, v.rx, W[6]); W[7] = fmaf(-fz, v.ry, W[7]); W[8] = fmaf(-fz, v.rz, W[8]);
       // dE_i/dr_ij (summed over the groups) stays in i's own compact slot,
       // where j's gather finds it
-      float4* own = fA + (int64_t)k * n_slots + p;
       if (h == 0) {
         *own = make_float4(fx, fy, fz, 0.f);
       } else {
         const float4 o = *own;
         *own = make_float4(o.x + fx, o.y + fy, o.z + fz, 0.f);
       }
-    }
+      own += n_slots;
+    });
   }
   frad[p] = make_float4(Fx, Fy, Fz, 0.f);
   const int i = orig[p];
