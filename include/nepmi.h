@@ -207,6 +207,41 @@ int nepmi_md_step_timed(nepmi_md *md, int32_t n_steps, double *ms_per_launch, vo
 int nepmi_md_time_kernels(nepmi_md *md, int32_t reps, double *ms_per_launch, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Float64 variant (Sec. 3.2: every operator exists in float32 and float64).
+ *
+ * Same quantities as nepmi_compute and nepmi_backward_params, with positions,
+ * parameters and every result in float64 and all arithmetic in float64.
+ * Parameters are passed per call (dev_params: device double[param_count], the
+ * layout of nepmi_set_params), so a caller can differentiate with respect to
+ * them; the model handle supplies the shape, the cutoffs and the work space.
+ * Neighbour lists come from the float32 rounding of the positions with a
+ * 0.01 A skin; every pair is then tested against the cutoffs in float64.
+ * Cell widths must be at least 2 (rc_radial + 0.01) (NEPMI_CELL_TOO_SMALL).
+ * Asynchronous on `stream`.
+ * ------------------------------------------------------------------------- */
+
+/* Energy, forces and virial of a batch (Eq. 1-4) in float64.
+ * atom_off host int64[n_cfg + 1], cells host double[9 * n_cfg] (rows a, b, c);
+ * dev_pos double[N*3], dev_species int32[N] (caller order);
+ * outputs: dev_energy double[n_cfg], dev_forces double[N*3],
+ * dev_virial double[9 * n_cfg] (row-major, sum over atoms of
+ * -dE_i/dr_ij (x) r_ij), dev_atom_energy double[N] or NULL. */
+int nepmi_compute_f64(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, const double *cells,
+                      const double *dev_pos, const int32_t *dev_species, const double *dev_params, double *dev_energy,
+                      double *dev_forces, double *dev_virial, double *dev_atom_energy, void *stream);
+
+/* Vector-Jacobian product of (E, F, V) with respect to the parameters, in
+ * float64 (the float64 twin of nepmi_backward_params):
+ *   dev_grad[p] = sum_c ebar_c dE_c/dtheta_p + sum_i lambda_i . dF_i/dtheta_p
+ *               + sum_c mu_c : dV_c/dtheta_p
+ * dev_ebar double[n_cfg], dev_lambda double[N*3], dev_mu double[9*n_cfg];
+ * dev_grad double[param_count] is overwritten. */
+int nepmi_backward_params_f64(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, const double *cells,
+                              const double *dev_pos, const int32_t *dev_species, const double *dev_params,
+                              const double *dev_ebar, const double *dev_lambda, const double *dev_mu,
+                              double *dev_grad, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Optimisation protocol (Sec. 3.3).
  * ------------------------------------------------------------------------- */
 

@@ -59,6 +59,8 @@ SIGNATURES = [
     ("nepmi_backward_params", C.c_int, [_vp, _i32, _i64p, _dp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     ("nepmi_loss_grad", C.c_int, [_vp, _i32, _i64p, _dp, _vp, _vp, _vp, _vp, _vp, _dp, _i32, _vp, _vp, _vp]),
     ("nepmi_md_create", C.c_int, [_vp, _i32, _i64p, _dp, _vp, _vp, _vp, _dp, _d, _d, C.POINTER(_vp), _vp]),
+    ("nepmi_compute_f64", C.c_int, [_vp, _i32, _i64p, _dp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    ("nepmi_backward_params_f64", C.c_int, [_vp, _i32, _i64p, _dp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     ("nepmi_adam_step", C.c_int, [C.c_int64, _vp, _vp, _vp, _vp, C.c_int64, C.c_double, C.c_double, C.c_double,
                                   C.c_double, _vp]),
     ("nepmi_lr_schedule", C.c_int, [C.c_int64, C.c_int64, C.c_int64, C.c_double, C.c_double, C.c_double, _dp]),

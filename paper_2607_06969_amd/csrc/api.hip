@@ -19,7 +19,8 @@ int hip_fail(hipError_t e, const char* what) {
 template <class S>
 static const Ops* ops_of() {
   static const Ops o = {&Launch<S>::desc, &Launch<S>::force, &Launch<S>::gather, &Launch<S>::derive,
-                        &TrainLaunch<S>::seeds, &TrainLaunch<S>::backward, S::T, S::NR, S::NA, S::BR, S::BA, S::L,
+                        &TrainLaunch<S>::seeds, &TrainLaunch<S>::backward,
+                        &TrainLaunch<S>::forward64, &TrainLaunch<S>::backward64, S::T, S::NR, S::NA, S::BR, S::BA, S::L,
                         S::D, S::NANG, S::H, S::K, S::P, S::P + S::PCR + S::PCA};
   return &o;
 }
@@ -66,9 +67,9 @@ static int64_t param_count(const nepmi_hparams& h) {
 using namespace nepmi;
 
 int nepmi_model::prepare(int n_cfg, const int64_t* atom_off, const double* cells, const float* pos,
-                         const int32_t* species, hipStream_t st) {
+                         const int32_t* species, hipStream_t st, double skin) {
   int rc;
-  if ((rc = nbr.setup(n_cfg, atom_off, cells, ops->T, hp.rc_radial, hp.rc_angular, 0.0, st))) return rc;
+  if ((rc = nbr.setup(n_cfg, atom_off, cells, ops->T, hp.rc_radial, hp.rc_angular, skin, st))) return rc;
   if ((rc = nbr.build(st, pos, species))) return rc;
   if ((rc = red.setup(n_cfg, atom_off, st))) return rc;
   const size_t ns = (size_t)nbr.n_slots, N = (size_t)(nbr.N > 0 ? nbr.N : 1);

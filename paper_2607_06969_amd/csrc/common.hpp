@@ -14,6 +14,51 @@
 
 namespace nepmi {
 
+// ------------------------------------------------- precision-generic helpers
+
+// The float32 kernels and the float64 variants share the templated helpers
+// below; each call resolves to the single- or double-precision function.
+__device__ __forceinline__ float fma_(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fma_(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ float sqrt_(float x) { return sqrtf(x); }
+__device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
+__device__ __forceinline__ float tanh_(float x) { return tanhf(x); }
+__device__ __forceinline__ double tanh_(double x) { return tanh(x); }
+__device__ __forceinline__ float cospi_(float x) { return cospif(x); }
+__device__ __forceinline__ double cospi_(double x) { return cospi(x); }
+__device__ __forceinline__ void sincospi_(float x, float* s, float* c) { sincospif(x, s, c); }
+__device__ __forceinline__ void sincospi_(double x, double* s, double* c) { sincospi(x, s, c); }
+
+// Position (x, y, z) and species of a slot: float4 with the species bits in w,
+// or double4 with the species value in w.
+template <class R>
+struct Vec4T;
+template <>
+struct Vec4T<float> {
+  using type = float4;
+};
+template <>
+struct Vec4T<double> {
+  using type = double4;
+};
+template <class R>
+using Vec4 = typename Vec4T<R>::type;
+__device__ __forceinline__ int species_of(const float4& x) { return __float_as_int(x.w); }
+__device__ __forceinline__ int species_of(const double4& x) { return (int)x.w; }
+template <class R>
+__device__ __forceinline__ Vec4<R> make_v4(R x, R y, R z, R w);
+template <>
+__device__ __forceinline__ float4 make_v4<float>(float x, float y, float z, float w) {
+  return make_float4(x, y, z, w);
+}
+template <>
+__device__ __forceinline__ double4 make_v4<double>(double x, double y, double z, double w) {
+  return make_double4(x, y, z, w);
+}
+
+template <class R>
+struct ShC;  // constants of the real spherical harmonics, per precision
+
 // ---------------------------------------------------------------- model shape
 
 // Compile-time NEP shape.  Kernels keep per-atom accumulators in registers, so
@@ -65,11 +110,13 @@ struct CfgDev {
 };
 
 // Runtime (non-shape) parameters of a launch.
-struct Cutoffs {
-  float rcR, rcA;        // cutoffs of the potential
-  float rcR2, rcA2;      // squared
-  float rclR2, rclA2;    // squared list cutoffs (cutoff + skin)
+template <class R>
+struct CutoffsT {
+  R rcR, rcA;        // cutoffs of the potential
+  R rcR2, rcA2;      // squared
+  R rclR2, rclA2;    // squared list cutoffs (cutoff + skin)
 };
+using Cutoffs = CutoffsT<float>;
 
 // ------------------------------------------------------------ device helpers
 
@@ -78,16 +125,16 @@ struct Cutoffs {
 // (exact for code < 27: floor(57 c / 512) = floor(c / 9), floor(11 r / 32) =
 // floor(r / 3) for r < 9).  Every w_a is -1, 0 or 1, so the shift of code
 // 26 - code is the exact negative of the shift of code.
-__device__ __forceinline__ void image_shift(const float* __restrict__ H, uint32_t code, float& sx, float& sy,
-                                            float& sz) {
+template <class R>
+__device__ __forceinline__ void image_shift(const R* __restrict__ H, uint32_t code, R& sx, R& sy, R& sz) {
   // 24-bit products (full-rate multiplies; every operand is below 2^9)
   const uint32_t d0 = __umul24(code, 57u) >> 9;
   const uint32_t r = code - __umul24(9u, d0);
   const uint32_t d1 = __umul24(r, 11u) >> 5;
   const uint32_t d2 = r - __umul24(3u, d1);
-  const float w0 = (float)((int)d0 - 1);
-  const float w1 = (float)((int)d1 - 1);
-  const float w2 = (float)((int)d2 - 1);
+  const R w0 = (R)((int)d0 - 1);
+  const R w1 = (R)((int)d1 - 1);
+  const R w2 = (R)((int)d2 - 1);
   sx = w0 * H[0] + w1 * H[3] + w2 * H[6];
   sy = w0 * H[1] + w1 * H[4] + w2 * H[7];
   sz = w0 * H[2] + w1 * H[5] + w2 * H[8];
@@ -96,53 +143,55 @@ __device__ __forceinline__ void image_shift(const float* __restrict__ H, uint32_
 // Chebyshev radial basis of Eq. 12-15:
 //   x = 2 (d/rc - 1)^2 - 1,  f_c = (1 + cos(pi d/rc)) / 2,  Q_k = (T_k(x) + 1)/2 f_c.
 // Valid for d < rc (the caller tests the cutoff).
-template <int B>
-__device__ __forceinline__ void cheb_basis(float d, float rc_inv, float (&Q)[B]) {
-  const float t = d * rc_inv;
-  const float y = t - 1.0f;
-  const float x = 2.0f * y * y - 1.0f;
-  const float fc = 0.5f * (1.0f + cospif(t));
-  const float hf = 0.5f * fc;
-  float tm = 1.0f, tk = x;
+template <int B, class R>
+__device__ __forceinline__ void cheb_basis(R d, R rc_inv, R (&Q)[B]) {
+  using C = ShC<R>;
+  const R t = d * rc_inv;
+  const R y = t - R(1.0);
+  const R x = R(2.0) * y * y - R(1.0);
+  const R fc = R(0.5) * (R(1.0) + cospi_(t));
+  const R hf = R(0.5) * fc;
+  R tm = R(1.0), tk = x;
   Q[0] = fc;
-  if (B > 1) Q[1] = hf * (x + 1.0f);
+  if (B > 1) Q[1] = hf * (x + R(1.0));
 #pragma unroll
   for (int k = 2; k < B; ++k) {
-    const float tn = 2.0f * x * tk - tm;
+    const R tn = R(2.0) * x * tk - tm;
     tm = tk;
     tk = tn;
-    Q[k] = hf * (tn + 1.0f);
+    Q[k] = hf * (tn + R(1.0));
   }
 }
 
 // Basis and its radial derivative dQ_k/dd.
-template <int B>
-__device__ __forceinline__ void cheb_basis_d(float d, float rc_inv, float (&Q)[B], float (&dQ)[B]) {
-  const float t = d * rc_inv;
-  const float y = t - 1.0f;
-  const float x = 2.0f * y * y - 1.0f;
-  const float dx = 4.0f * y * rc_inv;
-  float sn, cs;
-  sincospif(t, &sn, &cs);
-  const float fc = 0.5f * (1.0f + cs);
-  const float dfc = -0.5f * 3.14159265358979323846f * rc_inv * sn;
-  float tm = 1.0f, tk = x, dtm = 0.0f, dtk = 1.0f;
+template <int B, class R>
+__device__ __forceinline__ void cheb_basis_d(R d, R rc_inv, R (&Q)[B], R (&dQ)[B]) {
+  using C = ShC<R>;
+  const R t = d * rc_inv;
+  const R y = t - R(1.0);
+  const R x = R(2.0) * y * y - R(1.0);
+  const R dx = R(4.0) * y * rc_inv;
+  R sn, cs;
+  sincospi_(t, &sn, &cs);
+  const R fc = R(0.5) * (R(1.0) + cs);
+  const R dfc = -R(0.5) * C::pi * rc_inv * sn;
+  R tm = R(1.0), tk = x, dtm = R(0.0), dtk = R(1.0);
   Q[0] = fc;
   dQ[0] = dfc;
   if (B > 1) {
-    Q[1] = 0.5f * (x + 1.0f) * fc;
-    dQ[1] = 0.5f * (dx * fc + (x + 1.0f) * dfc);
+    Q[1] = R(0.5) * (x + R(1.0)) * fc;
+    dQ[1] = R(0.5) * (dx * fc + (x + R(1.0)) * dfc);
   }
 #pragma unroll
   for (int k = 2; k < B; ++k) {
-    const float tn = 2.0f * x * tk - tm;
-    const float dtn = 2.0f * tk + 2.0f * x * dtk - dtm;
+    const R tn = R(2.0) * x * tk - tm;
+    const R dtn = R(2.0) * tk + R(2.0) * x * dtk - dtm;
     tm = tk;
     tk = tn;
     dtm = dtk;
     dtk = dtn;
-    Q[k] = 0.5f * (tn + 1.0f) * fc;
-    dQ[k] = 0.5f * (dtn * dx * fc + (tn + 1.0f) * dfc);
+    Q[k] = R(0.5) * (tn + R(1.0)) * fc;
+    dQ[k] = R(0.5) * (dtn * dx * fc + (tn + R(1.0)) * dfc);
   }
 }
 
@@ -160,9 +209,14 @@ __device__ __forceinline__ int64_t xcd_tile() {
 
 // |r|^2 with a fixed operation order (fused), shared by every kernel that
 // compares pair distances so that all of them agree on which pairs are in.
-__device__ __forceinline__ float pair_d2(float rx, float ry, float rz) {
-  return fmaf(rz, rz, fmaf(ry, ry, rx * rx));
+template <class R>
+__device__ __forceinline__ R pair_d2(R rx, R ry, R rz) {
+  return fma_(rz, rz, fma_(ry, ry, rx * rx));
 }
+
+// Lattice rows of a configuration in the precision of the caller.
+__device__ __forceinline__ const float* cell_rows(const CfgDev& C, float) { return C.H; }
+__device__ __forceinline__ const double* cell_rows(const CfgDev& C, double) { return C.Hd; }
 
 // 1/sqrt(x) with the hardware reciprocal square root (1 ulp).
 __device__ __forceinline__ float rsqrt_hw(float x) { return __builtin_amdgcn_rsqf(x); }
@@ -284,41 +338,86 @@ constexpr float k44 = 0.625835735449176135f;    // (3/16) sqrt(35/pi)
 constexpr float k44s = 2.503342941796704538f;   // (3/4) sqrt(35/pi)
 }  // namespace sh
 
-template <int L>
-__device__ __forceinline__ void real_sph(float x, float y, float z, float (&Y)[L * L + 2 * L]) {
-  using namespace sh;
-  Y[0] = c1 * z;
-  Y[1] = c1 * x;
-  Y[2] = c1 * y;
+// Precision traits of the templated helpers: the float members are the float
+// constants above, the double members the same quantities to double precision.
+template <class R>
+struct ShC;
+template <>
+struct ShC<float> {
+  static constexpr float c1 = sh::c1;
+  static constexpr float k20 = sh::k20;
+  static constexpr float k21 = sh::k21;
+  static constexpr float k22 = sh::k22;
+  static constexpr float k30 = sh::k30;
+  static constexpr float k31 = sh::k31;
+  static constexpr float k32 = sh::k32;
+  static constexpr float k32s = sh::k32s;
+  static constexpr float k33 = sh::k33;
+  static constexpr float k40 = sh::k40;
+  static constexpr float k41 = sh::k41;
+  static constexpr float k42 = sh::k42;
+  static constexpr float k42s = sh::k42s;
+  static constexpr float k43 = sh::k43;
+  static constexpr float k44 = sh::k44;
+  static constexpr float k44s = sh::k44s;
+  static constexpr float pi = 3.14159265358979323846f;
+};
+template <>
+struct ShC<double> {
+  static constexpr double c1 = 0.48860251190291992158;
+  static constexpr double k20 = 0.31539156525252000603;
+  static constexpr double k21 = 1.09254843059207907054;
+  static constexpr double k22 = 0.54627421529603953527;
+  static constexpr double k30 = 0.37317633259011539141;
+  static constexpr double k31 = 0.45704579946446573615;
+  static constexpr double k32 = 1.44530572132027702769;
+  static constexpr double k32s = 2.89061144264055405538;
+  static constexpr double k33 = 0.59004358992664351034;
+  static constexpr double k40 = 0.10578554691520430380;
+  static constexpr double k41 = 0.66904654355728916795;
+  static constexpr double k42 = 0.47308734787878000904;
+  static constexpr double k42s = 0.94617469575756001809;
+  static constexpr double k43 = 1.77013076977993053103;
+  static constexpr double k44 = 0.62583573544917613458;
+  static constexpr double k44s = 2.50334294179670453834;
+  static constexpr double pi = 3.14159265358979323846;
+};
+
+template <int L, class R>
+__device__ __forceinline__ void real_sph(R x, R y, R z, R (&Y)[L * L + 2 * L]) {
+  using C = ShC<R>;
+  Y[0] = C::c1 * z;
+  Y[1] = C::c1 * x;
+  Y[2] = C::c1 * y;
   if constexpr (L >= 2) {
-    const float z2 = z * z;
-    Y[3] = k20 * (3.0f * z2 - 1.0f);
-    Y[4] = k21 * x * z;
-    Y[5] = k21 * y * z;
-    Y[6] = k22 * (x * x - y * y);
-    Y[7] = k21 * x * y;
+    const R z2 = z * z;
+    Y[3] = C::k20 * (R(3.0) * z2 - R(1.0));
+    Y[4] = C::k21 * x * z;
+    Y[5] = C::k21 * y * z;
+    Y[6] = C::k22 * (x * x - y * y);
+    Y[7] = C::k21 * x * y;
     if constexpr (L >= 3) {
-      const float x2my2 = x * x - y * y;
-      const float p = 5.0f * z2 - 1.0f;
-      Y[8] = k30 * z * (5.0f * z2 - 3.0f);
-      Y[9] = k31 * x * p;
-      Y[10] = k31 * y * p;
-      Y[11] = k32 * z * x2my2;
-      Y[12] = k32s * x * y * z;
-      Y[13] = k33 * x * (x * x - 3.0f * y * y);
-      Y[14] = k33 * y * (3.0f * x * x - y * y);
+      const R x2my2 = x * x - y * y;
+      const R p = R(5.0) * z2 - R(1.0);
+      Y[8] = C::k30 * z * (R(5.0) * z2 - R(3.0));
+      Y[9] = C::k31 * x * p;
+      Y[10] = C::k31 * y * p;
+      Y[11] = C::k32 * z * x2my2;
+      Y[12] = C::k32s * x * y * z;
+      Y[13] = C::k33 * x * (x * x - R(3.0) * y * y);
+      Y[14] = C::k33 * y * (R(3.0) * x * x - y * y);
       if constexpr (L >= 4) {
-        const float q = 7.0f * z2 - 3.0f;
-        const float r = 7.0f * z2 - 1.0f;
-        Y[15] = k40 * (35.0f * z2 * z2 - 30.0f * z2 + 3.0f);
-        Y[16] = k41 * x * z * q;
-        Y[17] = k41 * y * z * q;
-        Y[18] = k42 * x2my2 * r;
-        Y[19] = k42s * x * y * r;
-        Y[20] = k43 * x * z * (x * x - 3.0f * y * y);
-        Y[21] = k43 * y * z * (3.0f * x * x - y * y);
-        Y[22] = k44 * (x2my2 * x2my2 - 4.0f * x * x * y * y);
-        Y[23] = k44s * x * y * x2my2;
+        const R q = R(7.0) * z2 - R(3.0);
+        const R r = R(7.0) * z2 - R(1.0);
+        Y[15] = C::k40 * (R(35.0) * z2 * z2 - R(30.0) * z2 + R(3.0));
+        Y[16] = C::k41 * x * z * q;
+        Y[17] = C::k41 * y * z * q;
+        Y[18] = C::k42 * x2my2 * r;
+        Y[19] = C::k42s * x * y * r;
+        Y[20] = C::k43 * x * z * (x * x - R(3.0) * y * y);
+        Y[21] = C::k43 * y * z * (R(3.0) * x * x - y * y);
+        Y[22] = C::k44 * (x2my2 * x2my2 - R(4.0) * x * x * y * y);
+        Y[23] = C::k44s * x * y * x2my2;
       }
     }
   }
@@ -327,106 +426,106 @@ __device__ __forceinline__ void real_sph(float x, float y, float z, float (&Y)[L
 // g = sum_lm G_lm grad_u P_lm(u), where P_lm is the polynomial of real_sph
 // (extended off the unit sphere).  The gradient of Y_lm(r/|r|) with respect to
 // r is (I - u u^T) grad_u P_lm / |r|; the caller applies that projection.
-template <int L>
-__device__ __forceinline__ void real_sph_grad_dot(float x, float y, float z, const float (&G)[L * L + 2 * L],
-                                                  float& gx, float& gy, float& gz) {
-  using namespace sh;
-  gx = c1 * G[1];
-  gy = c1 * G[2];
-  gz = c1 * G[0];
+template <int L, class R>
+__device__ __forceinline__ void real_sph_grad_dot(R x, R y, R z, const R (&G)[L * L + 2 * L],
+                                                  R& gx, R& gy, R& gz) {
+  using C = ShC<R>;
+  gx = C::c1 * G[1];
+  gy = C::c1 * G[2];
+  gz = C::c1 * G[0];
   if constexpr (L >= 2) {
-    gz += 6.0f * k20 * z * G[3];
-    gx += k21 * z * G[4];
-    gz += k21 * x * G[4];
-    gy += k21 * z * G[5];
-    gz += k21 * y * G[5];
-    gx += 2.0f * k22 * x * G[6];
-    gy -= 2.0f * k22 * y * G[6];
-    gx += k21 * y * G[7];
-    gy += k21 * x * G[7];
+    gz += R(6.0) * C::k20 * z * G[3];
+    gx += C::k21 * z * G[4];
+    gz += C::k21 * x * G[4];
+    gy += C::k21 * z * G[5];
+    gz += C::k21 * y * G[5];
+    gx += R(2.0) * C::k22 * x * G[6];
+    gy -= R(2.0) * C::k22 * y * G[6];
+    gx += C::k21 * y * G[7];
+    gy += C::k21 * x * G[7];
     if constexpr (L >= 3) {
-      const float z2 = z * z, x2 = x * x, y2 = y * y;
-      const float p = 5.0f * z2 - 1.0f;
-      gz += k30 * (15.0f * z2 - 3.0f) * G[8];
-      gx += k31 * p * G[9];
-      gz += 10.0f * k31 * x * z * G[9];
-      gy += k31 * p * G[10];
-      gz += 10.0f * k31 * y * z * G[10];
-      gx += 2.0f * k32 * x * z * G[11];
-      gy -= 2.0f * k32 * y * z * G[11];
-      gz += k32 * (x2 - y2) * G[11];
-      gx += k32s * y * z * G[12];
-      gy += k32s * x * z * G[12];
-      gz += k32s * x * y * G[12];
-      gx += 3.0f * k33 * (x2 - y2) * G[13];
-      gy -= 6.0f * k33 * x * y * G[13];
-      gx += 6.0f * k33 * x * y * G[14];
-      gy += 3.0f * k33 * (x2 - y2) * G[14];
+      const R z2 = z * z, x2 = x * x, y2 = y * y;
+      const R p = R(5.0) * z2 - R(1.0);
+      gz += C::k30 * (R(15.0) * z2 - R(3.0)) * G[8];
+      gx += C::k31 * p * G[9];
+      gz += R(10.0) * C::k31 * x * z * G[9];
+      gy += C::k31 * p * G[10];
+      gz += R(10.0) * C::k31 * y * z * G[10];
+      gx += R(2.0) * C::k32 * x * z * G[11];
+      gy -= R(2.0) * C::k32 * y * z * G[11];
+      gz += C::k32 * (x2 - y2) * G[11];
+      gx += C::k32s * y * z * G[12];
+      gy += C::k32s * x * z * G[12];
+      gz += C::k32s * x * y * G[12];
+      gx += R(3.0) * C::k33 * (x2 - y2) * G[13];
+      gy -= R(6.0) * C::k33 * x * y * G[13];
+      gx += R(6.0) * C::k33 * x * y * G[14];
+      gy += R(3.0) * C::k33 * (x2 - y2) * G[14];
       if constexpr (L >= 4) {
-        const float q = 7.0f * z2 - 3.0f;
-        const float r = 7.0f * z2 - 1.0f;
-        gz += k40 * (140.0f * z2 * z - 60.0f * z) * G[15];
-        gx += k41 * z * q * G[16];
-        gz += k41 * x * (21.0f * z2 - 3.0f) * G[16];
-        gy += k41 * z * q * G[17];
-        gz += k41 * y * (21.0f * z2 - 3.0f) * G[17];
-        gx += 2.0f * k42 * x * r * G[18];
-        gy -= 2.0f * k42 * y * r * G[18];
-        gz += 14.0f * k42 * z * (x2 - y2) * G[18];
-        gx += k42s * y * r * G[19];
-        gy += k42s * x * r * G[19];
-        gz += 14.0f * k42s * x * y * z * G[19];
-        gx += 3.0f * k43 * z * (x2 - y2) * G[20];
-        gy -= 6.0f * k43 * x * y * z * G[20];
-        gz += k43 * x * (x2 - 3.0f * y2) * G[20];
-        gx += 6.0f * k43 * x * y * z * G[21];
-        gy += 3.0f * k43 * z * (x2 - y2) * G[21];
-        gz += k43 * y * (3.0f * x2 - y2) * G[21];
-        gx += 4.0f * k44 * x * (x2 - 3.0f * y2) * G[22];
-        gy += 4.0f * k44 * y * (y2 - 3.0f * x2) * G[22];
-        gx += k44s * y * (3.0f * x2 - y2) * G[23];
-        gy += k44s * x * (x2 - 3.0f * y2) * G[23];
+        const R q = R(7.0) * z2 - R(3.0);
+        const R r = R(7.0) * z2 - R(1.0);
+        gz += C::k40 * (R(140.0) * z2 * z - R(60.0) * z) * G[15];
+        gx += C::k41 * z * q * G[16];
+        gz += C::k41 * x * (R(21.0) * z2 - R(3.0)) * G[16];
+        gy += C::k41 * z * q * G[17];
+        gz += C::k41 * y * (R(21.0) * z2 - R(3.0)) * G[17];
+        gx += R(2.0) * C::k42 * x * r * G[18];
+        gy -= R(2.0) * C::k42 * y * r * G[18];
+        gz += R(14.0) * C::k42 * z * (x2 - y2) * G[18];
+        gx += C::k42s * y * r * G[19];
+        gy += C::k42s * x * r * G[19];
+        gz += R(14.0) * C::k42s * x * y * z * G[19];
+        gx += R(3.0) * C::k43 * z * (x2 - y2) * G[20];
+        gy -= R(6.0) * C::k43 * x * y * z * G[20];
+        gz += C::k43 * x * (x2 - R(3.0) * y2) * G[20];
+        gx += R(6.0) * C::k43 * x * y * z * G[21];
+        gy += R(3.0) * C::k43 * z * (x2 - y2) * G[21];
+        gz += C::k43 * y * (R(3.0) * x2 - y2) * G[21];
+        gx += R(4.0) * C::k44 * x * (x2 - R(3.0) * y2) * G[22];
+        gy += R(4.0) * C::k44 * y * (y2 - R(3.0) * x2) * G[22];
+        gx += C::k44s * y * (R(3.0) * x2 - y2) * G[23];
+        gy += C::k44s * x * (x2 - R(3.0) * y2) * G[23];
       }
     }
   }
 }
 
 // Dl[lm] = w . grad_u P_lm(u) for every component (P_lm as in real_sph).
-template <int L>
-__device__ __forceinline__ void real_sph_dir(float x, float y, float z, float wx, float wy, float wz,
-                                             float (&Dl)[L * L + 2 * L]) {
-  using namespace sh;
-  Dl[0] = c1 * wz;
-  Dl[1] = c1 * wx;
-  Dl[2] = c1 * wy;
+template <int L, class R>
+__device__ __forceinline__ void real_sph_dir(R x, R y, R z, R wx, R wy, R wz,
+                                             R (&Dl)[L * L + 2 * L]) {
+  using C = ShC<R>;
+  Dl[0] = C::c1 * wz;
+  Dl[1] = C::c1 * wx;
+  Dl[2] = C::c1 * wy;
   if constexpr (L >= 2) {
-    Dl[3] = 6.0f * k20 * z * wz;
-    Dl[4] = k21 * (z * wx + x * wz);
-    Dl[5] = k21 * (z * wy + y * wz);
-    Dl[6] = 2.0f * k22 * (x * wx - y * wy);
-    Dl[7] = k21 * (y * wx + x * wy);
+    Dl[3] = R(6.0) * C::k20 * z * wz;
+    Dl[4] = C::k21 * (z * wx + x * wz);
+    Dl[5] = C::k21 * (z * wy + y * wz);
+    Dl[6] = R(2.0) * C::k22 * (x * wx - y * wy);
+    Dl[7] = C::k21 * (y * wx + x * wy);
     if constexpr (L >= 3) {
-      const float z2 = z * z, x2 = x * x, y2 = y * y;
-      const float p = 5.0f * z2 - 1.0f;
-      Dl[8] = k30 * (15.0f * z2 - 3.0f) * wz;
-      Dl[9] = k31 * (p * wx + 10.0f * x * z * wz);
-      Dl[10] = k31 * (p * wy + 10.0f * y * z * wz);
-      Dl[11] = k32 * (2.0f * x * z * wx - 2.0f * y * z * wy + (x2 - y2) * wz);
-      Dl[12] = k32s * (y * z * wx + x * z * wy + x * y * wz);
-      Dl[13] = k33 * (3.0f * (x2 - y2) * wx - 6.0f * x * y * wy);
-      Dl[14] = k33 * (6.0f * x * y * wx + 3.0f * (x2 - y2) * wy);
+      const R z2 = z * z, x2 = x * x, y2 = y * y;
+      const R p = R(5.0) * z2 - R(1.0);
+      Dl[8] = C::k30 * (R(15.0) * z2 - R(3.0)) * wz;
+      Dl[9] = C::k31 * (p * wx + R(10.0) * x * z * wz);
+      Dl[10] = C::k31 * (p * wy + R(10.0) * y * z * wz);
+      Dl[11] = C::k32 * (R(2.0) * x * z * wx - R(2.0) * y * z * wy + (x2 - y2) * wz);
+      Dl[12] = C::k32s * (y * z * wx + x * z * wy + x * y * wz);
+      Dl[13] = C::k33 * (R(3.0) * (x2 - y2) * wx - R(6.0) * x * y * wy);
+      Dl[14] = C::k33 * (R(6.0) * x * y * wx + R(3.0) * (x2 - y2) * wy);
       if constexpr (L >= 4) {
-        const float q = 7.0f * z2 - 3.0f;
-        const float r = 7.0f * z2 - 1.0f;
-        Dl[15] = k40 * (140.0f * z2 * z - 60.0f * z) * wz;
-        Dl[16] = k41 * (z * q * wx + x * (21.0f * z2 - 3.0f) * wz);
-        Dl[17] = k41 * (z * q * wy + y * (21.0f * z2 - 3.0f) * wz);
-        Dl[18] = k42 * (2.0f * x * r * wx - 2.0f * y * r * wy + 14.0f * z * (x2 - y2) * wz);
-        Dl[19] = k42s * (y * r * wx + x * r * wy + 14.0f * x * y * z * wz);
-        Dl[20] = k43 * (3.0f * z * (x2 - y2) * wx - 6.0f * x * y * z * wy + x * (x2 - 3.0f * y2) * wz);
-        Dl[21] = k43 * (6.0f * x * y * z * wx + 3.0f * z * (x2 - y2) * wy + y * (3.0f * x2 - y2) * wz);
-        Dl[22] = k44 * (4.0f * x * (x2 - 3.0f * y2) * wx + 4.0f * y * (y2 - 3.0f * x2) * wy);
-        Dl[23] = k44s * (y * (3.0f * x2 - y2) * wx + x * (x2 - 3.0f * y2) * wy);
+        const R q = R(7.0) * z2 - R(3.0);
+        const R r = R(7.0) * z2 - R(1.0);
+        Dl[15] = C::k40 * (R(140.0) * z2 * z - R(60.0) * z) * wz;
+        Dl[16] = C::k41 * (z * q * wx + x * (R(21.0) * z2 - R(3.0)) * wz);
+        Dl[17] = C::k41 * (z * q * wy + y * (R(21.0) * z2 - R(3.0)) * wz);
+        Dl[18] = C::k42 * (R(2.0) * x * r * wx - R(2.0) * y * r * wy + R(14.0) * z * (x2 - y2) * wz);
+        Dl[19] = C::k42s * (y * r * wx + x * r * wy + R(14.0) * x * y * z * wz);
+        Dl[20] = C::k43 * (R(3.0) * z * (x2 - y2) * wx - R(6.0) * x * y * z * wy + x * (x2 - R(3.0) * y2) * wz);
+        Dl[21] = C::k43 * (R(6.0) * x * y * z * wx + R(3.0) * z * (x2 - y2) * wy + y * (R(3.0) * x2 - y2) * wz);
+        Dl[22] = C::k44 * (R(4.0) * x * (x2 - R(3.0) * y2) * wx + R(4.0) * y * (y2 - R(3.0) * x2) * wy);
+        Dl[23] = C::k44s * (y * (R(3.0) * x2 - y2) * wx + x * (x2 - R(3.0) * y2) * wy);
       }
     }
   }

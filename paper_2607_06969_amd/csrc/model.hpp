@@ -16,6 +16,9 @@ struct Ops {
   int (*seeds)(hipStream_t, const TrainSeedArgs&);
   int (*backward)(hipStream_t, TrainIO, const Cutoffs&, const float*, const float*, const int*, double*, double*,
                   float*);
+  int (*forward64)(hipStream_t, TrainIOT<double>, const CutoffsT<double>&, const F64Args&, double*, double*, double*);
+  int (*backward64)(hipStream_t, TrainIOT<double>, const CutoffsT<double>&, const F64Args&, const double*, const int*,
+                    double*, double*);
   int T, NR, NA, BR, BA, L, D, NANG, H, K;
   int64_t P;
   int64_t P_alloc;  // P parameters + the derived coefficient table
@@ -29,6 +32,12 @@ struct TrainBufs {
   DevBuf Sst, Sdt, q, qd, Pb, Pdn, abar, zneg, gw1, eat, qbR, FpR, GA, part, grad64, gradf;
 };
 
+// Buffers of the float64 variant (see train.hip).
+struct F64Bufs {
+  DevBuf posf, pos4, lam4, ebar1, mu0, Ei, Wi;
+  DevBuf Sst, Sdt, q, qd, Pb, Pdn, abar, zneg, gw1, eat, qbR, FpR, GA, part;
+};
+
 }  // namespace nepmi
 
 struct nepmi_model {
@@ -39,12 +48,14 @@ struct nepmi_model {
   nepmi::Reducer red;
   nepmi::DevBuf fp, aR, Ei, frad, fA, amask, Wi, Eproc;
   nepmi::TrainBufs tr;
+  nepmi::F64Bufs f64;
   int device = 0;
   int vdesc = 0, vforce = 0;  // kernel variants in use (see nepmi_autotune)
   bool pinned = false;        // variants chosen by nepmi_set_variants: MD creation keeps them
-  // Prepare the batch: neighbour lists, work buffers and reduction plan.
+  // Prepare the batch: neighbour lists (pairs within the cutoffs + skin),
+  // work buffers and reduction plan.
   int prepare(int n_cfg, const int64_t* atom_off, const double* cells, const float* pos, const int32_t* species,
-              hipStream_t st);
+              hipStream_t st, double skin = 0.0);
   nepmi::NepIO io(float* Fuser, float4* Fproc, float* qout);
 };
 

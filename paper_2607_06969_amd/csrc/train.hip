@@ -22,21 +22,23 @@ constexpr int kTB = 256;
 
 // Symmetric 3x3 as (xx, yy, zz, xy, xz, yz); full-matrix gradient convention
 // dE = sum_ab M_ab dA_ab.  A_n from S_n2m (l = 2 content of S).
-__device__ __forceinline__ void sym_from_s2(const float* s2, float (&A)[6]) {
-  const float azz = s2[0] * (1.0f / (3.0f * sh::k20));
-  const float dif = s2[3] * (1.0f / sh::k22);
-  A[0] = 0.5f * (dif - azz);
-  A[1] = -0.5f * (dif + azz);
+template <class R>
+__device__ __forceinline__ void sym_from_s2(const R* s2, R (&A)[6]) {
+  const R azz = s2[0] * (R(1.0) / (R(3.0) * ShC<R>::k20));
+  const R dif = s2[3] * (R(1.0) / ShC<R>::k22);
+  A[0] = R(0.5) * (dif - azz);
+  A[1] = -R(0.5) * (dif + azz);
   A[2] = azz;
-  A[3] = s2[4] * (1.0f / sh::k21);
-  A[4] = s2[1] * (1.0f / sh::k21);
-  A[5] = s2[2] * (1.0f / sh::k21);
+  A[3] = s2[4] * (R(1.0) / ShC<R>::k21);
+  A[4] = s2[1] * (R(1.0) / ShC<R>::k21);
+  A[5] = s2[2] * (R(1.0) / ShC<R>::k21);
 }
 
-__device__ __forceinline__ void sym_mul_sym(const float (&A)[6], const float (&B)[6], float (&C)[9]) {
+template <class R>
+__device__ __forceinline__ void sym_mul_sym(const R (&A)[6], const R (&B)[6], R (&C)[9]) {
   // C = A B (general 3x3, row-major)
-  const float a[9] = {A[0], A[3], A[4], A[3], A[1], A[5], A[4], A[5], A[2]};
-  const float b[9] = {B[0], B[3], B[4], B[3], B[1], B[5], B[4], B[5], B[2]};
+  const R a[9] = {A[0], A[3], A[4], A[3], A[1], A[5], A[4], A[5], A[2]};
+  const R b[9] = {B[0], B[3], B[4], B[3], B[1], B[5], B[4], B[5], B[2]};
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -44,21 +46,24 @@ __device__ __forceinline__ void sym_mul_sym(const float (&A)[6], const float (&B
 }
 
 // sum_ab M_ab N_ab for symmetric M, N
-__device__ __forceinline__ float sym_dot(const float (&M)[6], const float (&N)[6]) {
-  return M[0] * N[0] + M[1] * N[1] + M[2] * N[2] + 2.0f * (M[3] * N[3] + M[4] * N[4] + M[5] * N[5]);
+template <class R>
+__device__ __forceinline__ R sym_dot(const R (&M)[6], const R (&N)[6]) {
+  return M[0] * N[0] + M[1] * N[1] + M[2] * N[2] + R(2.0) * (M[3] * N[3] + M[4] * N[4] + M[5] * N[5]);
 }
 
 // Gradient with respect to S_n2m of a function whose gradient w.r.t. A is M.
-__device__ __forceinline__ void chain_s2(const float (&M)[6], float (&g)[5]) {
-  g[0] = (M[2] - 0.5f * (M[0] + M[1])) * (1.0f / (3.0f * sh::k20));
-  g[1] = 2.0f * M[4] * (1.0f / sh::k21);
-  g[2] = 2.0f * M[5] * (1.0f / sh::k21);
-  g[3] = 0.5f * (M[0] - M[1]) * (1.0f / sh::k22);
-  g[4] = 2.0f * M[3] * (1.0f / sh::k21);
+template <class R>
+__device__ __forceinline__ void chain_s2(const R (&M)[6], R (&g)[5]) {
+  g[0] = (M[2] - R(0.5) * (M[0] + M[1])) * (R(1.0) / (R(3.0) * ShC<R>::k20));
+  g[1] = R(2.0) * M[4] * (R(1.0) / ShC<R>::k21);
+  g[2] = R(2.0) * M[5] * (R(1.0) / ShC<R>::k21);
+  g[3] = R(0.5) * (M[0] - M[1]) * (R(1.0) / ShC<R>::k22);
+  g[4] = R(2.0) * M[3] * (R(1.0) / ShC<R>::k21);
 }
 
-__device__ __forceinline__ void sym_sq6(const float (&A)[6], float (&B)[6]) {
-  const float xx = A[0], yy = A[1], zz = A[2], xy = A[3], xz = A[4], yz = A[5];
+template <class R>
+__device__ __forceinline__ void sym_sq6(const R (&A)[6], R (&B)[6]) {
+  const R xx = A[0], yy = A[1], zz = A[2], xy = A[3], xz = A[4], yz = A[5];
   B[0] = xx * xx + xy * xy + xz * xz;
   B[1] = xy * xy + yy * yy + yz * yz;
   B[2] = xz * xz + yz * yz + zz * zz;
@@ -67,27 +72,30 @@ __device__ __forceinline__ void sym_sq6(const float (&A)[6], float (&B)[6]) {
   B[5] = xy * xz + yy * yz + yz * zz;
 }
 
-__device__ __forceinline__ void load_cell9(const CfgDev* __restrict__ cfgs, int c, float (&H)[9]) {
+template <class R>
+__device__ __forceinline__ void load_cell9(const CfgDev* __restrict__ cfgs, int c, R (&H)[9]) {
 #pragma unroll
-  for (int x = 0; x < 9; ++x) H[x] = c >= 0 ? cfgs[c].H[x] : 0.f;
+  for (int x = 0; x < 9; ++x) H[x] = c >= 0 ? cell_rows(cfgs[c], R())[x] : R(0);
 }
 
+template <class R>
 struct PV {
-  float rx, ry, rz, d2;
+  R rx, ry, rz, d2;
   int q, zj;
 };
 
-__device__ __forceinline__ PV pvec(const float4* __restrict__ pos4, uint32_t e, float4 xi, const float (&H)[9]) {
-  PV v;
+template <class R>
+__device__ __forceinline__ PV<R> pvec(const Vec4<R>* __restrict__ pos4, uint32_t e, Vec4<R> xi, const R (&H)[9]) {
+  PV<R> v;
   v.q = (int)(e & kNbrMask);
-  const float4 xq = pos4[v.q];
-  float sx, sy, sz;
+  const Vec4<R> xq = pos4[v.q];
+  R sx, sy, sz;
   image_shift(H, e >> kNbrShift, sx, sy, sz);
   v.rx = (xq.x - xi.x) + sx;
   v.ry = (xq.y - xi.y) + sy;
   v.rz = (xq.z - xi.z) + sz;
   v.d2 = pair_d2(v.rx, v.ry, v.rz);
-  v.zj = __float_as_int(xq.w);
+  v.zj = species_of(xq);
   return v;
 }
 
@@ -148,90 +156,91 @@ __global__ void k_loss_final(int n_cfg, int form, double wE, double wV, const in
   loss[3] = LV;
 }
 
-// lambda to slot order (float4); zero on padding slots
-__global__ void k_lam_slots(int64_t ns, const int* __restrict__ orig, const float* __restrict__ lam,
-                            float4* __restrict__ lam4) {
+// lambda to slot order (Vec4<R>); zero on padding slots
+template <class R>
+__global__ void k_lam_slots(int64_t ns, const int* __restrict__ orig, const R* __restrict__ lam,
+                            Vec4<R>* __restrict__ lam4) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= ns) return;
   const int i = orig[p];
-  lam4[p] = i >= 0 ? make_float4(lam[3 * (int64_t)i], lam[3 * (int64_t)i + 1], lam[3 * (int64_t)i + 2], 0.f)
-                   : make_float4(0.f, 0.f, 0.f, 0.f);
+  lam4[p] = i >= 0 ? make_v4<R>(lam[3 * (int64_t)i], lam[3 * (int64_t)i + 1], lam[3 * (int64_t)i + 2], R(0))
+                   : make_v4<R>(R(0), R(0), R(0), R(0));
 }
 
 // ------------------------------------------------- tangent + network adjoint
 
-template <class S, int NC>
-__global__ __launch_bounds__(kTB) void k_train_atom(TrainIO io, Cutoffs cut, const float* __restrict__ params) {
+template <class S, int NC, class R>
+__global__ __launch_bounds__(kTB) void k_train_atom(TrainIOT<R> io, CutoffsT<R> cut, const R* __restrict__ params) {
   constexpr int T = S::T, NR = S::NR, NA = S::NA, BR = S::BR, BA = S::BA, L = S::L, K = S::K, D = S::D, H = S::H;
   static_assert(NA % NC == 0, "chunk must divide n_angular");
-  __shared__ float cA_s[T * T * NA * BA];
+  __shared__ R cA_s[T * T * NA * BA];
   for (int t = threadIdx.x; t < T * T * NA * BA; t += kTB) cA_s[t] = params[S::PCR + t];
   __syncthreads();
   const int64_t ns = io.ns;
   const int64_t p = (int64_t)blockIdx.x * kTB + threadIdx.x;
   if (p >= ns) return;
-  const float4 xi = io.pos4[p];
-  const int Zs = __builtin_amdgcn_readfirstlane(__float_as_int(xi.w));
+  const Vec4<R> xi = io.pos4[p];
+  const int Zs = __builtin_amdgcn_readfirstlane(species_of(xi));
   const int c = io.cfg_of[p];
   if (c < 0) {
     // padding: zero every per-slot output that is summed over species ranges
-    for (int d = 0; d < D; ++d) io.q[d * ns + p] = io.qd[d * ns + p] = 0.f;
-    for (int h = 0; h < H; ++h) io.abar[h * ns + p] = io.zneg[h * ns + p] = io.gw1[h * ns + p] = 0.f;
-    for (int k = 0; k < T * BR; ++k) io.Pb[k * ns + p] = io.Pdn[k * ns + p] = 0.f;
-    for (int n = 0; n < NR; ++n) io.qbR[n * ns + p] = io.FpR[n * ns + p] = 0.f;
-    io.eat[p] = 0.f;
+    for (int d = 0; d < D; ++d) io.q[d * ns + p] = io.qd[d * ns + p] = R(0);
+    for (int h = 0; h < H; ++h) io.abar[h * ns + p] = io.zneg[h * ns + p] = io.gw1[h * ns + p] = R(0);
+    for (int k = 0; k < T * BR; ++k) io.Pb[k * ns + p] = io.Pdn[k * ns + p] = R(0);
+    for (int n = 0; n < NR; ++n) io.qbR[n * ns + p] = io.FpR[n * ns + p] = R(0);
+    io.eat[p] = R(0);
     return;
   }
-  float Hc[9];
+  R Hc[9];
   load_cell9(io.cfgs, c, Hc);
-  const float rcR_inv = 1.0f / cut.rcR, rcA_inv = 1.0f / cut.rcA;
-  const float4 li = io.lam4[p];
-  float mu[9];
+  const R rcR_inv = R(1.0) / cut.rcR, rcA_inv = R(1.0) / cut.rcA;
+  const Vec4<R> li = io.lam4[p];
+  R mu[9];
 #pragma unroll
-  for (int x = 0; x < 9; ++x) mu[x] = (float)io.mu[9 * c + x];
-  const float eb = (float)io.ebar[c];
+  for (int x = 0; x < 9; ++x) mu[x] = (R)io.mu[9 * c + x];
+  const R eb = (R)io.ebar[c];
 
   // ---- radial: P_b[k] = sum_{j in b} Q_k, Pd_b[k] = sum_{j in b} dQ_k (u.t)
   {
-    float P[T][BR], Pd[T][BR];
+    R P[T][BR], Pd[T][BR];
 #pragma unroll
     for (int b = 0; b < T; ++b)
 #pragma unroll
-      for (int k = 0; k < BR; ++k) P[b][k] = Pd[b][k] = 0.f;
+      for (int k = 0; k < BR; ++k) P[b][k] = Pd[b][k] = R(0);
     const int n = io.cntR[p];
     for (int k = 0; k < n; ++k) {
-      const PV v = pvec(io.pos4, io.nbrR[(int64_t)k * ns + p], xi, Hc);
+      const PV<R> v = pvec(io.pos4, io.nbrR[(int64_t)k * ns + p], xi, Hc);
       if (v.d2 < cut.rcR2) {
-        const float d = sqrtf(v.d2), inv = 1.0f / d;
-        float Q[BR], dQ[BR];
+        const R d = sqrt_(v.d2), inv = R(1.0) / d;
+        R Q[BR], dQ[BR];
         cheb_basis_d<BR>(d, rcR_inv, Q, dQ);
-        const float4 lj = io.lam4[v.q];
-        const float tx = lj.x - li.x + mu[0] * v.rx + mu[1] * v.ry + mu[2] * v.rz;
-        const float ty = lj.y - li.y + mu[3] * v.rx + mu[4] * v.ry + mu[5] * v.rz;
-        const float tz = lj.z - li.z + mu[6] * v.rx + mu[7] * v.ry + mu[8] * v.rz;
-        const float ut = (v.rx * tx + v.ry * ty + v.rz * tz) * inv;
+        const Vec4<R> lj = io.lam4[v.q];
+        const R tx = lj.x - li.x + mu[0] * v.rx + mu[1] * v.ry + mu[2] * v.rz;
+        const R ty = lj.y - li.y + mu[3] * v.rx + mu[4] * v.ry + mu[5] * v.rz;
+        const R tz = lj.z - li.z + mu[6] * v.rx + mu[7] * v.ry + mu[8] * v.rz;
+        const R ut = (v.rx * tx + v.ry * ty + v.rz * tz) * inv;
 #pragma unroll
         for (int b = 0; b < T; ++b) {
-          const float m = (T == 1 || v.zj == b) ? 1.0f : 0.0f;
-          const float mut = m * ut;
+          const R m = (T == 1 || v.zj == b) ? R(1.0) : R(0.0);
+          const R mut = m * ut;
 #pragma unroll
           for (int kk = 0; kk < BR; ++kk) {
-            P[b][kk] = fmaf(m, Q[kk], P[b][kk]);
-            Pd[b][kk] = fmaf(mut, dQ[kk], Pd[b][kk]);
+            P[b][kk] = fma_(m, Q[kk], P[b][kk]);
+            Pd[b][kk] = fma_(mut, dQ[kk], Pd[b][kk]);
           }
         }
       }
     }
-    const float* cR = params + (int64_t)Zs * (T * NR * BR);
+    const R* cR = params + (int64_t)Zs * (T * NR * BR);
 #pragma unroll
     for (int nn = 0; nn < NR; ++nn) {
-      float a = 0.f, ad = 0.f;
+      R a = R(0), ad = R(0);
 #pragma unroll
       for (int b = 0; b < T; ++b)
 #pragma unroll
         for (int kk = 0; kk < BR; ++kk) {
-          a = fmaf(cR[(b * NR + nn) * BR + kk], P[b][kk], a);
-          ad = fmaf(cR[(b * NR + nn) * BR + kk], Pd[b][kk], ad);
+          a = fma_(cR[(b * NR + nn) * BR + kk], P[b][kk], a);
+          ad = fma_(cR[(b * NR + nn) * BR + kk], Pd[b][kk], ad);
         }
       io.q[(int64_t)nn * ns + p] = a;
       io.qd[(int64_t)nn * ns + p] = ad;
@@ -247,41 +256,41 @@ __global__ __launch_bounds__(kTB) void k_train_atom(TrainIO io, Cutoffs cut, con
   // ---- angular: S and Sdot in chunks of NC functions (stored for the adjoint)
   const int nA = io.cntA[p];
   for (int h = 0; h < NA / NC; ++h) {
-    float Sg[NC][K], Sd[NC][K];
+    R Sg[NC][K], Sd[NC][K];
 #pragma unroll
     for (int nn = 0; nn < NC; ++nn)
 #pragma unroll
-      for (int lm = 0; lm < K; ++lm) Sg[nn][lm] = Sd[nn][lm] = 0.f;
+      for (int lm = 0; lm < K; ++lm) Sg[nn][lm] = Sd[nn][lm] = R(0);
     for (int k = 0; k < nA; ++k) {
-      const PV v = pvec(io.pos4, io.nbrA[(int64_t)k * ns + p], xi, Hc);
+      const PV<R> v = pvec(io.pos4, io.nbrA[(int64_t)k * ns + p], xi, Hc);
       if (v.d2 < cut.rcA2) {
-        const float d = sqrtf(v.d2), inv = 1.0f / d;
-        const float ux = v.rx * inv, uy = v.ry * inv, uz = v.rz * inv;
-        float Q[BA], dQ[BA];
+        const R d = sqrt_(v.d2), inv = R(1.0) / d;
+        const R ux = v.rx * inv, uy = v.ry * inv, uz = v.rz * inv;
+        R Q[BA], dQ[BA];
         cheb_basis_d<BA>(d, rcA_inv, Q, dQ);
-        const float4 lj = io.lam4[v.q];
-        const float tx = lj.x - li.x + mu[0] * v.rx + mu[1] * v.ry + mu[2] * v.rz;
-        const float ty = lj.y - li.y + mu[3] * v.rx + mu[4] * v.ry + mu[5] * v.rz;
-        const float tz = lj.z - li.z + mu[6] * v.rx + mu[7] * v.ry + mu[8] * v.rz;
-        const float ut = ux * tx + uy * ty + uz * tz;
-        float Y[K], Dl[K];
+        const Vec4<R> lj = io.lam4[v.q];
+        const R tx = lj.x - li.x + mu[0] * v.rx + mu[1] * v.ry + mu[2] * v.rz;
+        const R ty = lj.y - li.y + mu[3] * v.rx + mu[4] * v.ry + mu[5] * v.rz;
+        const R tz = lj.z - li.z + mu[6] * v.rx + mu[7] * v.ry + mu[8] * v.rz;
+        const R ut = ux * tx + uy * ty + uz * tz;
+        R Y[K], Dl[K];
         real_sph<L>(ux, uy, uz, Y);
         // grad_r Y_lm . t = grad P_lm . (t - (u.t) u) / d
         real_sph_dir<L>(ux, uy, uz, (tx - ut * ux) * inv, (ty - ut * uy) * inv, (tz - ut * uz) * inv, Dl);
-        const float* cl = cA_s + ((Zs * T + v.zj) * NA + h * NC) * BA;
+        const R* cl = cA_s + ((Zs * T + v.zj) * NA + h * NC) * BA;
 #pragma unroll
         for (int nn = 0; nn < NC; ++nn) {
-          float g = 0.f, gp = 0.f;
+          R g = R(0), gp = R(0);
 #pragma unroll
           for (int kk = 0; kk < BA; ++kk) {
-            g = fmaf(cl[nn * BA + kk], Q[kk], g);
-            gp = fmaf(cl[nn * BA + kk], dQ[kk], gp);
+            g = fma_(cl[nn * BA + kk], Q[kk], g);
+            gp = fma_(cl[nn * BA + kk], dQ[kk], gp);
           }
-          const float gput = gp * ut;
+          const R gput = gp * ut;
 #pragma unroll
           for (int lm = 0; lm < K; ++lm) {
-            Sg[nn][lm] = fmaf(g, Y[lm], Sg[nn][lm]);
-            Sd[nn][lm] = fmaf(gput, Y[lm], fmaf(g, Dl[lm], Sd[nn][lm]));
+            Sg[nn][lm] = fma_(g, Y[lm], Sg[nn][lm]);
+            Sd[nn][lm] = fma_(gput, Y[lm], fma_(g, Dl[lm], Sd[nn][lm]));
           }
         }
       }
@@ -294,73 +303,78 @@ __global__ __launch_bounds__(kTB) void k_train_atom(TrainIO io, Cutoffs cut, con
         io.Sst[(int64_t)(n * K + lm) * ns + p] = Sg[nn][lm];
         io.Sdt[(int64_t)(n * K + lm) * ns + p] = Sd[nn][lm];
       }
-      float q1 = 0.f, qd1 = 0.f;
+      R q1 = R(0), qd1 = R(0);
 #pragma unroll
       for (int l = 1; l <= L; ++l) {
-        float s = 0.f, sd = 0.f;
+        R s = R(0), sd = R(0);
 #pragma unroll
         for (int lm = l * l - 1; lm < (l + 1) * (l + 1) - 1; ++lm) {
-          s = fmaf(Sg[nn][lm], Sg[nn][lm], s);
-          sd = fmaf(Sg[nn][lm], Sd[nn][lm], sd);
+          s = fma_(Sg[nn][lm], Sg[nn][lm], s);
+          sd = fma_(Sg[nn][lm], Sd[nn][lm], sd);
         }
         io.q[(int64_t)(NR + (l - 1) * NA + n) * ns + p] = s;
-        io.qd[(int64_t)(NR + (l - 1) * NA + n) * ns + p] = 2.0f * sd;
+        io.qd[(int64_t)(NR + (l - 1) * NA + n) * ns + p] = R(2.0) * sd;
         if (l == 1) {
           q1 = s;
-          qd1 = 2.0f * sd;
+          qd1 = R(2.0) * sd;
         }
       }
       if constexpr (S::F4) {
-        float A[6], Ad[6], A2[6];
+        R A[6], Ad[6], A2[6];
         sym_from_s2(&Sg[nn][3], A);
         sym_from_s2(&Sd[nn][3], Ad);
         sym_sq6(A, A2);
         io.q[(int64_t)(S::OFF4 + n) * ns + p] = sym_dot(A2, A);
-        io.qd[(int64_t)(S::OFF4 + n) * ns + p] = 3.0f * sym_dot(A2, Ad);
+        io.qd[(int64_t)(S::OFF4 + n) * ns + p] = R(3.0) * sym_dot(A2, Ad);
       }
       if constexpr (S::F5) {
         io.q[(int64_t)(S::OFF5 + n) * ns + p] = q1 * q1;
-        io.qd[(int64_t)(S::OFF5 + n) * ns + p] = 2.0f * q1 * qd1;
+        io.qd[(int64_t)(S::OFF5 + n) * ns + p] = R(2.0) * q1 * qd1;
       }
     }
   }
   // ---- network, second-order adjoint; pass 1: abar, z, dj/dw1
-  const float* W0 = params + S::PCR + S::PCA + (int64_t)Zs * S::PMLP;
-  const float* b0 = W0 + H * D;
-  const float* w1 = b0 + H;
+  const R* W0 = params + S::PCR + S::PCA + (int64_t)Zs * S::PMLP;
+  const R* b0 = W0 + H * D;
+  const R* w1 = b0 + H;
   {
-    float q[D], qd[D];
+    R q[D], qd[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       q[d] = io.q[(int64_t)d * ns + p];
       qd[d] = io.qd[(int64_t)d * ns + p];
     }
+    R Esite = w1[H];  // E_i = b1 + sum_h w1_h h_h (written by the float64 variant)
     for (int hh = 0; hh < H; ++hh) {
-      float a = b0[hh], ad = 0.f;
+      R a = b0[hh], ad = R(0);
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        a = fmaf(W0[hh * D + d], q[d], a);
-        ad = fmaf(W0[hh * D + d], qd[d], ad);
+        a = fma_(W0[hh * D + d], q[d], a);
+        ad = fma_(W0[hh * D + d], qd[d], ad);
       }
-      const float t = tanhf(a);
-      const float s2 = 1.0f - t * t;
-      const float z = w1[hh] * s2;
-      io.abar[(int64_t)hh * ns + p] = z * (eb + 2.0f * t * ad);
+      const R t = tanh_(a);
+      Esite = fma_(w1[hh], t, Esite);
+      const R s2 = R(1.0) - t * t;
+      const R z = w1[hh] * s2;
+      io.abar[(int64_t)hh * ns + p] = z * (eb + R(2.0) * t * ad);
       io.zneg[(int64_t)hh * ns + p] = -z;
       io.gw1[(int64_t)hh * ns + p] = eb * t - s2 * ad;
+    }
+    if constexpr (sizeof(R) == 8) {
+      if (io.Ei) io.Ei[io.orig[p]] = Esite;
     }
   }
   io.eat[p] = eb;
   // pass 2: qbar = W0^T abar, Fp = W0^T z
-  float qb[D], Fp[D];
+  R qb[D], Fp[D];
 #pragma unroll
-  for (int d = 0; d < D; ++d) qb[d] = Fp[d] = 0.f;
+  for (int d = 0; d < D; ++d) qb[d] = Fp[d] = R(0);
   for (int hh = 0; hh < H; ++hh) {
-    const float ab = io.abar[(int64_t)hh * ns + p], z = -io.zneg[(int64_t)hh * ns + p];
+    const R ab = io.abar[(int64_t)hh * ns + p], z = -io.zneg[(int64_t)hh * ns + p];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-      qb[d] = fmaf(ab, W0[hh * D + d], qb[d]);
-      Fp[d] = fmaf(z, W0[hh * D + d], Fp[d]);
+      qb[d] = fma_(ab, W0[hh * D + d], qb[d]);
+      Fp[d] = fma_(z, W0[hh * D + d], Fp[d]);
     }
   }
 #pragma unroll
@@ -370,22 +384,22 @@ __global__ __launch_bounds__(kTB) void k_train_atom(TrainIO io, Cutoffs cut, con
   }
   // ---- sigma = dE/dS and Sbar = dj/dS from the stored S and Sdot
   for (int n = 0; n < NA; ++n) {
-    float Sg[K], Sd[K];
+    R Sg[K], Sd[K];
 #pragma unroll
     for (int lm = 0; lm < K; ++lm) {
       Sg[lm] = io.Sst[(int64_t)(n * K + lm) * ns + p];
       Sd[lm] = io.Sdt[(int64_t)(n * K + lm) * ns + p];
     }
-    float g4s[5] = {0, 0, 0, 0, 0}, g4b[5] = {0, 0, 0, 0, 0};
+    R g4s[5] = {0, 0, 0, 0, 0}, g4b[5] = {0, 0, 0, 0, 0};
     if constexpr (S::F4) {
-      float A[6], Ad[6], A2[6], Msig[6], Mbar[6];
+      R A[6], Ad[6], A2[6], Msig[6], Mbar[6];
       sym_from_s2(&Sg[3], A);
       sym_from_s2(&Sd[3], Ad);
       sym_sq6(A, A2);
-      float AAd[9], AdA[9];
+      R AAd[9], AdA[9];
       sym_mul_sym(A, Ad, AAd);
       sym_mul_sym(Ad, A, AdA);
-      float fp4 = 0.f, qb4 = 0.f;
+      R fp4 = R(0), qb4 = R(0);
 #pragma unroll
       for (int x = 0; x < NA; ++x)
         if (x == n) {
@@ -395,16 +409,16 @@ __global__ __launch_bounds__(kTB) void k_train_atom(TrainIO io, Cutoffs cut, con
       const int ix[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
 #pragma unroll
       for (int x = 0; x < 6; ++x) {
-        const float sym = AAd[3 * ix[x][0] + ix[x][1]] + AdA[3 * ix[x][0] + ix[x][1]];
-        Msig[x] = 3.0f * fp4 * A2[x];
-        Mbar[x] = 3.0f * qb4 * A2[x] - 3.0f * fp4 * sym;
+        const R sym = AAd[3 * ix[x][0] + ix[x][1]] + AdA[3 * ix[x][0] + ix[x][1]];
+        Msig[x] = R(3.0) * fp4 * A2[x];
+        Mbar[x] = R(3.0) * qb4 * A2[x] - R(3.0) * fp4 * sym;
       }
       chain_s2(Msig, g4s);
       chain_s2(Mbar, g4b);
     }
 #pragma unroll
     for (int l = 1; l <= L; ++l) {
-      float fp3 = 0.f, qb3 = 0.f, fp5 = 0.f, qb5 = 0.f;
+      R fp3 = R(0), qb3 = R(0), fp5 = R(0), qb5 = R(0);
 #pragma unroll
       for (int x = 0; x < NA; ++x)
         if (x == n) {
@@ -415,19 +429,19 @@ __global__ __launch_bounds__(kTB) void k_train_atom(TrainIO io, Cutoffs cut, con
             qb5 = qb[S::OFF5 + x];
           }
         }
-      float cs = 2.0f * fp3;   // sigma = cs S
-      float cbS = 2.0f * qb3;  // Sbar = cbS S + cbD Sdot
-      float cbD = -2.0f * fp3;
+      R cs = R(2.0) * fp3;   // sigma = cs S
+      R cbS = R(2.0) * qb3;  // Sbar = cbS S + cbD Sdot
+      R cbD = -R(2.0) * fp3;
       if (S::F5 && l == 1) {
-        const float q1 = io.q[(int64_t)(NR + n) * ns + p], qd1 = io.qd[(int64_t)(NR + n) * ns + p];
-        cs += 4.0f * fp5 * q1;
-        cbS += 4.0f * qb5 * q1 - 4.0f * fp5 * qd1;
-        cbD += -4.0f * fp5 * q1;
+        const R q1 = io.q[(int64_t)(NR + n) * ns + p], qd1 = io.qd[(int64_t)(NR + n) * ns + p];
+        cs += R(4.0) * fp5 * q1;
+        cbS += R(4.0) * qb5 * q1 - R(4.0) * fp5 * qd1;
+        cbD += -R(4.0) * fp5 * q1;
       }
 #pragma unroll
       for (int lm = l * l - 1; lm < (l + 1) * (l + 1) - 1; ++lm) {
-        float sg = cs * Sg[lm];
-        float sb = cbS * Sg[lm] + cbD * Sd[lm];
+        R sg = cs * Sg[lm];
+        R sb = cbS * Sg[lm] + cbD * Sd[lm];
         if (S::F4 && l == 2) {
           sg += g4s[lm - 3];
           sb += g4b[lm - 3];
@@ -444,67 +458,67 @@ __global__ __launch_bounds__(kTB) void k_train_atom(TrainIO io, Cutoffs cut, con
 // GA[(b NA + n) BA + k] = sum over angular pairs j of species b of
 //   (alpha_n + gamma_n) Q_k + beta_n dQ_k,
 // alpha_n = sum_lm Sbar Y, beta_n = -(u.t) sum_lm sigma Y, gamma_n = -sum_lm sigma grad Y.t
-template <class S>
-__global__ __launch_bounds__(kTB) void k_train_coefA(TrainIO io, Cutoffs cut, const float* __restrict__ params) {
+template <class S, class R>
+__global__ __launch_bounds__(kTB) void k_train_coefA(TrainIOT<R> io, CutoffsT<R> cut, const R* __restrict__ params) {
   constexpr int T = S::T, NA = S::NA, BA = S::BA, L = S::L, K = S::K;
   const int64_t ns = io.ns;
   const int64_t p = (int64_t)blockIdx.x * kTB + threadIdx.x;
   if (p >= ns) return;
   const int c = io.cfg_of[p];
   if (c < 0) {
-    for (int x = 0; x < T * NA * BA; ++x) io.GA[(int64_t)x * ns + p] = 0.f;
+    for (int x = 0; x < T * NA * BA; ++x) io.GA[(int64_t)x * ns + p] = R(0);
     return;
   }
-  const float4 xi = io.pos4[p];
-  float Hc[9];
+  const Vec4<R> xi = io.pos4[p];
+  R Hc[9];
   load_cell9(io.cfgs, c, Hc);
-  const float rcA_inv = 1.0f / cut.rcA;
-  const float4 li = io.lam4[p];
-  float mu[9];
+  const R rcA_inv = R(1.0) / cut.rcA;
+  const Vec4<R> li = io.lam4[p];
+  R mu[9];
 #pragma unroll
-  for (int x = 0; x < 9; ++x) mu[x] = (float)io.mu[9 * c + x];
+  for (int x = 0; x < 9; ++x) mu[x] = (R)io.mu[9 * c + x];
   const int nA = io.cntA[p];
   for (int n = 0; n < NA; ++n) {
-    float sg[K], sb[K];
+    R sg[K], sb[K];
 #pragma unroll
     for (int lm = 0; lm < K; ++lm) {
       sg[lm] = io.Sst[(int64_t)(n * K + lm) * ns + p];
       sb[lm] = io.Sdt[(int64_t)(n * K + lm) * ns + p];
     }
-    float G[T][BA];
+    R G[T][BA];
 #pragma unroll
     for (int b = 0; b < T; ++b)
 #pragma unroll
-      for (int k = 0; k < BA; ++k) G[b][k] = 0.f;
+      for (int k = 0; k < BA; ++k) G[b][k] = R(0);
     for (int k = 0; k < nA; ++k) {
-      const PV v = pvec(io.pos4, io.nbrA[(int64_t)k * ns + p], xi, Hc);
+      const PV<R> v = pvec(io.pos4, io.nbrA[(int64_t)k * ns + p], xi, Hc);
       if (v.d2 < cut.rcA2) {
-        const float d = sqrtf(v.d2), inv = 1.0f / d;
-        const float ux = v.rx * inv, uy = v.ry * inv, uz = v.rz * inv;
-        float Q[BA], dQ[BA];
+        const R d = sqrt_(v.d2), inv = R(1.0) / d;
+        const R ux = v.rx * inv, uy = v.ry * inv, uz = v.rz * inv;
+        R Q[BA], dQ[BA];
         cheb_basis_d<BA>(d, rcA_inv, Q, dQ);
-        const float4 lj = io.lam4[v.q];
-        const float tx = lj.x - li.x + mu[0] * v.rx + mu[1] * v.ry + mu[2] * v.rz;
-        const float ty = lj.y - li.y + mu[3] * v.rx + mu[4] * v.ry + mu[5] * v.rz;
-        const float tz = lj.z - li.z + mu[6] * v.rx + mu[7] * v.ry + mu[8] * v.rz;
-        const float ut = ux * tx + uy * ty + uz * tz;
-        float Y[K], Dl[K];
+        const Vec4<R> lj = io.lam4[v.q];
+        const R tx = lj.x - li.x + mu[0] * v.rx + mu[1] * v.ry + mu[2] * v.rz;
+        const R ty = lj.y - li.y + mu[3] * v.rx + mu[4] * v.ry + mu[5] * v.rz;
+        const R tz = lj.z - li.z + mu[6] * v.rx + mu[7] * v.ry + mu[8] * v.rz;
+        const R ut = ux * tx + uy * ty + uz * tz;
+        R Y[K], Dl[K];
         real_sph<L>(ux, uy, uz, Y);
         real_sph_dir<L>(ux, uy, uz, (tx - ut * ux) * inv, (ty - ut * uy) * inv, (tz - ut * uz) * inv, Dl);
-        float al = 0.f, sy = 0.f, ga = 0.f;
+        R al = R(0), sy = R(0), ga = R(0);
 #pragma unroll
         for (int lm = 0; lm < K; ++lm) {
-          al = fmaf(sb[lm], Y[lm], al);
-          sy = fmaf(sg[lm], Y[lm], sy);
-          ga = fmaf(sg[lm], Dl[lm], ga);
+          al = fma_(sb[lm], Y[lm], al);
+          sy = fma_(sg[lm], Y[lm], sy);
+          ga = fma_(sg[lm], Dl[lm], ga);
         }
-        const float cq = al - ga, cd = -ut * sy;
+        const R cq = al - ga, cd = -ut * sy;
 #pragma unroll
         for (int b = 0; b < T; ++b) {
-          const float m = (T == 1 || v.zj == b) ? 1.0f : 0.0f;
-          const float mq = m * cq, md = m * cd;
+          const R m = (T == 1 || v.zj == b) ? R(1.0) : R(0.0);
+          const R mq = m * cq, md = m * cd;
 #pragma unroll
-          for (int kk = 0; kk < BA; ++kk) G[b][kk] = fmaf(mq, Q[kk], fmaf(md, dQ[kk], G[b][kk]));
+          for (int kk = 0; kk < BA; ++kk) G[b][kk] = fma_(mq, Q[kk], fma_(md, dQ[kk], G[b][kk]));
         }
       }
     }
@@ -524,15 +538,16 @@ constexpr int kMaxE = 16;      // entries per thread (A*B <= 4096)
 
 // part[(s * kRBlocks + blk) * A*B + e] = sum over slots i of species s handled
 // by block blk of  X1[a][i] Y1[b][i] + X2[a][i] Y2[b][i]  (e = a*B + b).
+template <class X>
 __global__ __launch_bounds__(kRB) void k_outer(int64_t ns, const int* __restrict__ base, int A, int B,
-                                               const float* __restrict__ X1, const float* __restrict__ Y1,
-                                               const float* __restrict__ X2, const float* __restrict__ Y2,
+                                               const X* __restrict__ X1, const X* __restrict__ Y1,
+                                               const X* __restrict__ X2, const X* __restrict__ Y2,
                                                double* __restrict__ part) {
-  extern __shared__ float smem[];
-  float* sx1 = smem;
-  float* sy1 = sx1 + A * kRChunk;
-  float* sx2 = sy1 + B * kRChunk;
-  float* sy2 = sx2 + A * kRChunk;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  X* sx1 = reinterpret_cast<X*>(smem_raw);
+  X* sy1 = sx1 + A * kRChunk;
+  X* sx2 = sy1 + B * kRChunk;
+  X* sy2 = sx2 + A * kRChunk;
   const int s = blockIdx.y, blk = blockIdx.x;
   const int p0 = base[s], p1 = base[s + 1];
   const int AB = A * B;
@@ -544,13 +559,13 @@ __global__ __launch_bounds__(kRB) void k_outer(int64_t ns, const int* __restrict
     __syncthreads();
     for (int t = threadIdx.x; t < A * kRChunk; t += kRB) {
       const int a = t / kRChunk, i = t % kRChunk;
-      sx1[t] = i < nc ? X1[(int64_t)a * ns + c0 + i] : 0.f;
-      sx2[t] = i < nc ? X2[(int64_t)a * ns + c0 + i] : 0.f;
+      sx1[t] = i < nc ? X1[(int64_t)a * ns + c0 + i] : X(0);
+      sx2[t] = i < nc ? X2[(int64_t)a * ns + c0 + i] : X(0);
     }
     for (int t = threadIdx.x; t < B * kRChunk; t += kRB) {
       const int b = t / kRChunk, i = t % kRChunk;
-      sy1[t] = i < nc ? Y1[(int64_t)b * ns + c0 + i] : 0.f;
-      sy2[t] = i < nc ? Y2[(int64_t)b * ns + c0 + i] : 0.f;
+      sy1[t] = i < nc ? Y1[(int64_t)b * ns + c0 + i] : X(0);
+      sy2[t] = i < nc ? Y2[(int64_t)b * ns + c0 + i] : X(0);
     }
     __syncthreads();
 #pragma unroll
@@ -558,9 +573,9 @@ __global__ __launch_bounds__(kRB) void k_outer(int64_t ns, const int* __restrict
       const int e = threadIdx.x + j * kRB;
       if (e < AB) {
         const int a = e / B, b = e % B;
-        float s1 = 0.f;
+        X s1 = X(0);
         for (int i = 0; i < kRChunk; ++i)
-          s1 = fmaf(sx1[a * kRChunk + i], sy1[b * kRChunk + i], fmaf(sx2[a * kRChunk + i], sy2[b * kRChunk + i], s1));
+          s1 = fma_(sx1[a * kRChunk + i], sy1[b * kRChunk + i], fma_(sx2[a * kRChunk + i], sy2[b * kRChunk + i], s1));
         acc[j] += (double)s1;
       }
     }
@@ -573,16 +588,17 @@ __global__ __launch_bounds__(kRB) void k_outer(int64_t ns, const int* __restrict
 }
 
 // part[(s * kRBlocks + blk) * A + a] = sum over the block's slots of X[a][i]
+template <class X>
 __global__ __launch_bounds__(kRB) void k_colsum(int64_t ns, const int* __restrict__ base, int A,
-                                                const float* __restrict__ X, double* __restrict__ part) {
+                                                const X* __restrict__ Xa, double* __restrict__ part) {
   const int s = blockIdx.y, blk = blockIdx.x;
   const int p0 = base[s], p1 = base[s + 1];
   for (int a = threadIdx.x; a < A; a += kRB) {
     double acc = 0.0;
     for (int c0 = p0 + blk * kRChunk; c0 < p1; c0 += kRBlocks * kRChunk) {
       const int c1 = min(c0 + kRChunk, p1);
-      float s1 = 0.f;
-      for (int i = c0; i < c1; ++i) s1 += X[(int64_t)a * ns + i];
+      X s1 = X(0);
+      for (int i = c0; i < c1; ++i) s1 += Xa[(int64_t)a * ns + i];
       acc += (double)s1;
     }
     part[((int64_t)s * kRBlocks + blk) * A + a] = acc;
@@ -613,6 +629,191 @@ __global__ void k_to_float(int64_t n, const double* __restrict__ a, float* __res
 
 static inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// ------------------------------------------------------- float64 variant
+
+__global__ void k_fill64(int64_t n, double v, double* __restrict__ a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+__global__ void k_round_pos(int64_t n, const double* __restrict__ a, float* __restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
+
+// Positions in slot order, float64, wrapped by the same lattice vector as the
+// float32 staging that built the lists: that vector is the integer nearest to
+// (x_f - x_f,wrapped) H^-1, where x_f is the float32 rounding of the position.
+__global__ void k_stage64(int64_t ns, const int* __restrict__ orig, const int* __restrict__ cfg_of,
+                          const CfgDev* __restrict__ cfgs, const float4* __restrict__ pos4f,
+                          const double* __restrict__ pos, double4* __restrict__ pos4) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= ns) return;
+  const float4 wf = pos4f[p];
+  const int i = orig[p], c = cfg_of[p];
+  if (i < 0 || c < 0) {
+    pos4[p] = make_double4(0.0, 0.0, 0.0, (double)species_of(wf));
+    return;
+  }
+  const CfgDev& C = cfgs[c];
+  const double x[3] = {pos[3 * (int64_t)i], pos[3 * (int64_t)i + 1], pos[3 * (int64_t)i + 2]};
+  const double dx[3] = {(double)(float)x[0] - (double)wf.x, (double)(float)x[1] - (double)wf.y,
+                        (double)(float)x[2] - (double)wf.z};
+  double m[3];
+  for (int a = 0; a < 3; ++a) m[a] = rint(dx[0] * C.Hinv[a] + dx[1] * C.Hinv[3 + a] + dx[2] * C.Hinv[6 + a]);
+  double w[3];
+  for (int a = 0; a < 3; ++a) w[a] = x[a] - m[0] * C.Hd[a] - m[1] * C.Hd[3 + a] - m[2] * C.Hd[6 + a];
+  pos4[p] = make_double4(w[0], w[1], w[2], (double)species_of(wf));
+}
+
+// dE_a/dr_ab for centre a (species Za) and neighbour b (species Zb) at
+// r_ab = d u, from a's sigma = dE_a/dS_a (rows [n K + lm] of stride ns at
+// slot sa): with g_n = sum_k c[Za][Zb][n][k] Q_k (Eq. 11-15, 16),
+//   dE_a/dr_ab = u sum_n g'_n Z_n + (I - u u^T) grad_u(sum_lm G_lm Y_lm) / d,
+//   Z_n = sum_lm sigma_nlm Y_lm(u),  G_lm = sum_n sigma_nlm g_n.
+template <class S>
+__device__ void angular_pair_grad(const double* __restrict__ sigma, int64_t ns, int64_t sa, const double* cA, int Za,
+                                  int Zb, double ux, double uy, double uz, double d, double rcA_inv, double& fx,
+                                  double& fy, double& fz) {
+  constexpr int T = S::T, NA = S::NA, BA = S::BA, L = S::L, K = S::K;
+  double Q[BA], dQ[BA], Y[K], G[K];
+  cheb_basis_d<BA>(d, rcA_inv, Q, dQ);
+  real_sph<L>(ux, uy, uz, Y);
+#pragma unroll
+  for (int lm = 0; lm < K; ++lm) G[lm] = 0.0;
+  double s = 0.0;
+  const double* cl = cA + ((int64_t)(Za * T + Zb) * NA) * BA;
+#pragma unroll 1
+  for (int n = 0; n < NA; ++n) {
+    double g = 0.0, gp = 0.0;
+#pragma unroll
+    for (int k = 0; k < BA; ++k) {
+      g = fma(cl[n * BA + k], Q[k], g);
+      gp = fma(cl[n * BA + k], dQ[k], gp);
+    }
+    double zn = 0.0;
+#pragma unroll
+    for (int lm = 0; lm < K; ++lm) {
+      const double sg = sigma[(int64_t)(n * K + lm) * ns + sa];
+      zn = fma(sg, Y[lm], zn);
+      G[lm] = fma(sg, g, G[lm]);
+    }
+    s = fma(gp, zn, s);
+  }
+  double gx, gy, gz;
+  real_sph_grad_dot<L>(ux, uy, uz, G, gx, gy, gz);
+  const double ug = ux * gx + uy * gy + uz * gz;
+  fx = s * ux + (gx - ug * ux) / d;
+  fy = s * uy + (gy - ug * uy) / d;
+  fz = s * uz + (gz - ug * uz) / d;
+}
+
+// F_i = sum_j (dE_i/dr_ij - dE_j/dr_ji) (Eq. 3) and the per-atom virial
+// W_i = - sum_j dE_i/dr_ij (x) r_ij, from the per-atom adjoints that the atom
+// pass leaves with zero tangent seeds: FpR = dE/dq (radial) and
+// Sst = sigma = dE/dS.  Caller order for F and W.
+template <class S>
+__global__ __launch_bounds__(kTB) void k_pair_force64(TrainIOT<double> io, CutoffsT<double> cut,
+                                                      const double* __restrict__ params, double* __restrict__ F,
+                                                      double* __restrict__ W) {
+  constexpr int T = S::T, NR = S::NR, BR = S::BR;
+  const int64_t ns = io.ns;
+  const int64_t p = (int64_t)blockIdx.x * kTB + threadIdx.x;
+  if (p >= ns) return;
+  const int c = io.cfg_of[p];
+  if (c < 0) return;
+  const int i = io.orig[p];
+  const double4 xi = io.pos4[p];
+  const int Zi = species_of(xi);
+  double Hc[9];
+  load_cell9(io.cfgs, c, Hc);
+  const double rcR_inv = 1.0 / cut.rcR, rcA_inv = 1.0 / cut.rcA;
+  double fpi[NR];
+#pragma unroll
+  for (int n = 0; n < NR; ++n) fpi[n] = io.FpR[(int64_t)n * ns + p];
+  double Fx = 0.0, Fy = 0.0, Fz = 0.0, Wm[9];
+#pragma unroll
+  for (int x = 0; x < 9; ++x) Wm[x] = 0.0;
+  const double* cA = params + S::PCR;
+  const int n = io.cntR[p];
+  for (int k = 0; k < n; ++k) {
+    const PV<double> v = pvec(io.pos4, io.nbrR[(int64_t)k * ns + p], xi, Hc);
+    if (!(v.d2 < cut.rcR2)) continue;
+    const double d = sqrt(v.d2);
+    const double ux = v.rx / d, uy = v.ry / d, uz = v.rz / d;
+    // radial: dE_i/dd and dE_j/dd through q_n = sum_j sum_k c[Zi][Zj][n][k] Q_k
+    double Q[BR], dQ[BR];
+    cheb_basis_d<BR>(d, rcR_inv, Q, dQ);
+    const double* ci = params + ((int64_t)(Zi * T + v.zj) * NR) * BR;
+    const double* cj = params + ((int64_t)(v.zj * T + Zi) * NR) * BR;
+    double own = 0.0, rev = 0.0;
+#pragma unroll 1
+    for (int nn = 0; nn < NR; ++nn) {
+      double gi = 0.0, gj = 0.0;
+#pragma unroll
+      for (int kk = 0; kk < BR; ++kk) {
+        gi = fma(ci[nn * BR + kk], dQ[kk], gi);
+        gj = fma(cj[nn * BR + kk], dQ[kk], gj);
+      }
+      own = fma(fpi[nn], gi, own);
+      rev = fma(io.FpR[(int64_t)nn * ns + v.q], gj, rev);
+    }
+    double fx = own * ux, fy = own * uy, fz = own * uz;  // dE_i/dr_ij
+    double bx = -rev * ux, by = -rev * uy, bz = -rev * uz;  // dE_j/dr_ji (r_ji = -r_ij)
+    if (v.d2 < cut.rcA2) {
+      double ax, ay, az, cx, cy, cz;
+      angular_pair_grad<S>(io.Sst, ns, p, cA, Zi, v.zj, ux, uy, uz, d, rcA_inv, ax, ay, az);
+      angular_pair_grad<S>(io.Sst, ns, v.q, cA, v.zj, Zi, -ux, -uy, -uz, d, rcA_inv, cx, cy, cz);
+      fx += ax;
+      fy += ay;
+      fz += az;
+      bx += cx;
+      by += cy;
+      bz += cz;
+    }
+    Fx += fx - bx;
+    Fy += fy - by;
+    Fz += fz - bz;
+    const double f[3] = {fx, fy, fz}, r[3] = {v.rx, v.ry, v.rz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) Wm[3 * a + b] -= f[a] * r[b];
+  }
+  F[3 * (int64_t)i] = Fx;
+  F[3 * (int64_t)i + 1] = Fy;
+  F[3 * (int64_t)i + 2] = Fz;
+#pragma unroll
+  for (int x = 0; x < 9; ++x) W[9 * (int64_t)i + x] = Wm[x];
+}
+
+// Per configuration (one block each, fixed order): E_c = sum_i E_i and
+// V_c = sum_i W_i over the configuration's atoms (caller order).
+constexpr int kSB = 256;
+__global__ __launch_bounds__(kSB) void k_cfg_sum64(const int64_t* __restrict__ off, const double* __restrict__ Ei,
+                                                   const double* __restrict__ Wi, double* __restrict__ E,
+                                                   double* __restrict__ V) {
+  __shared__ double sh[10][kSB];
+  const int c = blockIdx.x;
+  double acc[10];
+  for (int x = 0; x < 10; ++x) acc[x] = 0.0;
+  for (int64_t i = off[c] + threadIdx.x; i < off[c + 1]; i += kSB) {
+    acc[0] += Ei[i];
+    for (int x = 0; x < 9; ++x) acc[1 + x] += Wi[9 * i + x];
+  }
+  for (int x = 0; x < 10; ++x) sh[x][threadIdx.x] = acc[x];
+  __syncthreads();
+  for (int s = kSB / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+      for (int x = 0; x < 10; ++x) sh[x][threadIdx.x] += sh[x][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    E[c] = sh[0][0];
+    for (int x = 0; x < 9; ++x) V[9 * c + x] = sh[1 + x][0];
+  }
+}
+
 // ------------------------------------------------------------ launchers
 
 template <class S>
@@ -629,18 +830,18 @@ template <class S>
 int TrainLaunch<S>::backward(hipStream_t st, TrainIO io, const Cutoffs& cut, const float* params, const float* lam,
                              const int* base, double* part, double* grad64, float* grad) {
   const int64_t ns = io.ns;
-  hipLaunchKernelGGL(k_lam_slots, dim3(blocks(ns, 256)), dim3(256), 0, st, ns, io.orig, lam,
+  hipLaunchKernelGGL(k_lam_slots<float>, dim3(blocks(ns, 256)), dim3(256), 0, st, ns, io.orig, lam,
                      const_cast<float4*>(io.lam4));
   constexpr int NC = S::NA >= 4 ? 2 : 1;
-  hipLaunchKernelGGL((k_train_atom<S, NC>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, params);
-  hipLaunchKernelGGL((k_train_coefA<S>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, params);
+  hipLaunchKernelGGL((k_train_atom<S, NC, float>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, params);
+  hipLaunchKernelGGL((k_train_coefA<S, float>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, params);
   constexpr int T = S::T;
   const dim3 g(kRBlocks, T);
   // W0: sum abar q^T - z qdot^T
   {
     const int A = S::H, B = S::D;
     const size_t sm = sizeof(float) * (size_t)(2 * A + 2 * B) * kRChunk;
-    hipLaunchKernelGGL(k_outer, g, dim3(kRB), sm, st, ns, base, A, B, io.abar, io.q, io.zneg, io.qd, part);
+    hipLaunchKernelGGL(k_outer<float>, g, dim3(kRB), sm, st, ns, base, A, B, io.abar, io.q, io.zneg, io.qd, part);
     hipLaunchKernelGGL(k_part_final, dim3(blocks((int64_t)T * A * B, 256)), dim3(256), 0, st, T, A * B, part,
                        S::PCR + S::PCA, S::PMLP, 0, 0, 0, grad64);
   }
@@ -648,31 +849,116 @@ int TrainLaunch<S>::backward(hipStream_t st, TrainIO io, const Cutoffs& cut, con
   {
     const int A = S::NR, B = T * S::BR;
     const size_t sm = sizeof(float) * (size_t)(2 * A + 2 * B) * kRChunk;
-    hipLaunchKernelGGL(k_outer, g, dim3(kRB), sm, st, ns, base, A, B, io.qbR, io.Pb, io.FpR, io.Pdn, part);
+    hipLaunchKernelGGL(k_outer<float>, g, dim3(kRB), sm, st, ns, base, A, B, io.qbR, io.Pb, io.FpR, io.Pdn, part);
     hipLaunchKernelGGL(k_part_final, dim3(blocks((int64_t)T * A * B, 256)), dim3(256), 0, st, T, A * B, part,
                        (int64_t)0, (int64_t)T * S::NR * S::BR, 1, S::NR, S::BR, grad64);
   }
   // c^A
   {
     const int A = T * S::NA * S::BA;
-    hipLaunchKernelGGL(k_colsum, g, dim3(kRB), 0, st, ns, base, A, io.GA, part);
+    hipLaunchKernelGGL(k_colsum<float>, g, dim3(kRB), 0, st, ns, base, A, io.GA, part);
     hipLaunchKernelGGL(k_part_final, dim3(blocks((int64_t)T * A, 256)), dim3(256), 0, st, T, A, part, S::PCR,
                        (int64_t)A, 0, 0, 0, grad64);
   }
   // b0, w1, b1
   {
     const int H = S::H;
-    hipLaunchKernelGGL(k_colsum, g, dim3(kRB), 0, st, ns, base, H, io.abar, part);
+    hipLaunchKernelGGL(k_colsum<float>, g, dim3(kRB), 0, st, ns, base, H, io.abar, part);
     hipLaunchKernelGGL(k_part_final, dim3(blocks((int64_t)T * H, 256)), dim3(256), 0, st, T, H, part,
                        S::PCR + S::PCA + (int64_t)H * S::D, S::PMLP, 0, 0, 0, grad64);
-    hipLaunchKernelGGL(k_colsum, g, dim3(kRB), 0, st, ns, base, H, io.gw1, part);
+    hipLaunchKernelGGL(k_colsum<float>, g, dim3(kRB), 0, st, ns, base, H, io.gw1, part);
     hipLaunchKernelGGL(k_part_final, dim3(blocks((int64_t)T * H, 256)), dim3(256), 0, st, T, H, part,
                        S::PCR + S::PCA + (int64_t)H * S::D + H, S::PMLP, 0, 0, 0, grad64);
-    hipLaunchKernelGGL(k_colsum, g, dim3(kRB), 0, st, ns, base, 1, io.eat, part);
+    hipLaunchKernelGGL(k_colsum<float>, g, dim3(kRB), 0, st, ns, base, 1, io.eat, part);
     hipLaunchKernelGGL(k_part_final, dim3(1), dim3(64), 0, st, T, 1, part,
                        S::PCR + S::PCA + (int64_t)H * S::D + 2 * H, S::PMLP, 0, 0, 0, grad64);
   }
   hipLaunchKernelGGL(k_to_float, dim3(blocks(S::P, 256)), dim3(256), 0, st, (int64_t)S::P, grad64, grad);
+  NEPMI_HIP(hipGetLastError());
+  return NEPMI_OK;
+}
+
+// float64: positions staged, then the atom pass with zero tangent seeds
+// (lambda = 0, mu = 0, ebar = 1), which leaves E_i, dE/dq and dE/dS.
+static int stage64(hipStream_t st, const TrainIOT<double>& io, const F64Args& a, const float4* pos4f) {
+  hipLaunchKernelGGL(k_stage64, dim3(blocks(io.ns, 256)), dim3(256), 0, st, io.ns, io.orig, io.cfg_of, io.cfgs, pos4f,
+                     a.pos, a.pos4);
+  NEPMI_HIP(hipGetLastError());
+  return NEPMI_OK;
+}
+
+template <class S>
+int TrainLaunch<S>::forward64(hipStream_t st, TrainIOT<double> io, const CutoffsT<double>& cut, const F64Args& a,
+                              double* energy, double* forces, double* virial) {
+  const int64_t ns = io.ns;
+  hipLaunchKernelGGL(k_fill64, dim3(blocks(4 * ns, 256)), dim3(256), 0, st, 4 * ns, 0.0,
+                     reinterpret_cast<double*>(io.lam4));
+  constexpr int NC = S::NA >= 4 ? 2 : 1;
+  hipLaunchKernelGGL((k_train_atom<S, NC, double>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params);
+  hipLaunchKernelGGL((k_pair_force64<S>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params, forces, a.Wi);
+  hipLaunchKernelGGL(k_cfg_sum64, dim3(a.n_cfg), dim3(kSB), 0, st, a.atom_off, io.Ei, a.Wi, energy, virial);
+  NEPMI_HIP(hipGetLastError());
+  return NEPMI_OK;
+}
+
+template <class S>
+int TrainLaunch<S>::backward64(hipStream_t st, TrainIOT<double> io, const CutoffsT<double>& cut, const F64Args& a,
+                               const double* lam, const int* base, double* part, double* grad) {
+  const int64_t ns = io.ns;
+  hipLaunchKernelGGL(k_lam_slots<double>, dim3(blocks(ns, 256)), dim3(256), 0, st, ns, io.orig, lam, io.lam4);
+  constexpr int NC = S::NA >= 4 ? 2 : 1;
+  hipLaunchKernelGGL((k_train_atom<S, NC, double>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params);
+  hipLaunchKernelGGL((k_train_coefA<S, double>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params);
+  constexpr int T = S::T;
+  const dim3 g(kRBlocks, T);
+  {
+    const int A = S::H, B = S::D;
+    const size_t sm = sizeof(double) * (size_t)(2 * A + 2 * B) * kRChunk;
+    hipLaunchKernelGGL(k_outer<double>, g, dim3(kRB), sm, st, ns, base, A, B, io.abar, io.q, io.zneg, io.qd, part);
+    hipLaunchKernelGGL(k_part_final, dim3(blocks((int64_t)T * A * B, 256)), dim3(256), 0, st, T, A * B, part,
+                       S::PCR + S::PCA, S::PMLP, 0, 0, 0, grad);
+  }
+  {
+    const int A = S::NR, B = T * S::BR;
+    const size_t sm = sizeof(double) * (size_t)(2 * A + 2 * B) * kRChunk;
+    hipLaunchKernelGGL(k_outer<double>, g, dim3(kRB), sm, st, ns, base, A, B, io.qbR, io.Pb, io.FpR, io.Pdn, part);
+    hipLaunchKernelGGL(k_part_final, dim3(blocks((int64_t)T * A * B, 256)), dim3(256), 0, st, T, A * B, part,
+                       (int64_t)0, (int64_t)T * S::NR * S::BR, 1, S::NR, S::BR, grad);
+  }
+  {
+    const int A = T * S::NA * S::BA;
+    hipLaunchKernelGGL(k_colsum<double>, g, dim3(kRB), 0, st, ns, base, A, io.GA, part);
+    hipLaunchKernelGGL(k_part_final, dim3(blocks((int64_t)T * A, 256)), dim3(256), 0, st, T, A, part, S::PCR,
+                       (int64_t)A, 0, 0, 0, grad);
+  }
+  {
+    const int H = S::H;
+    hipLaunchKernelGGL(k_colsum<double>, g, dim3(kRB), 0, st, ns, base, H, io.abar, part);
+    hipLaunchKernelGGL(k_part_final, dim3(blocks((int64_t)T * H, 256)), dim3(256), 0, st, T, H, part,
+                       S::PCR + S::PCA + (int64_t)H * S::D, S::PMLP, 0, 0, 0, grad);
+    hipLaunchKernelGGL(k_colsum<double>, g, dim3(kRB), 0, st, ns, base, H, io.gw1, part);
+    hipLaunchKernelGGL(k_part_final, dim3(blocks((int64_t)T * H, 256)), dim3(256), 0, st, T, H, part,
+                       S::PCR + S::PCA + (int64_t)H * S::D + H, S::PMLP, 0, 0, 0, grad);
+    hipLaunchKernelGGL(k_colsum<double>, g, dim3(kRB), 0, st, ns, base, 1, io.eat, part);
+    hipLaunchKernelGGL(k_part_final, dim3(1), dim3(64), 0, st, T, 1, part,
+                       S::PCR + S::PCA + (int64_t)H * S::D + 2 * H, S::PMLP, 0, 0, 0, grad);
+  }
+  NEPMI_HIP(hipGetLastError());
+  return NEPMI_OK;
+}
+
+int launch_stage64(hipStream_t st, const TrainIOT<double>& io, const F64Args& a, const float4* pos4f) {
+  return stage64(st, io, a, pos4f);
+}
+
+int launch_round_pos(hipStream_t st, int64_t n, const double* a, float* b) {
+  if (n > 0) hipLaunchKernelGGL(k_round_pos, dim3(blocks(n, 256)), dim3(256), 0, st, n, a, b);
+  NEPMI_HIP(hipGetLastError());
+  return NEPMI_OK;
+}
+
+int launch_fill64(hipStream_t st, int64_t n, double v, double* a) {
+  if (n > 0) hipLaunchKernelGGL(k_fill64, dim3(blocks(n, 256)), dim3(256), 0, st, n, v, a);
   NEPMI_HIP(hipGetLastError());
   return NEPMI_OK;
 }

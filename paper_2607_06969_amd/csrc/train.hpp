@@ -5,10 +5,12 @@
 
 namespace nepmi {
 
-// Per-slot training state; every array is column-major [dim][ns].
-struct TrainIO {
+// Per-slot training state; every array is column-major [dim][ns].  R is the
+// arithmetic precision (float, or double for the float64 variant).
+template <class R>
+struct TrainIOT {
   int64_t ns;
-  const float4* pos4;
+  const Vec4<R>* pos4;
   const int* cfg_of;
   const int* orig;
   const CfgDev* cfgs;
@@ -16,23 +18,25 @@ struct TrainIO {
   const int* cntR;
   const uint32_t* nbrA;
   const int* cntA;
-  float4* lam4;        // [ns] dL/dF in slot order
+  Vec4<R>* lam4;       // [ns] dL/dF in slot order
   const double* mu;    // [n_cfg][9] dL/dV
   const double* ebar;  // [n_cfg] dL/dE
-  float* Sst;          // [NA*K] S, then sigma = dE/dS
-  float* Sdt;          // [NA*K] Sdot, then Sbar = dj/dS
-  float* q;            // [D]
-  float* qd;           // [D]
-  float* Pb;           // [T*BR] sum_j Q_k per neighbour species
-  float* Pdn;          // [T*BR] -sum_j dQ_k (u.t)
-  float* abar;         // [H]
-  float* zneg;         // [H] -w1 (1 - h^2)
-  float* gw1;          // [H] dj/dw1
-  float* eat;          // [1] ebar of the atom's configuration
-  float* qbR;          // [NR] dj/dq (radial)
-  float* FpR;          // [NR] dE/dq (radial)
-  float* GA;           // [T*NA*BA] angular coefficient gradient of the atom
+  R* Sst;              // [NA*K] S, then sigma = dE/dS
+  R* Sdt;              // [NA*K] Sdot, then Sbar = dj/dS
+  R* q;                // [D]
+  R* qd;               // [D]
+  R* Pb;               // [T*BR] sum_j Q_k per neighbour species
+  R* Pdn;              // [T*BR] -sum_j dQ_k (u.t)
+  R* abar;             // [H]
+  R* zneg;             // [H] -w1 (1 - h^2)
+  R* gw1;              // [H] dj/dw1
+  R* eat;              // [1] ebar of the atom's configuration
+  R* qbR;              // [NR] dj/dq (radial)
+  R* FpR;              // [NR] dE/dq (radial)
+  R* GA;               // [T*NA*BA] angular coefficient gradient of the atom
+  R* Ei;               // [N] site energies, caller order (float64 variant only; may be null)
 };
+using TrainIO = TrainIOT<float>;
 
 struct TrainSeedArgs {
   const RedItem* items;
@@ -56,11 +60,36 @@ struct TrainSeedArgs {
   double* loss;
 };
 
+// Inputs of the float64 variant: positions in caller order, float64 (the
+// neighbour lists are built from their float32 rounding; every pair is then
+// tested and evaluated in float64).
+struct F64Args {
+  const int64_t* atom_off;  // device [n_cfg + 1]
+  int n_cfg;
+  const double* pos;        // device [N][3]
+  const double* params;     // device [P], the parameter layout of the model
+  double4* pos4;            // work: [ns] positions in slot order
+  double* Wi;               // work: [N][9] per-atom virial, caller order
+};
+
 template <class S>
 struct TrainLaunch {
   static int seeds(hipStream_t st, const TrainSeedArgs& a);
   static int backward(hipStream_t st, TrainIO io, const Cutoffs& cut, const float* params, const float* lam,
                       const int* base, double* part, double* grad64, float* grad);
+  // float64 variant: energy, forces and virial (per configuration; forces and
+  // site energies in caller order) ...
+  static int forward64(hipStream_t st, TrainIOT<double> io, const CutoffsT<double>& cut, const F64Args& a,
+                       double* energy, double* forces, double* virial);
+  // ... and the parameter gradient of ebar.E + lambda.F + mu:V
+  static int backward64(hipStream_t st, TrainIOT<double> io, const CutoffsT<double>& cut, const F64Args& a,
+                        const double* lam, const int* base, double* part, double* grad);
 };
+
+// float64 helpers: stage positions in slot order, round positions to float32
+// (for the neighbour lists), fill a float64 array.
+int launch_stage64(hipStream_t st, const TrainIOT<double>& io, const F64Args& a, const float4* pos4f);
+int launch_round_pos(hipStream_t st, int64_t n, const double* a, float* b);
+int launch_fill64(hipStream_t st, int64_t n, double v, double* a);
 
 }  // namespace nepmi

@@ -57,6 +57,7 @@ TrainIO train_io(nepmi_model* m, const double* mu, const double* ebar) {
   io.qbR = t.qbR.ptr<float>();
   io.FpR = t.FpR.ptr<float>();
   io.GA = t.GA.ptr<float>();
+  io.Ei = nullptr;
   return io;
 }
 
@@ -69,9 +70,141 @@ int run_backward(nepmi_model* m, hipStream_t st, const double* ebar, const float
                           t.grad64.ptr<double>(), dev_grad);
 }
 
+// ---- float64 variant
+
+int ensure_f64(nepmi_model* m) {
+  const Ops* o = m->ops;
+  F64Bufs& f = m->f64;
+  const size_t ns = (size_t)m->nbr.n_slots, N = (size_t)(m->nbr.N > 0 ? m->nbr.N : 1);
+  const size_t nc = (size_t)(m->nbr.n_cfg > 0 ? m->nbr.n_cfg : 1);
+  const size_t maxE = std::max({(size_t)o->H * o->D, (size_t)o->NR * o->T * o->BR, (size_t)o->T * o->NA * o->BA,
+                                (size_t)o->H});
+  int rc;
+  if ((rc = f.pos4.ensure(32 * ns)) || (rc = f.lam4.ensure(32 * ns)) || (rc = f.ebar1.ensure(8 * nc)) ||
+      (rc = f.mu0.ensure(72 * nc)) || (rc = f.Ei.ensure(8 * N)) || (rc = f.Wi.ensure(72 * N)) ||
+      (rc = f.Sst.ensure(8 * ns * o->NA * o->K)) || (rc = f.Sdt.ensure(8 * ns * o->NA * o->K)) ||
+      (rc = f.q.ensure(8 * ns * o->D)) || (rc = f.qd.ensure(8 * ns * o->D)) ||
+      (rc = f.Pb.ensure(8 * ns * o->T * o->BR)) || (rc = f.Pdn.ensure(8 * ns * o->T * o->BR)) ||
+      (rc = f.abar.ensure(8 * ns * o->H)) || (rc = f.zneg.ensure(8 * ns * o->H)) || (rc = f.gw1.ensure(8 * ns * o->H)) ||
+      (rc = f.eat.ensure(8 * ns)) || (rc = f.qbR.ensure(8 * ns * o->NR)) || (rc = f.FpR.ensure(8 * ns * o->NR)) ||
+      (rc = f.GA.ensure(8 * ns * o->T * o->NA * o->BA)) || (rc = f.part.ensure(8 * (size_t)o->T * 64 * maxE)))
+    return rc;
+  return NEPMI_OK;
+}
+
+TrainIOT<double> f64_io(nepmi_model* m, const double* mu, const double* ebar, double* Ei) {
+  F64Bufs& f = m->f64;
+  TrainIOT<double> io;
+  io.ns = m->nbr.n_slots;
+  io.pos4 = f.pos4.ptr<double4>();
+  io.cfg_of = m->nbr.cfg_of.ptr<int>();
+  io.orig = m->nbr.orig.ptr<int>();
+  io.cfgs = m->nbr.cfgs.ptr<CfgDev>();
+  // the full lists (cutoff, no skin); every kernel tests each pair in float64
+  io.nbrR = m->nbr.nbrR.ptr<uint32_t>();
+  io.cntR = m->nbr.cntR.ptr<int>();
+  io.nbrA = m->nbr.nbrR.ptr<uint32_t>();
+  io.cntA = m->nbr.cntR.ptr<int>();
+  io.lam4 = f.lam4.ptr<double4>();
+  io.mu = mu;
+  io.ebar = ebar;
+  io.Sst = f.Sst.ptr<double>();
+  io.Sdt = f.Sdt.ptr<double>();
+  io.q = f.q.ptr<double>();
+  io.qd = f.qd.ptr<double>();
+  io.Pb = f.Pb.ptr<double>();
+  io.Pdn = f.Pdn.ptr<double>();
+  io.abar = f.abar.ptr<double>();
+  io.zneg = f.zneg.ptr<double>();
+  io.gw1 = f.gw1.ptr<double>();
+  io.eat = f.eat.ptr<double>();
+  io.qbR = f.qbR.ptr<double>();
+  io.FpR = f.FpR.ptr<double>();
+  io.GA = f.GA.ptr<double>();
+  io.Ei = Ei;
+  return io;
+}
+
+CutoffsT<double> f64_cut(const nepmi_model* m) {
+  CutoffsT<double> c;
+  c.rcR = m->hp.rc_radial;
+  c.rcA = m->hp.rc_angular;
+  c.rcR2 = c.rcR * c.rcR;
+  c.rcA2 = c.rcA * c.rcA;
+  c.rclR2 = c.rcR2;
+  c.rclA2 = c.rcA2;
+  return c;
+}
+
+// Lists from the float32 rounding of the positions with a skin far above its
+// rounding error (~1e-5 A at 100 A), so that every pair within a cutoff in
+// float64 is listed; the kernels then test each pair in float64.
+constexpr double kSkin64 = 0.01;
+
+// lists from the float32 rounding of the positions, then the float64 staging
+int prepare64(nepmi_model* m, int n_cfg, const int64_t* atom_off, const double* cells, const double* dev_pos,
+              const int32_t* dev_species, const double* dev_params, hipStream_t st, F64Args& a) {
+  if (n_cfg < 1 || !atom_off || atom_off[0] != 0 || atom_off[n_cfg] < 0) {
+    set_error("invalid batch");
+    return NEPMI_INVALID_ARG;
+  }
+  const int64_t N = atom_off[n_cfg];
+  int rc;
+  if ((rc = m->f64.posf.ensure(12 * (size_t)(N > 0 ? N : 1))) ||
+      (rc = launch_round_pos(st, 3 * N, dev_pos, m->f64.posf.ptr<float>())) ||
+      (rc = m->prepare(n_cfg, atom_off, cells, m->f64.posf.ptr<float>(), dev_species, st, kSkin64)) ||
+      (rc = ensure_f64(m)))
+    return rc;
+  a.atom_off = m->nbr.atom_off_dev.ptr<int64_t>();
+  a.n_cfg = n_cfg;
+  a.pos = dev_pos;
+  a.params = dev_params;
+  a.pos4 = m->f64.pos4.ptr<double4>();
+  a.Wi = m->f64.Wi.ptr<double>();
+  return launch_stage64(st, f64_io(m, nullptr, nullptr, nullptr), a, m->nbr.pos4.ptr<float4>());
+}
+
 }  // namespace
 
 extern "C" {
+
+int nepmi_compute_f64(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, const double* cells,
+                      const double* dev_pos, const int32_t* dev_species, const double* dev_params, double* dev_energy,
+                      double* dev_forces, double* dev_virial, double* dev_atom_energy, void* stream) {
+  if (!m || !cells || !dev_pos || !dev_species || !dev_params || !dev_energy || !dev_forces || !dev_virial) {
+    set_error("null argument");
+    return NEPMI_INVALID_ARG;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  F64Args a;
+  int rc;
+  if ((rc = prepare64(m, n_cfg, atom_off, cells, dev_pos, dev_species, dev_params, st, a))) return rc;
+  F64Bufs& f = m->f64;
+  if ((rc = launch_fill64(st, n_cfg, 1.0, f.ebar1.ptr<double>())) ||
+      (rc = launch_fill64(st, 9 * (int64_t)n_cfg, 0.0, f.mu0.ptr<double>())))
+    return rc;
+  double* Ei = dev_atom_energy ? dev_atom_energy : f.Ei.ptr<double>();
+  TrainIOT<double> io = f64_io(m, f.mu0.ptr<double>(), f.ebar1.ptr<double>(), Ei);
+  return m->ops->forward64(st, io, f64_cut(m), a, dev_energy, dev_forces, dev_virial);
+}
+
+int nepmi_backward_params_f64(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, const double* cells,
+                              const double* dev_pos, const int32_t* dev_species, const double* dev_params,
+                              const double* dev_ebar, const double* dev_lambda, const double* dev_mu,
+                              double* dev_grad, void* stream) {
+  if (!m || !cells || !dev_pos || !dev_species || !dev_params || !dev_ebar || !dev_lambda || !dev_mu || !dev_grad) {
+    set_error("null argument");
+    return NEPMI_INVALID_ARG;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  F64Args a;
+  int rc;
+  if ((rc = prepare64(m, n_cfg, atom_off, cells, dev_pos, dev_species, dev_params, st, a))) return rc;
+  TrainIOT<double> io = f64_io(m, dev_mu, dev_ebar, nullptr);
+  return m->ops->backward64(st, io, f64_cut(m), a, dev_lambda, m->nbr.base.ptr<int>(), m->f64.part.ptr<double>(),
+                            dev_grad);
+}
+
 
 int nepmi_backward_params(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, const double* cells,
                           const float* dev_pos, const int32_t* dev_species, const double* dev_ebar,

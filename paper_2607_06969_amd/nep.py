@@ -142,6 +142,42 @@ class NepModel:
             _ptr(_dev(mu.reshape(-1, 9).contiguous(), torch.float64)), _ptr(g), _stream()))
         return g
 
+    def _f64_inputs(self, batch: Batch, params, pos):
+        P = _dev(torch.as_tensor(params).contiguous(), torch.float64)
+        if P.numel() != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters, got {P.numel()}")
+        X = batch.pos.double().contiguous() if pos is None else _dev(pos.contiguous(), torch.float64)
+        return P, X
+
+    def compute64(self, batch: Batch, params, pos=None, atom_energy=False):
+        """Float64 variant (every operator has float32 and float64 forms, Sec. 3.2): energy (n_cfg,),
+        forces (N, 3) and virial (n_cfg, 3, 3), all float64, at the float64 parameter vector `params`
+        (CUDA tensor, P).  Positions default to the batch's, widened to float64."""
+        P, X = self._f64_inputs(batch, params, pos)
+        dev = batch.pos.device
+        E = torch.empty(batch.n_cfg, dtype=torch.float64, device=dev)
+        F = torch.empty(batch.n_atoms, 3, dtype=torch.float64, device=dev)
+        V = torch.empty(batch.n_cfg, 9, dtype=torch.float64, device=dev)
+        Ea = torch.empty(batch.n_atoms, dtype=torch.float64, device=dev) if atom_energy else None
+        keep, poff, pcel = batch._meta()
+        check(load().nepmi_compute_f64(self._h, batch.n_cfg, poff, pcel, _ptr(X), _ptr(batch.species), _ptr(P),
+                                       _ptr(E), _ptr(F), _ptr(V), _ptr(Ea), _stream()))
+        out = {"E": E, "F": F, "V": V.view(-1, 3, 3)}
+        if atom_energy:
+            out["Ei"] = Ea
+        return out
+
+    def backward_params64(self, batch: Batch, params, ebar, lam, mu, pos=None):
+        """Float64 twin of backward_params, at the float64 parameter vector `params`."""
+        P, X = self._f64_inputs(batch, params, pos)
+        g = torch.empty(self.n_params, dtype=torch.float64, device=batch.pos.device)
+        keep, poff, pcel = batch._meta()
+        check(load().nepmi_backward_params_f64(
+            self._h, batch.n_cfg, poff, pcel, _ptr(X), _ptr(batch.species), _ptr(P),
+            _ptr(_dev(ebar.contiguous(), torch.float64)), _ptr(_dev(lam.reshape(-1, 3).contiguous(), torch.float64)),
+            _ptr(_dev(mu.reshape(-1, 9).contiguous(), torch.float64)), _ptr(g), _stream()))
+        return g
+
     def loss_grad(self, batch: Batch, E_ref, F_ref, V_ref, weights=(1.0, 1.0, 0.1), loss_form=0, grad=True):
         """Loss parts (4,) float64 on the GPU and the gradient (P,) float32 (or None)."""
         dev = batch.pos.device
@@ -237,6 +273,29 @@ class NepFunction(torch.autograd.Function):
         gF = torch.zeros(batch.n_atoms, 3, dtype=torch.float32, device=dev) if gF is None else gF.to(torch.float32)
         gV = torch.zeros(batch.n_cfg, 3, 3, dtype=torch.float64, device=dev) if gV is None else gV.to(torch.float64)
         g = model.backward_params(batch, gE.contiguous(), gF.contiguous(), gV.contiguous())
+        return g, None, None
+
+
+class NepFunction64(torch.autograd.Function):
+    """(params float64) -> (E, F, V) float64 with the float64 parameter backward,
+    so that torch.autograd.gradcheck can verify the hand-written adjoint on the GPU."""
+
+    @staticmethod
+    def forward(ctx, params, model: NepModel, batch: Batch):
+        out = model.compute64(batch, params.detach())
+        ctx.model, ctx.batch = model, batch
+        ctx.save_for_backward(params)
+        return out["E"], out["F"], out["V"]
+
+    @staticmethod
+    def backward(ctx, gE, gF, gV):
+        (params,) = ctx.saved_tensors
+        b = ctx.batch
+        dev = b.pos.device
+        gE = torch.zeros(b.n_cfg, dtype=torch.float64, device=dev) if gE is None else gE.to(torch.float64)
+        gF = torch.zeros(b.n_atoms, 3, dtype=torch.float64, device=dev) if gF is None else gF.to(torch.float64)
+        gV = torch.zeros(b.n_cfg, 3, 3, dtype=torch.float64, device=dev) if gV is None else gV.to(torch.float64)
+        g = ctx.model.backward_params64(b, params.detach(), gE.contiguous(), gF.contiguous(), gV.contiguous())
         return g, None, None
 
 
