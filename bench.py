@@ -227,6 +227,53 @@ def bench_fit(nep, W, hp, epochs=40, minibatch=32):
             "weighted_loss_first_epoch": first, "weighted_loss_last_epoch": last}
 
 
+def bench_fp64(nep, W, hp, params, system, reps=3):
+    """Float64 variant against float32 on the same inputs: energy + forces +
+    virial of the MD cell (atoms/s), and forward + parameter gradient (the
+    vector-Jacobian product with fixed seeds) of the 256-configuration
+    training batch (configs/s)."""
+    import torch
+
+    def timed(f):
+        f()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            f()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    m = nep.NepModel(hp, params)
+    P64 = torch.tensor(params, dtype=torch.float64, device="cuda")
+    b = nep.Batch.from_system(system)
+    t32 = timed(lambda: m.compute(b))
+    t64 = timed(lambda: m.compute64(b, P64))
+    s = W.amorphous_batch()
+    bt = nep.Batch.from_system(s)
+    rng = np.random.default_rng(7)
+    eb = torch.tensor(rng.normal(size=s.n_cfg), device="cuda")
+    lam = torch.tensor(rng.normal(size=(s.n_atoms, 3)), device="cuda")
+    mu = torch.tensor(rng.normal(size=(s.n_cfg, 9)), device="cuda")
+    lam32 = lam.float().contiguous()
+
+    def fwd_bwd32():
+        m.compute(bt)
+        m.backward_params(bt, eb, lam32, mu)
+
+    def fwd_bwd64():
+        m.compute64(bt, P64)
+        m.backward_params64(bt, P64, eb, lam, mu)
+
+    g32 = timed(fwd_bwd32)
+    g64 = timed(fwd_bwd64)
+    n = system.n_atoms
+    return {"workload": f"E+F+V of the {n}-atom MD cell; forward + parameter VJP of {s.n_cfg} amorphous cells "
+                        f"({s.n_atoms} atoms)",
+            "efv_atoms_per_s_f64": n / t64, "efv_atoms_per_s_f32": n / t32, "efv_f64_over_f32_time": t64 / t32,
+            "train_configs_per_s_f64": s.n_cfg / g64, "train_configs_per_s_f32": s.n_cfg / g32,
+            "train_f64_over_f32_time": g64 / g32}
+
+
 def bench_serving(nep, W, hp, params, steps=20):
     """64 independent rocksalt cells of 1e3-2e5 atoms (log-uniform) stepped
     together in one MD handle, against one handle per cell stepped in turn."""
@@ -278,6 +325,7 @@ def main():
                     help="run a plain fill and elementwise add of this many MiB first (counter calibration)")
     ap.add_argument("--no-train", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU path is not built",
@@ -395,6 +443,9 @@ def main():
         out["training"] = bench_training(nep, W, hp)
         print("[bench] fit leg", file=sys.stderr, flush=True)
         out["fit"] = bench_fit(nep, W, hp)
+    if not a.no_fp64:
+        print("[bench] float64 leg", file=sys.stderr, flush=True)
+        out["fp64"] = bench_fp64(nep, W, hp, params, system)
     if not a.no_serve:
         print("[bench] serving leg", file=sys.stderr, flush=True)
         out["serving"] = bench_serving(nep, W, hp, params)

@@ -42,6 +42,8 @@ def test_compute64_matches_oracle(oracle_lib, name):
     got = m.compute64(b, torch.tensor(p, dtype=torch.float64, device="cuda"), atom_energy=True)
     got = {k: v.cpu().numpy() for k, v in got.items()}
     n = np.diff(s.atom_off)
+    print(f"[fp64] {name}: dE/N {np.max(np.abs(got['E'] - ref['E']) / n):.2e} F {rel(got['F'], ref['F']):.2e} "
+          f"V {rel(got['V'].reshape(-1, 9), ref['V'].reshape(-1, 9)):.2e}", flush=True)
     assert np.max(np.abs(got["E"] - ref["E"]) / n) <= 1e-10
     assert rel(got["F"], ref["F"]) <= 1e-10, rel(got["F"], ref["F"])
     assert rel(got["V"].reshape(-1, 9), ref["V"].reshape(-1, 9)) <= 1e-10
@@ -85,6 +87,7 @@ def test_backward64_matches_oracle_loss_gradient(oracle_lib, form):
     g = m.backward_params64(b, P, torch.tensor(eb, device="cuda"), torch.tensor(lam, device="cuda"),
                             torch.tensor(mu, device="cuda")).cpu().numpy()
     parts, g_ref = oracle_lib.loss_grad(hp, student, s, Er, Fr, Vr, weights=w, loss_form=form, nbr_mode=0)
+    print(f"[fp64] loss form {form}: gradient rel {rel(g, g_ref):.2e}", flush=True)
     assert rel(g, g_ref) <= 1e-9, rel(g, g_ref)
 
 
