@@ -662,6 +662,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
 // summed by k_force.  f_ji = dE_j/dr_ji sits in j's compact angular slot of
 // i, whose index is the number of j's Verlet entries before i's that are in
 // j's compact angular list: a popcount of j's entry mask.
+// Gather pipeline ring (a power of two, >= 4), measured at 900k atoms:
+// 4 slots 0.099 ms, 8 slots 0.115 ms, no pipeline 0.125 ms.
+constexpr int kGR = 4;
+
 __global__ __launch_bounds__(kBlock) void k_gather(int64_t n_slots, const int* __restrict__ orig,
                                                    const uint32_t* __restrict__ cnA, const uint32_t* __restrict__ cpA,
                                                    const int* __restrict__ ccA, const uint64_t* __restrict__ amask,
@@ -676,16 +680,63 @@ __global__ __launch_bounds__(kBlock) void k_gather(int64_t n_slots, const int* _
   }
   float4 F = frad[p];
   const int n = ccA[p];
-  for (int k = 0; k < n; ++k) {
-    const int64_t j = cnA[(int64_t)k * n_slots + p] & kNbrMask;
-    const uint32_t rv = cpA[(int64_t)k * n_slots + p] >> 16;  // position of i in j's Verlet list
-    int jc = 0;
-    for (uint32_t w = 0; w < (rv >> 6); ++w) jc += __popcll(amask[(int64_t)w * n_slots + j]);
-    jc += __popcll(amask[(int64_t)(rv >> 6) * n_slots + j] & ((1ull << (rv & 63)) - 1ull));
-    const float4 b = fA[(int64_t)jc * n_slots + j];
-    F.x -= b.x;
-    F.y -= b.y;
-    F.z -= b.z;
+  if (n > 0) {
+    // Three dependent loads per pair (entry, j's mask word, j's pair force),
+    // software-pipelined over a ring of kGR slots: entries kGR pairs ahead,
+    // mask words kGR / 2 ahead, pair forces kGR / 4 ahead.  The loop is
+    // unrolled by kGR so that every slot is a fixed register; rows past the
+    // end are clamped to the last pair.
+    constexpr int R = kGR, RM = R - 1, DM = R / 2, DF = R / 4;
+    uint32_t ej[R], rv[R];
+    uint64_t mw[R];
+    float4 fv[R];
+    const uint32_t* le = cnA + p;
+    const uint32_t* lr = cpA + p;
+    auto entry = [&](int u) {
+      ej[u & RM] = *le & kNbrMask;
+      rv[u & RM] = *lr >> 16;  // position of i in j's Verlet list
+    };
+    auto advance = [&](int k) {  // rows follow pair k + 1, clamped
+      if (k + 1 < n - 1) {
+        le += n_slots;
+        lr += n_slots;
+      }
+    };
+    auto mask = [&](int u) { mw[u & RM] = amask[(int64_t)(rv[u & RM] >> 6) * n_slots + ej[u & RM]]; };
+    auto force = [&](int u) {
+      const uint32_t r = rv[u & RM];
+      const int64_t j = ej[u & RM];
+      int jc = __popcll(mw[u & RM] & ((1ull << (r & 63)) - 1ull));
+      for (uint32_t w = 0; w < (r >> 6); ++w) jc += __popcll(amask[(int64_t)w * n_slots + j]);
+      fv[u & RM] = fA[(int64_t)jc * n_slots + j];
+    };
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      entry(u);
+      advance(u - 1);
+    }
+#pragma unroll
+    for (int u = 0; u < DM; ++u) mask(u);
+#pragma unroll
+    for (int u = 0; u < DF; ++u) force(u);
+    for (int k0 = 0; k0 < n; k0 += R) {
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        const int k = k0 + u;
+        const float4 b = fv[u];
+        // the slot of pair k is free once its force is loaded: refill it
+        // with pair k + R, then move pairs k + DM and k + DF one stage on
+        entry(u);
+        advance(k + R - 1);
+        mask(u + DM);
+        force(u + DF);
+        if (k < n) {
+          F.x -= b.x;
+          F.y -= b.y;
+          F.z -= b.z;
+        }
+      }
+    }
   }
   if (Fuser) {
     Fuser[(int64_t)i * 3 + 0] = F.x;
