@@ -140,30 +140,9 @@ __device__ __forceinline__ void image_shift(const R* __restrict__ H, uint32_t co
   sz = w0 * H[2] + w1 * H[5] + w2 * H[8];
 }
 
-// Chebyshev radial basis of Eq. 12-15:
+// Chebyshev radial basis of Eq. 12-15 and its radial derivative dQ_k/dd:
 //   x = 2 (d/rc - 1)^2 - 1,  f_c = (1 + cos(pi d/rc)) / 2,  Q_k = (T_k(x) + 1)/2 f_c.
 // Valid for d < rc (the caller tests the cutoff).
-template <int B, class R>
-__device__ __forceinline__ void cheb_basis(R d, R rc_inv, R (&Q)[B]) {
-  using C = ShC<R>;
-  const R t = d * rc_inv;
-  const R y = t - R(1.0);
-  const R x = R(2.0) * y * y - R(1.0);
-  const R fc = R(0.5) * (R(1.0) + cospi_(t));
-  const R hf = R(0.5) * fc;
-  R tm = R(1.0), tk = x;
-  Q[0] = fc;
-  if (B > 1) Q[1] = hf * (x + R(1.0));
-#pragma unroll
-  for (int k = 2; k < B; ++k) {
-    const R tn = R(2.0) * x * tk - tm;
-    tm = tk;
-    tk = tn;
-    Q[k] = hf * (tn + R(1.0));
-  }
-}
-
-// Basis and its radial derivative dQ_k/dd.
 template <int B, class R>
 __device__ __forceinline__ void cheb_basis_d(R d, R rc_inv, R (&Q)[B], R (&dQ)[B]) {
   using C = ShC<R>;
