@@ -116,17 +116,8 @@ __global__ void k_md_repermute(int64_t n_slots, const int* __restrict__ orig, co
   ref4[p] = pos4[p];
 }
 
-// Second half kick and per-atom kinetic energy.  Thread 0 also closes the
-// step: it counts the step (and the rebuild, if one ran) and clears the
-// rebuild flag, which no kernel reads after the lists are built.
 __global__ void k_md_kick2(int64_t n_slots, MdConst mc, const int* __restrict__ orig, const float4* __restrict__ pos4,
-                           const float4* __restrict__ F4, float4* __restrict__ vel4, float* __restrict__ Ki,
-                           int* __restrict__ flags, long long* __restrict__ counters) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    if (flags[kFlagRebuild]) counters[1] += 1;
-    counters[0] += 1;
-    flags[kFlagRebuild] = 0;
-  }
+                           const float4* __restrict__ F4, float4* __restrict__ vel4, float* __restrict__ Ki) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n_slots) return;
   const int i = orig[p];
@@ -149,6 +140,14 @@ __global__ void k_md_kin(int64_t n_slots, MdConst mc, const int* __restrict__ or
   if (i < 0) return;
   const float4 v = vel4[p];
   Ki[i] = mc.kin[__float_as_int(pos4[p].w)] * (v.x * v.x + v.y * v.y + v.z * v.z);
+}
+
+__global__ void k_md_finish(int* __restrict__ flags, long long* __restrict__ counters) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    if (flags[kFlagRebuild]) counters[1] += 1;
+    counters[0] += 1;
+    flags[kFlagRebuild] = 0;
+  }
 }
 
 __global__ void k_md_export(int64_t n_slots, const int* __restrict__ orig, const Dbl3* __restrict__ xd,
@@ -344,11 +343,11 @@ struct nepmi_md {
     if ((rc = rebuild(st, flags + kFlagRebuild))) return rc;
     if ((rc = forces(st, true))) return rc;
     hipLaunchKernelGGL(k_md_kick2, dim3(nb256(ns)), dim3(256), 0, st, ns, mc, nbr.orig.ptr<int>(),
-                       nbr.pos4.ptr<float4>(), F4.ptr<float4>(), vel4.ptr<float4>(), Ki.ptr<float>(), flags,
-                       counters.ptr<long long>());
+                       nbr.pos4.ptr<float4>(), F4.ptr<float4>(), vel4.ptr<float4>(), Ki.ptr<float>());
     if ((rc = red.run(st, Ei.ptr<float>(), Wi.ptr<float>(), Ki.ptr<float>(), epot.ptr<double>(), vir.ptr<double>(),
                       ekin.ptr<double>())))
       return rc;
+    hipLaunchKernelGGL(k_md_finish, dim3(1), dim3(64), 0, st, flags, counters.ptr<long long>());
     NEPMI_HIP(hipGetLastError());
     return NEPMI_OK;
   }

@@ -90,7 +90,8 @@ __global__ void k_stage(int64_t N, int n_cfg, const int64_t* __restrict__ atom_o
 // ------------------------------------------------------------ exclusive scan
 
 constexpr int kScanBlock = 1024;
-constexpr int kSortSpecies = 256;  // species the sort keys can hold (a bound for the scan's LDS)
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kScanBlock * kScanItems;
 
 __device__ int block_exclusive_scan(int v, int* sh, int& total) {
   // Hillis-Steele within a block of kScanBlock threads (deterministic).
@@ -109,53 +110,69 @@ __device__ int block_exclusive_scan(int v, int* sh, int& total) {
   return incl - v;
 }
 
-// The whole scan in one workgroup: start[0..M] = exclusive prefix sum of
-// cnt[0..M-1] (start[M] = total), cursor[0..M-1] = start, cnt[0..M] cleared
-// for the next sort, and the species bases base[z] = first slot of species z
-// (groups padded to the wavefront size).  Each thread owns a contiguous chunk;
-// the result is deterministic.  One launch instead of five: inside the MD step
-// graph the gated launches cost about 4 us each even when they return at once.
-__global__ __launch_bounds__(kScanBlock) void k_scan_fused(int* __restrict__ cnt, int M, int total_bins,
-                                                           int n_species, int* __restrict__ start,
-                                                           int* __restrict__ cursor, int* __restrict__ base,
-                                                           const int* __restrict__ gate) {
+// out[0..M] = exclusive prefix sum of in[0..M-1] (out[M] = total), tile level.
+__global__ __launch_bounds__(kScanBlock) void k_scan_tiles(const int* __restrict__ in, int M, int* __restrict__ out,
+                                                           int* __restrict__ tile_sums, const int* __restrict__ gate) {
   if (gate && *gate == 0) return;
   __shared__ int sh[kScanBlock];
-  __shared__ int zstart[kSortSpecies + 1];
-  const int t = threadIdx.x;
-  const int chunk = (M + kScanBlock - 1) / kScanBlock;
-  const int a = min(t * chunk, M), b = min(a + chunk, M);
-  int s = 0;
-#pragma unroll 8
-  for (int i = a; i < b; ++i) s += cnt[i];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  int v[kScanItems], s = 0;
+  for (int j = 0; j < kScanItems; ++j) {
+    v[j] = (base + j < M) ? in[base + j] : 0;
+    s += v[j];
+  }
   int total;
   int ex = block_exclusive_scan(s, sh, total);
-  for (int i = a; i < b; ++i) {
-    const int c = cnt[i];
-    if (i % total_bins == 0) zstart[i / total_bins] = ex;
-    start[i] = ex;
-    cursor[i] = ex;
-    cnt[i] = 0;
-    ex += c;
+  for (int j = 0; j < kScanItems; ++j) {
+    if (base + j < M) out[base + j] = ex;
+    ex += v[j];
   }
-  if (t == 0) {
-    start[M] = total;
-    cnt[M] = 0;
-    zstart[n_species] = total;
+  if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
+}
+
+// Scan of the tile sums (one block; n_tiles <= kScanTile) and the final total.
+__global__ __launch_bounds__(kScanBlock) void k_scan_sums(int* __restrict__ tile_sums, int n_tiles,
+                                                          int* __restrict__ out, int M,
+                                                          const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  __shared__ int sh[kScanBlock];
+  const int base = threadIdx.x * kScanItems;
+  int v[kScanItems], s = 0;
+  for (int j = 0; j < kScanItems; ++j) {
+    v[j] = (base + j < n_tiles) ? tile_sums[base + j] : 0;
+    s += v[j];
   }
-  __syncthreads();
-  if (t == 0) {
-    int acc = 0;
-    for (int z = 0; z < n_species; ++z) {
-      base[z] = acc;
-      const int c = zstart[z + 1] - zstart[z];
-      acc += (c + kWave - 1) / kWave * kWave;
-    }
-    base[n_species] = acc;
+  int total;
+  int ex = block_exclusive_scan(s, sh, total);
+  for (int j = 0; j < kScanItems; ++j) {
+    if (base + j < n_tiles) tile_sums[base + j] = ex;
+    ex += v[j];
   }
+  if (threadIdx.x == 0) out[M] = total;
+}
+
+__global__ void k_scan_add(int* __restrict__ out, int M, const int* __restrict__ tile_sums,
+                           const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < M) out[i] += tile_sums[i / kScanTile];
 }
 
 // ------------------------------------------------------- processing order
+
+// base[z] = first slot of species z; groups are padded to the wavefront size.
+__global__ void k_species_base(const int* __restrict__ start, int total_bins, int n_species, int* __restrict__ base,
+                               const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int acc = 0;
+  for (int z = 0; z < n_species; ++z) {
+    base[z] = acc;
+    const int c = start[(z + 1) * total_bins] - start[z * total_bins];
+    acc += (c + kWave - 1) / kWave * kWave;
+  }
+  base[n_species] = acc;
+}
 
 // Slot of every atom (order inside a key decided by an atomic; made
 // deterministic by k_sort_keys).
@@ -374,6 +391,13 @@ __global__ void k_fill_int(int* __restrict__ p, int64_t n, int v, const int* __r
   if (i < n) p[i] = v;
 }
 
+__global__ void k_copy_int(int* __restrict__ dst, const int* __restrict__ src, int64_t n,
+                           const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
 void fill_int(hipStream_t st, int* p, int64_t n, int v, const int* gate) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_fill_int, dim3(nblk(n, 256)), dim3(256), 0, st, p, n, v, gate);
@@ -416,10 +440,6 @@ int NbrPipeline::setup(int n_cfg_, const int64_t* atom_off, const double* cells,
                        double rcA, double skin_, hipStream_t st) {
   if (n_cfg_ < 1 || !atom_off || !cells) {
     set_error("n_cfg must be >= 1 and atom_off, cells non-null");
-    return NEPMI_INVALID_ARG;
-  }
-  if (n_species_ < 1 || n_species_ > kSortSpecies) {
-    set_error("n_species must be in 1.." + std::to_string(kSortSpecies));
     return NEPMI_INVALID_ARG;
   }
   if (atom_off[0] != 0) {
@@ -485,11 +505,16 @@ int NbrPipeline::setup(int n_cfg_, const int64_t* atom_off, const double* cells,
   host_cfgs = hc;
   host_off.assign(atom_off, atom_off + n_cfg_ + 1);
   const int64_t M = (int64_t)n_species_ * bins;
+  const int64_t n_tiles = (M + kScanTile - 1) / kScanTile;
+  if (n_tiles > kScanTile) {
+    set_error("too many sort keys");
+    return NEPMI_INVALID_ARG;
+  }
   int rc;
   const size_t Na = (size_t)(N > 0 ? N : 1);
   if ((rc = cfgs.ensure(sizeof(CfgDev) * (size_t)n_cfg_)) || (rc = atom_off_dev.ensure(8 * (size_t)(n_cfg_ + 1))) ||
       (rc = key.ensure(4 * Na)) || (rc = cnt.ensure(4 * (size_t)(M + 1))) || (rc = start.ensure(4 * (size_t)(M + 1))) ||
-      (rc = cursor.ensure(4 * (size_t)(M + 1))) ||
+      (rc = cursor.ensure(4 * (size_t)(M + 1))) || (rc = tile_sums.ensure(4 * (size_t)(n_tiles + 1))) ||
       (rc = base.ensure(4 * (size_t)(n_species_ + 1))) || (rc = perm.ensure(4 * (size_t)n_slots)) ||
       (rc = pos_tmp.ensure(16 * Na)) || (rc = cfg_tmp.ensure(4 * Na)) || (rc = crd_tmp.ensure(4 * Na)) || (rc = pos4.ensure(16 * (size_t)n_slots)) ||
       (rc = cfg_of.ensure(4 * (size_t)n_slots)) || (rc = orig.ensure(4 * (size_t)n_slots)) ||
@@ -500,8 +525,6 @@ int NbrPipeline::setup(int n_cfg_, const int64_t* atom_off, const double* cells,
     return rc;
   NEPMI_HIP(hipMemcpyAsync(cfgs.p, hc.data(), sizeof(CfgDev) * (size_t)n_cfg_, hipMemcpyHostToDevice, st));
   NEPMI_HIP(hipMemcpyAsync(atom_off_dev.p, atom_off, 8 * (size_t)(n_cfg_ + 1), hipMemcpyHostToDevice, st));
-  // the sort counts start at zero; the scan of every sort clears them again
-  fill_int(st, cnt.ptr<int>(), M + 1, 0, nullptr);
   if (capR == 0) {
     // initial capacity from the densest configuration
     double dmax = 0.0;
@@ -578,13 +601,22 @@ int NbrPipeline::build(hipStream_t st, const float* pos, const int32_t* species)
 int NbrPipeline::launch_sort(hipStream_t st, const float* pos, int pos_stride, const int32_t* species, int n_species,
                              const int* gate) {
   const int M = n_species * total_bins;
-  // cnt is zero here: cleared by setup() and by the previous sort's scan
+  fill_int(st, cnt.ptr<int>(), M + 1, 0, gate);
   if (N > 0)
   hipLaunchKernelGGL(k_stage, dim3(nblk(N, 256)), dim3(256), 0, st, N, n_cfg, atom_off_dev.ptr<int64_t>(),
                      cfgs.ptr<CfgDev>(), pos, pos_stride, species, n_species, total_bins, pos_tmp.ptr<float4>(),
                      cfg_tmp.ptr<int>(), crd_tmp.ptr<int>(), key.ptr<int>(), cnt.ptr<int>(), flags.ptr<int>(), gate);
-  hipLaunchKernelGGL(k_scan_fused, dim3(1), dim3(kScanBlock), 0, st, cnt.ptr<int>(), M, total_bins, n_species,
-                     start.ptr<int>(), cursor.ptr<int>(), base.ptr<int>(), gate);
+  const int n_tiles = (M + kScanTile - 1) / kScanTile;
+  hipLaunchKernelGGL(k_scan_tiles, dim3(n_tiles), dim3(kScanBlock), 0, st, cnt.ptr<int>(), M, start.ptr<int>(),
+                     tile_sums.ptr<int>(), gate);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, st, tile_sums.ptr<int>(), n_tiles, start.ptr<int>(),
+                     M, gate);
+  hipLaunchKernelGGL(k_scan_add, dim3(nblk(M, 256)), dim3(256), 0, st, start.ptr<int>(), M, tile_sums.ptr<int>(),
+                     gate);
+  hipLaunchKernelGGL(k_species_base, dim3(1), dim3(64), 0, st, start.ptr<int>(), total_bins, n_species,
+                     base.ptr<int>(), gate);
+  hipLaunchKernelGGL(k_copy_int, dim3(nblk(M, 256)), dim3(256), 0, st, cursor.ptr<int>(), start.ptr<int>(), (int64_t)M,
+                     gate);
   if (N > 0)
   hipLaunchKernelGGL(k_scatter, dim3(nblk(N, 256)), dim3(256), 0, st, N, key.ptr<int>(), start.ptr<int>(),
                      cursor.ptr<int>(), base.ptr<int>(), total_bins, perm.ptr<int>(), gate);

@@ -52,7 +52,7 @@ struct NbrPipeline {
   std::vector<int64_t> host_off;
 
   DevBuf cfgs, atom_off_dev;
-  DevBuf key, cnt, start, cursor, base, perm, pos_tmp, cfg_tmp, crd_tmp;
+  DevBuf key, cnt, start, cursor, tile_sums, base, perm, pos_tmp, cfg_tmp, crd_tmp;
   DevBuf pos4, cfg_of, orig, bin_of, slot_of;
   DevBuf nbrR, cntR;             // Verlet list (rc_radial + skin)
   DevBuf nbrT;                   // the same list row-major, rows of rowT entries (reverse search)
