@@ -127,16 +127,19 @@ __global__ __launch_bounds__(kTB) void k_loss_forces(const RedItem* __restrict__
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0] * cF;
 }
 
-// Energy and virial terms, seeds ebar_c and mu_c, and the loss parts.
-__global__ void k_loss_final(int n_cfg, int form, double wE, double wV, const int64_t* __restrict__ off,
-                             const int* __restrict__ item_start, const double* __restrict__ partF,
-                             const double* __restrict__ E, const double* __restrict__ Eref,
-                             const double* __restrict__ V, const double* __restrict__ Vref, double* __restrict__ ebar,
-                             double* __restrict__ mu, double* __restrict__ loss) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Energy and virial terms, seeds ebar_c and mu_c, and the loss parts.  One
+// block: a thread per configuration, then fixed-order sums in float64.
+__global__ __launch_bounds__(kTB) void k_loss_final(int n_cfg, int form, double wE, double wV,
+                                                    const int64_t* __restrict__ off,
+                                                    const int* __restrict__ item_start,
+                                                    const double* __restrict__ partF, const double* __restrict__ E,
+                                                    const double* __restrict__ Eref, const double* __restrict__ V,
+                                                    const double* __restrict__ Vref, double* __restrict__ ebar,
+                                                    double* __restrict__ mu, double* __restrict__ loss) {
+  __shared__ double sh[3][kTB];
   double LE = 0.0, LF = 0.0, LV = 0.0;
   const double B = (double)n_cfg;
-  for (int c = 0; c < n_cfg; ++c) {
+  for (int c = threadIdx.x; c < n_cfg; c += kTB) {
     const double Nc = (double)(off[c + 1] - off[c]);
     const double cE = form == 0 ? wE / (B * Nc * Nc) : wE / (B * Nc);
     const double cV = form == 0 ? wV / (9.0 * B * Nc * Nc) : wV / (9.0 * B * Nc);
@@ -150,10 +153,21 @@ __global__ void k_loss_final(int n_cfg, int form, double wE, double wV, const in
     }
     for (int w = item_start[c]; w < item_start[c + 1]; ++w) LF += partF[w];
   }
-  loss[0] = LE + LF + LV;
-  loss[1] = LE;
-  loss[2] = LF;
-  loss[3] = LV;
+  sh[0][threadIdx.x] = LE;
+  sh[1][threadIdx.x] = LF;
+  sh[2][threadIdx.x] = LV;
+  __syncthreads();
+  for (int st = kTB / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st)
+      for (int x = 0; x < 3; ++x) sh[x][threadIdx.x] += sh[x][threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    loss[0] = sh[0][0] + sh[1][0] + sh[2][0];
+    loss[1] = sh[0][0];
+    loss[2] = sh[1][0];
+    loss[3] = sh[2][0];
+  }
 }
 
 // lambda to slot order (Vec4<R>); zero on padding slots
@@ -533,7 +547,6 @@ __global__ __launch_bounds__(kTB) void k_train_coefA(TrainIOT<R> io, CutoffsT<R>
 
 constexpr int kRB = 256;       // threads per reduction block
 constexpr int kRChunk = 32;    // slots staged per step
-constexpr int kRBlocks = 64;   // blocks per species (fixed: deterministic order)
 constexpr int kMaxE = 16;      // entries per thread (A*B <= 4096)
 
 // part[(s * kRBlocks + blk) * A*B + e] = sum over slots i of species s handled
@@ -820,7 +833,7 @@ template <class S>
 int TrainLaunch<S>::seeds(hipStream_t st, const TrainSeedArgs& a) {
   hipLaunchKernelGGL(k_loss_forces, dim3(a.n_items), dim3(kTB), 0, st, a.items, a.form, a.w[1], a.inv_3ntot, a.n_cfg,
                      a.off, a.F, a.Fref, a.lam, a.partF);
-  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, st, a.n_cfg, a.form, a.w[0], a.w[2], a.off, a.item_start,
+  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(kTB), 0, st, a.n_cfg, a.form, a.w[0], a.w[2], a.off, a.item_start,
                      a.partF, a.E, a.Eref, a.V, a.Vref, a.ebar, a.mu, a.loss);
   NEPMI_HIP(hipGetLastError());
   return NEPMI_OK;

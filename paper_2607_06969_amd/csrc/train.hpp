@@ -5,6 +5,13 @@
 
 namespace nepmi {
 
+// Blocks per species of the gradient sums over atoms (a fixed number: the
+// summation order, hence every bit of the gradient, does not depend on the
+// launch).  The partial-sum buffer holds T * kRBlocks * (largest sum) doubles.
+// On the 256-cell batch: 64 blocks 2.27 ms per loss and gradient, 128 1.96,
+// 256 1.88, 512 2.06.
+constexpr int kRBlocks = 256;
+
 // Per-slot training state; every array is column-major [dim][ns].  R is the
 // arithmetic precision (float, or double for the float64 variant).
 template <class R>

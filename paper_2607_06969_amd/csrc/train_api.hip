@@ -23,7 +23,7 @@ int ensure_train(nepmi_model* m) {
       (rc = t.Pb.ensure(4 * ns * o->T * o->BR)) || (rc = t.Pdn.ensure(4 * ns * o->T * o->BR)) ||
       (rc = t.abar.ensure(4 * ns * o->H)) || (rc = t.zneg.ensure(4 * ns * o->H)) || (rc = t.gw1.ensure(4 * ns * o->H)) ||
       (rc = t.eat.ensure(4 * ns)) || (rc = t.qbR.ensure(4 * ns * o->NR)) || (rc = t.FpR.ensure(4 * ns * o->NR)) ||
-      (rc = t.GA.ensure(4 * ns * o->T * o->NA * o->BA)) || (rc = t.part.ensure(8 * (size_t)o->T * 64 * maxE)) ||
+      (rc = t.GA.ensure(4 * ns * o->T * o->NA * o->BA)) || (rc = t.part.ensure(8 * (size_t)o->T * kRBlocks * maxE)) ||
       (rc = t.grad64.ensure(8 * (size_t)o->P)) || (rc = t.gradf.ensure(4 * (size_t)o->P)))
     return rc;
   return NEPMI_OK;
@@ -87,7 +87,7 @@ int ensure_f64(nepmi_model* m) {
       (rc = f.Pb.ensure(8 * ns * o->T * o->BR)) || (rc = f.Pdn.ensure(8 * ns * o->T * o->BR)) ||
       (rc = f.abar.ensure(8 * ns * o->H)) || (rc = f.zneg.ensure(8 * ns * o->H)) || (rc = f.gw1.ensure(8 * ns * o->H)) ||
       (rc = f.eat.ensure(8 * ns)) || (rc = f.qbR.ensure(8 * ns * o->NR)) || (rc = f.FpR.ensure(8 * ns * o->NR)) ||
-      (rc = f.GA.ensure(8 * ns * o->T * o->NA * o->BA)) || (rc = f.part.ensure(8 * (size_t)o->T * 64 * maxE)))
+      (rc = f.GA.ensure(8 * ns * o->T * o->NA * o->BA)) || (rc = f.part.ensure(8 * (size_t)o->T * kRBlocks * maxE)))
     return rc;
   return NEPMI_OK;
 }
