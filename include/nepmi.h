@@ -92,6 +92,18 @@ int nepmi_supported(const nepmi_hparams *hp);
  * The site energy is E_i = w1 . tanh(W0 q_i + b0) + b1 (Sec. 2.3). */
 int nepmi_model_set_params(nepmi_model *m, const float *dev_params, void *stream);
 
+/* Keep neighbour lists between calls on a fixed batch (off by default).
+ * When enabled, a call of nepmi_compute, nepmi_descriptors, nepmi_neighbors,
+ * nepmi_backward_params, nepmi_loss_grad or nepmi_autotune whose batch is
+ * the previous such call's batch (same n_cfg, atom_off and cells, and the
+ * same device addresses of positions and species) keeps the neighbour lists,
+ * processing order and reduction plan of that call instead of rebuilding
+ * them.  The caller guarantees that the positions and species at those
+ * addresses have not changed, as for a training set of fixed configurations
+ * (Sec. 3.3).  The float64 variant always rebuilds.  Enabling or disabling
+ * clears what is kept.  NEPMI_INVALID_ARG on a null model. */
+int nepmi_model_reuse_lists(nepmi_model *m, int32_t enable);
+
 void nepmi_model_destroy(nepmi_model *m);
 
 /* Energy, forces and virial of n_cfg periodic configurations (Eq. 1, 3, 4).

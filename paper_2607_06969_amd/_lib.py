@@ -49,6 +49,7 @@ SIGNATURES = [
     ("nepmi_model_create", C.c_int, [_hp, C.POINTER(_vp)]),
     ("nepmi_supported", C.c_int, [_hp]),
     ("nepmi_model_set_params", C.c_int, [_vp, _vp, _vp]),
+    ("nepmi_model_reuse_lists", C.c_int, [_vp, _i32]),
     ("nepmi_model_destroy", None, [_vp]),
     ("nepmi_compute", C.c_int, [_vp, _i32, _i64p, _dp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     ("nepmi_descriptors", C.c_int, [_vp, _i32, _i64p, _dp, _vp, _vp, _vp, _vp]),

@@ -1,4 +1,5 @@
 // api.hip -- extern "C" entry points: model handle, compute, descriptors.
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
@@ -67,7 +68,13 @@ static int64_t param_count(const nepmi_hparams& h) {
 using namespace nepmi;
 
 int nepmi_model::prepare(int n_cfg, const int64_t* atom_off, const double* cells, const float* pos,
-                         const int32_t* species, hipStream_t st, double skin) {
+                         const int32_t* species, hipStream_t st, double skin, bool may_reuse) {
+  if (n_cfg >= 1 && atom_off && cells && reuse_lists && may_reuse && last.valid && last.pos == pos &&
+      last.species == species && last.skin == skin && last.off.size() == (size_t)n_cfg + 1 &&
+      std::equal(last.off.begin(), last.off.end(), atom_off) &&
+      std::equal(last.cells.begin(), last.cells.end(), cells))
+    return NEPMI_OK;
+  last.valid = false;
   int rc;
   if ((rc = nbr.setup(n_cfg, atom_off, cells, ops->T, hp.rc_radial, hp.rc_angular, skin, st))) return rc;
   if ((rc = nbr.build(st, pos, species))) return rc;
@@ -77,6 +84,14 @@ int nepmi_model::prepare(int n_cfg, const int64_t* atom_off, const double* cells
       (rc = Ei.ensure(4 * N)) || (rc = frad.ensure(16 * ns)) || (rc = amask.ensure(8 * ns * (size_t)((nbr.capR + 63) / 64))) || (rc = fA.ensure(16 * ns * (size_t)nbr.capA)) ||
       (rc = Wi.ensure(36 * N)) || (rc = Eproc.ensure(4 * ns)))
     return rc;
+  if (may_reuse) {
+    last.valid = true;
+    last.pos = pos;
+    last.species = species;
+    last.skin = skin;
+    last.off.assign(atom_off, atom_off + n_cfg + 1);
+    last.cells.assign(cells, cells + 9 * (size_t)n_cfg);
+  }
   return NEPMI_OK;
 }
 
@@ -174,6 +189,16 @@ int nepmi_model_set_params(nepmi_model* m, const float* dev_params, void* stream
   NEPMI_HIP(hipMemcpyAsync(m->params.p, dev_params, 4 * (size_t)m->ops->P, hipMemcpyDeviceToDevice,
                            (hipStream_t)stream));
   return m->ops->derive((hipStream_t)stream, m->params.ptr<float>());
+}
+
+int nepmi_model_reuse_lists(nepmi_model* m, int32_t enable) {
+  if (!m) {
+    set_error("null model");
+    return NEPMI_INVALID_ARG;
+  }
+  m->reuse_lists = enable != 0;
+  m->last.valid = false;
+  return NEPMI_OK;
 }
 
 void nepmi_model_destroy(nepmi_model* m) { delete m; }

@@ -1,6 +1,8 @@
 // model.hpp -- the model handle and per-shape kernel dispatch.
 #pragma once
 
+#include <vector>
+
 #include "nep_kernels.hpp"
 #include "reduce.hpp"
 #include "train.hpp"
@@ -53,9 +55,20 @@ struct nepmi_model {
   int vdesc = 0, vforce = 0;  // kernel variants in use (see nepmi_autotune)
   bool pinned = false;        // variants chosen by nepmi_set_variants: MD creation keeps them
   // Prepare the batch: neighbour lists (pairs within the cutoffs + skin),
-  // work buffers and reduction plan.
+  // work buffers and reduction plan.  With reuse_lists set and may_reuse, a
+  // batch identical to the previous one (same sizes, cells and device
+  // pointers) keeps what the previous call prepared.
   int prepare(int n_cfg, const int64_t* atom_off, const double* cells, const float* pos, const int32_t* species,
-              hipStream_t st, double skin = 0.0);
+              hipStream_t st, double skin = 0.0, bool may_reuse = true);
+  bool reuse_lists = false;
+  struct {
+    bool valid = false;
+    const float* pos = nullptr;
+    const int32_t* species = nullptr;
+    double skin = 0.0;
+    std::vector<int64_t> off;
+    std::vector<double> cells;
+  } last;
   nepmi::NepIO io(float* Fuser, float4* Fproc, float* qout);
 };
 

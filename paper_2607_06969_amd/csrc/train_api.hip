@@ -152,7 +152,7 @@ int prepare64(nepmi_model* m, int n_cfg, const int64_t* atom_off, const double* 
   int rc;
   if ((rc = m->f64.posf.ensure(12 * (size_t)(N > 0 ? N : 1))) ||
       (rc = launch_round_pos(st, 3 * N, dev_pos, m->f64.posf.ptr<float>())) ||
-      (rc = m->prepare(n_cfg, atom_off, cells, m->f64.posf.ptr<float>(), dev_species, st, kSkin64)) ||
+      (rc = m->prepare(n_cfg, atom_off, cells, m->f64.posf.ptr<float>(), dev_species, st, kSkin64, false)) ||
       (rc = ensure_f64(m)))
     return rc;
   a.atom_off = m->nbr.atom_off_dev.ptr<int64_t>();

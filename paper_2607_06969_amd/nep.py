@@ -79,6 +79,11 @@ class NepModel:
         self._params = p
         check(load().nepmi_model_set_params(self._h, _ptr(p), _stream()))
 
+    def reuse_lists(self, enable=True):
+        """Keep neighbour lists between calls on an unchanged batch (same tensors, same contents);
+        the caller guarantees the positions and species have not changed (fixed training sets)."""
+        check(load().nepmi_model_reuse_lists(self._h, 1 if enable else 0))
+
     def compute(self, batch: Batch, atom_energy=False, atom_virial=False):
         """Energy (n_cfg,) float64, forces (N, 3) float32, virial (n_cfg, 3, 3) float64."""
         dev = batch.pos.device
@@ -225,8 +230,12 @@ class Trainer:
 
     def __init__(self, model: NepModel, total_steps, warmup_steps, lr_start=1e-3, lr_end=1e-5,
                  w_start=(1.0, 1.0, 0.1), w_end=(1.0, 1.0, 0.1), normalised=True, loss_form=1,
-                 betas=(0.9, 0.999), eps=1e-8):
+                 betas=(0.9, 0.999), eps=1e-8, reuse_lists=False):
+        """reuse_lists: the batches passed to step() are fixed configurations whose tensors are never
+        modified, so neighbour lists are kept while the same batch comes back."""
         self.model = model
+        if reuse_lists:
+            model.reuse_lists(True)
         self.params = model._params.clone()
         self.m = torch.zeros_like(self.params)
         self.v = torch.zeros_like(self.params)

@@ -113,3 +113,27 @@ def test_autograd_function():
     obj.backward()
     g_vjp = m.backward_params(b, cE, cF, cV)
     assert torch.allclose(p.grad, g_vjp, rtol=1e-6, atol=1e-9)
+
+
+def test_reuse_lists_on_fixed_batches():
+    """With lists kept between calls, results are bitwise those of a model that
+    rebuilds every time, and a different batch (new tensors) is rebuilt."""
+    from paper_2607_06969_amd import nep
+    hp = W.hp_gst()
+    s1 = W.amorphous_batch(n_cfg=5, n_min=64, n_max=200, seed=74)
+    s2 = W.amorphous_batch(n_cfg=3, n_min=64, n_max=200, seed=75)
+    teacher = nep.NepModel(hp, W.random_params(hp, W.SEED_TEACHER))
+    p = W.random_params(hp, W.SEED_STUDENT)
+    fresh, kept = nep.NepModel(hp, p), nep.NepModel(hp, p)
+    kept.reuse_lists(True)
+    data = []
+    for s in (s1, s2):
+        b = nep.Batch.from_system(s)
+        lab = teacher.compute(b)
+        data.append((b, lab["E"], lab["F"].contiguous(), lab["V"].reshape(-1, 9).contiguous()))
+    for b, E, F, V in (data[0], data[0], data[1], data[1], data[0]):
+        l0, g0 = fresh.loss_grad(b, E, F, V, loss_form=1)
+        l1, g1 = kept.loss_grad(b, E, F, V, loss_form=1)
+        assert torch.equal(l0, l1) and torch.equal(g0, g1)
+        c0, c1 = fresh.compute(b), kept.compute(b)
+        assert torch.equal(c0["F"], c1["F"]) and torch.equal(c0["E"], c1["E"])
