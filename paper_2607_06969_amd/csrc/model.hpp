@@ -31,13 +31,13 @@ const Ops* find_ops(const nepmi_hparams& hp);
 // Training-only buffers (see train.hip).
 struct TrainBufs {
   DevBuf F, E, V, lam, ebar, mu, partF, lam4;
-  DevBuf Sst, Sdt, q, qd, Pb, Pdn, abar, zneg, gw1, eat, qbR, FpR, GA, part, grad64, gradf;
+  DevBuf Sst, Sdt, q, qd, Pb, Pdn, abar, zneg, gw1, eat, qbR, FpR, GA, part, grad64, gradf, FpA, qbA;
 };
 
 // Buffers of the float64 variant (see train.hip).
 struct F64Bufs {
   DevBuf posf, pos4, lam4, ebar1, mu0, Ei, Wi;
-  DevBuf Sst, Sdt, q, qd, Pb, Pdn, abar, zneg, gw1, eat, qbR, FpR, GA, part;
+  DevBuf Sst, Sdt, q, qd, Pb, Pdn, abar, zneg, gw1, eat, qbR, FpR, GA, part, FpA, qbA;
 };
 
 }  // namespace nepmi

@@ -183,13 +183,22 @@ __global__ void k_lam_slots(int64_t ns, const int* __restrict__ orig, const R* _
 
 // ------------------------------------------------- tangent + network adjoint
 
-template <class S, int NC, class R>
+// PHASE 1: the tangent pass (radial and angular sums, q and qdot, S and Sdot);
+// PHASE 2: the network adjoint (abar, z, dj/dw1, dE/dq, dj/dq), from q and qdot;
+// PHASE 3: sigma = dE/dS and Sbar = dj/dS, from S, Sdot, dE/dq and dj/dq;
+// PHASE 0: all three in one kernel.  Apart, the phases need far fewer
+// registers; every hand-over goes through the per-slot arrays of io.
+template <class S, int NC, class R, int PHASE>
 __global__ __launch_bounds__(kTB) void k_train_atom(TrainIOT<R> io, CutoffsT<R> cut, const R* __restrict__ params) {
   constexpr int T = S::T, NR = S::NR, NA = S::NA, BR = S::BR, BA = S::BA, L = S::L, K = S::K, D = S::D, H = S::H;
   static_assert(NA % NC == 0, "chunk must divide n_angular");
-  __shared__ R cA_s[T * T * NA * BA];
-  for (int t = threadIdx.x; t < T * T * NA * BA; t += kTB) cA_s[t] = params[S::PCR + t];
-  __syncthreads();
+  constexpr bool kTangent = PHASE == 0 || PHASE == 1, kNet = PHASE == 0 || PHASE == 2;
+  constexpr bool kSigma = PHASE == 0 || PHASE == 3;
+  __shared__ R cA_s[kTangent ? T * T * NA * BA : 1];
+  if constexpr (kTangent) {
+    for (int t = threadIdx.x; t < T * T * NA * BA; t += kTB) cA_s[t] = params[S::PCR + t];
+    __syncthreads();
+  }
   const int64_t ns = io.ns;
   const int64_t p = (int64_t)blockIdx.x * kTB + threadIdx.x;
   if (p >= ns) return;
@@ -198,13 +207,19 @@ __global__ __launch_bounds__(kTB) void k_train_atom(TrainIOT<R> io, CutoffsT<R> 
   const int c = io.cfg_of[p];
   if (c < 0) {
     // padding: zero every per-slot output that is summed over species ranges
-    for (int d = 0; d < D; ++d) io.q[d * ns + p] = io.qd[d * ns + p] = R(0);
-    for (int h = 0; h < H; ++h) io.abar[h * ns + p] = io.zneg[h * ns + p] = io.gw1[h * ns + p] = R(0);
-    for (int k = 0; k < T * BR; ++k) io.Pb[k * ns + p] = io.Pdn[k * ns + p] = R(0);
-    for (int n = 0; n < NR; ++n) io.qbR[n * ns + p] = io.FpR[n * ns + p] = R(0);
-    io.eat[p] = R(0);
+    if constexpr (kTangent) {
+      for (int d = 0; d < D; ++d) io.q[d * ns + p] = io.qd[d * ns + p] = R(0);
+      for (int k = 0; k < T * BR; ++k) io.Pb[k * ns + p] = io.Pdn[k * ns + p] = R(0);
+    }
+    if constexpr (kNet) {
+      for (int h = 0; h < H; ++h) io.abar[h * ns + p] = io.zneg[h * ns + p] = io.gw1[h * ns + p] = R(0);
+      for (int n = 0; n < NR; ++n) io.qbR[n * ns + p] = io.FpR[n * ns + p] = R(0);
+      io.eat[p] = R(0);
+    }
     return;
   }
+  const R eb = (R)io.ebar[c];
+  if constexpr (kTangent) {
   R Hc[9];
   load_cell9(io.cfgs, c, Hc);
   const R rcR_inv = R(1.0) / cut.rcR, rcA_inv = R(1.0) / cut.rcA;
@@ -212,7 +227,6 @@ __global__ __launch_bounds__(kTB) void k_train_atom(TrainIOT<R> io, CutoffsT<R> 
   R mu[9];
 #pragma unroll
   for (int x = 0; x < 9; ++x) mu[x] = (R)io.mu[9 * c + x];
-  const R eb = (R)io.ebar[c];
 
   // ---- radial: P_b[k] = sum_{j in b} Q_k, Pd_b[k] = sum_{j in b} dQ_k (u.t)
   {
@@ -347,6 +361,8 @@ __global__ __launch_bounds__(kTB) void k_train_atom(TrainIOT<R> io, CutoffsT<R> 
       }
     }
   }
+  }  // tangent pass
+  if constexpr (kNet) {
   // ---- network, second-order adjoint; pass 1: abar, z, dj/dw1
   const R* W0 = params + S::PCR + S::PCA + (int64_t)Zs * S::PMLP;
   const R* b0 = W0 + H * D;
@@ -396,6 +412,16 @@ __global__ __launch_bounds__(kTB) void k_train_atom(TrainIOT<R> io, CutoffsT<R> 
     io.qbR[(int64_t)nn * ns + p] = qb[nn];
     io.FpR[(int64_t)nn * ns + p] = Fp[nn];
   }
+#pragma unroll
+  for (int d = NR; d < D; ++d) {
+    io.qbA[(int64_t)d * ns + p] = qb[d];
+    io.FpA[(int64_t)d * ns + p] = Fp[d];
+  }
+  }  // network
+  if constexpr (!kSigma) return;
+  // dE/dq_d and dj/dq_d of descriptor d, as the network pass stored them
+  auto Fp_at = [&](int d) { return io.FpA[(int64_t)d * ns + p]; };
+  auto qb_at = [&](int d) { return io.qbA[(int64_t)d * ns + p]; };
   // ---- sigma = dE/dS and Sbar = dj/dS from the stored S and Sdot
   for (int n = 0; n < NA; ++n) {
     R Sg[K], Sd[K];
@@ -413,13 +439,7 @@ __global__ __launch_bounds__(kTB) void k_train_atom(TrainIOT<R> io, CutoffsT<R> 
       R AAd[9], AdA[9];
       sym_mul_sym(A, Ad, AAd);
       sym_mul_sym(Ad, A, AdA);
-      R fp4 = R(0), qb4 = R(0);
-#pragma unroll
-      for (int x = 0; x < NA; ++x)
-        if (x == n) {
-          fp4 = Fp[S::OFF4 + x];
-          qb4 = qb[S::OFF4 + x];
-        }
+      const R fp4 = Fp_at(S::OFF4 + n), qb4 = qb_at(S::OFF4 + n);
       const int ix[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
 #pragma unroll
       for (int x = 0; x < 6; ++x) {
@@ -432,17 +452,12 @@ __global__ __launch_bounds__(kTB) void k_train_atom(TrainIOT<R> io, CutoffsT<R> 
     }
 #pragma unroll
     for (int l = 1; l <= L; ++l) {
-      R fp3 = R(0), qb3 = R(0), fp5 = R(0), qb5 = R(0);
-#pragma unroll
-      for (int x = 0; x < NA; ++x)
-        if (x == n) {
-          fp3 = Fp[NR + (l - 1) * NA + x];
-          qb3 = qb[NR + (l - 1) * NA + x];
-          if (S::F5) {
-            fp5 = Fp[S::OFF5 + x];
-            qb5 = qb[S::OFF5 + x];
-          }
-        }
+      const R fp3 = Fp_at(NR + (l - 1) * NA + n), qb3 = qb_at(NR + (l - 1) * NA + n);
+      R fp5 = R(0), qb5 = R(0);
+      if constexpr (S::F5) {
+        fp5 = Fp_at(S::OFF5 + n);
+        qb5 = qb_at(S::OFF5 + n);
+      }
       R cs = R(2.0) * fp3;   // sigma = cs S
       R cbS = R(2.0) * qb3;  // Sbar = cbS S + cbD Sdot
       R cbD = -R(2.0) * fp3;
@@ -846,7 +861,9 @@ int TrainLaunch<S>::backward(hipStream_t st, TrainIO io, const Cutoffs& cut, con
   hipLaunchKernelGGL(k_lam_slots<float>, dim3(blocks(ns, 256)), dim3(256), 0, st, ns, io.orig, lam,
                      const_cast<float4*>(io.lam4));
   constexpr int NC = S::NA >= 4 ? 2 : 1;
-  hipLaunchKernelGGL((k_train_atom<S, NC, float>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, params);
+  hipLaunchKernelGGL((k_train_atom<S, NC, float, 1>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, params);
+  hipLaunchKernelGGL((k_train_atom<S, NC, float, 2>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, params);
+  hipLaunchKernelGGL((k_train_atom<S, NC, float, 3>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, params);
   hipLaunchKernelGGL((k_train_coefA<S, float>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, params);
   constexpr int T = S::T;
   const dim3 g(kRBlocks, T);
@@ -907,7 +924,7 @@ int TrainLaunch<S>::forward64(hipStream_t st, TrainIOT<double> io, const Cutoffs
   hipLaunchKernelGGL(k_fill64, dim3(blocks(4 * ns, 256)), dim3(256), 0, st, 4 * ns, 0.0,
                      reinterpret_cast<double*>(io.lam4));
   constexpr int NC = S::NA >= 4 ? 2 : 1;
-  hipLaunchKernelGGL((k_train_atom<S, NC, double>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params);
+  hipLaunchKernelGGL((k_train_atom<S, NC, double, 0>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params);
   hipLaunchKernelGGL((k_pair_force64<S>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params, forces, a.Wi);
   hipLaunchKernelGGL(k_cfg_sum64, dim3(a.n_cfg), dim3(kSB), 0, st, a.atom_off, io.Ei, a.Wi, energy, virial);
   NEPMI_HIP(hipGetLastError());
@@ -920,7 +937,7 @@ int TrainLaunch<S>::backward64(hipStream_t st, TrainIOT<double> io, const Cutoff
   const int64_t ns = io.ns;
   hipLaunchKernelGGL(k_lam_slots<double>, dim3(blocks(ns, 256)), dim3(256), 0, st, ns, io.orig, lam, io.lam4);
   constexpr int NC = S::NA >= 4 ? 2 : 1;
-  hipLaunchKernelGGL((k_train_atom<S, NC, double>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params);
+  hipLaunchKernelGGL((k_train_atom<S, NC, double, 0>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params);
   hipLaunchKernelGGL((k_train_coefA<S, double>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params);
   constexpr int T = S::T;
   const dim3 g(kRBlocks, T);

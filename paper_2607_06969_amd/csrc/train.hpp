@@ -41,6 +41,8 @@ struct TrainIOT {
   R* qbR;              // [NR] dj/dq (radial)
   R* FpR;              // [NR] dE/dq (radial)
   R* GA;               // [T*NA*BA] angular coefficient gradient of the atom
+  R* FpA;              // [D] dE/dq (rows NR..D-1 used), network pass -> sigma pass
+  R* qbA;              // [D] dj/dq (rows NR..D-1 used), network pass -> sigma pass
   R* Ei;               // [N] site energies, caller order (float64 variant only; may be null)
 };
 using TrainIO = TrainIOT<float>;

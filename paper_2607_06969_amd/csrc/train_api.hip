@@ -24,7 +24,8 @@ int ensure_train(nepmi_model* m) {
       (rc = t.abar.ensure(4 * ns * o->H)) || (rc = t.zneg.ensure(4 * ns * o->H)) || (rc = t.gw1.ensure(4 * ns * o->H)) ||
       (rc = t.eat.ensure(4 * ns)) || (rc = t.qbR.ensure(4 * ns * o->NR)) || (rc = t.FpR.ensure(4 * ns * o->NR)) ||
       (rc = t.GA.ensure(4 * ns * o->T * o->NA * o->BA)) || (rc = t.part.ensure(8 * (size_t)o->T * kRBlocks * maxE)) ||
-      (rc = t.grad64.ensure(8 * (size_t)o->P)) || (rc = t.gradf.ensure(4 * (size_t)o->P)))
+      (rc = t.grad64.ensure(8 * (size_t)o->P)) || (rc = t.gradf.ensure(4 * (size_t)o->P)) ||
+      (rc = t.FpA.ensure(4 * ns * o->D)) || (rc = t.qbA.ensure(4 * ns * o->D)))
     return rc;
   return NEPMI_OK;
 }
@@ -57,6 +58,8 @@ TrainIO train_io(nepmi_model* m, const double* mu, const double* ebar) {
   io.qbR = t.qbR.ptr<float>();
   io.FpR = t.FpR.ptr<float>();
   io.GA = t.GA.ptr<float>();
+  io.FpA = t.FpA.ptr<float>();
+  io.qbA = t.qbA.ptr<float>();
   io.Ei = nullptr;
   return io;
 }
@@ -87,7 +90,8 @@ int ensure_f64(nepmi_model* m) {
       (rc = f.Pb.ensure(8 * ns * o->T * o->BR)) || (rc = f.Pdn.ensure(8 * ns * o->T * o->BR)) ||
       (rc = f.abar.ensure(8 * ns * o->H)) || (rc = f.zneg.ensure(8 * ns * o->H)) || (rc = f.gw1.ensure(8 * ns * o->H)) ||
       (rc = f.eat.ensure(8 * ns)) || (rc = f.qbR.ensure(8 * ns * o->NR)) || (rc = f.FpR.ensure(8 * ns * o->NR)) ||
-      (rc = f.GA.ensure(8 * ns * o->T * o->NA * o->BA)) || (rc = f.part.ensure(8 * (size_t)o->T * kRBlocks * maxE)))
+      (rc = f.GA.ensure(8 * ns * o->T * o->NA * o->BA)) || (rc = f.part.ensure(8 * (size_t)o->T * kRBlocks * maxE)) ||
+      (rc = f.FpA.ensure(8 * ns * o->D)) || (rc = f.qbA.ensure(8 * ns * o->D)))
     return rc;
   return NEPMI_OK;
 }
@@ -121,6 +125,8 @@ TrainIOT<double> f64_io(nepmi_model* m, const double* mu, const double* ebar, do
   io.qbR = f.qbR.ptr<double>();
   io.FpR = f.FpR.ptr<double>();
   io.GA = f.GA.ptr<double>();
+  io.FpA = f.FpA.ptr<double>();
+  io.qbA = f.qbA.ptr<double>();
   io.Ei = Ei;
   return io;
 }
