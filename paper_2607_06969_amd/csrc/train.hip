@@ -640,8 +640,16 @@ __global__ void k_part_final(int T, int E, const double* __restrict__ part, int6
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)T * E) return;
   const int s = (int)(t / E), e = (int)(t % E);
-  double acc = 0.0;
-  for (int blk = 0; blk < kRBlocks; ++blk) acc += part[((int64_t)s * kRBlocks + blk) * E + e];
+  // four interleaved partial sums (independent loads in flight), combined in
+  // a fixed order
+  static_assert(kRBlocks % 4 == 0, "partials come in fours");
+  double a4[4] = {0.0, 0.0, 0.0, 0.0};
+  const double* src = part + (int64_t)s * kRBlocks * E + e;
+  for (int blk = 0; blk < kRBlocks; blk += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a4[u] += src[(int64_t)(blk + u) * E];
+  }
+  const double acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
   int64_t dst = e;
   if (kind == 1) {
     const int n = e / (T * BR), r = e % (T * BR), b = r / BR, k = r % BR;
