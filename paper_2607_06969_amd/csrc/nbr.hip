@@ -271,7 +271,17 @@ __global__ __launch_bounds__(256) void k_build_lists(int64_t n_slots, int n_spec
   const float4 xi = pos4[p];
   const int pb = bin_of[p];
   const int b0 = pb & 1023, b1 = (pb >> 10) & 1023, b2 = pb >> 20;
-  int kR = 0, kA = 0;
+  // The 27 stencil bins in ascending bin key, visited per species: slots are
+  // ordered by (species, bin key), so the list comes out in slot order.
+  // Neighbouring atoms then tend to have their k-th neighbours in the same
+  // cache lines, and a wavefront's gather of the k-th neighbours touches fewer
+  // lines than with the stencil order.  Each bin is packed with its image code
+  // (bin key << 5 | code: unique, so the order is total; bin keys are below
+  // 2^27) and sorted by a compare-exchange network with fixed indices, which
+  // stays in registers; the sorted bins wait in this thread's LDS column.
+  __shared__ uint32_t sorted_bins[27 * 256];
+  uint32_t sb[27];
+#pragma unroll
   for (int o = 0; o < 27; ++o) {
     int t0 = b0 + o / 9 - 1, t1 = b1 + (o / 3) % 3 - 1, t2 = b2 + o % 3 - 1;
     const int w0 = t0 < 0 ? -1 : (t0 >= C.nb[0] ? 1 : 0);
@@ -281,10 +291,27 @@ __global__ __launch_bounds__(256) void k_build_lists(int64_t n_slots, int n_spec
     t1 -= w1 * C.nb[1];
     t2 -= w2 * C.nb[2];
     const uint32_t code = (uint32_t)((w0 + 1) * 9 + (w1 + 1) * 3 + (w2 + 1));
-    float sx, sy, sz;
-    image_shift(C.H, code, sx, sy, sz);
-    const int tb = bin_key(C, t0, t1, t2);
-    for (int z = 0; z < n_species; ++z) {
+    sb[o] = ((uint32_t)bin_key(C, t0, t1, t2) << 5) | code;
+  }
+#pragma unroll
+  for (int i = 1; i < 27; ++i)
+#pragma unroll
+    for (int j = i; j > 0; --j) {
+      const uint32_t lo = sb[j - 1] < sb[j] ? sb[j - 1] : sb[j];
+      const uint32_t hi = sb[j - 1] < sb[j] ? sb[j] : sb[j - 1];
+      sb[j - 1] = lo;
+      sb[j] = hi;
+    }
+#pragma unroll
+  for (int o = 0; o < 27; ++o) sorted_bins[o * 256 + threadIdx.x] = sb[o];
+  int kR = 0, kA = 0;
+  for (int z = 0; z < n_species; ++z) {
+    for (int o = 0; o < 27; ++o) {
+      const uint32_t sbo = sorted_bins[o * 256 + threadIdx.x];
+      const int tb = (int)(sbo >> 5);
+      const uint32_t code = sbo & 31u;
+      float sx, sy, sz;
+      image_shift(C.H, code, sx, sy, sz);
       const int k = z * total_bins + tb;
       const int q0 = base[z] + start[k] - start[z * total_bins];
       const int q1 = q0 + start[k + 1] - start[k];
@@ -489,7 +516,9 @@ int NbrPipeline::setup(int n_cfg_, const int64_t* atom_off, const double* cells,
     C.pad = 0;
     bins += (int64_t)((C.nb[0] + 3) / 4) * ((C.nb[1] + 3) / 4) * ((C.nb[2] + 3) / 4) * 64;
   }
-  if (bins * n_species_ > (int64_t)1 << 30) {
+  // bin keys below 2^27: the list build packs a key and a 5-bit image code
+  // into 32 bits
+  if (bins >= (int64_t)1 << 27 || bins * n_species_ > (int64_t)1 << 30) {
     set_error("too many cell bins");
     return NEPMI_INVALID_ARG;
   }

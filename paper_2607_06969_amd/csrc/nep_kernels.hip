@@ -28,6 +28,12 @@ __device__ __forceinline__ PairVec pair_vec(uint32_t e, float4 xq, float4 xi, co
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
+// One neighbour's radial adjoint row (B_R floats).
+template <int BR>
+struct AdjRow {
+  float4 v[BR / 4];
+};
+
 // Network dimensions padded to the 4-wide groups of the matrix instructions.
 template <class S>
 struct MlpPad {
@@ -42,19 +48,43 @@ __device__ __forceinline__ float tanh_fast(float x) {
   return fmaf(-2.0f, __builtin_amdgcn_rcpf(1.0f + e), 1.0f);
 }
 
+// Register copy the compiler cannot see through.  A ring slot is read through
+// it before the slot is reloaded, so the old value is dead when the load
+// issues and the load lands in the slot's own register.  Otherwise the load
+// goes to a fresh register and the loop latch copies it back, which waits for
+// the load just issued and drains the prefetch ring once per trip.
+__device__ __forceinline__ uint32_t take_slot(uint32_t v) {
+  uint32_t r;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "v"(v) : "memory");
+  return r;
+}
+
+// No per-pair loads ahead of the ring's prefetches.
+struct NoPre {
+  __device__ __forceinline__ int operator()(int, uint32_t) const { return 0; }
+};
+
 // Software-pipelined walk over one atom's column of a pair list, calling
-// f(k, entry, neighbour position, aux entry) for k = 0 .. n-1 in order.
-// A pair needs two dependent loads: the list entry (a stream from HBM), then
-// the neighbour's position (a gather, mostly from L2).  Entries (and the
-// optional aux column of the same layout) are loaded DE pairs ahead and
-// positions DX pairs ahead.  The loop is unrolled by DE so that every ring
-// slot is a fixed register: no value is copied while its load is in flight,
-// so a load really has DE (or DX) pairs of work to arrive.  Rows are reached
-// by adding the column stride to a pointer, clamped at the last row, so the
-// loads are unconditional and always in bounds.  An empty list loads nothing.
-template <int DE, int DX, bool AUX, class F>
+// f(k, entry, neighbour position, aux entry, pre(k, entry)) for k = 0 .. n-1
+// in order.  A pair needs two dependent loads: the list entry (a stream from
+// HBM), then the neighbour's position (a gather, mostly from L2).  Entries
+// (and the optional aux column of the same layout) are loaded DE pairs ahead
+// and positions DX pairs ahead.  The loop is unrolled by DE so that every ring
+// slot is a fixed register.  Rows are reached by adding the column stride to a
+// pointer, clamped at the last row, so the loads are unconditional and always
+// in bounds.  An empty list loads nothing.
+//
+// Loads complete in issue order as far as the wait counter is concerned:
+// waiting for a load waits for every load issued before it.  So pair k's own
+// loads (pre, e.g. a row of the neighbour) are issued before the prefetches
+// of this step, and waiting for them leaves the prefetches in flight; pre runs
+// for every lane, on the clamped last entry past the end of a short list.  The
+// prologue issues its loads in the steady state's order, so that the wait
+// counts of the first trip are those of every later one.
+template <int DE, int DX, bool AUX, class Pre, class F>
 __device__ __forceinline__ void walk_pairs(const uint32_t* __restrict__ list, const uint32_t* __restrict__ aux,
-                                           int64_t ns, int64_t p, int n, const float4* __restrict__ pos4, F&& f) {
+                                           int64_t ns, int64_t p, int n, const float4* __restrict__ pos4, Pre&& pre,
+                                           F&& f) {
   static_assert(DX >= 1 && DX < DE && DE % DX == 0, "ring sizes");
   if (n <= 0) return;
   uint32_t e[DE], a[AUX ? DE : 1];
@@ -69,17 +99,19 @@ __device__ __forceinline__ void walk_pairs(const uint32_t* __restrict__ list, co
       lp += ns;
       if constexpr (AUX) ap += ns;
     }
+    if (u >= DE - DX) x[u - (DE - DX)] = pos4[e[u - (DE - DX)] & kNbrMask];
+    __builtin_amdgcn_sched_barrier(0);
   }
   // lp (ap) now points at row min(DE, n - 1)
-#pragma unroll
-  for (int u = 0; u < DX; ++u) x[u] = pos4[e[u] & kNbrMask];
   for (int k0 = 0; k0 < n; k0 += DE) {
 #pragma unroll
     for (int u = 0; u < DE; ++u) {
       const int k = k0 + u;
-      const uint32_t ek = e[u];
-      const uint32_t ak = AUX ? a[u] : 0u;
+      const uint32_t ek = take_slot(e[u]);
+      const uint32_t ak = AUX ? take_slot(a[u]) : 0u;
       const float4 xk = x[u % DX];
+      const auto pk = pre(k, ek);
+      asm volatile("" ::: "memory");  // keeps pre's loads ahead of the prefetches (no sinking into f)
       // entry (and aux) of pair k + DE into the slot just read, then the
       // position of pair k + DX, whose entry arrived DE - DX pairs ago
       e[u] = *lp;
@@ -89,7 +121,7 @@ __device__ __forceinline__ void walk_pairs(const uint32_t* __restrict__ list, co
         if constexpr (AUX) ap += ns;
       }
       x[u % DX] = pos4[e[(u + DX) % DE] & kNbrMask];
-      if (k < n) f(k, ek, xk, ak);
+      if (k < n) f(k, ek, xk, ak, pk);
     }
   }
 }
@@ -152,7 +184,8 @@ __device__ __forceinline__ void angular_sums(const float4* __restrict__ pos4, co
   for (int nn = 0; nn < NH; ++nn)
 #pragma unroll
     for (int lm = 0; lm < K; ++lm) Sg[nn][lm] = 0.f;
-  walk_pairs<kWalkDE, kWalkDX, false>(cnA, nullptr, n_slots, p, nA, pos4, [&](int, uint32_t e, float4 xq, uint32_t) {
+  walk_pairs<kWalkDE, kWalkDX, false>(cnA, nullptr, n_slots, p, nA, pos4, NoPre{},
+                                      [&](int, uint32_t e, float4 xq, uint32_t, int) {
     const PairVec v = pair_vec(e, xq, xi, Hc);
     const float inv = rsqrt_hw(v.d2);
     const RadialF f = radial_f(v.d2 * inv * rcA_inv);
@@ -255,7 +288,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
     uint32_t* cpa = cpA + p;
     uint64_t* mw = amask + p;
     uint64_t mword = 0;  // bit k % 64: entry k of the Verlet list is in the compact angular list
-    walk_pairs<kWalkDE, kWalkDX, true>(nbrR, vrev, n_slots, p, n, pos4, [&](int k, uint32_t e, float4 xq, uint32_t rvk) {
+    walk_pairs<kWalkDE, kWalkDX, true>(nbrR, vrev, n_slots, p, n, pos4, NoPre{},
+                                       [&](int k, uint32_t e, float4 xq, uint32_t rvk, int) {
       const PairVec v = pair_vec(e, xq, xi, Hc);
       if (v.d2 < cut.rcR2) {
         *cr = e;
@@ -449,7 +483,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
     int64_t n_slots, const float4* __restrict__ pos4, const int* __restrict__ cfg_of,
     const int* __restrict__ orig, const CfgDev* __restrict__ cfgs, const uint32_t* __restrict__ cnR,
     const int* __restrict__ ccR, const uint32_t* __restrict__ cnA, const int* __restrict__ ccA, Cutoffs cut, const float* __restrict__ params, const float* __restrict__ fp,
-    const float* __restrict__ aR, float4* __restrict__ frad, float4* __restrict__ fA, float* __restrict__ Wi) {
+    const float* aR, float4* __restrict__ frad, float4* __restrict__ fA, float* __restrict__ Wi) {
+  // aR is not declared restrict: loads through a restrict read-only pointer may
+  // be sunk past the pair walker's barrier, into the pair body after the
+  // prefetches, where waiting for them would drain the prefetch ring
   constexpr int T = S::T, NR = S::NR, NA = S::NA, BR = S::BR, BA = S::BA, L = S::L, K = S::K;
   constexpr int NH = NA / NSPLIT;
   constexpr int RW = lds_row<T * BR>();
@@ -490,12 +527,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
         for (int kk = 0; kk < BR; ++kk) mine[b * BR + kk] = aR[((int64_t)b * n_slots + p) * BR + kk];
     }
     const int n = ccR[p];
-    const float* aRz = aR + (int64_t)Zs * n_slots * BR;
-    walk_pairs<kWalkDE, kWalkDX, false>(cnR, nullptr, n_slots, p, n, pos4, [&](int, uint32_t e, float4 xq, uint32_t) {
+    // the neighbour's adjoint row atil_j[Z_i] (part Z_i of the adjoint, stored
+    // part-major so that a wavefront reads one compact array), loaded ahead of
+    // the ring's prefetches
+    static_assert(BR % 4 == 0, "adjoint rows are read as float4");
+    const float4* aRz = reinterpret_cast<const float4*>(aR + (int64_t)Zs * n_slots * BR);
+    auto row = [&](int, uint32_t e) {
+      AdjRow<BR> r;
+      const float4* src = aRz + (int64_t)(e & kNbrMask) * (BR / 4);
+#pragma unroll
+      for (int c = 0; c < BR / 4; ++c) r.v[c] = src[c];
+      return r;
+    };
+    walk_pairs<kWalkDE, kWalkDX, false>(cnR, nullptr, n_slots, p, n, pos4, row,
+                                        [&](int, uint32_t e, float4 xq, uint32_t, const AdjRow<BR>& arow) {
       const PairVec v = pair_vec(e, xq, xi, Hc);
-      // the neighbour's adjoint row atil_j[Z_i] (part Z_i of the adjoint,
-      // stored part-major so that a wavefront reads one compact array)
-      const float* ar = aRz + (int64_t)v.q * BR;
+      const float* ar = reinterpret_cast<const float*>(arow.v);
       const float inv = rsqrt_hw(v.d2);
       const RadialFD f = radial_fd(v.d2 * inv * rcR_inv, rcR_inv);
       float Tk[BR], Dk[BR];
@@ -586,7 +633,19 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
     // pair forces of this group: f = u sum_n g'_n Z_n + (I - u u^T) v / d,
     // Z_n = sum_lm sigma_nlm P_lm, v = sum_lm G_lm grad P_lm, G_lm = sum_n sigma_nlm g_n
     float4* own = fA + p;  // i's compact slot k of the pair-force buffer
-    walk_pairs<kWalkDE, kWalkDX, false>(cnA, nullptr, n_slots, p, nA, pos4, [&](int, uint32_t e, float4 xq, uint32_t) {
+    // the earlier groups' sum for slot k, loaded ahead of the ring's
+    // prefetches (row clamped at the last pair)
+    const float4* own_ld = fA + p;
+    auto prev = [&](int k, uint32_t) {
+      float4 o = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (h > 0) {
+        o = *own_ld;
+        if (k + 1 < nA) own_ld += n_slots;
+      }
+      return o;
+    };
+    walk_pairs<kWalkDE, kWalkDX, false>(cnA, nullptr, n_slots, p, nA, pos4, prev,
+                                        [&](int, uint32_t e, float4 xq, uint32_t, float4 o) {
       const PairVec v = pair_vec(e, xq, xi, Hc);
       const float inv = rsqrt_hw(v.d2);
       const float ux = v.rx * inv, uy = v.ry * inv, uz = v.rz * inv;
@@ -640,12 +699,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
       W[6] = fmaf(-fz, v.rx, W[6]); W[7] = fmaf(-fz, v.ry, W[7]); W[8] = fmaf(-fz, v.rz, W[8]);
       // dE_i/dr_ij (summed over the groups) stays in i's own compact slot,
       // where j's gather finds it
-      if (h == 0) {
-        *own = make_float4(fx, fy, fz, 0.f);
-      } else {
-        const float4 o = *own;
-        *own = make_float4(o.x + fx, o.y + fy, o.z + fz, 0.f);
-      }
+      *own = h == 0 ? make_float4(fx, fy, fz, 0.f) : make_float4(o.x + fx, o.y + fy, o.z + fz, 0.f);
       own += n_slots;
     });
   }
