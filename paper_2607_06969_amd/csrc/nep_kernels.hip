@@ -48,84 +48,6 @@ __device__ __forceinline__ float tanh_fast(float x) {
   return fmaf(-2.0f, __builtin_amdgcn_rcpf(1.0f + e), 1.0f);
 }
 
-// Register copy the compiler cannot see through.  A ring slot is read through
-// it before the slot is reloaded, so the old value is dead when the load
-// issues and the load lands in the slot's own register.  Otherwise the load
-// goes to a fresh register and the loop latch copies it back, which waits for
-// the load just issued and drains the prefetch ring once per trip.
-__device__ __forceinline__ uint32_t take_slot(uint32_t v) {
-  uint32_t r;
-  asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "v"(v) : "memory");
-  return r;
-}
-
-// No per-pair loads ahead of the ring's prefetches.
-struct NoPre {
-  __device__ __forceinline__ int operator()(int, uint32_t) const { return 0; }
-};
-
-// Software-pipelined walk over one atom's column of a pair list, calling
-// f(k, entry, neighbour position, aux entry, pre(k, entry)) for k = 0 .. n-1
-// in order.  A pair needs two dependent loads: the list entry (a stream from
-// HBM), then the neighbour's position (a gather, mostly from L2).  Entries
-// (and the optional aux column of the same layout) are loaded DE pairs ahead
-// and positions DX pairs ahead.  The loop is unrolled by DE so that every ring
-// slot is a fixed register.  Rows are reached by adding the column stride to a
-// pointer, clamped at the last row, so the loads are unconditional and always
-// in bounds.  An empty list loads nothing.
-//
-// Loads complete in issue order as far as the wait counter is concerned:
-// waiting for a load waits for every load issued before it.  So pair k's own
-// loads (pre, e.g. a row of the neighbour) are issued before the prefetches
-// of this step, and waiting for them leaves the prefetches in flight; pre runs
-// for every lane, on the clamped last entry past the end of a short list.  The
-// prologue issues its loads in the steady state's order, so that the wait
-// counts of the first trip are those of every later one.
-template <int DE, int DX, bool AUX, class Pre, class F>
-__device__ __forceinline__ void walk_pairs(const uint32_t* __restrict__ list, const uint32_t* __restrict__ aux,
-                                           int64_t ns, int64_t p, int n, const float4* __restrict__ pos4, Pre&& pre,
-                                           F&& f) {
-  static_assert(DX >= 1 && DX < DE && DE % DX == 0, "ring sizes");
-  if (n <= 0) return;
-  uint32_t e[DE], a[AUX ? DE : 1];
-  float4 x[DX];
-  const uint32_t* lp = list + p;
-  const uint32_t* ap = AUX ? aux + p : nullptr;
-#pragma unroll
-  for (int u = 0; u < DE; ++u) {
-    e[u] = *lp;
-    if constexpr (AUX) a[u] = *ap;
-    if (u + 1 < n) {
-      lp += ns;
-      if constexpr (AUX) ap += ns;
-    }
-    if (u >= DE - DX) x[u - (DE - DX)] = pos4[e[u - (DE - DX)] & kNbrMask];
-    __builtin_amdgcn_sched_barrier(0);
-  }
-  // lp (ap) now points at row min(DE, n - 1)
-  for (int k0 = 0; k0 < n; k0 += DE) {
-#pragma unroll
-    for (int u = 0; u < DE; ++u) {
-      const int k = k0 + u;
-      const uint32_t ek = take_slot(e[u]);
-      const uint32_t ak = AUX ? take_slot(a[u]) : 0u;
-      const float4 xk = x[u % DX];
-      const auto pk = pre(k, ek);
-      asm volatile("" ::: "memory");  // keeps pre's loads ahead of the prefetches (no sinking into f)
-      // entry (and aux) of pair k + DE into the slot just read, then the
-      // position of pair k + DX, whose entry arrived DE - DX pairs ago
-      e[u] = *lp;
-      if constexpr (AUX) a[u] = *ap;
-      if (k + DE < n - 1) {
-        lp += ns;
-        if constexpr (AUX) ap += ns;
-      }
-      x[u % DX] = pos4[e[(u + DX) % DE] & kNbrMask];
-      if (k < n) f(k, ek, xk, ak, pk);
-    }
-  }
-}
-
 // Prefetch distances, measured at 900k atoms: entries 4 and positions 2
 // pairs ahead; deeper rings (6/2, 6/3, 8/2, 8/4) are no faster.
 constexpr int kWalkDE = 4;

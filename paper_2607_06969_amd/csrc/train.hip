@@ -84,11 +84,11 @@ struct PV {
   int q, zj;
 };
 
+// Pair vector of list entry e whose neighbour position xq is already loaded.
 template <class R>
-__device__ __forceinline__ PV<R> pvec(const Vec4<R>* __restrict__ pos4, uint32_t e, Vec4<R> xi, const R (&H)[9]) {
+__device__ __forceinline__ PV<R> pvec_at(uint32_t e, Vec4<R> xq, Vec4<R> xi, const R (&H)[9]) {
   PV<R> v;
   v.q = (int)(e & kNbrMask);
-  const Vec4<R> xq = pos4[v.q];
   R sx, sy, sz;
   image_shift(H, e >> kNbrShift, sx, sy, sz);
   v.rx = (xq.x - xi.x) + sx;
@@ -98,6 +98,15 @@ __device__ __forceinline__ PV<R> pvec(const Vec4<R>* __restrict__ pos4, uint32_t
   v.zj = species_of(xq);
   return v;
 }
+
+template <class R>
+__device__ __forceinline__ PV<R> pvec(const Vec4<R>* __restrict__ pos4, uint32_t e, Vec4<R> xi, const R (&H)[9]) {
+  return pvec_at(e, pos4[e & kNbrMask], xi, H);
+}
+
+// Pair-walker ring sizes of the training kernels (entries, positions ahead).
+constexpr int kTWalkDE = 4;
+constexpr int kTWalkDX = 2;
 
 // ---------------------------------------------------------------- seeds
 
@@ -224,6 +233,8 @@ __global__ __launch_bounds__(kTB) void k_train_atom(TrainIOT<R> io, CutoffsT<R> 
   load_cell9(io.cfgs, c, Hc);
   const R rcR_inv = R(1.0) / cut.rcR, rcA_inv = R(1.0) / cut.rcA;
   const Vec4<R> li = io.lam4[p];
+  // lambda_j of each pair, loaded by the pair walker ahead of its prefetches
+  auto lam_of = [&](int, uint32_t e) { return io.lam4[e & kNbrMask]; };
   R mu[9];
 #pragma unroll
   for (int x = 0; x < 9; ++x) mu[x] = (R)io.mu[9 * c + x];
@@ -236,13 +247,13 @@ __global__ __launch_bounds__(kTB) void k_train_atom(TrainIOT<R> io, CutoffsT<R> 
 #pragma unroll
       for (int k = 0; k < BR; ++k) P[b][k] = Pd[b][k] = R(0);
     const int n = io.cntR[p];
-    for (int k = 0; k < n; ++k) {
-      const PV<R> v = pvec(io.pos4, io.nbrR[(int64_t)k * ns + p], xi, Hc);
+    walk_pairs<kTWalkDE, kTWalkDX, false>(io.nbrR, nullptr, ns, p, n, io.pos4, lam_of,
+                                          [&](int, uint32_t e, Vec4<R> xq, uint32_t, Vec4<R> lj) {
+      const PV<R> v = pvec_at(e, xq, xi, Hc);
       if (v.d2 < cut.rcR2) {
         const R d = sqrt_(v.d2), inv = R(1.0) / d;
         R Q[BR], dQ[BR];
         cheb_basis_d<BR>(d, rcR_inv, Q, dQ);
-        const Vec4<R> lj = io.lam4[v.q];
         const R tx = lj.x - li.x + mu[0] * v.rx + mu[1] * v.ry + mu[2] * v.rz;
         const R ty = lj.y - li.y + mu[3] * v.rx + mu[4] * v.ry + mu[5] * v.rz;
         const R tz = lj.z - li.z + mu[6] * v.rx + mu[7] * v.ry + mu[8] * v.rz;
@@ -258,7 +269,7 @@ __global__ __launch_bounds__(kTB) void k_train_atom(TrainIOT<R> io, CutoffsT<R> 
           }
         }
       }
-    }
+    });
     const R* cR = params + (int64_t)Zs * (T * NR * BR);
 #pragma unroll
     for (int nn = 0; nn < NR; ++nn) {
@@ -289,14 +300,14 @@ __global__ __launch_bounds__(kTB) void k_train_atom(TrainIOT<R> io, CutoffsT<R> 
     for (int nn = 0; nn < NC; ++nn)
 #pragma unroll
       for (int lm = 0; lm < K; ++lm) Sg[nn][lm] = Sd[nn][lm] = R(0);
-    for (int k = 0; k < nA; ++k) {
-      const PV<R> v = pvec(io.pos4, io.nbrA[(int64_t)k * ns + p], xi, Hc);
+    walk_pairs<kTWalkDE, kTWalkDX, false>(io.nbrA, nullptr, ns, p, nA, io.pos4, lam_of,
+                                          [&](int, uint32_t e, Vec4<R> xq, uint32_t, Vec4<R> lj) {
+      const PV<R> v = pvec_at(e, xq, xi, Hc);
       if (v.d2 < cut.rcA2) {
         const R d = sqrt_(v.d2), inv = R(1.0) / d;
         const R ux = v.rx * inv, uy = v.ry * inv, uz = v.rz * inv;
         R Q[BA], dQ[BA];
         cheb_basis_d<BA>(d, rcA_inv, Q, dQ);
-        const Vec4<R> lj = io.lam4[v.q];
         const R tx = lj.x - li.x + mu[0] * v.rx + mu[1] * v.ry + mu[2] * v.rz;
         const R ty = lj.y - li.y + mu[3] * v.rx + mu[4] * v.ry + mu[5] * v.rz;
         const R tz = lj.z - li.z + mu[6] * v.rx + mu[7] * v.ry + mu[8] * v.rz;
@@ -322,7 +333,7 @@ __global__ __launch_bounds__(kTB) void k_train_atom(TrainIOT<R> io, CutoffsT<R> 
           }
         }
       }
-    }
+    });
 #pragma unroll
     for (int nn = 0; nn < NC; ++nn) {
       const int n = h * NC + nn;
@@ -503,6 +514,8 @@ __global__ __launch_bounds__(kTB) void k_train_coefA(TrainIOT<R> io, CutoffsT<R>
   load_cell9(io.cfgs, c, Hc);
   const R rcA_inv = R(1.0) / cut.rcA;
   const Vec4<R> li = io.lam4[p];
+  // lambda_j of each pair, loaded by the pair walker ahead of its prefetches
+  auto lam_of = [&](int, uint32_t e) { return io.lam4[e & kNbrMask]; };
   R mu[9];
 #pragma unroll
   for (int x = 0; x < 9; ++x) mu[x] = (R)io.mu[9 * c + x];
@@ -519,14 +532,14 @@ __global__ __launch_bounds__(kTB) void k_train_coefA(TrainIOT<R> io, CutoffsT<R>
     for (int b = 0; b < T; ++b)
 #pragma unroll
       for (int k = 0; k < BA; ++k) G[b][k] = R(0);
-    for (int k = 0; k < nA; ++k) {
-      const PV<R> v = pvec(io.pos4, io.nbrA[(int64_t)k * ns + p], xi, Hc);
+    walk_pairs<kTWalkDE, kTWalkDX, false>(io.nbrA, nullptr, ns, p, nA, io.pos4, lam_of,
+                                          [&](int, uint32_t e, Vec4<R> xq, uint32_t, Vec4<R> lj) {
+      const PV<R> v = pvec_at(e, xq, xi, Hc);
       if (v.d2 < cut.rcA2) {
         const R d = sqrt_(v.d2), inv = R(1.0) / d;
         const R ux = v.rx * inv, uy = v.ry * inv, uz = v.rz * inv;
         R Q[BA], dQ[BA];
         cheb_basis_d<BA>(d, rcA_inv, Q, dQ);
-        const Vec4<R> lj = io.lam4[v.q];
         const R tx = lj.x - li.x + mu[0] * v.rx + mu[1] * v.ry + mu[2] * v.rz;
         const R ty = lj.y - li.y + mu[3] * v.rx + mu[4] * v.ry + mu[5] * v.rz;
         const R tz = lj.z - li.z + mu[6] * v.rx + mu[7] * v.ry + mu[8] * v.rz;
@@ -550,7 +563,7 @@ __global__ __launch_bounds__(kTB) void k_train_coefA(TrainIOT<R> io, CutoffsT<R>
           for (int kk = 0; kk < BA; ++kk) G[b][kk] = fma_(mq, Q[kk], fma_(md, dQ[kk], G[b][kk]));
         }
       }
-    }
+    });
 #pragma unroll
     for (int b = 0; b < T; ++b)
 #pragma unroll
@@ -562,74 +575,147 @@ __global__ __launch_bounds__(kTB) void k_train_coefA(TrainIOT<R> io, CutoffsT<R>
 
 constexpr int kRB = 256;       // threads per reduction block
 constexpr int kRChunk = 32;    // slots staged per step
-constexpr int kMaxE = 16;      // entries per thread (A*B <= 4096)
+constexpr int kRS = kRChunk + 1;  // LDS row stride: odd, so that lanes reading
+                                  // one column of different rows hit distinct banks
 
 // part[(s * kRBlocks + blk) * A*B + e] = sum over slots i of species s handled
 // by block blk of  X1[a][i] Y1[b][i] + X2[a][i] Y2[b][i]  (e = a*B + b).
-template <class X>
-__global__ __launch_bounds__(kRB) void k_outer(int64_t ns, const int* __restrict__ base, int A, int B,
-                                               const X* __restrict__ X1, const X* __restrict__ Y1,
-                                               const X* __restrict__ X2, const X* __restrict__ Y2,
-                                               double* __restrict__ part) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  X* sx1 = reinterpret_cast<X*>(smem_raw);
-  X* sy1 = sx1 + A * kRChunk;
-  X* sx2 = sy1 + B * kRChunk;
-  X* sy2 = sx2 + A * kRChunk;
+// Chunks of kRChunk slots are staged in LDS, every load of a chunk issued
+// before the first store (so a chunk costs one memory latency); each thread
+// owns a kOB x kOB block of entries, so one set of LDS reads feeds kOB^2
+// products.  Per chunk an entry is summed in float in slot order, then added
+// in float64.
+constexpr int kOB = 4;
+template <class X, int A, int B>
+__global__ __launch_bounds__(kRB) void k_outer(int64_t ns, const int* __restrict__ base, const X* __restrict__ X1,
+                                               const X* __restrict__ Y1, const X* __restrict__ X2,
+                                               const X* __restrict__ Y2, double* __restrict__ part) {
+  __shared__ X sx1[A * kRS], sx2[A * kRS], sy1[B * kRS], sy2[B * kRS];
+  constexpr int nbB = (B + kOB - 1) / kOB, nblk = ((A + kOB - 1) / kOB) * nbB;
+  static_assert(nblk <= kRB, "one entry block per thread");
+  constexpr int TA = (A * kRChunk + kRB - 1) / kRB, TB = (B * kRChunk + kRB - 1) / kRB;
   const int s = blockIdx.y, blk = blockIdx.x;
   const int p0 = base[s], p1 = base[s + 1];
-  const int AB = A * B;
-  double acc[kMaxE];
+  const bool own = (int)threadIdx.x < nblk;
+  const int a0 = own ? ((int)threadIdx.x / nbB) * kOB : 0, b0 = own ? ((int)threadIdx.x % nbB) * kOB : 0;
+  int ra[kOB], rb[kOB];  // LDS rows, clamped (entries past A or B are computed and dropped)
 #pragma unroll
-  for (int j = 0; j < kMaxE; ++j) acc[j] = 0.0;
+  for (int r = 0; r < kOB; ++r) {
+    ra[r] = min(a0 + r, A - 1) * kRS;
+    rb[r] = min(b0 + r, B - 1) * kRS;
+  }
+  double acc[kOB][kOB];
+#pragma unroll
+  for (int r = 0; r < kOB; ++r)
+#pragma unroll
+    for (int c = 0; c < kOB; ++c) acc[r][c] = 0.0;
   for (int c0 = p0 + blk * kRChunk; c0 < p1; c0 += kRBlocks * kRChunk) {
     const int nc = min(kRChunk, p1 - c0);
-    __syncthreads();
-    for (int t = threadIdx.x; t < A * kRChunk; t += kRB) {
-      const int a = t / kRChunk, i = t % kRChunk;
-      sx1[t] = i < nc ? X1[(int64_t)a * ns + c0 + i] : X(0);
-      sx2[t] = i < nc ? X2[(int64_t)a * ns + c0 + i] : X(0);
-    }
-    for (int t = threadIdx.x; t < B * kRChunk; t += kRB) {
-      const int b = t / kRChunk, i = t % kRChunk;
-      sy1[t] = i < nc ? Y1[(int64_t)b * ns + c0 + i] : X(0);
-      sy2[t] = i < nc ? Y2[(int64_t)b * ns + c0 + i] : X(0);
-    }
-    __syncthreads();
+    X va1[TA], va2[TA], vb1[TB], vb2[TB];
 #pragma unroll
-    for (int j = 0; j < kMaxE; ++j) {
-      const int e = threadIdx.x + j * kRB;
-      if (e < AB) {
-        const int a = e / B, b = e % B;
-        X s1 = X(0);
-        for (int i = 0; i < kRChunk; ++i)
-          s1 = fma_(sx1[a * kRChunk + i], sy1[b * kRChunk + i], fma_(sx2[a * kRChunk + i], sy2[b * kRChunk + i], s1));
-        acc[j] += (double)s1;
+    for (int u = 0; u < TA; ++u) {
+      const int t = threadIdx.x + u * kRB, r = t / kRChunk, i = t % kRChunk;
+      const bool ok = t < A * kRChunk && i < nc;
+      va1[u] = ok ? X1[(int64_t)r * ns + c0 + i] : X(0);
+      va2[u] = ok ? X2[(int64_t)r * ns + c0 + i] : X(0);
+    }
+#pragma unroll
+    for (int u = 0; u < TB; ++u) {
+      const int t = threadIdx.x + u * kRB, r = t / kRChunk, i = t % kRChunk;
+      const bool ok = t < B * kRChunk && i < nc;
+      vb1[u] = ok ? Y1[(int64_t)r * ns + c0 + i] : X(0);
+      vb2[u] = ok ? Y2[(int64_t)r * ns + c0 + i] : X(0);
+    }
+    __syncthreads();  // the previous chunk's LDS reads are done
+#pragma unroll
+    for (int u = 0; u < TA; ++u) {
+      const int t = threadIdx.x + u * kRB;
+      if (t < A * kRChunk) {
+        sx1[(t / kRChunk) * kRS + t % kRChunk] = va1[u];
+        sx2[(t / kRChunk) * kRS + t % kRChunk] = va2[u];
       }
     }
-  }
 #pragma unroll
-  for (int j = 0; j < kMaxE; ++j) {
-    const int e = threadIdx.x + j * kRB;
-    if (e < AB) part[((int64_t)s * kRBlocks + blk) * AB + e] = acc[j];
+    for (int u = 0; u < TB; ++u) {
+      const int t = threadIdx.x + u * kRB;
+      if (t < B * kRChunk) {
+        sy1[(t / kRChunk) * kRS + t % kRChunk] = vb1[u];
+        sy2[(t / kRChunk) * kRS + t % kRChunk] = vb2[u];
+      }
+    }
+    __syncthreads();
+    if (own) {
+      X s1[kOB][kOB];
+#pragma unroll
+      for (int r = 0; r < kOB; ++r)
+#pragma unroll
+        for (int c = 0; c < kOB; ++c) s1[r][c] = X(0);
+      for (int i = 0; i < kRChunk; ++i) {
+        X x1[kOB], x2[kOB], y1[kOB], y2[kOB];
+#pragma unroll
+        for (int r = 0; r < kOB; ++r) {
+          x1[r] = sx1[ra[r] + i];
+          x2[r] = sx2[ra[r] + i];
+          y1[r] = sy1[rb[r] + i];
+          y2[r] = sy2[rb[r] + i];
+        }
+#pragma unroll
+        for (int r = 0; r < kOB; ++r)
+#pragma unroll
+          for (int c = 0; c < kOB; ++c) s1[r][c] = fma_(x1[r], y1[c], fma_(x2[r], y2[c], s1[r][c]));
+      }
+#pragma unroll
+      for (int r = 0; r < kOB; ++r)
+#pragma unroll
+        for (int c = 0; c < kOB; ++c) acc[r][c] += (double)s1[r][c];
+    }
   }
+  if (!own) return;
+#pragma unroll
+  for (int r = 0; r < kOB; ++r)
+#pragma unroll
+    for (int c = 0; c < kOB; ++c)
+      if (a0 + r < A && b0 + c < B) part[((int64_t)s * kRBlocks + blk) * (A * B) + (a0 + r) * B + b0 + c] = acc[r][c];
 }
 
-// part[(s * kRBlocks + blk) * A + a] = sum over the block's slots of X[a][i]
-template <class X>
-__global__ __launch_bounds__(kRB) void k_colsum(int64_t ns, const int* __restrict__ base, int A,
-                                                const X* __restrict__ Xa, double* __restrict__ part) {
+// part[(s * kRBlocks + blk) * A + a] = sum over the block's slots of X[a][i].
+// A block of kCB threads; wavefront w takes rows w, w + kCB/64, ...  Lanes sit
+// on consecutive slots (coalesced), and all of a wavefront's rows are loaded
+// before any is reduced (one memory latency per 64-slot chunk); each chunk is
+// summed across the lanes in a fixed butterfly order (lane 0's sum is used),
+// then added in float64.
+constexpr int kCB = 1024;
+template <class X, int A>
+__global__ __launch_bounds__(kCB) void k_colsum(int64_t ns, const int* __restrict__ base, const X* __restrict__ Xa,
+                                                double* __restrict__ part) {
+  constexpr int NW = kCB / kWave, RPW = (A + NW - 1) / NW;
   const int s = blockIdx.y, blk = blockIdx.x;
   const int p0 = base[s], p1 = base[s + 1];
-  for (int a = threadIdx.x; a < A; a += kRB) {
-    double acc = 0.0;
-    for (int c0 = p0 + blk * kRChunk; c0 < p1; c0 += kRBlocks * kRChunk) {
-      const int c1 = min(c0 + kRChunk, p1);
-      X s1 = X(0);
-      for (int i = c0; i < c1; ++i) s1 += Xa[(int64_t)a * ns + i];
-      acc += (double)s1;
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  double acc[RPW];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) acc[r] = 0.0;
+  for (int c0 = p0 + blk * kWave; c0 < p1; c0 += kRBlocks * kWave) {
+    const int i = c0 + lane;
+    X v[RPW];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      const int a = wv + NW * r;
+      v[r] = (a < A && i < p1) ? Xa[(int64_t)a * ns + i] : X(0);
     }
-    part[((int64_t)s * kRBlocks + blk) * A + a] = acc;
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+#pragma unroll
+      for (int off = kWave / 2; off > 0; off >>= 1) v[r] += __shfl_xor(v[r], off);
+      acc[r] += (double)v[r];
+    }
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      const int a = wv + NW * r;
+      if (a < A) part[((int64_t)s * kRBlocks + blk) * A + a] = acc[r];
+    }
   }
 }
 
@@ -640,14 +726,17 @@ __global__ void k_part_final(int T, int E, const double* __restrict__ part, int6
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)T * E) return;
   const int s = (int)(t / E), e = (int)(t % E);
-  // four interleaved partial sums (independent loads in flight), combined in
-  // a fixed order
-  static_assert(kRBlocks % 4 == 0, "partials come in fours");
+  // four interleaved partial sums, combined in a fixed order; 64 loads are
+  // issued per round trip
+  static_assert(kRBlocks % 64 == 0, "partials come in sixty-fours");
   double a4[4] = {0.0, 0.0, 0.0, 0.0};
   const double* src = part + (int64_t)s * kRBlocks * E + e;
-  for (int blk = 0; blk < kRBlocks; blk += 4) {
+  for (int blk = 0; blk < kRBlocks; blk += 64) {
+    double v[64];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) a4[u] += src[(int64_t)(blk + u) * E];
+    for (int u = 0; u < 64; ++u) v[u] = src[(int64_t)(blk + u) * E];
+#pragma unroll
+    for (int u = 0; u < 64; ++u) a4[u & 3] += v[u];
   }
   const double acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
   int64_t dst = e;
@@ -878,36 +967,36 @@ int TrainLaunch<S>::backward(hipStream_t st, TrainIO io, const Cutoffs& cut, con
   // W0: sum abar q^T - z qdot^T
   {
     const int A = S::H, B = S::D;
-    const size_t sm = sizeof(float) * (size_t)(2 * A + 2 * B) * kRChunk;
-    hipLaunchKernelGGL(k_outer<float>, g, dim3(kRB), sm, st, ns, base, A, B, io.abar, io.q, io.zneg, io.qd, part);
+    hipLaunchKernelGGL((k_outer<float, S::H, S::D>), g, dim3(kRB), 0, st, ns, base, io.abar, io.q, io.zneg, io.qd,
+                       part);
     hipLaunchKernelGGL(k_part_final, dim3(blocks((int64_t)T * A * B, 256)), dim3(256), 0, st, T, A * B, part,
                        S::PCR + S::PCA, S::PMLP, 0, 0, 0, grad64);
   }
   // c^R: sum qbar_R (x) P - Fp_R (x) P'
   {
     const int A = S::NR, B = T * S::BR;
-    const size_t sm = sizeof(float) * (size_t)(2 * A + 2 * B) * kRChunk;
-    hipLaunchKernelGGL(k_outer<float>, g, dim3(kRB), sm, st, ns, base, A, B, io.qbR, io.Pb, io.FpR, io.Pdn, part);
+    hipLaunchKernelGGL((k_outer<float, S::NR, S::T * S::BR>), g, dim3(kRB), 0, st, ns, base, io.qbR, io.Pb, io.FpR,
+                       io.Pdn, part);
     hipLaunchKernelGGL(k_part_final, dim3(blocks((int64_t)T * A * B, 256)), dim3(256), 0, st, T, A * B, part,
                        (int64_t)0, (int64_t)T * S::NR * S::BR, 1, S::NR, S::BR, grad64);
   }
   // c^A
   {
     const int A = T * S::NA * S::BA;
-    hipLaunchKernelGGL(k_colsum<float>, g, dim3(kRB), 0, st, ns, base, A, io.GA, part);
+    hipLaunchKernelGGL((k_colsum<float, S::T * S::NA * S::BA>), g, dim3(kCB), 0, st, ns, base, io.GA, part);
     hipLaunchKernelGGL(k_part_final, dim3(blocks((int64_t)T * A, 256)), dim3(256), 0, st, T, A, part, S::PCR,
                        (int64_t)A, 0, 0, 0, grad64);
   }
   // b0, w1, b1
   {
     const int H = S::H;
-    hipLaunchKernelGGL(k_colsum<float>, g, dim3(kRB), 0, st, ns, base, H, io.abar, part);
+    hipLaunchKernelGGL((k_colsum<float, S::H>), g, dim3(kCB), 0, st, ns, base, io.abar, part);
     hipLaunchKernelGGL(k_part_final, dim3(blocks((int64_t)T * H, 256)), dim3(256), 0, st, T, H, part,
                        S::PCR + S::PCA + (int64_t)H * S::D, S::PMLP, 0, 0, 0, grad64);
-    hipLaunchKernelGGL(k_colsum<float>, g, dim3(kRB), 0, st, ns, base, H, io.gw1, part);
+    hipLaunchKernelGGL((k_colsum<float, S::H>), g, dim3(kCB), 0, st, ns, base, io.gw1, part);
     hipLaunchKernelGGL(k_part_final, dim3(blocks((int64_t)T * H, 256)), dim3(256), 0, st, T, H, part,
                        S::PCR + S::PCA + (int64_t)H * S::D + H, S::PMLP, 0, 0, 0, grad64);
-    hipLaunchKernelGGL(k_colsum<float>, g, dim3(kRB), 0, st, ns, base, 1, io.eat, part);
+    hipLaunchKernelGGL((k_colsum<float, 1>), g, dim3(kCB), 0, st, ns, base, io.eat, part);
     hipLaunchKernelGGL(k_part_final, dim3(1), dim3(64), 0, st, T, 1, part,
                        S::PCR + S::PCA + (int64_t)H * S::D + 2 * H, S::PMLP, 0, 0, 0, grad64);
   }
@@ -951,33 +1040,33 @@ int TrainLaunch<S>::backward64(hipStream_t st, TrainIOT<double> io, const Cutoff
   const dim3 g(kRBlocks, T);
   {
     const int A = S::H, B = S::D;
-    const size_t sm = sizeof(double) * (size_t)(2 * A + 2 * B) * kRChunk;
-    hipLaunchKernelGGL(k_outer<double>, g, dim3(kRB), sm, st, ns, base, A, B, io.abar, io.q, io.zneg, io.qd, part);
+    hipLaunchKernelGGL((k_outer<double, S::H, S::D>), g, dim3(kRB), 0, st, ns, base, io.abar, io.q, io.zneg, io.qd,
+                       part);
     hipLaunchKernelGGL(k_part_final, dim3(blocks((int64_t)T * A * B, 256)), dim3(256), 0, st, T, A * B, part,
                        S::PCR + S::PCA, S::PMLP, 0, 0, 0, grad);
   }
   {
     const int A = S::NR, B = T * S::BR;
-    const size_t sm = sizeof(double) * (size_t)(2 * A + 2 * B) * kRChunk;
-    hipLaunchKernelGGL(k_outer<double>, g, dim3(kRB), sm, st, ns, base, A, B, io.qbR, io.Pb, io.FpR, io.Pdn, part);
+    hipLaunchKernelGGL((k_outer<double, S::NR, S::T * S::BR>), g, dim3(kRB), 0, st, ns, base, io.qbR, io.Pb, io.FpR,
+                       io.Pdn, part);
     hipLaunchKernelGGL(k_part_final, dim3(blocks((int64_t)T * A * B, 256)), dim3(256), 0, st, T, A * B, part,
                        (int64_t)0, (int64_t)T * S::NR * S::BR, 1, S::NR, S::BR, grad);
   }
   {
     const int A = T * S::NA * S::BA;
-    hipLaunchKernelGGL(k_colsum<double>, g, dim3(kRB), 0, st, ns, base, A, io.GA, part);
+    hipLaunchKernelGGL((k_colsum<double, S::T * S::NA * S::BA>), g, dim3(kCB), 0, st, ns, base, io.GA, part);
     hipLaunchKernelGGL(k_part_final, dim3(blocks((int64_t)T * A, 256)), dim3(256), 0, st, T, A, part, S::PCR,
                        (int64_t)A, 0, 0, 0, grad);
   }
   {
     const int H = S::H;
-    hipLaunchKernelGGL(k_colsum<double>, g, dim3(kRB), 0, st, ns, base, H, io.abar, part);
+    hipLaunchKernelGGL((k_colsum<double, S::H>), g, dim3(kCB), 0, st, ns, base, io.abar, part);
     hipLaunchKernelGGL(k_part_final, dim3(blocks((int64_t)T * H, 256)), dim3(256), 0, st, T, H, part,
                        S::PCR + S::PCA + (int64_t)H * S::D, S::PMLP, 0, 0, 0, grad);
-    hipLaunchKernelGGL(k_colsum<double>, g, dim3(kRB), 0, st, ns, base, H, io.gw1, part);
+    hipLaunchKernelGGL((k_colsum<double, S::H>), g, dim3(kCB), 0, st, ns, base, io.gw1, part);
     hipLaunchKernelGGL(k_part_final, dim3(blocks((int64_t)T * H, 256)), dim3(256), 0, st, T, H, part,
                        S::PCR + S::PCA + (int64_t)H * S::D + H, S::PMLP, 0, 0, 0, grad);
-    hipLaunchKernelGGL(k_colsum<double>, g, dim3(kRB), 0, st, ns, base, 1, io.eat, part);
+    hipLaunchKernelGGL((k_colsum<double, 1>), g, dim3(kCB), 0, st, ns, base, io.eat, part);
     hipLaunchKernelGGL(k_part_final, dim3(1), dim3(64), 0, st, T, 1, part,
                        S::PCR + S::PCA + (int64_t)H * S::D + 2 * H, S::PMLP, 0, 0, 0, grad);
   }

@@ -49,6 +49,24 @@ def test_neighbor_sets_match_bruteforce(oracle_lib, sysf, which, rc):
             assert np.max(np.abs(ref[k] - got[k])) < 1e-4
 
 
+def test_list_rows_in_processing_order():
+    """Verlet rows are built in processing-slot order, whose major key is the
+    species (then bin key, then caller index), so that neighbouring atoms'
+    k-th neighbours share cache lines.  Along every row the neighbour species
+    therefore never decrease (the stencil order interleaved them bin by
+    bin)."""
+    nep = _nep()
+    hp = W.hp_gst()
+    for s in (W.rocksalt_gst(8, seed=84), W.amorphous_batch(n_cfg=3, n_min=64, n_max=200, seed=85)):
+        m = nep.NepModel(hp, W.random_params(hp, 1))
+        for which in (0, 1):
+            cnt, nb, _ = m.neighbors(nep.Batch.from_system(s), which, cap=160)
+            cnt, nb = cnt.cpu().numpy(), nb.cpu().numpy()
+            for i in range(s.n_atoms):
+                z = s.species[nb[i, :cnt[i]]]
+                assert np.all(np.diff(z) >= 0), (which, i, z)
+
+
 def test_triclinic_cell_and_unwrapped_positions(oracle_lib):
     nep = _nep()
     hp = W.hp_gst()
