@@ -741,8 +741,9 @@ __global__ void k_derive(const float* __restrict__ params, float* __restrict__ o
 
 // ------------------------------------------------------------- launchers
 
-// Kernel variants: (groups of angular functions per pass, waves per SIMD the
-// register allocation must allow).  Every variant computes the same result;
+// Kernel variants: (passes over the angular pairs, each for n_A / passes of the
+// angular functions; waves per SIMD the register allocation must allow).
+// Every variant computes the same result;
 // descriptor variants are bitwise identical, force variants differ only in
 // the order the per-group pair forces are added.
 template <class S, int NS>

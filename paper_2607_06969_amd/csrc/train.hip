@@ -194,15 +194,15 @@ __global__ void k_lam_slots(int64_t ns, const int* __restrict__ orig, const R* _
 
 // PHASE 1: the tangent pass (radial and angular sums, q and qdot, S and Sdot);
 // PHASE 2: the network adjoint (abar, z, dj/dw1, dE/dq, dj/dq), from q and qdot;
-// PHASE 3: sigma = dE/dS and Sbar = dj/dS, from S, Sdot, dE/dq and dj/dq;
-// PHASE 0: all three in one kernel.  Apart, the phases need far fewer
-// registers; every hand-over goes through the per-slot arrays of io.
+// PHASE 3: sigma = dE/dS and Sbar = dj/dS, from S, Sdot, dE/dq and dj/dq.
+// Apart, the phases need far fewer registers than one kernel doing all three;
+// every hand-over goes through the per-slot arrays of io.
 template <class S, int NC, class R, int PHASE>
 __global__ __launch_bounds__(kTB) void k_train_atom(TrainIOT<R> io, CutoffsT<R> cut, const R* __restrict__ params) {
   constexpr int T = S::T, NR = S::NR, NA = S::NA, BR = S::BR, BA = S::BA, L = S::L, K = S::K, D = S::D, H = S::H;
   static_assert(NA % NC == 0, "chunk must divide n_angular");
-  constexpr bool kTangent = PHASE == 0 || PHASE == 1, kNet = PHASE == 0 || PHASE == 2;
-  constexpr bool kSigma = PHASE == 0 || PHASE == 3;
+  static_assert(PHASE >= 1 && PHASE <= 3, "phases 1-3");
+  constexpr bool kTangent = PHASE == 1, kNet = PHASE == 2, kSigma = PHASE == 3;
   __shared__ R cA_s[kTangent ? T * T * NA * BA : 1];
   if constexpr (kTangent) {
     for (int t = threadIdx.x; t < T * T * NA * BA; t += kTB) cA_s[t] = params[S::PCR + t];
@@ -1021,7 +1021,9 @@ int TrainLaunch<S>::forward64(hipStream_t st, TrainIOT<double> io, const Cutoffs
   hipLaunchKernelGGL(k_fill64, dim3(blocks(4 * ns, 256)), dim3(256), 0, st, 4 * ns, 0.0,
                      reinterpret_cast<double*>(io.lam4));
   constexpr int NC = S::NA >= 4 ? 2 : 1;
-  hipLaunchKernelGGL((k_train_atom<S, NC, double, 0>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params);
+  hipLaunchKernelGGL((k_train_atom<S, NC, double, 1>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params);
+  hipLaunchKernelGGL((k_train_atom<S, NC, double, 2>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params);
+  hipLaunchKernelGGL((k_train_atom<S, NC, double, 3>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params);
   hipLaunchKernelGGL((k_pair_force64<S>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params, forces, a.Wi);
   hipLaunchKernelGGL(k_cfg_sum64, dim3(a.n_cfg), dim3(kSB), 0, st, a.atom_off, io.Ei, a.Wi, energy, virial);
   NEPMI_HIP(hipGetLastError());
@@ -1034,7 +1036,9 @@ int TrainLaunch<S>::backward64(hipStream_t st, TrainIOT<double> io, const Cutoff
   const int64_t ns = io.ns;
   hipLaunchKernelGGL(k_lam_slots<double>, dim3(blocks(ns, 256)), dim3(256), 0, st, ns, io.orig, lam, io.lam4);
   constexpr int NC = S::NA >= 4 ? 2 : 1;
-  hipLaunchKernelGGL((k_train_atom<S, NC, double, 0>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params);
+  hipLaunchKernelGGL((k_train_atom<S, NC, double, 1>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params);
+  hipLaunchKernelGGL((k_train_atom<S, NC, double, 2>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params);
+  hipLaunchKernelGGL((k_train_atom<S, NC, double, 3>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params);
   hipLaunchKernelGGL((k_train_coefA<S, double>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params);
   constexpr int T = S::T;
   const dim3 g(kRBlocks, T);
