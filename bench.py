@@ -185,6 +185,35 @@ def bench_training(nep, W, hp, reps=3):
             "grad_rel_diff_batched_vs_plain": diff, "loss": float(loss[0])}
 
 
+def bench_training_batched(nep, W, hp, reps):
+    """Only the batched forward + loss + parameter gradient of the 256-cell
+    training batch, reps times with the neighbour lists rebuilt and reps times
+    with them kept (for kernel traces of the training path: no other launch
+    shapes are mixed in)."""
+    import torch
+    s = W.amorphous_batch()
+    teacher = nep.NepModel(hp, W.random_params(hp, W.SEED_TEACHER))
+    b = nep.Batch.from_system(s)
+    lab = teacher.compute(b)
+    Er, Fr, Vr = lab["E"], lab["F"].contiguous(), lab["V"].reshape(-1, 9).contiguous()
+    m = nep.NepModel(hp, W.random_params(hp, W.SEED_STUDENT))
+    out = {}
+    for keep in (False, True):
+        m.reuse_lists(keep)
+        m.loss_grad(b, Er, Fr, Vr, loss_form=1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            m.loss_grad(b, Er, Fr, Vr, loss_form=1)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / reps
+        out["lists_kept_ms" if keep else "batched_ms"] = t * 1e3
+        out["lists_kept_configs_per_s" if keep else "batched_configs_per_s"] = s.n_cfg / t
+    m.reuse_lists(False)
+    out.update({"workload": f"{s.n_cfg} amorphous Ge-Sb-Te cells, {s.n_atoms} atoms (64-512 each)", "reps": reps})
+    return out
+
+
 def bench_fit(nep, W, hp, epochs=40, minibatch=32):
     """The optimisation protocol of Sec. 3.3 with the NEP settings of Table 2
     (Adam; lr 1e-3 -> 1e-6 with one epoch of linear warmup from 1e-4 of lr_start,
@@ -337,6 +366,8 @@ def main():
     ap.add_argument("--no-train", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--train-only", type=int, default=0, metavar="REPS",
+                    help="only time REPS batched training calls (lists rebuilt, then kept) and print that line")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU path is not built",
@@ -345,6 +376,13 @@ def main():
 
     import torch
     from paper_2607_06969_amd import nep, workloads as W
+
+    if a.train_only > 0:
+        r = bench_training_batched(nep, W, W.hp_gst(), a.train_only)
+        print(json.dumps({"metric": "training configs/s (forward + loss + parameter gradient, batched)",
+                          "value": r["batched_configs_per_s"], "unit": "configs/s", "n_gpus": 1,
+                          "higher_is_better": True, "dtype": "f32", "data": "synthetic", "config": r}))
+        return
 
     if a.copy_mib > 0:
         # plain elementwise kernels of known size: a fill writing copy_mib MiB,

@@ -583,14 +583,19 @@ constexpr int kRS = kRChunk + 1;  // LDS row stride: odd, so that lanes reading
 // Chunks of kRChunk slots are staged in LDS, every load of a chunk issued
 // before the first store (so a chunk costs one memory latency); each thread
 // owns a kOB x kOB block of entries, so one set of LDS reads feeds kOB^2
-// products.  Per chunk an entry is summed in float in slot order, then added
-// in float64.
-constexpr int kOB = 4;
+// products: 4 x 4 when that still leaves at least 128 blocks of entries, else
+// 2 x 2 (small products would otherwise run on a few threads).  Per chunk an
+// entry is summed in float in slot order, then added in float64.
+template <int A, int B>
+constexpr int outer_block() {
+  return ((A + 3) / 4) * ((B + 3) / 4) >= 128 ? 4 : 2;
+}
 template <class X, int A, int B>
 __global__ __launch_bounds__(kRB) void k_outer(int64_t ns, const int* __restrict__ base, const X* __restrict__ X1,
                                                const X* __restrict__ Y1, const X* __restrict__ X2,
                                                const X* __restrict__ Y2, double* __restrict__ part) {
   __shared__ X sx1[A * kRS], sx2[A * kRS], sy1[B * kRS], sy2[B * kRS];
+  constexpr int kOB = outer_block<A, B>();
   constexpr int nbB = (B + kOB - 1) / kOB, nblk = ((A + kOB - 1) / kOB) * nbB;
   static_assert(nblk <= kRB, "one entry block per thread");
   constexpr int TA = (A * kRChunk + kRB - 1) / kRB, TB = (B * kRChunk + kRB - 1) / kRB;
