@@ -797,15 +797,17 @@ __global__ void k_stage64(int64_t ns, const int* __restrict__ orig, const int* _
 }
 
 // dE_a/dr_ab for centre a (species Za) and neighbour b (species Zb) at
-// r_ab = d u, from a's sigma = dE_a/dS_a (rows [n K + lm] of stride ns at
-// slot sa): with g_n = sum_k c[Za][Zb][n][k] Q_k (Eq. 11-15, 16),
+// r_ab = d u, from a's sigma = dE_a/dS_a (slot-major: the NA K values of slot
+// sa are contiguous, so a lane reads whole cache lines of its neighbour's
+// row): with g_n = sum_k c[Za][Zb][n][k] Q_k (Eq. 11-15, 16),
 //   dE_a/dr_ab = u sum_n g'_n Z_n + (I - u u^T) grad_u(sum_lm G_lm Y_lm) / d,
 //   Z_n = sum_lm sigma_nlm Y_lm(u),  G_lm = sum_n sigma_nlm g_n.
 template <class S>
-__device__ void angular_pair_grad(const double* __restrict__ sigma, int64_t ns, int64_t sa, const double* cA, int Za,
+__device__ void angular_pair_grad(const double* __restrict__ sigmaT, int64_t sa, const double* cA, int Za,
                                   int Zb, double ux, double uy, double uz, double d, double rcA_inv, double& fx,
                                   double& fy, double& fz) {
   constexpr int T = S::T, NA = S::NA, BA = S::BA, L = S::L, K = S::K;
+  const double* sigma = sigmaT + sa * (int64_t)(NA * K);
   double Q[BA], dQ[BA], Y[K], G[K];
   cheb_basis_d<BA>(d, rcA_inv, Q, dQ);
   real_sph<L>(ux, uy, uz, Y);
@@ -824,7 +826,7 @@ __device__ void angular_pair_grad(const double* __restrict__ sigma, int64_t ns, 
     double zn = 0.0;
 #pragma unroll
     for (int lm = 0; lm < K; ++lm) {
-      const double sg = sigma[(int64_t)(n * K + lm) * ns + sa];
+      const double sg = sigma[n * K + lm];
       zn = fma(sg, Y[lm], zn);
       G[lm] = fma(sg, g, G[lm]);
     }
@@ -838,13 +840,25 @@ __device__ void angular_pair_grad(const double* __restrict__ sigma, int64_t ns, 
   fz = s * uz + (gz - ug * uz) / d;
 }
 
+// dst[p][r] = src[r][p] for r < R rows of stride ns (slot-minor to slot-major).
+// Reads coalesce across the lanes; each lane's writes fill its own row, whose
+// lines complete in L2.
+__global__ __launch_bounds__(256) void k_slot_major64(int64_t ns, int R, const double* __restrict__ src,
+                                                      double* __restrict__ dst) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= ns) return;
+  double* row = dst + p * R;
+  for (int r = 0; r < R; ++r) row[r] = src[(int64_t)r * ns + p];
+}
+
 // F_i = sum_j (dE_i/dr_ij - dE_j/dr_ji) (Eq. 3) and the per-atom virial
 // W_i = - sum_j dE_i/dr_ij (x) r_ij, from the per-atom adjoints that the atom
-// pass leaves with zero tangent seeds: FpR = dE/dq (radial) and
-// Sst = sigma = dE/dS.  Caller order for F and W.
+// pass leaves with zero tangent seeds: FpR = dE/dq (radial) and sigma =
+// dE/dS (sigmaT: its slot-major copy).  Caller order for F and W.
 template <class S>
 __global__ __launch_bounds__(kTB) void k_pair_force64(TrainIOT<double> io, CutoffsT<double> cut,
-                                                      const double* __restrict__ params, double* __restrict__ F,
+                                                      const double* __restrict__ params,
+                                                      const double* __restrict__ sigmaT, double* __restrict__ F,
                                                       double* __restrict__ W) {
   constexpr int T = S::T, NR = S::NR, BR = S::BR;
   const int64_t ns = io.ns;
@@ -876,8 +890,12 @@ __global__ __launch_bounds__(kTB) void k_pair_force64(TrainIOT<double> io, Cutof
     cheb_basis_d<BR>(d, rcR_inv, Q, dQ);
     const double* ci = params + ((int64_t)(Zi * T + v.zj) * NR) * BR;
     const double* cj = params + ((int64_t)(v.zj * T + Zi) * NR) * BR;
+    // the neighbour's dE/dq_R, all rows loaded together (one memory latency)
+    double fpj[NR];
+#pragma unroll
+    for (int nn = 0; nn < NR; ++nn) fpj[nn] = io.FpR[(int64_t)nn * ns + v.q];
     double own = 0.0, rev = 0.0;
-#pragma unroll 1
+#pragma unroll
     for (int nn = 0; nn < NR; ++nn) {
       double gi = 0.0, gj = 0.0;
 #pragma unroll
@@ -886,14 +904,14 @@ __global__ __launch_bounds__(kTB) void k_pair_force64(TrainIOT<double> io, Cutof
         gj = fma(cj[nn * BR + kk], dQ[kk], gj);
       }
       own = fma(fpi[nn], gi, own);
-      rev = fma(io.FpR[(int64_t)nn * ns + v.q], gj, rev);
+      rev = fma(fpj[nn], gj, rev);
     }
     double fx = own * ux, fy = own * uy, fz = own * uz;  // dE_i/dr_ij
     double bx = -rev * ux, by = -rev * uy, bz = -rev * uz;  // dE_j/dr_ji (r_ji = -r_ij)
     if (v.d2 < cut.rcA2) {
       double ax, ay, az, cx, cy, cz;
-      angular_pair_grad<S>(io.Sst, ns, p, cA, Zi, v.zj, ux, uy, uz, d, rcA_inv, ax, ay, az);
-      angular_pair_grad<S>(io.Sst, ns, v.q, cA, v.zj, Zi, -ux, -uy, -uz, d, rcA_inv, cx, cy, cz);
+      angular_pair_grad<S>(sigmaT, p, cA, Zi, v.zj, ux, uy, uz, d, rcA_inv, ax, ay, az);
+      angular_pair_grad<S>(sigmaT, v.q, cA, v.zj, Zi, -ux, -uy, -uz, d, rcA_inv, cx, cy, cz);
       fx += ax;
       fy += ay;
       fz += az;
@@ -1029,7 +1047,11 @@ int TrainLaunch<S>::forward64(hipStream_t st, TrainIOT<double> io, const Cutoffs
   hipLaunchKernelGGL((k_train_atom<S, NC, double, 1>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params);
   hipLaunchKernelGGL((k_train_atom<S, NC, double, 2>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params);
   hipLaunchKernelGGL((k_train_atom<S, NC, double, 3>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params);
-  hipLaunchKernelGGL((k_pair_force64<S>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params, forces, a.Wi);
+  // sigma, slot-major, into the Sdot buffer (free once the dE/dS pass is done;
+  // the backward recomputes it)
+  hipLaunchKernelGGL(k_slot_major64, dim3(blocks(ns, 256)), dim3(256), 0, st, ns, S::NA * S::K, io.Sst, io.Sdt);
+  hipLaunchKernelGGL((k_pair_force64<S>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params, io.Sdt, forces,
+                     a.Wi);
   hipLaunchKernelGGL(k_cfg_sum64, dim3(a.n_cfg), dim3(kSB), 0, st, a.atom_off, io.Ei, a.Wi, energy, virial);
   NEPMI_HIP(hipGetLastError());
   return NEPMI_OK;
