@@ -840,15 +840,26 @@ __device__ void angular_pair_grad(const double* __restrict__ sigmaT, int64_t sa,
   fz = s * uz + (gz - ug * uz) / d;
 }
 
-// dst[p][r] = src[r][p] for r < R rows of stride ns (slot-minor to slot-major).
-// Reads coalesce across the lanes; each lane's writes fill its own row, whose
-// lines complete in L2.
-__global__ __launch_bounds__(256) void k_slot_major64(int64_t ns, int R, const double* __restrict__ src,
-                                                      double* __restrict__ dst) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= ns) return;
-  double* row = dst + p * R;
-  for (int r = 0; r < R; ++r) row[r] = src[(int64_t)r * ns + p];
+// dst[p][r] = src[r][p] for r < R rows of stride ns (slot-minor to slot-major),
+// through a 32 x 32 LDS tile so that both the reads and the writes coalesce.
+constexpr int kTT = 32;
+__global__ __launch_bounds__(kTT * 8) void k_slot_major64(int64_t ns, int R, const double* __restrict__ src,
+                                                          double* __restrict__ dst) {
+  __shared__ double tile[kTT][kTT + 1];
+  const int64_t p0 = (int64_t)blockIdx.x * kTT;
+  const int r0 = blockIdx.y * kTT;
+  const int tx = threadIdx.x % kTT, ty = threadIdx.x / kTT;  // 32 x 8 threads
+  for (int y = ty; y < kTT; y += 8) {
+    const int r = r0 + y;
+    const int64_t p = p0 + tx;
+    tile[y][tx] = (r < R && p < ns) ? src[(int64_t)r * ns + p] : 0.0;
+  }
+  __syncthreads();
+  for (int y = ty; y < kTT; y += 8) {
+    const int64_t p = p0 + y;
+    const int r = r0 + tx;
+    if (p < ns && r < R) dst[p * R + r] = tile[tx][y];
+  }
 }
 
 // F_i = sum_j (dE_i/dr_ij - dE_j/dr_ji) (Eq. 3) and the per-atom virial
@@ -1049,7 +1060,8 @@ int TrainLaunch<S>::forward64(hipStream_t st, TrainIOT<double> io, const Cutoffs
   hipLaunchKernelGGL((k_train_atom<S, NC, double, 3>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params);
   // sigma, slot-major, into the Sdot buffer (free once the dE/dS pass is done;
   // the backward recomputes it)
-  hipLaunchKernelGGL(k_slot_major64, dim3(blocks(ns, 256)), dim3(256), 0, st, ns, S::NA * S::K, io.Sst, io.Sdt);
+  hipLaunchKernelGGL(k_slot_major64, dim3(blocks(ns, kTT), (S::NA * S::K + kTT - 1) / kTT), dim3(kTT * 8), 0, st, ns,
+                     S::NA * S::K, io.Sst, io.Sdt);
   hipLaunchKernelGGL((k_pair_force64<S>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params, io.Sdt, forces,
                      a.Wi);
   hipLaunchKernelGGL(k_cfg_sum64, dim3(a.n_cfg), dim3(kSB), 0, st, a.atom_off, io.Ei, a.Wi, energy, virial);
