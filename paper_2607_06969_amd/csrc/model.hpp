@@ -18,7 +18,7 @@ struct Ops {
   int (*seeds)(hipStream_t, const TrainSeedArgs&);
   int (*backward)(hipStream_t, TrainIO, const Cutoffs&, const float*, const float*, const int*, double*, double*,
                   float*);
-  int (*forward64)(hipStream_t, TrainIOT<double>, const CutoffsT<double>&, const F64Args&, double*, double*, double*);
+  int (*forward64)(hipStream_t, TrainIOT<double>, const CutoffsT<double>&, const F64Args&, double*);
   int (*backward64)(hipStream_t, TrainIOT<double>, const CutoffsT<double>&, const F64Args&, const double*, const int*,
                     double*, double*);
   int T, NR, NA, BR, BA, L, D, NANG, H, K;

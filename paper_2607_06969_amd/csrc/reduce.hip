@@ -11,10 +11,11 @@ namespace nepmi {
 
 constexpr int kRedBlock = 256;
 
+template <class T>
 __global__ __launch_bounds__(kRedBlock) void k_reduce_chunks(const RedItem* __restrict__ items,
-                                                             const float* __restrict__ Ei,
-                                                             const float* __restrict__ Wi,
-                                                             const float* __restrict__ Ki,
+                                                             const T* __restrict__ Ei,
+                                                             const T* __restrict__ Wi,
+                                                             const T* __restrict__ Ki,
                                                              double* __restrict__ part) {
   constexpr int NV = kRedValues;
   __shared__ double sh[NV][kRedBlock];
@@ -106,10 +107,19 @@ int Reducer::setup(int n_cfg_, const int64_t* atom_off, hipStream_t st) {
 
 int Reducer::run(hipStream_t st, const float* Ei, const float* Wi, const float* Ki, double* E, double* V,
                  double* Kout) {
-  hipLaunchKernelGGL(k_reduce_chunks, dim3(n_items), dim3(kRedBlock), 0, st, items_dev.ptr<RedItem>(), Ei, Wi, Ki,
-                     part.ptr<double>());
+  hipLaunchKernelGGL(k_reduce_chunks<float>, dim3(n_items), dim3(kRedBlock), 0, st, items_dev.ptr<RedItem>(), Ei, Wi,
+                     Ki, part.ptr<double>());
   hipLaunchKernelGGL(k_reduce_final, dim3(n_cfg), dim3(kRedBlock), 0, st, n_cfg, start_dev.ptr<int>(),
                      part.ptr<double>(), E, V, Kout);
+  NEPMI_HIP(hipGetLastError());
+  return NEPMI_OK;
+}
+
+int Reducer::run64(hipStream_t st, const double* Ei, const double* Wi, double* E, double* V) {
+  hipLaunchKernelGGL(k_reduce_chunks<double>, dim3(n_items), dim3(kRedBlock), 0, st, items_dev.ptr<RedItem>(), Ei,
+                     Wi, static_cast<const double*>(nullptr), part.ptr<double>());
+  hipLaunchKernelGGL(k_reduce_final, dim3(n_cfg), dim3(kRedBlock), 0, st, n_cfg, start_dev.ptr<int>(),
+                     part.ptr<double>(), E, V, static_cast<double*>(nullptr));
   NEPMI_HIP(hipGetLastError());
   return NEPMI_OK;
 }

@@ -22,6 +22,8 @@ struct Reducer {
   int setup(int n_cfg, const int64_t* atom_off, hipStream_t st);
   // Any input or output may be null.
   int run(hipStream_t st, const float* Ei, const float* Wi, const float* Ki, double* E, double* V, double* Kout);
+  // The same sums of float64 per-atom energies and virials.
+  int run64(hipStream_t st, const double* Ei, const double* Wi, double* E, double* V);
 };
 
 }  // namespace nepmi

@@ -946,33 +946,6 @@ __global__ __launch_bounds__(kTB) void k_pair_force64(TrainIOT<double> io, Cutof
   for (int x = 0; x < 9; ++x) W[9 * (int64_t)i + x] = Wm[x];
 }
 
-// Per configuration (one block each, fixed order): E_c = sum_i E_i and
-// V_c = sum_i W_i over the configuration's atoms (caller order).
-constexpr int kSB = 256;
-__global__ __launch_bounds__(kSB) void k_cfg_sum64(const int64_t* __restrict__ off, const double* __restrict__ Ei,
-                                                   const double* __restrict__ Wi, double* __restrict__ E,
-                                                   double* __restrict__ V) {
-  __shared__ double sh[10][kSB];
-  const int c = blockIdx.x;
-  double acc[10];
-  for (int x = 0; x < 10; ++x) acc[x] = 0.0;
-  for (int64_t i = off[c] + threadIdx.x; i < off[c + 1]; i += kSB) {
-    acc[0] += Ei[i];
-    for (int x = 0; x < 9; ++x) acc[1 + x] += Wi[9 * i + x];
-  }
-  for (int x = 0; x < 10; ++x) sh[x][threadIdx.x] = acc[x];
-  __syncthreads();
-  for (int s = kSB / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s)
-      for (int x = 0; x < 10; ++x) sh[x][threadIdx.x] += sh[x][threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    E[c] = sh[0][0];
-    for (int x = 0; x < 9; ++x) V[9 * c + x] = sh[1 + x][0];
-  }
-}
-
 // ------------------------------------------------------------ launchers
 
 template <class S>
@@ -1050,7 +1023,7 @@ static int stage64(hipStream_t st, const TrainIOT<double>& io, const F64Args& a,
 
 template <class S>
 int TrainLaunch<S>::forward64(hipStream_t st, TrainIOT<double> io, const CutoffsT<double>& cut, const F64Args& a,
-                              double* energy, double* forces, double* virial) {
+                              double* forces) {
   const int64_t ns = io.ns;
   hipLaunchKernelGGL(k_fill64, dim3(blocks(4 * ns, 256)), dim3(256), 0, st, 4 * ns, 0.0,
                      reinterpret_cast<double*>(io.lam4));
@@ -1064,7 +1037,6 @@ int TrainLaunch<S>::forward64(hipStream_t st, TrainIOT<double> io, const Cutoffs
                      S::NA * S::K, io.Sst, io.Sdt);
   hipLaunchKernelGGL((k_pair_force64<S>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params, io.Sdt, forces,
                      a.Wi);
-  hipLaunchKernelGGL(k_cfg_sum64, dim3(a.n_cfg), dim3(kSB), 0, st, a.atom_off, io.Ei, a.Wi, energy, virial);
   NEPMI_HIP(hipGetLastError());
   return NEPMI_OK;
 }

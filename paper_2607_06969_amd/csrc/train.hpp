@@ -86,10 +86,10 @@ struct TrainLaunch {
   static int seeds(hipStream_t st, const TrainSeedArgs& a);
   static int backward(hipStream_t st, TrainIO io, const Cutoffs& cut, const float* params, const float* lam,
                       const int* base, double* part, double* grad64, float* grad);
-  // float64 variant: energy, forces and virial (per configuration; forces and
-  // site energies in caller order) ...
+  // float64 variant: forces, site energies (io.Ei) and per-atom virials
+  // (a.Wi), all in caller order; the caller sums them per configuration ...
   static int forward64(hipStream_t st, TrainIOT<double> io, const CutoffsT<double>& cut, const F64Args& a,
-                       double* energy, double* forces, double* virial);
+                       double* forces);
   // ... and the parameter gradient of ebar.E + lambda.F + mu:V
   static int backward64(hipStream_t st, TrainIOT<double> io, const CutoffsT<double>& cut, const F64Args& a,
                         const double* lam, const int* base, double* part, double* grad);

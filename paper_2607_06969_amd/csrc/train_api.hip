@@ -191,7 +191,9 @@ int nepmi_compute_f64(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, co
     return rc;
   double* Ei = dev_atom_energy ? dev_atom_energy : f.Ei.ptr<double>();
   TrainIOT<double> io = f64_io(m, f.mu0.ptr<double>(), f.ebar1.ptr<double>(), Ei);
-  return m->ops->forward64(st, io, f64_cut(m), a, dev_energy, dev_forces, dev_virial);
+  if ((rc = m->ops->forward64(st, io, f64_cut(m), a, dev_forces))) return rc;
+  // per-configuration float64 sums in the fixed chunking of the float32 path
+  return m->red.run64(st, Ei, a.Wi, dev_energy, dev_virial);
 }
 
 int nepmi_backward_params_f64(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, const double* cells,
