@@ -498,15 +498,20 @@ __global__ __launch_bounds__(kTB) void k_train_atom(TrainIOT<R> io, CutoffsT<R> 
 // GA[(b NA + n) BA + k] = sum over angular pairs j of species b of
 //   (alpha_n + gamma_n) Q_k + beta_n dQ_k,
 // alpha_n = sum_lm Sbar Y, beta_n = -(u.t) sum_lm sigma Y, gamma_n = -sum_lm sigma grad Y.t
+// One thread per (atom, n): grid (slot blocks, NA).  The NA walks of an atom's
+// pairs run side by side instead of one after another, so a batch of a few
+// ten thousand atoms still puts several waves on every SIMD.
 template <class S, class R>
 __global__ __launch_bounds__(kTB) void k_train_coefA(TrainIOT<R> io, CutoffsT<R> cut, const R* __restrict__ params) {
   constexpr int T = S::T, NA = S::NA, BA = S::BA, L = S::L, K = S::K;
   const int64_t ns = io.ns;
   const int64_t p = (int64_t)blockIdx.x * kTB + threadIdx.x;
+  const int n = blockIdx.y;
   if (p >= ns) return;
   const int c = io.cfg_of[p];
   if (c < 0) {
-    for (int x = 0; x < T * NA * BA; ++x) io.GA[(int64_t)x * ns + p] = R(0);
+    for (int b = 0; b < T; ++b)
+      for (int kk = 0; kk < BA; ++kk) io.GA[(int64_t)((b * NA + n) * BA + kk) * ns + p] = R(0);
     return;
   }
   const Vec4<R> xi = io.pos4[p];
@@ -520,7 +525,7 @@ __global__ __launch_bounds__(kTB) void k_train_coefA(TrainIOT<R> io, CutoffsT<R>
 #pragma unroll
   for (int x = 0; x < 9; ++x) mu[x] = (R)io.mu[9 * c + x];
   const int nA = io.cntA[p];
-  for (int n = 0; n < NA; ++n) {
+  {
     R sg[K], sb[K];
 #pragma unroll
     for (int lm = 0; lm < K; ++lm) {
@@ -968,7 +973,7 @@ int TrainLaunch<S>::backward(hipStream_t st, TrainIO io, const Cutoffs& cut, con
   hipLaunchKernelGGL((k_train_atom<S, NC, float, 1>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, params);
   hipLaunchKernelGGL((k_train_atom<S, NC, float, 2>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, params);
   hipLaunchKernelGGL((k_train_atom<S, NC, float, 3>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, params);
-  hipLaunchKernelGGL((k_train_coefA<S, float>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, params);
+  hipLaunchKernelGGL((k_train_coefA<S, float>), dim3(blocks(ns, kTB), S::NA), dim3(kTB), 0, st, io, cut, params);
   constexpr int T = S::T;
   const dim3 g(kRBlocks, T);
   // W0: sum abar q^T - z qdot^T
@@ -1050,7 +1055,7 @@ int TrainLaunch<S>::backward64(hipStream_t st, TrainIOT<double> io, const Cutoff
   hipLaunchKernelGGL((k_train_atom<S, NC, double, 1>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params);
   hipLaunchKernelGGL((k_train_atom<S, NC, double, 2>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params);
   hipLaunchKernelGGL((k_train_atom<S, NC, double, 3>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params);
-  hipLaunchKernelGGL((k_train_coefA<S, double>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params);
+  hipLaunchKernelGGL((k_train_coefA<S, double>), dim3(blocks(ns, kTB), S::NA), dim3(kTB), 0, st, io, cut, a.params);
   constexpr int T = S::T;
   const dim3 g(kRBlocks, T);
   {
