@@ -197,6 +197,10 @@ __global__ void k_lam_slots(int64_t ns, const int* __restrict__ orig, const R* _
 // PHASE 3: sigma = dE/dS and Sbar = dj/dS, from S, Sdot, dE/dq and dj/dq.
 // Apart, the phases need far fewer registers than one kernel doing all three;
 // every hand-over goes through the per-slot arrays of io.
+// PHASE 1 runs on a grid (slot blocks, 1 + NA / NC): blockIdx.y = 0 takes the
+// radial sums, blockIdx.y = 1 + h the angular chunk h.  The parts write
+// disjoint outputs, and running them side by side rather than one after
+// another keeps a batch of a few ten thousand atoms from leaving SIMDs idle.
 template <class S, int NC, class R, int PHASE>
 __global__ __launch_bounds__(kTB) void k_train_atom(TrainIOT<R> io, CutoffsT<R> cut, const R* __restrict__ params) {
   constexpr int T = S::T, NR = S::NR, NA = S::NA, BR = S::BR, BA = S::BA, L = S::L, K = S::K, D = S::D, H = S::H;
@@ -217,6 +221,7 @@ __global__ __launch_bounds__(kTB) void k_train_atom(TrainIOT<R> io, CutoffsT<R> 
   if (c < 0) {
     // padding: zero every per-slot output that is summed over species ranges
     if constexpr (kTangent) {
+      if (blockIdx.y != 0) return;
       for (int d = 0; d < D; ++d) io.q[d * ns + p] = io.qd[d * ns + p] = R(0);
       for (int k = 0; k < T * BR; ++k) io.Pb[k * ns + p] = io.Pdn[k * ns + p] = R(0);
     }
@@ -240,7 +245,7 @@ __global__ __launch_bounds__(kTB) void k_train_atom(TrainIOT<R> io, CutoffsT<R> 
   for (int x = 0; x < 9; ++x) mu[x] = (R)io.mu[9 * c + x];
 
   // ---- radial: P_b[k] = sum_{j in b} Q_k, Pd_b[k] = sum_{j in b} dQ_k (u.t)
-  {
+  if (blockIdx.y == 0) {
     R P[T][BR], Pd[T][BR];
 #pragma unroll
     for (int b = 0; b < T; ++b)
@@ -293,8 +298,9 @@ __global__ __launch_bounds__(kTB) void k_train_atom(TrainIOT<R> io, CutoffsT<R> 
       }
   }
   // ---- angular: S and Sdot in chunks of NC functions (stored for the adjoint)
-  const int nA = io.cntA[p];
-  for (int h = 0; h < NA / NC; ++h) {
+  if (blockIdx.y > 0) {
+    const int h = (int)blockIdx.y - 1;
+    const int nA = io.cntA[p];
     R Sg[NC][K], Sd[NC][K];
 #pragma unroll
     for (int nn = 0; nn < NC; ++nn)
@@ -970,7 +976,7 @@ int TrainLaunch<S>::backward(hipStream_t st, TrainIO io, const Cutoffs& cut, con
   hipLaunchKernelGGL(k_lam_slots<float>, dim3(blocks(ns, 256)), dim3(256), 0, st, ns, io.orig, lam,
                      const_cast<float4*>(io.lam4));
   constexpr int NC = S::NA >= 4 ? 2 : 1;
-  hipLaunchKernelGGL((k_train_atom<S, NC, float, 1>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, params);
+  hipLaunchKernelGGL((k_train_atom<S, NC, float, 1>), dim3(blocks(ns, kTB), 1 + S::NA / NC), dim3(kTB), 0, st, io, cut, params);
   hipLaunchKernelGGL((k_train_atom<S, NC, float, 2>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, params);
   hipLaunchKernelGGL((k_train_atom<S, NC, float, 3>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, params);
   hipLaunchKernelGGL((k_train_coefA<S, float>), dim3(blocks(ns, kTB), S::NA), dim3(kTB), 0, st, io, cut, params);
@@ -1033,7 +1039,7 @@ int TrainLaunch<S>::forward64(hipStream_t st, TrainIOT<double> io, const Cutoffs
   hipLaunchKernelGGL(k_fill64, dim3(blocks(4 * ns, 256)), dim3(256), 0, st, 4 * ns, 0.0,
                      reinterpret_cast<double*>(io.lam4));
   constexpr int NC = S::NA >= 4 ? 2 : 1;
-  hipLaunchKernelGGL((k_train_atom<S, NC, double, 1>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params);
+  hipLaunchKernelGGL((k_train_atom<S, NC, double, 1>), dim3(blocks(ns, kTB), 1 + S::NA / NC), dim3(kTB), 0, st, io, cut, a.params);
   hipLaunchKernelGGL((k_train_atom<S, NC, double, 2>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params);
   hipLaunchKernelGGL((k_train_atom<S, NC, double, 3>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params);
   // sigma, slot-major, into the Sdot buffer (free once the dE/dS pass is done;
@@ -1052,7 +1058,7 @@ int TrainLaunch<S>::backward64(hipStream_t st, TrainIOT<double> io, const Cutoff
   const int64_t ns = io.ns;
   hipLaunchKernelGGL(k_lam_slots<double>, dim3(blocks(ns, 256)), dim3(256), 0, st, ns, io.orig, lam, io.lam4);
   constexpr int NC = S::NA >= 4 ? 2 : 1;
-  hipLaunchKernelGGL((k_train_atom<S, NC, double, 1>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params);
+  hipLaunchKernelGGL((k_train_atom<S, NC, double, 1>), dim3(blocks(ns, kTB), 1 + S::NA / NC), dim3(kTB), 0, st, io, cut, a.params);
   hipLaunchKernelGGL((k_train_atom<S, NC, double, 2>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params);
   hipLaunchKernelGGL((k_train_atom<S, NC, double, 3>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params);
   hipLaunchKernelGGL((k_train_coefA<S, double>), dim3(blocks(ns, kTB), S::NA), dim3(kTB), 0, st, io, cut, a.params);
