@@ -201,6 +201,7 @@ __global__ void k_lam_slots(int64_t ns, const int* __restrict__ orig, const R* _
 // radial sums, blockIdx.y = 1 + h the angular chunk h.  The parts write
 // disjoint outputs, and running them side by side rather than one after
 // another keeps a batch of a few ten thousand atoms from leaving SIMDs idle.
+// PHASE 3 runs on a grid (slot blocks, NA), one angular function per row.
 template <class S, int NC, class R, int PHASE>
 __global__ __launch_bounds__(kTB) void k_train_atom(TrainIOT<R> io, CutoffsT<R> cut, const R* __restrict__ params) {
   constexpr int T = S::T, NR = S::NR, NA = S::NA, BR = S::BR, BA = S::BA, L = S::L, K = S::K, D = S::D, H = S::H;
@@ -440,7 +441,8 @@ __global__ __launch_bounds__(kTB) void k_train_atom(TrainIOT<R> io, CutoffsT<R> 
   auto Fp_at = [&](int d) { return io.FpA[(int64_t)d * ns + p]; };
   auto qb_at = [&](int d) { return io.qbA[(int64_t)d * ns + p]; };
   // ---- sigma = dE/dS and Sbar = dj/dS from the stored S and Sdot
-  for (int n = 0; n < NA; ++n) {
+  {
+    const int n = blockIdx.y;
     R Sg[K], Sd[K];
 #pragma unroll
     for (int lm = 0; lm < K; ++lm) {
@@ -978,7 +980,7 @@ int TrainLaunch<S>::backward(hipStream_t st, TrainIO io, const Cutoffs& cut, con
   constexpr int NC = S::NA >= 4 ? 2 : 1;
   hipLaunchKernelGGL((k_train_atom<S, NC, float, 1>), dim3(blocks(ns, kTB), 1 + S::NA / NC), dim3(kTB), 0, st, io, cut, params);
   hipLaunchKernelGGL((k_train_atom<S, NC, float, 2>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, params);
-  hipLaunchKernelGGL((k_train_atom<S, NC, float, 3>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, params);
+  hipLaunchKernelGGL((k_train_atom<S, NC, float, 3>), dim3(blocks(ns, kTB), S::NA), dim3(kTB), 0, st, io, cut, params);
   hipLaunchKernelGGL((k_train_coefA<S, float>), dim3(blocks(ns, kTB), S::NA), dim3(kTB), 0, st, io, cut, params);
   constexpr int T = S::T;
   const dim3 g(kRBlocks, T);
@@ -1041,7 +1043,7 @@ int TrainLaunch<S>::forward64(hipStream_t st, TrainIOT<double> io, const Cutoffs
   constexpr int NC = S::NA >= 4 ? 2 : 1;
   hipLaunchKernelGGL((k_train_atom<S, NC, double, 1>), dim3(blocks(ns, kTB), 1 + S::NA / NC), dim3(kTB), 0, st, io, cut, a.params);
   hipLaunchKernelGGL((k_train_atom<S, NC, double, 2>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params);
-  hipLaunchKernelGGL((k_train_atom<S, NC, double, 3>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params);
+  hipLaunchKernelGGL((k_train_atom<S, NC, double, 3>), dim3(blocks(ns, kTB), S::NA), dim3(kTB), 0, st, io, cut, a.params);
   // sigma, slot-major, into the Sdot buffer (free once the dE/dS pass is done;
   // the backward recomputes it)
   hipLaunchKernelGGL(k_slot_major64, dim3(blocks(ns, kTT), (S::NA * S::K + kTT - 1) / kTT), dim3(kTT * 8), 0, st, ns,
@@ -1060,7 +1062,7 @@ int TrainLaunch<S>::backward64(hipStream_t st, TrainIOT<double> io, const Cutoff
   constexpr int NC = S::NA >= 4 ? 2 : 1;
   hipLaunchKernelGGL((k_train_atom<S, NC, double, 1>), dim3(blocks(ns, kTB), 1 + S::NA / NC), dim3(kTB), 0, st, io, cut, a.params);
   hipLaunchKernelGGL((k_train_atom<S, NC, double, 2>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params);
-  hipLaunchKernelGGL((k_train_atom<S, NC, double, 3>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params);
+  hipLaunchKernelGGL((k_train_atom<S, NC, double, 3>), dim3(blocks(ns, kTB), S::NA), dim3(kTB), 0, st, io, cut, a.params);
   hipLaunchKernelGGL((k_train_coefA<S, double>), dim3(blocks(ns, kTB), S::NA), dim3(kTB), 0, st, io, cut, a.params);
   constexpr int T = S::T;
   const dim3 g(kRBlocks, T);
