@@ -737,18 +737,56 @@ __global__ __launch_bounds__(kCB) void k_colsum(int64_t ns, const int* __restric
   }
 }
 
-// grad[dst(s, e)] = sum_blk part[s][blk][e];  dst = off + s * sstride + map(e)
+// The gradient sums of one backward pass, each with its own region of the
+// partial-sum buffer, finished by one launch.  Segment g covers threads
+// [first[g], first[g + 1]), one per (species s, entry e):
+// grad[dst(s, e)] = sum_blk part[part_off + (s kRBlocks + blk) E + e];  dst = off + s * sstride + map(e)
 // map: kind 0 identity; kind 1: e = n*(T*BR) + b*BR + k -> (b*NR + n)*BR + k
-__global__ void k_part_final(int T, int E, const double* __restrict__ part, int64_t off, int64_t sstride, int kind,
-                             int NR, int BR, double* __restrict__ grad) {
+constexpr int kPartSegs = 6;
+struct PartSeg {
+  int E, kind;
+  int64_t part_off, off, sstride;
+};
+struct PartPlan {
+  int T, NR, BR, n;
+  int64_t first[kPartSegs + 1];
+  PartSeg seg[kPartSegs];
+  int64_t used;  // doubles of the partial-sum buffer taken so far
+  // region of the next segment's partial sums (host side)
+  double* add(double* part, int E, int64_t off, int64_t sstride, int kind) {
+    PartSeg& g = seg[n];
+    g.E = E;
+    g.kind = kind;
+    g.part_off = used;
+    g.off = off;
+    g.sstride = sstride;
+    first[n + 1] = first[n] + (int64_t)T * E;
+    ++n;
+    used += (int64_t)T * kRBlocks * E;
+    return part + g.part_off;
+  }
+};
+static PartPlan part_plan(int T, int NR, int BR) {
+  PartPlan pl{};
+  pl.T = T;
+  pl.NR = NR;
+  pl.BR = BR;
+  return pl;
+}
+__global__ void k_part_final(PartPlan pl, const double* __restrict__ part, double* __restrict__ grad) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)T * E) return;
-  const int s = (int)(t / E), e = (int)(t % E);
+  if (t >= pl.first[pl.n]) return;
+  int g = 0;
+  while (g + 1 < pl.n && t >= pl.first[g + 1]) ++g;
+  const int E = pl.seg[g].E, kind = pl.seg[g].kind, T = pl.T, NR = pl.NR, BR = pl.BR;
+  const int64_t off = pl.seg[g].off, sstride = pl.seg[g].sstride;
+  const int64_t u = t - pl.first[g];
+  const int s = (int)(u / E), e = (int)(u % E);
   // four interleaved partial sums, combined in a fixed order; 64 loads are
   // issued per round trip
   static_assert(kRBlocks % 64 == 0, "partials come in sixty-fours");
   double a4[4] = {0.0, 0.0, 0.0, 0.0};
-  const double* src = part + (int64_t)s * kRBlocks * E + e;
+  const double* src = part + pl.seg[g].part_off + (int64_t)s * kRBlocks * E + e;
   for (int blk = 0; blk < kRBlocks; blk += 64) {
     double v[64];
 #pragma unroll
@@ -971,6 +1009,31 @@ int TrainLaunch<S>::seeds(hipStream_t st, const TrainSeedArgs& a) {
   return NEPMI_OK;
 }
 
+// Per-species sums over atoms of every parameter gradient, each into its own
+// region of part, then one launch finishes them all into grad (float64):
+//   W0: sum abar q^T - z qdot^T;  c^R: sum qbar_R (x) P - dE/dq_R (x) P';
+//   c^A: sum of the per-atom bins;  b0: sum abar;  w1: sum dj/dw1;  b1: sum ebar.
+template <class S, class R>
+static void species_sums(hipStream_t st, const TrainIOT<R>& io, const int* base, double* part, double* grad) {
+  constexpr int T = S::T, H = S::H;
+  const int64_t ns = io.ns;
+  const dim3 g(kRBlocks, T);
+  PartPlan pl = part_plan(T, S::NR, S::BR);
+  hipLaunchKernelGGL((k_outer<R, S::H, S::D>), g, dim3(kRB), 0, st, ns, base, io.abar, io.q, io.zneg, io.qd,
+                     pl.add(part, S::H * S::D, S::PCR + S::PCA, S::PMLP, 0));
+  hipLaunchKernelGGL((k_outer<R, S::NR, S::T * S::BR>), g, dim3(kRB), 0, st, ns, base, io.qbR, io.Pb, io.FpR, io.Pdn,
+                     pl.add(part, S::NR * T * S::BR, 0, (int64_t)T * S::NR * S::BR, 1));
+  hipLaunchKernelGGL((k_colsum<R, S::T * S::NA * S::BA>), g, dim3(kCB), 0, st, ns, base, io.GA,
+                     pl.add(part, T * S::NA * S::BA, S::PCR, (int64_t)T * S::NA * S::BA, 0));
+  hipLaunchKernelGGL((k_colsum<R, S::H>), g, dim3(kCB), 0, st, ns, base, io.abar,
+                     pl.add(part, H, S::PCR + S::PCA + (int64_t)H * S::D, S::PMLP, 0));
+  hipLaunchKernelGGL((k_colsum<R, S::H>), g, dim3(kCB), 0, st, ns, base, io.gw1,
+                     pl.add(part, H, S::PCR + S::PCA + (int64_t)H * S::D + H, S::PMLP, 0));
+  hipLaunchKernelGGL((k_colsum<R, 1>), g, dim3(kCB), 0, st, ns, base, io.eat,
+                     pl.add(part, 1, S::PCR + S::PCA + (int64_t)H * S::D + 2 * H, S::PMLP, 0));
+  hipLaunchKernelGGL(k_part_final, dim3(blocks(pl.first[pl.n], 256)), dim3(256), 0, st, pl, part, grad);
+}
+
 template <class S>
 int TrainLaunch<S>::backward(hipStream_t st, TrainIO io, const Cutoffs& cut, const float* params, const float* lam,
                              const int* base, double* part, double* grad64, float* grad) {
@@ -982,44 +1045,7 @@ int TrainLaunch<S>::backward(hipStream_t st, TrainIO io, const Cutoffs& cut, con
   hipLaunchKernelGGL((k_train_atom<S, NC, float, 2>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, params);
   hipLaunchKernelGGL((k_train_atom<S, NC, float, 3>), dim3(blocks(ns, kTB), S::NA), dim3(kTB), 0, st, io, cut, params);
   hipLaunchKernelGGL((k_train_coefA<S, float>), dim3(blocks(ns, kTB), S::NA), dim3(kTB), 0, st, io, cut, params);
-  constexpr int T = S::T;
-  const dim3 g(kRBlocks, T);
-  // W0: sum abar q^T - z qdot^T
-  {
-    const int A = S::H, B = S::D;
-    hipLaunchKernelGGL((k_outer<float, S::H, S::D>), g, dim3(kRB), 0, st, ns, base, io.abar, io.q, io.zneg, io.qd,
-                       part);
-    hipLaunchKernelGGL(k_part_final, dim3(blocks((int64_t)T * A * B, 256)), dim3(256), 0, st, T, A * B, part,
-                       S::PCR + S::PCA, S::PMLP, 0, 0, 0, grad64);
-  }
-  // c^R: sum qbar_R (x) P - Fp_R (x) P'
-  {
-    const int A = S::NR, B = T * S::BR;
-    hipLaunchKernelGGL((k_outer<float, S::NR, S::T * S::BR>), g, dim3(kRB), 0, st, ns, base, io.qbR, io.Pb, io.FpR,
-                       io.Pdn, part);
-    hipLaunchKernelGGL(k_part_final, dim3(blocks((int64_t)T * A * B, 256)), dim3(256), 0, st, T, A * B, part,
-                       (int64_t)0, (int64_t)T * S::NR * S::BR, 1, S::NR, S::BR, grad64);
-  }
-  // c^A
-  {
-    const int A = T * S::NA * S::BA;
-    hipLaunchKernelGGL((k_colsum<float, S::T * S::NA * S::BA>), g, dim3(kCB), 0, st, ns, base, io.GA, part);
-    hipLaunchKernelGGL(k_part_final, dim3(blocks((int64_t)T * A, 256)), dim3(256), 0, st, T, A, part, S::PCR,
-                       (int64_t)A, 0, 0, 0, grad64);
-  }
-  // b0, w1, b1
-  {
-    const int H = S::H;
-    hipLaunchKernelGGL((k_colsum<float, S::H>), g, dim3(kCB), 0, st, ns, base, io.abar, part);
-    hipLaunchKernelGGL(k_part_final, dim3(blocks((int64_t)T * H, 256)), dim3(256), 0, st, T, H, part,
-                       S::PCR + S::PCA + (int64_t)H * S::D, S::PMLP, 0, 0, 0, grad64);
-    hipLaunchKernelGGL((k_colsum<float, S::H>), g, dim3(kCB), 0, st, ns, base, io.gw1, part);
-    hipLaunchKernelGGL(k_part_final, dim3(blocks((int64_t)T * H, 256)), dim3(256), 0, st, T, H, part,
-                       S::PCR + S::PCA + (int64_t)H * S::D + H, S::PMLP, 0, 0, 0, grad64);
-    hipLaunchKernelGGL((k_colsum<float, 1>), g, dim3(kCB), 0, st, ns, base, io.eat, part);
-    hipLaunchKernelGGL(k_part_final, dim3(1), dim3(64), 0, st, T, 1, part,
-                       S::PCR + S::PCA + (int64_t)H * S::D + 2 * H, S::PMLP, 0, 0, 0, grad64);
-  }
+  species_sums<S, float>(st, io, base, part, grad64);
   hipLaunchKernelGGL(k_to_float, dim3(blocks(S::P, 256)), dim3(256), 0, st, (int64_t)S::P, grad64, grad);
   NEPMI_HIP(hipGetLastError());
   return NEPMI_OK;
@@ -1064,40 +1090,7 @@ int TrainLaunch<S>::backward64(hipStream_t st, TrainIOT<double> io, const Cutoff
   hipLaunchKernelGGL((k_train_atom<S, NC, double, 2>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params);
   hipLaunchKernelGGL((k_train_atom<S, NC, double, 3>), dim3(blocks(ns, kTB), S::NA), dim3(kTB), 0, st, io, cut, a.params);
   hipLaunchKernelGGL((k_train_coefA<S, double>), dim3(blocks(ns, kTB), S::NA), dim3(kTB), 0, st, io, cut, a.params);
-  constexpr int T = S::T;
-  const dim3 g(kRBlocks, T);
-  {
-    const int A = S::H, B = S::D;
-    hipLaunchKernelGGL((k_outer<double, S::H, S::D>), g, dim3(kRB), 0, st, ns, base, io.abar, io.q, io.zneg, io.qd,
-                       part);
-    hipLaunchKernelGGL(k_part_final, dim3(blocks((int64_t)T * A * B, 256)), dim3(256), 0, st, T, A * B, part,
-                       S::PCR + S::PCA, S::PMLP, 0, 0, 0, grad);
-  }
-  {
-    const int A = S::NR, B = T * S::BR;
-    hipLaunchKernelGGL((k_outer<double, S::NR, S::T * S::BR>), g, dim3(kRB), 0, st, ns, base, io.qbR, io.Pb, io.FpR,
-                       io.Pdn, part);
-    hipLaunchKernelGGL(k_part_final, dim3(blocks((int64_t)T * A * B, 256)), dim3(256), 0, st, T, A * B, part,
-                       (int64_t)0, (int64_t)T * S::NR * S::BR, 1, S::NR, S::BR, grad);
-  }
-  {
-    const int A = T * S::NA * S::BA;
-    hipLaunchKernelGGL((k_colsum<double, S::T * S::NA * S::BA>), g, dim3(kCB), 0, st, ns, base, io.GA, part);
-    hipLaunchKernelGGL(k_part_final, dim3(blocks((int64_t)T * A, 256)), dim3(256), 0, st, T, A, part, S::PCR,
-                       (int64_t)A, 0, 0, 0, grad);
-  }
-  {
-    const int H = S::H;
-    hipLaunchKernelGGL((k_colsum<double, S::H>), g, dim3(kCB), 0, st, ns, base, io.abar, part);
-    hipLaunchKernelGGL(k_part_final, dim3(blocks((int64_t)T * H, 256)), dim3(256), 0, st, T, H, part,
-                       S::PCR + S::PCA + (int64_t)H * S::D, S::PMLP, 0, 0, 0, grad);
-    hipLaunchKernelGGL((k_colsum<double, S::H>), g, dim3(kCB), 0, st, ns, base, io.gw1, part);
-    hipLaunchKernelGGL(k_part_final, dim3(blocks((int64_t)T * H, 256)), dim3(256), 0, st, T, H, part,
-                       S::PCR + S::PCA + (int64_t)H * S::D + H, S::PMLP, 0, 0, 0, grad);
-    hipLaunchKernelGGL((k_colsum<double, 1>), g, dim3(kCB), 0, st, ns, base, io.eat, part);
-    hipLaunchKernelGGL(k_part_final, dim3(1), dim3(64), 0, st, T, 1, part,
-                       S::PCR + S::PCA + (int64_t)H * S::D + 2 * H, S::PMLP, 0, 0, 0, grad);
-  }
+  species_sums<S, double>(st, io, base, part, grad);
   NEPMI_HIP(hipGetLastError());
   return NEPMI_OK;
 }

@@ -12,8 +12,9 @@ int ensure_train(nepmi_model* m) {
   TrainBufs& t = m->tr;
   const size_t ns = (size_t)m->nbr.n_slots, N = (size_t)(m->nbr.N > 0 ? m->nbr.N : 1);
   const size_t nc = (size_t)m->nbr.n_cfg, ni = (size_t)m->red.n_items;
-  const size_t maxE = std::max({(size_t)o->H * o->D, (size_t)o->NR * o->T * o->BR, (size_t)o->T * o->NA * o->BA,
-                                (size_t)o->H});
+  // the parameter-gradient sums each keep their own partial sums
+  const size_t sumE = (size_t)o->H * o->D + (size_t)o->NR * o->T * o->BR + (size_t)o->T * o->NA * o->BA +
+                      2 * (size_t)o->H + 1;
   int rc;
   if ((rc = t.F.ensure(12 * N)) || (rc = t.E.ensure(8 * nc)) || (rc = t.V.ensure(72 * nc)) ||
       (rc = t.lam.ensure(12 * N)) || (rc = t.ebar.ensure(8 * nc)) || (rc = t.mu.ensure(72 * nc)) ||
@@ -23,7 +24,7 @@ int ensure_train(nepmi_model* m) {
       (rc = t.Pb.ensure(4 * ns * o->T * o->BR)) || (rc = t.Pdn.ensure(4 * ns * o->T * o->BR)) ||
       (rc = t.abar.ensure(4 * ns * o->H)) || (rc = t.zneg.ensure(4 * ns * o->H)) || (rc = t.gw1.ensure(4 * ns * o->H)) ||
       (rc = t.eat.ensure(4 * ns)) || (rc = t.qbR.ensure(4 * ns * o->NR)) || (rc = t.FpR.ensure(4 * ns * o->NR)) ||
-      (rc = t.GA.ensure(4 * ns * o->T * o->NA * o->BA)) || (rc = t.part.ensure(8 * (size_t)o->T * kRBlocks * maxE)) ||
+      (rc = t.GA.ensure(4 * ns * o->T * o->NA * o->BA)) || (rc = t.part.ensure(8 * (size_t)o->T * kRBlocks * sumE)) ||
       (rc = t.grad64.ensure(8 * (size_t)o->P)) || (rc = t.gradf.ensure(4 * (size_t)o->P)) ||
       (rc = t.FpA.ensure(4 * ns * o->D)) || (rc = t.qbA.ensure(4 * ns * o->D)))
     return rc;
@@ -80,8 +81,9 @@ int ensure_f64(nepmi_model* m) {
   F64Bufs& f = m->f64;
   const size_t ns = (size_t)m->nbr.n_slots, N = (size_t)(m->nbr.N > 0 ? m->nbr.N : 1);
   const size_t nc = (size_t)(m->nbr.n_cfg > 0 ? m->nbr.n_cfg : 1);
-  const size_t maxE = std::max({(size_t)o->H * o->D, (size_t)o->NR * o->T * o->BR, (size_t)o->T * o->NA * o->BA,
-                                (size_t)o->H});
+  // the parameter-gradient sums each keep their own partial sums
+  const size_t sumE = (size_t)o->H * o->D + (size_t)o->NR * o->T * o->BR + (size_t)o->T * o->NA * o->BA +
+                      2 * (size_t)o->H + 1;
   int rc;
   if ((rc = f.pos4.ensure(32 * ns)) || (rc = f.lam4.ensure(32 * ns)) || (rc = f.ebar1.ensure(8 * nc)) ||
       (rc = f.mu0.ensure(72 * nc)) || (rc = f.Ei.ensure(8 * N)) || (rc = f.Wi.ensure(72 * N)) ||
@@ -90,7 +92,7 @@ int ensure_f64(nepmi_model* m) {
       (rc = f.Pb.ensure(8 * ns * o->T * o->BR)) || (rc = f.Pdn.ensure(8 * ns * o->T * o->BR)) ||
       (rc = f.abar.ensure(8 * ns * o->H)) || (rc = f.zneg.ensure(8 * ns * o->H)) || (rc = f.gw1.ensure(8 * ns * o->H)) ||
       (rc = f.eat.ensure(8 * ns)) || (rc = f.qbR.ensure(8 * ns * o->NR)) || (rc = f.FpR.ensure(8 * ns * o->NR)) ||
-      (rc = f.GA.ensure(8 * ns * o->T * o->NA * o->BA)) || (rc = f.part.ensure(8 * (size_t)o->T * kRBlocks * maxE)) ||
+      (rc = f.GA.ensure(8 * ns * o->T * o->NA * o->BA)) || (rc = f.part.ensure(8 * (size_t)o->T * kRBlocks * sumE)) ||
       (rc = f.FpA.ensure(8 * ns * o->D)) || (rc = f.qbA.ensure(8 * ns * o->D)))
     return rc;
   return NEPMI_OK;
