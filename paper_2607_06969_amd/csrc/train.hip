@@ -13,7 +13,7 @@
 //
 //   k_train_atom    tangent pass + second-order network adjoint (per atom)
 //   k_train_coefA   angular coefficient gradient (per atom, over its pairs)
-//   k_outer / k_colsum  per-species sums over atoms (fixed order, float64)
+//   k_outer / k_colsum4 per-species sums over atoms (fixed order, float64)
 #include "train.hpp"
 
 namespace nepmi {
@@ -704,8 +704,8 @@ __global__ __launch_bounds__(kRB) void k_outer(int64_t ns, const int* __restrict
 // then added in float64.
 constexpr int kCB = 1024;
 template <class X, int A>
-__global__ __launch_bounds__(kCB) void k_colsum(int64_t ns, const int* __restrict__ base, const X* __restrict__ Xa,
-                                                double* __restrict__ part) {
+__device__ __forceinline__ void colsum_block(int64_t ns, const int* __restrict__ base, const X* __restrict__ Xa,
+                                             double* __restrict__ part) {
   constexpr int NW = kCB / kWave, RPW = (A + NW - 1) / NW;
   const int s = blockIdx.y, blk = blockIdx.x;
   const int p0 = base[s], p1 = base[s + 1];
@@ -734,6 +734,22 @@ __global__ __launch_bounds__(kCB) void k_colsum(int64_t ns, const int* __restric
       const int a = wv + NW * r;
       if (a < A) part[((int64_t)s * kRBlocks + blk) * A + a] = acc[r];
     }
+  }
+}
+
+// Four column sums in one launch, grid (kRBlocks, T, 4): blockIdx.z picks
+// the sum (X0 has A0 rows, X1 and X2 A1 rows, X3 one row).
+template <class X, int A0, int A1>
+__global__ __launch_bounds__(kCB) void k_colsum4(int64_t ns, const int* __restrict__ base, const X* __restrict__ X0,
+                                                 double* __restrict__ P0, const X* __restrict__ X1,
+                                                 double* __restrict__ P1, const X* __restrict__ X2,
+                                                 double* __restrict__ P2, const X* __restrict__ X3,
+                                                 double* __restrict__ P3) {
+  switch (blockIdx.z) {
+    case 0: colsum_block<X, A0>(ns, base, X0, P0); break;
+    case 1: colsum_block<X, A1>(ns, base, X1, P1); break;
+    case 2: colsum_block<X, A1>(ns, base, X2, P2); break;
+    default: colsum_block<X, 1>(ns, base, X3, P3); break;
   }
 }
 
@@ -1023,14 +1039,12 @@ static void species_sums(hipStream_t st, const TrainIOT<R>& io, const int* base,
                      pl.add(part, S::H * S::D, S::PCR + S::PCA, S::PMLP, 0));
   hipLaunchKernelGGL((k_outer<R, S::NR, S::T * S::BR>), g, dim3(kRB), 0, st, ns, base, io.qbR, io.Pb, io.FpR, io.Pdn,
                      pl.add(part, S::NR * T * S::BR, 0, (int64_t)T * S::NR * S::BR, 1));
-  hipLaunchKernelGGL((k_colsum<R, S::T * S::NA * S::BA>), g, dim3(kCB), 0, st, ns, base, io.GA,
-                     pl.add(part, T * S::NA * S::BA, S::PCR, (int64_t)T * S::NA * S::BA, 0));
-  hipLaunchKernelGGL((k_colsum<R, S::H>), g, dim3(kCB), 0, st, ns, base, io.abar,
-                     pl.add(part, H, S::PCR + S::PCA + (int64_t)H * S::D, S::PMLP, 0));
-  hipLaunchKernelGGL((k_colsum<R, S::H>), g, dim3(kCB), 0, st, ns, base, io.gw1,
-                     pl.add(part, H, S::PCR + S::PCA + (int64_t)H * S::D + H, S::PMLP, 0));
-  hipLaunchKernelGGL((k_colsum<R, 1>), g, dim3(kCB), 0, st, ns, base, io.eat,
-                     pl.add(part, 1, S::PCR + S::PCA + (int64_t)H * S::D + 2 * H, S::PMLP, 0));
+  double* pA = pl.add(part, T * S::NA * S::BA, S::PCR, (int64_t)T * S::NA * S::BA, 0);
+  double* pb0 = pl.add(part, H, S::PCR + S::PCA + (int64_t)H * S::D, S::PMLP, 0);
+  double* pw1 = pl.add(part, H, S::PCR + S::PCA + (int64_t)H * S::D + H, S::PMLP, 0);
+  double* pb1 = pl.add(part, 1, S::PCR + S::PCA + (int64_t)H * S::D + 2 * H, S::PMLP, 0);
+  hipLaunchKernelGGL((k_colsum4<R, S::T * S::NA * S::BA, S::H>), dim3(kRBlocks, T, 4), dim3(kCB), 0, st, ns, base,
+                     io.GA, pA, io.abar, pb0, io.gw1, pw1, io.eat, pb1);
   hipLaunchKernelGGL(k_part_final, dim3(blocks(pl.first[pl.n], 256)), dim3(256), 0, st, pl, part, grad);
 }
 
