@@ -23,27 +23,13 @@ __global__ __launch_bounds__(kRedBlock) void k_reduce_chunks(const RedItem* __re
   double acc[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-  // a chunk holds at most kRedChunk atoms: a fixed trip count, so that every
-  // load of the thread is issued before the first add (atoms in the same
-  // order as a strided loop)
-  static_assert(kRedChunk % kRedBlock == 0, "whole rounds per chunk");
-  constexpr int kPer = (int)(kRedChunk / kRedBlock);
-  T e[kPer], w[kPer][9], k[kPer];
+  for (int64_t a = it.a0 + threadIdx.x; a < it.a1; a += kRedBlock) {
+    if (Ei) acc[0] += (double)Ei[a];
+    if (Wi) {
 #pragma unroll
-  for (int u = 0; u < kPer; ++u) {
-    const int64_t a = it.a0 + threadIdx.x + (int64_t)u * kRedBlock;
-    const bool in = a < it.a1;
-    e[u] = (Ei && in) ? Ei[a] : T(0);
-#pragma unroll
-    for (int x = 0; x < 9; ++x) w[u][x] = (Wi && in) ? Wi[a * 9 + x] : T(0);
-    k[u] = (Ki && in) ? Ki[a] : T(0);
-  }
-#pragma unroll
-  for (int u = 0; u < kPer; ++u) {
-    acc[0] += (double)e[u];
-#pragma unroll
-    for (int x = 0; x < 9; ++x) acc[1 + x] += (double)w[u][x];
-    acc[10] += (double)k[u];
+      for (int x = 0; x < 9; ++x) acc[1 + x] += (double)Wi[a * 9 + x];
+    }
+    if (Ki) acc[10] += (double)Ki[a];
   }
 #pragma unroll
   for (int v = 0; v < NV; ++v) sh[v][threadIdx.x] = acc[v];
