@@ -13,7 +13,7 @@
 //
 //   k_train_atom    tangent pass + second-order network adjoint (per atom)
 //   k_train_coefA   angular coefficient gradient (per atom, over its pairs)
-//   k_outer / k_colsum4 per-species sums over atoms (fixed order, float64)
+//   k_outer2 / k_colsum4 per-species sums over atoms (fixed order, float64)
 #include "train.hpp"
 
 namespace nepmi {
@@ -604,10 +604,13 @@ constexpr int outer_block() {
   return ((A + 3) / 4) * ((B + 3) / 4) >= 128 ? 4 : 2;
 }
 template <class X, int A, int B>
-__global__ __launch_bounds__(kRB) void k_outer(int64_t ns, const int* __restrict__ base, const X* __restrict__ X1,
-                                               const X* __restrict__ Y1, const X* __restrict__ X2,
-                                               const X* __restrict__ Y2, double* __restrict__ part) {
-  __shared__ X sx1[A * kRS], sx2[A * kRS], sy1[B * kRS], sy2[B * kRS];
+__device__ __forceinline__ void outer_sum_block(int64_t ns, const int* __restrict__ base, const X* __restrict__ X1,
+                                                const X* __restrict__ Y1, const X* __restrict__ X2,
+                                                const X* __restrict__ Y2, double* __restrict__ part, X* lds) {
+  X* sx1 = lds;  // LDS rows of X1, X2, Y1, Y2 (2 (A + B) kRS values)
+  X* sx2 = sx1 + A * kRS;
+  X* sy1 = sx2 + A * kRS;
+  X* sy2 = sy1 + B * kRS;
   constexpr int kOB = outer_block<A, B>();
   constexpr int nbB = (B + kOB - 1) / kOB, nblk = ((A + kOB - 1) / kOB) * nbB;
   static_assert(nblk <= kRB, "one entry block per thread");
@@ -694,6 +697,23 @@ __global__ __launch_bounds__(kRB) void k_outer(int64_t ns, const int* __restrict
 #pragma unroll
     for (int c = 0; c < kOB; ++c)
       if (a0 + r < A && b0 + c < B) part[((int64_t)s * kRBlocks + blk) * (A * B) + (a0 + r) * B + b0 + c] = acc[r][c];
+}
+
+// Two outer-product sums in one launch, grid (kRBlocks, T, 2): blockIdx.z
+// picks the product (A0 x B0 or A1 x B1); one LDS buffer fits either.
+template <class X, int A0, int B0, int A1, int B1>
+__global__ __launch_bounds__(kRB) void k_outer2(int64_t ns, const int* __restrict__ base, const X* __restrict__ X1a,
+                                                const X* __restrict__ Y1a, const X* __restrict__ X2a,
+                                                const X* __restrict__ Y2a, double* __restrict__ Pa,
+                                                const X* __restrict__ X1b, const X* __restrict__ Y1b,
+                                                const X* __restrict__ X2b, const X* __restrict__ Y2b,
+                                                double* __restrict__ Pb) {
+  constexpr int L0 = 2 * (A0 + B0) * kRS, L1 = 2 * (A1 + B1) * kRS;
+  __shared__ X lds[L0 > L1 ? L0 : L1];
+  if (blockIdx.z == 0)
+    outer_sum_block<X, A0, B0>(ns, base, X1a, Y1a, X2a, Y2a, Pa, lds);
+  else
+    outer_sum_block<X, A1, B1>(ns, base, X1b, Y1b, X2b, Y2b, Pb, lds);
 }
 
 // part[(s * kRBlocks + blk) * A + a] = sum over the block's slots of X[a][i].
@@ -1033,12 +1053,11 @@ template <class S, class R>
 static void species_sums(hipStream_t st, const TrainIOT<R>& io, const int* base, double* part, double* grad) {
   constexpr int T = S::T, H = S::H;
   const int64_t ns = io.ns;
-  const dim3 g(kRBlocks, T);
   PartPlan pl = part_plan(T, S::NR, S::BR);
-  hipLaunchKernelGGL((k_outer<R, S::H, S::D>), g, dim3(kRB), 0, st, ns, base, io.abar, io.q, io.zneg, io.qd,
-                     pl.add(part, S::H * S::D, S::PCR + S::PCA, S::PMLP, 0));
-  hipLaunchKernelGGL((k_outer<R, S::NR, S::T * S::BR>), g, dim3(kRB), 0, st, ns, base, io.qbR, io.Pb, io.FpR, io.Pdn,
-                     pl.add(part, S::NR * T * S::BR, 0, (int64_t)T * S::NR * S::BR, 1));
+  double* pW0 = pl.add(part, S::H * S::D, S::PCR + S::PCA, S::PMLP, 0);
+  double* pcR = pl.add(part, S::NR * T * S::BR, 0, (int64_t)T * S::NR * S::BR, 1);
+  hipLaunchKernelGGL((k_outer2<R, S::H, S::D, S::NR, S::T * S::BR>), dim3(kRBlocks, T, 2), dim3(kRB), 0, st, ns, base,
+                     io.abar, io.q, io.zneg, io.qd, pW0, io.qbR, io.Pb, io.FpR, io.Pdn, pcR);
   double* pA = pl.add(part, T * S::NA * S::BA, S::PCR, (int64_t)T * S::NA * S::BA, 0);
   double* pb0 = pl.add(part, H, S::PCR + S::PCA + (int64_t)H * S::D, S::PMLP, 0);
   double* pw1 = pl.add(part, H, S::PCR + S::PCA + (int64_t)H * S::D + H, S::PMLP, 0);
