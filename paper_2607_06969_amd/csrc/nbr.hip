@@ -353,11 +353,15 @@ __global__ __launch_bounds__(256) void k_build_lists(int64_t n_slots, int n_spec
 // entry with i's slot and the opposite image code), else 0xFFFFFFFF.  The
 // pair-force buffer is indexed by these positions, so that each step's gather
 // reads without searching.  A pair found from one side only raises the
-// asymmetry flag.  Grid (slot tiles, kRevSplit): row y takes the entries
-// k = y, y + kRevSplit, ... of each list, so the searches of one atom run
-// side by side.  The x extent is a multiple of the XCD count, so that every
-// row maps a slot tile to the same XCD.
+// asymmetry flag.  Grid (slot tiles, rows): row y takes the entries
+// k = y, y + rows, ... of each list, so the searches of one atom run side by
+// side.  The x extent is a multiple of the XCD count, so that every row maps
+// a slot tile to the same XCD.  Small batches take kRevSplit rows; from
+// kRevOneRow tiles on, the slot tiles alone fill the chip and one row is used
+// (more rows there only add blocks, which cost time even when the rebuild
+// gate sends them home at once).
 constexpr int kRevSplit = 4;
+constexpr unsigned kRevOneRow = 2048;
 __global__ __launch_bounds__(256) void k_reverse(int64_t n_slots, const CfgDev* __restrict__ cfgs,
                                                  const float4* __restrict__ pos4, const int* __restrict__ cfg_of,
                                                  const uint32_t* __restrict__ nbrR, const uint32_t* __restrict__ nbrT,
@@ -375,7 +379,7 @@ __global__ __launch_bounds__(256) void k_reverse(int64_t n_slots, const CfgDev* 
   const float4 xi = pos4[p];
   const int n = cntR[p];
   bool missing = false;
-  for (int k = (int)blockIdx.y; k < n; k += kRevSplit) {
+  for (int k = (int)blockIdx.y; k < n; k += (int)gridDim.y) {
     const uint32_t e = nbrR[(int64_t)k * n_slots + p];
     const int q = (int)(e & kNbrMask);
     const uint32_t code = e >> kNbrShift;
@@ -669,7 +673,8 @@ int NbrPipeline::launch_lists(hipStream_t st, int n_species, const int* gate) {
                      base.ptr<int>(), rclR2, rclA2, capR, capA, rowT, nbrR.ptr<uint32_t>(), nbrT.ptr<uint32_t>(),
                      cntR.ptr<int>(), flags.ptr<int>(), gate);
   const unsigned rev_tiles = (nblk(n_slots, 256) + kXcds - 1) / kXcds * kXcds;
-  hipLaunchKernelGGL(k_reverse, dim3(rev_tiles, kRevSplit), dim3(256), 0, st, n_slots, cfgs.ptr<CfgDev>(),
+  const unsigned rev_rows = rev_tiles >= kRevOneRow ? 1u : (unsigned)kRevSplit;
+  hipLaunchKernelGGL(k_reverse, dim3(rev_tiles, rev_rows), dim3(256), 0, st, n_slots, cfgs.ptr<CfgDev>(),
                      pos4.ptr<float4>(), cfg_of.ptr<int>(), nbrR.ptr<uint32_t>(), nbrT.ptr<uint32_t>(), rowT,
                      cntR.ptr<int>(), rclA2, vrev.ptr<uint32_t>(), flags.ptr<int>(), gate);
   NEPMI_HIP(hipGetLastError());
