@@ -14,6 +14,8 @@
 //   k_train_atom    tangent pass + second-order network adjoint (per atom)
 //   k_train_coefA   angular coefficient gradient (per atom, over its pairs)
 //   k_outer2 / k_colsum4 per-species sums over atoms (fixed order, float64)
+#include <cstdlib>
+
 #include "train.hpp"
 
 namespace nepmi {
@@ -790,6 +792,7 @@ struct PartPlan {
   int64_t used;  // doubles of the partial-sum buffer taken so far
   // region of the next segment's partial sums (host side)
   double* add(double* part, int E, int64_t off, int64_t sstride, int kind) {
+    if (n >= kPartSegs) std::abort();  // a fixed set of sums per backward pass
     PartSeg& g = seg[n];
     g.E = E;
     g.kind = kind;
