@@ -58,6 +58,8 @@ def lib():
         L.orc_loss_grad.argtypes = [hp, dp, C.c_int32, lp, dp, ip, dp, C.c_int32, dp, dp, dp, dp, C.c_int32,
                                     dp, dp]
         L.orc_num_threads.argtypes = []
+        L.orc_set_num_threads.argtypes = [C.c_int]
+        L.orc_set_num_threads.restype = None
         _lib = L
     return _lib
 
@@ -181,3 +183,8 @@ def loss_grad(hp, params, system, E_ref, F_ref, V_ref, weights=(1.0, 1.0, 0.1), 
 
 def num_threads() -> int:
     return lib().orc_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops (n < 1: the OpenMP default)."""
+    lib().orc_set_num_threads(int(n))

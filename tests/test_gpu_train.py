@@ -137,3 +137,26 @@ def test_reuse_lists_on_fixed_batches():
         assert torch.equal(l0, l1) and torch.equal(g0, g1)
         c0, c1 = fresh.compute(b), kept.compute(b)
         assert torch.equal(c0["F"], c1["F"]) and torch.equal(c0["E"], c1["E"])
+
+
+@pytest.mark.parametrize("form", [0, 1])
+def test_loss_hand_evaluated_on_gpu(form):
+    """The GPU loss of both forms on the case worked out by hand in
+    loss_hand_case.py (a constant-energy model on a dimer and a trimer): the
+    loss parts within 1e-6 relative (the force labels are rounded to float32,
+    about 6e-8 relative) and the one gradient entry that the energy seed alone
+    determines (b1)."""
+    import loss_hand_case as H
+    from paper_2607_06969_amd import nep
+    hp, p = H.constant_energy_model()
+    s = H.two_config_batch()
+    case = H.FORM0 if form == 0 else H.FORM1
+    m = nep.NepModel(hp, p)
+    b = nep.Batch.from_system(s)
+    loss, g = m.loss_grad(b, torch.tensor(H.E_REF, device="cuda"),
+                          torch.tensor(H.F_REF, dtype=torch.float32, device="cuda"),
+                          torch.tensor(H.V_REF, device="cuda"), weights=case["w"], loss_form=form)
+    loss = loss.cpu().numpy()
+    np.testing.assert_allclose(loss[1:], case["parts"], rtol=1e-6)
+    np.testing.assert_allclose(loss[0], sum(case["parts"]), rtol=1e-6)
+    np.testing.assert_allclose(float(g[-1]), case["db1"], rtol=1e-6)
