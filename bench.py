@@ -460,6 +460,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-table2", action="store_true")
+    ap.add_argument("--no-amortised", action="store_true",
+                    help="skip the amortised-rebuild window (for short profiled runs)")
     ap.add_argument("--train-only", type=int, default=0, metavar="REPS",
                     help="only time REPS batched training calls (lists rebuilt, then kept) and print that line")
     a = ap.parse_args()
@@ -530,7 +532,7 @@ def main():
 
     # the cost per step with neighbour-list rebuilds amortised: a window of
     # steps after the timed ones that always holds at least two rebuilds
-    amort = amortised_window(md)
+    amort = amortised_window(md) if not a.no_amortised else None
     print(f"[bench] amortised window: {amort}", file=sys.stderr, flush=True)
     # a neighbour-list rebuild is timed separately (standalone launches on the final state)
     standalone = md.time_kernels(a.kernel_reps)
@@ -572,8 +574,8 @@ def main():
         "steps": a.steps,
         "warmup": a.warmup,
         "ms_per_step": dt / a.steps * 1e3,
-        "amortised_ms_per_step": amort["amortised_ms_per_step"],
-        "rebuild_interval_steps": amort["rebuild_interval_steps"],
+        "amortised_ms_per_step": amort["amortised_ms_per_step"] if amort else None,
+        "rebuild_interval_steps": amort["rebuild_interval_steps"] if amort else None,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -586,7 +588,8 @@ def main():
                    "rebuilds_in_timed_steps": st1["rebuilds"] - st0["rebuilds"],
                    "epot_per_atom_eV": epot / n, "ekin_per_atom_eV": ekin / n},
         "roofline": roofline,
-        "amortised": {**amort, "atom_steps_per_s": n / (amort["amortised_ms_per_step"] * 1e-3)},
+        "amortised": ({**amort, "atom_steps_per_s": n / (amort["amortised_ms_per_step"] * 1e-3)}
+                      if amort else None),
     }
     del md
     if not a.no_table2:

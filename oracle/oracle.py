@@ -54,8 +54,8 @@ def lib():
         L.orc_ylm_eval.argtypes = [C.c_int, dp, dp, dp]
         L.orc_pairs_of.argtypes = [C.c_int32, dp, dp, C.c_double, C.c_int32, C.c_int64, ip, dp]
         L.orc_pairs_of.restype = C.c_int64
-        L.orc_evaluate.argtypes = [hp, dp, C.c_int32, lp, dp, ip, dp, C.c_int32, dp, dp, dp, dp, dp]
-        L.orc_loss_grad.argtypes = [hp, dp, C.c_int32, lp, dp, ip, dp, C.c_int32, dp, dp, dp, dp, C.c_int32,
+        L.orc_evaluate.argtypes = [hp, dp, C.c_int32, lp, dp, ip, dp, ip, C.c_int32, dp, dp, dp, dp, dp]
+        L.orc_loss_grad.argtypes = [hp, dp, C.c_int32, lp, dp, ip, dp, ip, C.c_int32, dp, dp, dp, dp, C.c_int32,
                                     dp, dp]
         L.orc_num_threads.argtypes = []
         L.orc_set_num_threads.argtypes = [C.c_int]
@@ -133,20 +133,30 @@ def pairs(pos, cell, rc: float, mode: int = 0):
     return ij[:cnt], rv[:cnt]
 
 
+def _pbc(system):
+    """(array, pointer) of the system's periodicity, or (None, None) if periodic in all directions."""
+    pbc = getattr(system, "pbc", None)
+    if pbc is None:
+        return None, None
+    return _i32(np.asarray(pbc).reshape(-1))
+
+
 def evaluate(hp, params, system, nbr_mode: int = 2, want_q: bool = False):
-    """Return dict with E (n_cfg), F (N,3), V (n_cfg,3,3), Ei (N) and optionally q (N,D)."""
+    """Return dict with E (n_cfg), F (N,3), V (n_cfg,3,3), Ei (N) and optionally q (N,D).
+    Directions the system marks non-periodic (system.pbc) have no images."""
     h = _hp(hp)
     P, pP = _d(params)
     pos, ppos = _d(system.pos)
     spc, pspc = _i32(system.species)
     cells, pcell = _d(np.asarray(system.cells).reshape(-1, 9))
+    pb, ppb = _pbc(system)
     off, poff = _i64(system.atom_off)
     n_cfg = len(off) - 1
     N = int(off[-1])
     D = descriptor_dim(hp)
     E, F, V, Ei = np.zeros(n_cfg), np.zeros((N, 3)), np.zeros((n_cfg, 9)), np.zeros(N)
     q = np.zeros((N, D)) if want_q else None
-    rc = lib().orc_evaluate(C.byref(h), pP, n_cfg, poff, ppos, pspc, pcell, int(nbr_mode),
+    rc = lib().orc_evaluate(C.byref(h), pP, n_cfg, poff, ppos, pspc, pcell, ppb, int(nbr_mode),
                             E.ctypes.data_as(C.POINTER(C.c_double)), F.ctypes.data_as(C.POINTER(C.c_double)),
                             V.ctypes.data_as(C.POINTER(C.c_double)), Ei.ctypes.data_as(C.POINTER(C.c_double)),
                             q.ctypes.data_as(C.POINTER(C.c_double)) if want_q else None)
@@ -166,6 +176,7 @@ def loss_grad(hp, params, system, E_ref, F_ref, V_ref, weights=(1.0, 1.0, 0.1), 
     pos, ppos = _d(system.pos)
     spc, pspc = _i32(system.species)
     cells, pcell = _d(np.asarray(system.cells).reshape(-1, 9))
+    pb, ppb = _pbc(system)
     off, poff = _i64(system.atom_off)
     Er, pEr = _d(E_ref)
     Fr, pFr = _d(np.asarray(F_ref).reshape(-1))
@@ -173,7 +184,7 @@ def loss_grad(hp, params, system, E_ref, F_ref, V_ref, weights=(1.0, 1.0, 0.1), 
     w, pw = _d(np.asarray(weights, dtype=np.float64))
     parts = np.zeros(4)
     grad = np.zeros(len(P)) if want_grad else None
-    rc = lib().orc_loss_grad(C.byref(h), pP, len(off) - 1, poff, ppos, pspc, pcell, int(nbr_mode), pEr, pFr, pVr,
+    rc = lib().orc_loss_grad(C.byref(h), pP, len(off) - 1, poff, ppos, pspc, pcell, ppb, int(nbr_mode), pEr, pFr, pVr,
                              pw, int(loss_form), parts.ctypes.data_as(C.POINTER(C.c_double)),
                              grad.ctypes.data_as(C.POINTER(C.c_double)) if want_grad else None)
     if rc:

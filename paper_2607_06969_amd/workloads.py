@@ -106,7 +106,10 @@ class System:
 
     pos: (N, 3) float64 holding float32-representable values, wrapped into
     the cell; species: (N,) int32; cells: (n_cfg, 3, 3) float64 whose rows are
-    the lattice vectors (float32-representable); atom_off: (n_cfg + 1,) int64.
+    the lattice vectors (float32-representable); atom_off: (n_cfg + 1,) int64;
+    pbc: (n_cfg, 3) int32 periodicity of each lattice direction, or None for
+    periodic in all three (along a non-periodic direction the atoms lie inside
+    the cell and have no images).
     """
 
     pos: np.ndarray
@@ -114,6 +117,12 @@ class System:
     cells: np.ndarray
     atom_off: np.ndarray
     meta: dict = field(default_factory=dict)
+    pbc: np.ndarray | None = None
+
+    def pbc_array(self) -> np.ndarray:
+        if self.pbc is None:
+            return np.ones((self.n_cfg, 3), dtype=np.int32)
+        return np.ascontiguousarray(np.asarray(self.pbc, dtype=np.int32).reshape(self.n_cfg, 3))
 
     @property
     def n_atoms(self) -> int:
@@ -126,7 +135,8 @@ class System:
     def config(self, c: int) -> "System":
         a, b = int(self.atom_off[c]), int(self.atom_off[c + 1])
         return System(self.pos[a:b].copy(), self.species[a:b].copy(), self.cells[c:c + 1].copy(),
-                      np.array([0, b - a], dtype=np.int64), dict(self.meta))
+                      np.array([0, b - a], dtype=np.int64), dict(self.meta),
+                      None if self.pbc is None else self.pbc_array()[c:c + 1].copy())
 
 
 def _round_cell(cell: np.ndarray) -> np.ndarray:
@@ -285,8 +295,9 @@ def mixed_size_cells(n_cells: int = 64, n_min: float = 1e3, n_max: float = 2e5,
 def concat_systems(parts, meta=None) -> System:
     off = np.zeros(len(parts) + 1, dtype=np.int64)
     off[1:] = np.cumsum([p.n_atoms for p in parts])
+    pbc = None if all(p.pbc is None for p in parts) else np.concatenate([p.pbc_array() for p in parts])
     return System(np.concatenate([p.pos for p in parts]), np.concatenate([p.species for p in parts]),
-                  np.concatenate([p.cells for p in parts]), off, dict(meta or {}))
+                  np.concatenate([p.cells for p in parts]), off, dict(meta or {}), pbc)
 
 
 def maxwell_boltzmann(species: np.ndarray, masses, temperature: float, seed: int = SEED_VEL) -> np.ndarray:

@@ -435,3 +435,50 @@ def test_loss_hand_evaluated(oracle_lib, form):
     np.testing.assert_allclose(parts[1:], want, rtol=1e-14, atol=0)
     np.testing.assert_allclose(parts[0], sum(want), rtol=1e-14)
     np.testing.assert_allclose(g[-1], case["db1"], rtol=1e-13)
+
+
+# ---------------------------------------------------- non-periodic directions
+
+def _cell_with_vacuum(s, axes, factor=3.0):
+    """The same atoms in a cell whose lattice vectors along `axes` are
+    `factor` times longer: images along those axes are then farther than any
+    cutoff, so the system is effectively not periodic there."""
+    cells = s.cells.copy()
+    for a in axes:
+        cells[0, a] *= factor
+    return W.System(s.pos.copy(), s.species.copy(), cells, s.atom_off.copy())
+
+
+@pytest.mark.parametrize("pbc,axes", [((0, 0, 0), (0, 1, 2)), ((1, 1, 0), (2,)), ((0, 1, 1), (0,))])
+def test_non_periodic_directions_equal_vacuum(oracle_lib, pbc, axes):
+    """A direction marked non-periodic has no images: E, F and V equal those of
+    the same atoms in a cell padded with vacuum along that direction (brute
+    force over images in both)."""
+    hp = W.hp_gst()
+    s = W.amorphous_batch(n_cfg=1, n_min=140, n_max=140, seed=41)
+    p = W.random_params(hp, 2041)
+    s.pbc = np.array([pbc], dtype=np.int32)
+    got = oracle_lib.evaluate(hp, p, s, nbr_mode=0)
+    ref = oracle_lib.evaluate(hp, p, _cell_with_vacuum(s, axes), nbr_mode=0)
+    periodic = oracle_lib.evaluate(hp, p, W.System(s.pos, s.species, s.cells, s.atom_off), nbr_mode=0)
+    np.testing.assert_allclose(got["E"], ref["E"], rtol=1e-13)
+    np.testing.assert_allclose(got["F"], ref["F"], rtol=1e-11, atol=1e-12)
+    np.testing.assert_allclose(got["V"], ref["V"], rtol=1e-11, atol=1e-12)
+    # and it differs from the fully periodic system (atoms near the faces interact across them there)
+    assert abs(got["E"][0] - periodic["E"][0]) > 1e-6
+
+
+def test_cluster_conserves_momentum_and_angular_momentum(oracle_lib):
+    """An isolated cluster (no periodic direction): sum_i F_i = 0, sum_i r_i x F_i = 0
+    and a symmetric virial (translation and rotation invariance of Eq. 1)."""
+    hp = W.hp_gst()
+    s = W.amorphous_batch(n_cfg=1, n_min=120, n_max=120, seed=42)
+    s.pbc = np.zeros((1, 3), dtype=np.int32)
+    out = oracle_lib.evaluate(hp, W.random_params(hp, 2042), s, nbr_mode=0)
+    F = out["F"]
+    scale = np.abs(F).max()
+    assert np.abs(F.sum(axis=0)).max() < 1e-12 * scale * len(F)
+    torque = np.cross(s.pos, F).sum(axis=0)
+    assert np.abs(torque).max() < 1e-11 * scale * len(F) * np.abs(s.pos).max()
+    V = out["V"][0]
+    np.testing.assert_allclose(V, V.T, atol=1e-11 * np.abs(V).max())
