@@ -117,6 +117,23 @@ int nepmi_compute(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, const 
                   const float *dev_pos, const int32_t *dev_species, double *dev_energy, float *dev_forces,
                   double *dev_virial, float *dev_atom_energy, float *dev_atom_virial, void *stream);
 
+/* Allocation-free variant of nepmi_compute, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, results and errors as
+ * nepmi_compute; neighbour lists are rebuilt on every call.  Every work
+ * buffer (neighbour lists, processing order, per-atom arrays, reduction plan)
+ * is carved from one static device array of 64 MiB per GPU, which each GPU
+ * the library runs on holds until the process ends; no hipMalloc or hipFree
+ * is called (the model's parameters were allocated by nepmi_model_create).
+ * A batch whose work space exceeds 64 MiB (about 2.1 kB per atom with the
+ * three-species Ge-Sb-Te model: some 30,000 atoms) returns NEPMI_INVALID_ARG.
+ * All calls on one GPU share that array and it keeps the last call's
+ * contents: calls that overlap on one GPU (from other streams or threads)
+ * race and must not be made. */
+int nepmi_compute_noalloc(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, const double *cells,
+                          const float *dev_pos, const int32_t *dev_species, double *dev_energy, float *dev_forces,
+                          double *dev_virial, float *dev_atom_energy, float *dev_atom_virial, void *stream);
+
 /* Descriptors q_i (float[N*D], caller's atom order) of the same batch: the
  * radial q_n (Eq. 11), three-body q_nl (Eq. 17, l = 1..l_max, index
  * n_radial + (l-1) n_angular + n), then the 4-body and 5-body values. */

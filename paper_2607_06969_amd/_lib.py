@@ -52,6 +52,7 @@ SIGNATURES = [
     ("nepmi_model_reuse_lists", C.c_int, [_vp, _i32]),
     ("nepmi_model_destroy", None, [_vp]),
     ("nepmi_compute", C.c_int, [_vp, _i32, _i64p, _dp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    ("nepmi_compute_noalloc", C.c_int, [_vp, _i32, _i64p, _dp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     ("nepmi_descriptors", C.c_int, [_vp, _i32, _i64p, _dp, _vp, _vp, _vp, _vp]),
     ("nepmi_neighbors", C.c_int, [_vp, _i32, _i64p, _dp, _vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp]),
     ("nepmi_autotune", C.c_int, [_vp, _i32, _i64p, _dp, _vp, _vp, C.POINTER(C.c_int32), _vp]),

@@ -67,35 +67,26 @@ static int64_t param_count(const nepmi_hparams& h) {
 
 using namespace nepmi;
 
-int nepmi_model::prepare(int n_cfg, const int64_t* atom_off, const double* cells, const float* pos,
-                         const int32_t* species, hipStream_t st, double skin, bool may_reuse) {
-  if (n_cfg >= 1 && atom_off && cells && reuse_lists && may_reuse && last.valid && last.pos == pos &&
-      last.species == species && last.skin == skin && last.off.size() == (size_t)n_cfg + 1 &&
-      std::equal(last.off.begin(), last.off.end(), atom_off) &&
-      std::equal(last.cells.begin(), last.cells.end(), cells))
-    return NEPMI_OK;
-  last.valid = false;
+namespace nepmi {
+
+int prepare_eval(EvalWork& w, const Ops* ops, const nepmi_hparams& hp, int n_cfg, const int64_t* atom_off,
+                 const double* cells, const float* pos, const int32_t* species, hipStream_t st, double skin) {
   int rc;
-  if ((rc = nbr.setup(n_cfg, atom_off, cells, ops->T, hp.rc_radial, hp.rc_angular, skin, st))) return rc;
-  if ((rc = nbr.build(st, pos, species))) return rc;
-  if ((rc = red.setup(n_cfg, atom_off, st))) return rc;
-  const size_t ns = (size_t)nbr.n_slots, N = (size_t)(nbr.N > 0 ? nbr.N : 1);
-  if ((rc = fp.ensure(4 * ns * (size_t)ops->NANG)) || (rc = aR.ensure(4 * ns * (size_t)(ops->T * ops->BR))) ||
-      (rc = Ei.ensure(4 * N)) || (rc = frad.ensure(16 * ns)) || (rc = amask.ensure(8 * ns * (size_t)((nbr.capR + 63) / 64))) || (rc = fA.ensure(16 * ns * (size_t)nbr.capA)) ||
-      (rc = Wi.ensure(36 * N)) || (rc = Eproc.ensure(4 * ns)))
+  if ((rc = w.nbr.setup(n_cfg, atom_off, cells, ops->T, hp.rc_radial, hp.rc_angular, skin, st))) return rc;
+  if ((rc = w.nbr.build(st, pos, species))) return rc;
+  if ((rc = w.red.setup(n_cfg, atom_off, st))) return rc;
+  const NbrPipeline& nb = w.nbr;
+  const size_t ns = (size_t)nb.n_slots, N = (size_t)(nb.N > 0 ? nb.N : 1);
+  if ((rc = w.fp.ensure(4 * ns * (size_t)ops->NANG)) || (rc = w.aR.ensure(4 * ns * (size_t)(ops->T * ops->BR))) ||
+      (rc = w.Ei.ensure(4 * N)) || (rc = w.frad.ensure(16 * ns)) ||
+      (rc = w.amask.ensure(8 * ns * (size_t)((nb.capR + 63) / 64))) || (rc = w.fA.ensure(16 * ns * (size_t)nb.capA)) ||
+      (rc = w.Wi.ensure(36 * N)) || (rc = w.Eproc.ensure(4 * ns)))
     return rc;
-  if (may_reuse) {
-    last.valid = true;
-    last.pos = pos;
-    last.species = species;
-    last.skin = skin;
-    last.off.assign(atom_off, atom_off + n_cfg + 1);
-    last.cells.assign(cells, cells + 9 * (size_t)n_cfg);
-  }
   return NEPMI_OK;
 }
 
-NepIO nepmi_model::io(float* Fuser, float4* Fproc, float* qout) {
+NepIO eval_io(EvalWork& w, const nepmi_hparams& hp, float* Fuser, float4* Fproc, float* qout) {
+  const NbrPipeline& nbr = w.nbr;
   NepIO o;
   o.n_slots = nbr.n_slots;
   o.capR = nbr.capR;
@@ -120,19 +111,61 @@ NepIO nepmi_model::io(float* Fuser, float4* Fproc, float* qout) {
   o.cut.rcA2 = rcA * rcA;
   o.cut.rclR2 = nbr.rclR2;
   o.cut.rclA2 = nbr.rclA2;
-  o.fp = fp.ptr<float>();
-  o.aR = aR.ptr<float>();
-  o.Ei = Ei.ptr<float>();
+  o.fp = w.fp.ptr<float>();
+  o.aR = w.aR.ptr<float>();
+  o.Ei = w.Ei.ptr<float>();
   o.qout = qout;
-  o.frad = frad.ptr<float4>();
-  o.fA = fA.ptr<float4>();
-  o.amask = amask.ptr<uint64_t>();
-  o.Wi = Wi.ptr<float>();
+  o.frad = w.frad.ptr<float4>();
+  o.fA = w.fA.ptr<float4>();
+  o.amask = w.amask.ptr<uint64_t>();
+  o.Wi = w.Wi.ptr<float>();
   o.Fuser = Fuser;
   o.Fproc = Fproc;
-  o.Eproc = Eproc.ptr<float>();
+  o.Eproc = w.Eproc.ptr<float>();
   return o;
 }
+
+// E, F, V of a prepared batch: descriptors + network, pair forces, gather,
+// float64 sums, optional per-atom copies.
+int run_eval(EvalWork& w, const nepmi_model* m, float* dev_forces, double* dev_energy, double* dev_virial,
+             float* dev_atom_energy, float* dev_atom_virial, hipStream_t st) {
+  NepIO io = eval_io(w, m->hp, dev_forces, nullptr, nullptr);
+  const float* P = m->params.ptr<float>();
+  int rc;
+  if ((rc = m->ops->desc(st, io, P, true, m->vdesc)) || (rc = m->ops->force(st, io, P, m->vforce)) ||
+      (rc = m->ops->gather(st, io)))
+    return rc;
+  if ((rc = w.red.run(st, io.Ei, io.Wi, nullptr, dev_energy, dev_virial, nullptr))) return rc;
+  const size_t N = (size_t)w.nbr.N;
+  if (dev_atom_energy && N) NEPMI_HIP(hipMemcpyAsync(dev_atom_energy, io.Ei, 4 * N, hipMemcpyDeviceToDevice, st));
+  if (dev_atom_virial && N) NEPMI_HIP(hipMemcpyAsync(dev_atom_virial, io.Wi, 36 * N, hipMemcpyDeviceToDevice, st));
+  return NEPMI_OK;
+}
+
+}  // namespace nepmi
+
+int nepmi_model::prepare(int n_cfg, const int64_t* atom_off, const double* cells, const float* pos,
+                         const int32_t* species, hipStream_t st, double skin, bool may_reuse) {
+  if (n_cfg >= 1 && atom_off && cells && reuse_lists && may_reuse && last.valid && last.pos == pos &&
+      last.species == species && last.skin == skin && last.off.size() == (size_t)n_cfg + 1 &&
+      std::equal(last.off.begin(), last.off.end(), atom_off) &&
+      std::equal(last.cells.begin(), last.cells.end(), cells))
+    return NEPMI_OK;
+  last.valid = false;
+  int rc;
+  if ((rc = prepare_eval(*this, ops, hp, n_cfg, atom_off, cells, pos, species, st, skin))) return rc;
+  if (may_reuse) {
+    last.valid = true;
+    last.pos = pos;
+    last.species = species;
+    last.skin = skin;
+    last.off.assign(atom_off, atom_off + n_cfg + 1);
+    last.cells.assign(cells, cells + 9 * (size_t)n_cfg);
+  }
+  return NEPMI_OK;
+}
+
+NepIO nepmi_model::io(float* Fuser, float4* Fproc, float* qout) { return eval_io(*this, hp, Fuser, Fproc, qout); }
 
 extern "C" {
 
@@ -213,17 +246,7 @@ int nepmi_compute(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, const 
   hipStream_t st = (hipStream_t)stream;
   int rc = m->prepare(n_cfg, atom_off, cells, dev_pos, dev_species, st);
   if (rc) return rc;
-  NepIO io = m->io(dev_forces, nullptr, nullptr);
-  const float* P = m->params.ptr<float>();
-  if ((rc = m->ops->desc(st, io, P, true, m->vdesc)) || (rc = m->ops->force(st, io, P, m->vforce)) || (rc = m->ops->gather(st, io)))
-    return rc;
-  if ((rc = m->red.run(st, io.Ei, io.Wi, nullptr, dev_energy, dev_virial, nullptr))) return rc;
-  const size_t N = (size_t)m->nbr.N;
-  if (dev_atom_energy && N)
-    NEPMI_HIP(hipMemcpyAsync(dev_atom_energy, io.Ei, 4 * N, hipMemcpyDeviceToDevice, st));
-  if (dev_atom_virial && N)
-    NEPMI_HIP(hipMemcpyAsync(dev_atom_virial, io.Wi, 36 * N, hipMemcpyDeviceToDevice, st));
-  return NEPMI_OK;
+  return run_eval(*m, m, dev_forces, dev_energy, dev_virial, dev_atom_energy, dev_atom_virial, st);
 }
 
 int nepmi_descriptors(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, const double* cells,

@@ -40,15 +40,37 @@ struct F64Bufs {
   DevBuf Sst, Sdt, q, qd, Pb, Pdn, abar, zneg, gw1, eat, qbR, FpR, GA, part, FpA, qbA;
 };
 
+// Work space of one evaluation (E, F, V): neighbour lists and processing
+// order, reduction plan and the per-slot arrays the kernels hand to each other.
+struct EvalWork {
+  NbrPipeline nbr;
+  Reducer red;
+  DevBuf fp, aR, Ei, frad, fA, amask, Wi, Eproc;
+  // Take every buffer from `a` (see Arena); releases what is held.
+  void use_arena(Arena* a) {
+    nbr.use_arena(a);
+    red.use_arena(a);
+    for (DevBuf* b : {&fp, &aR, &Ei, &frad, &fA, &amask, &Wi, &Eproc}) {
+      b->release();
+      b->arena = a;
+    }
+  }
+};
+
+// Neighbour lists (pairs within the cutoffs + skin), work buffers and
+// reduction plan of a batch in `w`.
+int prepare_eval(EvalWork& w, const Ops* ops, const nepmi_hparams& hp, int n_cfg, const int64_t* atom_off,
+                 const double* cells, const float* pos, const int32_t* species, hipStream_t st, double skin);
+// Kernel arguments of an evaluation on `w` (optional caller-order forces,
+// slot-order forces and descriptors).
+NepIO eval_io(EvalWork& w, const nepmi_hparams& hp, float* Fuser, float4* Fproc, float* qout);
+
 }  // namespace nepmi
 
-struct nepmi_model {
+struct nepmi_model : nepmi::EvalWork {
   nepmi_hparams hp{};
   const nepmi::Ops* ops = nullptr;
   nepmi::DevBuf params;
-  nepmi::NbrPipeline nbr;
-  nepmi::Reducer red;
-  nepmi::DevBuf fp, aR, Ei, frad, fA, amask, Wi, Eproc;
   nepmi::TrainBufs tr;
   nepmi::F64Bufs f64;
   int device = 0;
@@ -73,6 +95,11 @@ struct nepmi_model {
 };
 
 namespace nepmi {
+// E, F, V of a batch prepared in `w` with the model's parameters and kernel
+// variants (descriptors + network, pair forces, gather, float64 sums, and the
+// optional per-atom copies).
+int run_eval(EvalWork& w, const nepmi_model* m, float* dev_forces, double* dev_energy, double* dev_virial,
+             float* dev_atom_energy, float* dev_atom_virial, hipStream_t st);
 // Time every compiled variant of k_desc and k_force on `io` and keep the
 // fastest in the model (see tune.hip).
 int autotune_io(nepmi_model* m, const NepIO& io, hipStream_t st, int reps);

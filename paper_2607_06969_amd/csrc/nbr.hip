@@ -440,6 +440,18 @@ void fill_int(hipStream_t st, int* p, int64_t n, int v, const int* gate) {
 
 int DevBuf::ensure(size_t n) {
   if (n <= bytes && p) return NEPMI_OK;
+  if (arena) {
+    const size_t want = ((n < 256 ? 256 : n) + 255) / 256 * 256;
+    if (arena->used + want > arena->cap) {
+      set_error("the batch needs more than the " + std::to_string(arena->cap >> 20) +
+                " MiB of the allocation-free workspace");
+      return NEPMI_INVALID_ARG;
+    }
+    p = arena->base + arena->used;
+    arena->used += want;
+    bytes = want;
+    return NEPMI_OK;
+  }
   release();
   const size_t want = n < 256 ? 256 : n;
   NEPMI_HIP(hipMalloc(&p, want));
@@ -448,7 +460,7 @@ int DevBuf::ensure(size_t n) {
 }
 
 void DevBuf::release() {
-  if (p) (void)hipFree(p);
+  if (p && !arena) (void)hipFree(p);
   p = nullptr;
   bytes = 0;
 }
@@ -577,6 +589,17 @@ int NbrPipeline::setup(int n_cfg_, const int64_t* atom_off, const double* cells,
     capA = (int)(1.5 * dmax * vA) + 16;
   }
   return ensure_lists(capR, capA);
+}
+
+void NbrPipeline::use_arena(Arena* a) {
+  DevBuf* all[] = {&cfgs, &atom_off_dev, &key, &cnt, &start, &cursor, &tile_sums, &base, &perm, &pos_tmp,
+                   &cfg_tmp, &crd_tmp, &pos4, &cfg_of, &orig, &bin_of, &slot_of, &nbrR, &cntR, &nbrT, &vrev,
+                   &cnbrR, &ccntR, &cnbrA, &ccntA, &cposA, &flags};
+  for (DevBuf* b : all) {
+    b->release();
+    b->arena = a;
+  }
+  capR = capA = 0;
 }
 
 int NbrPipeline::ensure_lists(int capR_, int capA_) {

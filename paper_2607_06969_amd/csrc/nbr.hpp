@@ -22,10 +22,22 @@ enum {
 // Largest Verlet list length: positions are kept in 16 bits.
 constexpr int kMaxListRows = 65535;
 
-// Device allocation that grows on demand (contents are not preserved).
+// A fixed block of device memory handed out front to back (a bump
+// allocator).  Buffers bound to an arena take their memory from it instead of
+// hipMalloc, and never free it; the owner resets `used` to reuse the block.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0;
+  size_t used = 0;
+};
+
+// Device allocation that grows on demand (contents are not preserved).  With
+// an arena, growing takes a new region of the arena (NEPMI_INVALID_ARG when
+// the arena is exhausted) and nothing is ever freed.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  Arena* arena = nullptr;
   template <class T>
   T* ptr() const {
     return static_cast<T*>(p);
@@ -67,6 +79,9 @@ struct NbrPipeline {
             double skin, hipStream_t st);
   // Sizes the lists for capR x capA entries per slot.
   int ensure_lists(int capR_, int capA_);
+  // Take every buffer from `a` from now on (releases what is held; the next
+  // setup sizes the lists afresh).
+  void use_arena(Arena* a);
   // Stage, bin and sort (pos: N x pos_stride floats).  gate: optional device
   // flag; every kernel returns at once when *gate == 0.
   int launch_sort(hipStream_t st, const float* pos, int pos_stride, const int32_t* species, int n_species,

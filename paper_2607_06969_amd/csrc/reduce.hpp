@@ -20,6 +20,12 @@ struct Reducer {
   int n_cfg = 0, n_items = 0;
   DevBuf items_dev, start_dev, part;
   int setup(int n_cfg, const int64_t* atom_off, hipStream_t st);
+  void use_arena(Arena* a) {
+    for (DevBuf* b : {&items_dev, &start_dev, &part}) {
+      b->release();
+      b->arena = a;
+    }
+  }
   // Any input or output may be null.
   int run(hipStream_t st, const float* Ei, const float* Wi, const float* Ki, double* E, double* V, double* Kout);
   // The same sums of float64 per-atom energies and virials.

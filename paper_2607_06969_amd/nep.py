@@ -84,8 +84,10 @@ class NepModel:
         the caller guarantees the positions and species have not changed (fixed training sets)."""
         check(load().nepmi_model_reuse_lists(self._h, 1 if enable else 0))
 
-    def compute(self, batch: Batch, atom_energy=False, atom_virial=False):
-        """Energy (n_cfg,) float64, forces (N, 3) float32, virial (n_cfg, 3, 3) float64."""
+    def compute(self, batch: Batch, atom_energy=False, atom_virial=False, noalloc=False):
+        """Energy (n_cfg,) float64, forces (N, 3) float32, virial (n_cfg, 3, 3) float64.
+        noalloc: use the allocation-free entry point (work space in the library's
+        static per-GPU array; the result tensors are still allocated here)."""
         dev = batch.pos.device
         E = torch.empty(batch.n_cfg, dtype=torch.float64, device=dev)
         F = torch.empty(batch.n_atoms, 3, dtype=torch.float32, device=dev)
@@ -93,8 +95,9 @@ class NepModel:
         Ea = torch.empty(batch.n_atoms, dtype=torch.float32, device=dev) if atom_energy else None
         Wa = torch.empty(batch.n_atoms, 9, dtype=torch.float32, device=dev) if atom_virial else None
         keep, poff, pcel = batch._meta()
-        check(load().nepmi_compute(self._h, batch.n_cfg, poff, pcel, _ptr(batch.pos), _ptr(batch.species),
-                                   _ptr(E), _ptr(F), _ptr(V), _ptr(Ea), _ptr(Wa), _stream()))
+        fn = load().nepmi_compute_noalloc if noalloc else load().nepmi_compute
+        check(fn(self._h, batch.n_cfg, poff, pcel, _ptr(batch.pos), _ptr(batch.species),
+                 _ptr(E), _ptr(F), _ptr(V), _ptr(Ea), _ptr(Wa), _stream()))
         out = {"E": E, "F": F, "V": V.view(-1, 3, 3)}
         if atom_energy:
             out["Ei"] = Ea
