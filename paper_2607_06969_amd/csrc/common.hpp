@@ -175,6 +175,81 @@ __device__ __forceinline__ void walk_pairs(const uint32_t* __restrict__ list, co
   }
 }
 
+// Compact pair lists are stored in groups of four entries: group g (entries
+// 4g .. 4g+3) of slot p is the uint4 at [g * n_slots + p].  A writer that
+// appends entries one lane at a time then stores once per four entries (each
+// such store touches one cache line per lane, so their number is what costs),
+// and a reader loads four entries with one coalesced 16-byte load.
+template <int G = 4>
+constexpr int list_groups(int entries) {
+  return (entries + G - 1) / G;
+}
+
+__device__ __forceinline__ uint32_t comp4(const uint4& v, int u) {
+  return u == 0 ? v.x : (u == 1 ? v.y : (u == 2 ? v.z : v.w));
+}
+
+// Opaque copy of a group (see take_slot).
+__device__ __forceinline__ uint4 take_group(const uint4& v) {
+  return make_uint4(take_slot(v.x), take_slot(v.y), take_slot(v.z), take_slot(v.w));
+}
+
+// walk_pairs for a list stored in groups of four.  Groups are loaded two at
+// a time (A = group 2i, B = group 2i+1), the next pair of groups three to
+// four pairs before their first position is needed, and neighbour positions
+// two pairs ahead.  The calls of f and pre are those of walk_pairs (k in
+// order, pre on every step, f only for k < n).
+template <class P, class Pre, class F>
+__device__ __forceinline__ void walk_groups(const uint4* __restrict__ list, int64_t ns, int64_t p, int n,
+                                            const P* __restrict__ pos4, Pre&& pre, F&& f) {
+  if (n <= 0) return;
+  const int ng = list_groups(n);
+  const uint4* lp = list + p;
+  // group g of this slot, clamped to the last group
+  auto group_at = [&](int g) { return lp[(int64_t)(g < ng ? g : ng - 1) * ns]; };
+  uint4 A = group_at(0), B = group_at(1);
+  P x[2];
+  x[0] = pos4[A.x & kNbrMask];
+  x[1] = pos4[A.y & kNbrMask];
+  __builtin_amdgcn_sched_barrier(0);
+  for (int g = 0; g < ng; g += 2) {
+    const int k0 = 4 * g;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int k = k0 + u;
+      const uint32_t ek = take_slot(comp4(u < 4 ? A : B, u & 3));
+      const P xk = x[u & 1];
+      const auto pk = pre(k, ek);
+      asm volatile("" ::: "memory");  // keeps pre's loads ahead of the prefetches
+      // the entry of pair k + 2 (from A, B or the next A), then its position
+      uint32_t en;
+      if (u < 2) {
+        en = comp4(A, u + 2);
+      } else if (u < 6) {
+        en = comp4(B, u - 2);
+      } else {
+        en = comp4(A, u - 6);
+      }
+      x[u & 1] = pos4[en & kNbrMask];
+      if (u == 3) A = group_at(g + 2);  // A is used up: the next even group
+      if (u == 7) B = group_at(g + 3);  // B is used up: the next odd group
+      if (k < n) f(k, ek, xk, 0u, pk);
+    }
+  }
+}
+
+// A pair walk over a list in either layout: grouped (compact lists) or one
+// entry per row (the Verlet list).
+template <bool GROUPED, int DE, int DX, class P, class Pre, class F>
+__device__ __forceinline__ void walk_list(const uint32_t* __restrict__ list, int64_t ns, int64_t p, int n,
+                                          const P* __restrict__ pos4, Pre&& pre, F&& f) {
+  if constexpr (GROUPED) {
+    walk_groups(reinterpret_cast<const uint4*>(list), ns, p, n, pos4, pre, f);
+  } else {
+    walk_pairs<DE, DX, false>(list, nullptr, ns, p, n, pos4, pre, f);
+  }
+}
+
 // One periodic configuration as the kernels see it.
 struct CfgDev {
   float H[9];       // lattice vectors as rows, float32

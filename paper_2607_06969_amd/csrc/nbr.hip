@@ -613,10 +613,12 @@ int NbrPipeline::ensure_lists(int capR_, int capA_) {
   int rc;
   const size_t ns = (size_t)n_slots;
   rowT = (capR + 3) / 4 * 4;
+  // the compact lists are stored in groups of four entries (see list_groups)
   if ((rc = nbrR.ensure(4 * (size_t)capR * ns)) || (rc = nbrT.ensure(4 * (size_t)rowT * ns)) ||
       (rc = vrev.ensure(4 * (size_t)capR * ns)) ||
-      (rc = cnbrR.ensure(4 * (size_t)capR * ns)) || (rc = cnbrA.ensure(4 * (size_t)capA * ns)) ||
-      (rc = cposA.ensure(4 * (size_t)capA * ns)))
+      (rc = cnbrR.ensure(16 * (size_t)list_groups(capR) * ns)) ||
+      (rc = cnbrA.ensure(16 * (size_t)list_groups(capA) * ns)) ||
+      (rc = cposA.ensure(16 * (size_t)list_groups(capA) * ns)))
     return rc;
   return NEPMI_OK;
 }

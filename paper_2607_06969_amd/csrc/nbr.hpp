@@ -70,7 +70,8 @@ struct NbrPipeline {
   DevBuf nbrT;                   // the same list row-major, rows of rowT entries (reverse search)
   int rowT = 0;
   DevBuf vrev;                   // reverse index of the Verlet list (see k_reverse)
-  DevBuf cnbrR, ccntR, cnbrA, ccntA, cposA;  // per-evaluation compact lists (rc_radial, rc_angular)
+  DevBuf cnbrR, ccntR, cnbrA, ccntA, cposA;  // per-evaluation compact lists (rc_radial, rc_angular),
+                                             // in groups of four entries (see list_groups)
   DevBuf flags;
 
   // Host-side setup of a batch: validates the cells, computes bins, sizes

@@ -28,6 +28,14 @@ __device__ __forceinline__ PairVec pair_vec(uint32_t e, float4 xq, float4 xi, co
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
+// v[u] = e for a lane-varying u in 0..3 (a select per component).
+__device__ __forceinline__ void put4(uint4& v, int u, uint32_t e) {
+  v.x = u == 0 ? e : v.x;
+  v.y = u == 1 ? e : v.y;
+  v.z = u == 2 ? e : v.z;
+  v.w = u == 3 ? e : v.w;
+}
+
 // One neighbour's radial adjoint row (B_R floats).
 template <int BR>
 struct AdjRow {
@@ -106,8 +114,8 @@ __device__ __forceinline__ void angular_sums(const float4* __restrict__ pos4, co
   for (int nn = 0; nn < NH; ++nn)
 #pragma unroll
     for (int lm = 0; lm < K; ++lm) Sg[nn][lm] = 0.f;
-  walk_pairs<kWalkDE, kWalkDX, false>(cnA, nullptr, n_slots, p, nA, pos4, NoPre{},
-                                      [&](int, uint32_t e, float4 xq, uint32_t, int) {
+  walk_groups(reinterpret_cast<const uint4*>(cnA), n_slots, p, nA, pos4, NoPre{},
+              [&](int, uint32_t e, float4 xq, uint32_t, int) {
     const PairVec v = pair_vec(e, xq, xi, Hc);
     const float inv = rsqrt_hw(v.d2);
     const RadialF f = radial_f(v.d2 * inv * rcA_inv);
@@ -205,28 +213,36 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
   if (active) {
     const int n = cntR[p];
     bool bad = false;
-    uint32_t* cr = cnR + p;   // next free row of the compact radial list
-    uint32_t* ca = cnA + p;   // ... and of the compact angular list
-    uint32_t* cpa = cpA + p;
+    // compact lists in groups of four entries: each lane collects a group in
+    // registers and stores it when full (one store per four kept pairs)
+    uint4* wr = reinterpret_cast<uint4*>(cnR) + p;   // next group of the compact radial list
+    uint4* wa = reinterpret_cast<uint4*>(cnA) + p;   // ... of the compact angular list
+    uint4* wp = reinterpret_cast<uint4*>(cpA) + p;   // ... and of its row pairs
+    uint4 gr = make_uint4(0u, 0u, 0u, 0u), ga = gr, gp = gr;
     uint64_t* mw = amask + p;
     uint64_t mword = 0;  // bit k % 64: entry k of the Verlet list is in the compact angular list
     walk_pairs<kWalkDE, kWalkDX, true>(nbrR, vrev, n_slots, p, n, pos4, NoPre{},
                                        [&](int k, uint32_t e, float4 xq, uint32_t rvk, int) {
       const PairVec v = pair_vec(e, xq, xi, Hc);
       if (v.d2 < cut.rcR2) {
-        *cr = e;
-        cr += n_slots;
-        ++nR;
+        put4(gr, nR & 3, e);
+        if ((++nR & 3) == 0) {
+          *wr = gr;
+          wr += n_slots;
+        }
         if (v.d2 < cut.rcA2) {
           // within rc_angular now implies within rc_angular + skin at the
           // last build, so nA stays below capA and the reverse row exists
           if (rvk <= 0xFFFFu && nA < capA) {
-            *ca = e;
-            *cpa = (uint32_t)k | (rvk << 16);
-            ca += n_slots;
-            cpa += n_slots;
+            put4(ga, nA & 3, e);
+            put4(gp, nA & 3, (uint32_t)k | (rvk << 16));
+            if ((++nA & 3) == 0) {
+              *wa = ga;
+              *wp = gp;
+              wa += n_slots;
+              wp += n_slots;
+            }
             mword |= 1ull << (k & 63);
-            ++nA;
           } else {
             bad = true;
           }
@@ -248,6 +264,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
         mword = 0;
       }
     });
+    // the last, partly filled groups
+    if (nR & 3) *wr = gr;
+    if (nA & 3) {
+      *wa = ga;
+      *wp = gp;
+    }
     if (bad) atomicOr(&flags[kFlagAsym], 1);
   }
   if (in_range) {
@@ -461,8 +483,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
       for (int c = 0; c < BR / 4; ++c) r.v[c] = src[c];
       return r;
     };
-    walk_pairs<kWalkDE, kWalkDX, false>(cnR, nullptr, n_slots, p, n, pos4, row,
-                                        [&](int, uint32_t e, float4 xq, uint32_t, const AdjRow<BR>& arow) {
+    walk_groups(reinterpret_cast<const uint4*>(cnR), n_slots, p, n, pos4, row,
+                [&](int, uint32_t e, float4 xq, uint32_t, const AdjRow<BR>& arow) {
       const PairVec v = pair_vec(e, xq, xi, Hc);
       const float* ar = reinterpret_cast<const float*>(arow.v);
       const float inv = rsqrt_hw(v.d2);
@@ -566,8 +588,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
       }
       return o;
     };
-    walk_pairs<kWalkDE, kWalkDX, false>(cnA, nullptr, n_slots, p, nA, pos4, prev,
-                                        [&](int, uint32_t e, float4 xq, uint32_t, float4 o) {
+    walk_groups(reinterpret_cast<const uint4*>(cnA), n_slots, p, nA, pos4, prev,
+                [&](int, uint32_t e, float4 xq, uint32_t, float4 o) {
       const PairVec v = pair_vec(e, xq, xi, Hc);
       const float inv = rsqrt_hw(v.d2);
       const float ux = v.rx * inv, uy = v.ry * inv, uz = v.rz * inv;
@@ -638,9 +660,32 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
 // summed by k_force.  f_ji = dE_j/dr_ji sits in j's compact angular slot of
 // i, whose index is the number of j's Verlet entries before i's that are in
 // j's compact angular list: a popcount of j's entry mask.
-// Gather pipeline ring (a power of two, >= 4), measured at 900k atoms:
-// 4 slots 0.099 ms, 8 slots 0.115 ms, no pipeline 0.125 ms.
-constexpr int kGR = 4;
+//
+// Each pair needs three dependent loads: its entry and row pair (from the
+// grouped compact lists, four pairs per load), j's mask word, then j's pair
+// force.  Groups are processed in a two-stage pipeline: while the pair
+// forces of group g are loaded, the mask words of group g + 1 are, and the
+// entries of group g + 2.
+struct GatherStage {
+  uint4 e, r;      // entries and row pairs of four pairs
+  uint64_t m[4];   // j's mask word holding i's entry, per pair
+};
+
+// Pair u of a group at list position k0 + u: positions past the end of the
+// list (the unused part of the last group) take the group's first pair, a real
+// one, so that every load they cause stays inside the lists of real pairs.
+__device__ __forceinline__ int real_pair(int k0, int u, int n) { return k0 + u < n ? u : 0; }
+
+__device__ __forceinline__ void gather_masks(GatherStage& st, const uint64_t* __restrict__ amask, int64_t ns, int k0,
+                                             int n) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int v = real_pair(k0, u, n);
+    const uint32_t j = comp4(st.e, v) & kNbrMask;
+    const uint32_t rv = comp4(st.r, v) >> 16;
+    st.m[u] = amask[(int64_t)(rv >> 6) * ns + j];
+  }
+}
 
 __global__ __launch_bounds__(kBlock) void k_gather(int64_t n_slots, const int* __restrict__ orig,
                                                    const uint32_t* __restrict__ cnA, const uint32_t* __restrict__ cpA,
@@ -657,61 +702,50 @@ __global__ __launch_bounds__(kBlock) void k_gather(int64_t n_slots, const int* _
   float4 F = frad[p];
   const int n = ccA[p];
   if (n > 0) {
-    // Three dependent loads per pair (entry, j's mask word, j's pair force),
-    // software-pipelined over a ring of kGR slots: entries kGR pairs ahead,
-    // mask words kGR / 2 ahead, pair forces kGR / 4 ahead.  The loop is
-    // unrolled by kGR so that every slot is a fixed register; rows past the
-    // end are clamped to the last pair.
-    constexpr int R = kGR, RM = R - 1, DM = R / 2, DF = R / 4;
-    uint32_t ej[R], rv[R];
-    uint64_t mw[R];
-    float4 fv[R];
-    const uint32_t* le = cnA + p;
-    const uint32_t* lr = cpA + p;
-    auto entry = [&](int u) {
-      ej[u & RM] = *le & kNbrMask;
-      rv[u & RM] = *lr >> 16;  // position of i in j's Verlet list
+    const int ng = list_groups(n);
+    const uint4* ge = reinterpret_cast<const uint4*>(cnA) + p;
+    const uint4* gr = reinterpret_cast<const uint4*>(cpA) + p;
+    // groups past the last are clamped to it: their loads stay in bounds and
+    // their pairs are skipped
+    auto load_group = [&](GatherStage& st, int g) {
+      const int64_t o = (int64_t)(g < ng ? g : ng - 1) * n_slots;
+      st.e = ge[o];
+      st.r = gr[o];
     };
-    auto advance = [&](int k) {  // rows follow pair k + 1, clamped
-      if (k + 1 < n - 1) {
-        le += n_slots;
-        lr += n_slots;
+    // one step: the pair forces of group g (stage cur, mask words loaded one
+    // step earlier), the entries of group g + 2 (into stage nn) and the mask
+    // words of group g + 1 (stage nxt); the loop is unrolled by three so that
+    // the stages keep their registers
+    auto step = [&](GatherStage& cur, GatherStage& nxt, GatherStage& nn, int g) {
+      float4 fv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int v = real_pair(4 * g, u, n);
+        const uint32_t rv = comp4(cur.r, v) >> 16;
+        const int64_t j = comp4(cur.e, v) & kNbrMask;
+        int jc = __popcll(cur.m[u] & ((1ull << (rv & 63)) - 1ull));
+        for (uint32_t w = 0; w < (rv >> 6); ++w) jc += __popcll(amask[(int64_t)w * n_slots + j]);
+        fv[u] = fA[(int64_t)jc * n_slots + j];
       }
-    };
-    auto mask = [&](int u) { mw[u & RM] = amask[(int64_t)(rv[u & RM] >> 6) * n_slots + ej[u & RM]]; };
-    auto force = [&](int u) {
-      const uint32_t r = rv[u & RM];
-      const int64_t j = ej[u & RM];
-      int jc = __popcll(mw[u & RM] & ((1ull << (r & 63)) - 1ull));
-      for (uint32_t w = 0; w < (r >> 6); ++w) jc += __popcll(amask[(int64_t)w * n_slots + j]);
-      fv[u & RM] = fA[(int64_t)jc * n_slots + j];
-    };
+      load_group(nn, g + 2);
+      gather_masks(nxt, amask, n_slots, 4 * (g + 1 < ng ? g + 1 : ng - 1), n);
 #pragma unroll
-    for (int u = 0; u < R; ++u) {
-      entry(u);
-      advance(u - 1);
-    }
-#pragma unroll
-    for (int u = 0; u < DM; ++u) mask(u);
-#pragma unroll
-    for (int u = 0; u < DF; ++u) force(u);
-    for (int k0 = 0; k0 < n; k0 += R) {
-#pragma unroll
-      for (int u = 0; u < R; ++u) {
-        const int k = k0 + u;
-        const float4 b = fv[u];
-        // the slot of pair k is free once its force is loaded: refill it
-        // with pair k + R, then move pairs k + DM and k + DF one stage on
-        entry(u);
-        advance(k + R - 1);
-        mask(u + DM);
-        force(u + DF);
-        if (k < n) {
-          F.x -= b.x;
-          F.y -= b.y;
-          F.z -= b.z;
+      for (int u = 0; u < 4; ++u) {
+        if (4 * g + u < n) {
+          F.x -= fv[u].x;
+          F.y -= fv[u].y;
+          F.z -= fv[u].z;
         }
       }
+    };
+    GatherStage sa, sb, sc;
+    load_group(sa, 0);
+    load_group(sb, 1);
+    gather_masks(sa, amask, n_slots, 0, n);
+    for (int g = 0; g < ng; g += 3) {
+      step(sa, sb, sc, g);
+      step(sb, sc, sa, g + 1);
+      step(sc, sa, sb, g + 2);
     }
   }
   if (Fuser) {

@@ -109,6 +109,10 @@ __device__ __forceinline__ PV<R> pvec(const Vec4<R>* __restrict__ pos4, uint32_t
 // Pair-walker ring sizes of the training kernels (entries, positions ahead).
 constexpr int kTWalkDE = 4;
 constexpr int kTWalkDX = 2;
+// The float32 kernels walk the compact lists of the forward (groups of four
+// entries); the float64 variant walks the Verlet list (one entry per row).
+template <class R>
+constexpr bool kGroupedLists = std::is_same<R, float>::value;
 
 // ---------------------------------------------------------------- seeds
 
@@ -255,7 +259,7 @@ __global__ __launch_bounds__(kTB) void k_train_atom(TrainIOT<R> io, CutoffsT<R> 
 #pragma unroll
       for (int k = 0; k < BR; ++k) P[b][k] = Pd[b][k] = R(0);
     const int n = io.cntR[p];
-    walk_pairs<kTWalkDE, kTWalkDX, false>(io.nbrR, nullptr, ns, p, n, io.pos4, lam_of,
+    walk_list<kGroupedLists<R>, kTWalkDE, kTWalkDX>(io.nbrR, ns, p, n, io.pos4, lam_of,
                                           [&](int, uint32_t e, Vec4<R> xq, uint32_t, Vec4<R> lj) {
       const PV<R> v = pvec_at(e, xq, xi, Hc);
       if (v.d2 < cut.rcR2) {
@@ -309,7 +313,7 @@ __global__ __launch_bounds__(kTB) void k_train_atom(TrainIOT<R> io, CutoffsT<R> 
     for (int nn = 0; nn < NC; ++nn)
 #pragma unroll
       for (int lm = 0; lm < K; ++lm) Sg[nn][lm] = Sd[nn][lm] = R(0);
-    walk_pairs<kTWalkDE, kTWalkDX, false>(io.nbrA, nullptr, ns, p, nA, io.pos4, lam_of,
+    walk_list<kGroupedLists<R>, kTWalkDE, kTWalkDX>(io.nbrA, ns, p, nA, io.pos4, lam_of,
                                           [&](int, uint32_t e, Vec4<R> xq, uint32_t, Vec4<R> lj) {
       const PV<R> v = pvec_at(e, xq, xi, Hc);
       if (v.d2 < cut.rcA2) {
@@ -547,7 +551,7 @@ __global__ __launch_bounds__(kTB) void k_train_coefA(TrainIOT<R> io, CutoffsT<R>
     for (int b = 0; b < T; ++b)
 #pragma unroll
       for (int k = 0; k < BA; ++k) G[b][k] = R(0);
-    walk_pairs<kTWalkDE, kTWalkDX, false>(io.nbrA, nullptr, ns, p, nA, io.pos4, lam_of,
+    walk_list<kGroupedLists<R>, kTWalkDE, kTWalkDX>(io.nbrA, ns, p, nA, io.pos4, lam_of,
                                           [&](int, uint32_t e, Vec4<R> xq, uint32_t, Vec4<R> lj) {
       const PV<R> v = pvec_at(e, xq, xi, Hc);
       if (v.d2 < cut.rcA2) {
