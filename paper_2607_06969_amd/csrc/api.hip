@@ -281,7 +281,7 @@ __global__ void k_export_lists(int64_t n_slots, const float4* __restrict__ pos4,
   for (int x = 0; x < 9; ++x) H[x] = cfgs[c].H[x];
   int n = 0;
   for (int k = 0; k < cnt[p]; ++k) {
-    const uint32_t e = nbr[(int64_t)k * n_slots + p];
+    const uint32_t e = nbr[group_index(n_slots, p, k)];
     const int q = (int)(e & kNbrMask);
     const float4 xq = pos4[q];
     float sx, sy, sz;

@@ -113,73 +113,12 @@ struct NoPre {
   __device__ __forceinline__ int operator()(int, uint32_t) const { return 0; }
 };
 
-// Software-pipelined walk over one atom's column of a pair list, calling
-// f(k, entry, neighbour position, aux entry, pre(k, entry)) for k = 0 .. n-1
-// in order.  A pair needs two dependent loads: the list entry (a stream from
-// HBM), then the neighbour's position (a gather, mostly from L2).  Entries
-// (and the optional aux column of the same layout) are loaded DE pairs ahead
-// and positions DX pairs ahead.  The loop is unrolled by DE so that every ring
-// slot is a fixed register.  Rows are reached by adding the column stride to a
-// pointer, clamped at the last row, so the loads are unconditional and always
-// in bounds.  An empty list loads nothing.
-//
-// Loads complete in issue order as far as the wait counter is concerned:
-// waiting for a load waits for every load issued before it.  So pair k's own
-// loads (pre, e.g. a row of the neighbour) are issued before the prefetches
-// of this step, and waiting for them leaves the prefetches in flight; pre runs
-// for every lane, on the clamped last entry past the end of a short list.  The
-// prologue issues its loads in the steady state's order, so that the wait
-// counts of the first trip are those of every later one.
-template <int DE, int DX, bool AUX, class P, class Pre, class F>
-__device__ __forceinline__ void walk_pairs(const uint32_t* __restrict__ list, const uint32_t* __restrict__ aux,
-                                           int64_t ns, int64_t p, int n, const P* __restrict__ pos4, Pre&& pre,
-                                           F&& f) {
-  static_assert(DX >= 1 && DX < DE && DE % DX == 0, "ring sizes");
-  if (n <= 0) return;
-  uint32_t e[DE], a[AUX ? DE : 1];
-  P x[DX];
-  const uint32_t* lp = list + p;
-  const uint32_t* ap = AUX ? aux + p : nullptr;
-#pragma unroll
-  for (int u = 0; u < DE; ++u) {
-    e[u] = *lp;
-    if constexpr (AUX) a[u] = *ap;
-    if (u + 1 < n) {
-      lp += ns;
-      if constexpr (AUX) ap += ns;
-    }
-    if (u >= DE - DX) x[u - (DE - DX)] = pos4[e[u - (DE - DX)] & kNbrMask];
-    __builtin_amdgcn_sched_barrier(0);
-  }
-  // lp (ap) now points at row min(DE, n - 1)
-  for (int k0 = 0; k0 < n; k0 += DE) {
-#pragma unroll
-    for (int u = 0; u < DE; ++u) {
-      const int k = k0 + u;
-      const uint32_t ek = take_slot(e[u]);
-      const uint32_t ak = AUX ? take_slot(a[u]) : 0u;
-      const P xk = x[u % DX];
-      const auto pk = pre(k, ek);
-      asm volatile("" ::: "memory");  // keeps pre's loads ahead of the prefetches (no sinking into f)
-      // entry (and aux) of pair k + DE into the slot just read, then the
-      // position of pair k + DX, whose entry arrived DE - DX pairs ago
-      e[u] = *lp;
-      if constexpr (AUX) a[u] = *ap;
-      if (k + DE < n - 1) {
-        lp += ns;
-        if constexpr (AUX) ap += ns;
-      }
-      x[u % DX] = pos4[e[(u + DX) % DE] & kNbrMask];
-      if (k < n) f(k, ek, xk, ak, pk);
-    }
-  }
-}
-
-// Compact pair lists are stored in groups of four entries: group g (entries
-// 4g .. 4g+3) of slot p is the uint4 at [g * n_slots + p].  A writer that
-// appends entries one lane at a time then stores once per four entries (each
-// such store touches one cache line per lane, so their number is what costs),
-// and a reader loads four entries with one coalesced 16-byte load.
+// Pair lists (the Verlet list, its reverse index and the compact lists) are
+// stored in groups of four entries: group g (entries 4g .. 4g+3) of slot p is
+// the uint4 at [g * n_slots + p].  A writer that appends entries one lane at
+// a time then stores once per four entries (each such store touches one cache
+// line per lane, so their number is what costs), and a reader loads four
+// entries with one coalesced 16-byte load.
 template <int G = 4>
 constexpr int list_groups(int entries) {
   return (entries + G - 1) / G;
@@ -194,20 +133,38 @@ __device__ __forceinline__ uint4 take_group(const uint4& v) {
   return make_uint4(take_slot(v.x), take_slot(v.y), take_slot(v.z), take_slot(v.w));
 }
 
-// walk_pairs for a list stored in groups of four.  Groups are loaded two at
-// a time (A = group 2i, B = group 2i+1), the next pair of groups three to
-// four pairs before their first position is needed, and neighbour positions
-// two pairs ahead.  The calls of f and pre are those of walk_pairs (k in
-// order, pre on every step, f only for k < n).
-template <class P, class Pre, class F>
+// Software-pipelined walk over one atom's pair list (groups of four), calling
+// f(k, entry, neighbour position, aux entry, pre(k, entry)) for k = 0 .. n-1
+// in order.  A pair needs two dependent loads: the list entry (a stream from
+// HBM), then the neighbour's position (a gather, mostly from L2).  Groups are
+// loaded two at a time (A = group 2i, B = group 2i+1), the next pair of
+// groups three to four pairs before their first position is needed, and
+// neighbour positions two pairs ahead; with AUX, a second list of the same
+// shape (aux) is loaded alongside and its entry reaches f as the fourth
+// argument.  The loop is unrolled by eight so that every ring slot is a fixed
+// register; groups past the last are clamped to it, so every load is in
+// bounds, and an empty list loads nothing.
+//
+// Loads complete in issue order as far as the wait counter is concerned:
+// waiting for a load waits for every load issued before it.  So pair k's own
+// loads (pre, e.g. a row of the neighbour) are issued before the prefetches
+// of this step, and waiting for them leaves the prefetches in flight; pre runs
+// on every step, also past the end of a short list (k >= n), where f is not
+// called.
+template <bool AUX = false, class P, class Pre, class F>
 __device__ __forceinline__ void walk_groups(const uint4* __restrict__ list, int64_t ns, int64_t p, int n,
-                                            const P* __restrict__ pos4, Pre&& pre, F&& f) {
+                                            const P* __restrict__ pos4, Pre&& pre, F&& f,
+                                            const uint4* __restrict__ aux = nullptr) {
   if (n <= 0) return;
   const int ng = list_groups(n);
-  const uint4* lp = list + p;
   // group g of this slot, clamped to the last group
-  auto group_at = [&](int g) { return lp[(int64_t)(g < ng ? g : ng - 1) * ns]; };
-  uint4 A = group_at(0), B = group_at(1);
+  auto at = [&](const uint4* l, int g) { return l[(int64_t)(g < ng ? g : ng - 1) * ns + p]; };
+  uint4 A = at(list, 0), B = at(list, 1);
+  uint4 XA = make_uint4(0u, 0u, 0u, 0u), XB = XA;
+  if constexpr (AUX) {
+    XA = at(aux, 0);
+    XB = at(aux, 1);
+  }
   P x[2];
   x[0] = pos4[A.x & kNbrMask];
   x[1] = pos4[A.y & kNbrMask];
@@ -218,6 +175,7 @@ __device__ __forceinline__ void walk_groups(const uint4* __restrict__ list, int6
     for (int u = 0; u < 8; ++u) {
       const int k = k0 + u;
       const uint32_t ek = take_slot(comp4(u < 4 ? A : B, u & 3));
+      const uint32_t ak = AUX ? take_slot(comp4(u < 4 ? XA : XB, u & 3)) : 0u;
       const P xk = x[u & 1];
       const auto pk = pre(k, ek);
       asm volatile("" ::: "memory");  // keeps pre's loads ahead of the prefetches
@@ -231,23 +189,22 @@ __device__ __forceinline__ void walk_groups(const uint4* __restrict__ list, int6
         en = comp4(A, u - 6);
       }
       x[u & 1] = pos4[en & kNbrMask];
-      if (u == 3) A = group_at(g + 2);  // A is used up: the next even group
-      if (u == 7) B = group_at(g + 3);  // B is used up: the next odd group
-      if (k < n) f(k, ek, xk, 0u, pk);
+      if (u == 3) {  // A is used up: the next even group
+        A = at(list, g + 2);
+        if constexpr (AUX) XA = at(aux, g + 2);
+      }
+      if (u == 7) {  // B is used up: the next odd group
+        B = at(list, g + 3);
+        if constexpr (AUX) XB = at(aux, g + 3);
+      }
+      if (k < n) f(k, ek, xk, ak, pk);
     }
   }
 }
 
-// A pair walk over a list in either layout: grouped (compact lists) or one
-// entry per row (the Verlet list).
-template <bool GROUPED, int DE, int DX, class P, class Pre, class F>
-__device__ __forceinline__ void walk_list(const uint32_t* __restrict__ list, int64_t ns, int64_t p, int n,
-                                          const P* __restrict__ pos4, Pre&& pre, F&& f) {
-  if constexpr (GROUPED) {
-    walk_groups(reinterpret_cast<const uint4*>(list), ns, p, n, pos4, pre, f);
-  } else {
-    walk_pairs<DE, DX, false>(list, nullptr, ns, p, n, pos4, pre, f);
-  }
+// Entry k of slot p of a list stored in groups of four.
+__device__ __forceinline__ int64_t group_index(int64_t ns, int64_t p, int k) {
+  return (((int64_t)(k >> 2) * ns + p) << 2) + (k & 3);
 }
 
 // One periodic configuration as the kernels see it.

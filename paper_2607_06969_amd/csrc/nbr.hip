@@ -304,6 +304,12 @@ __global__ __launch_bounds__(256) void k_build_lists(int64_t n_slots, int n_spec
     }
 #pragma unroll
   for (int o = 0; o < 27; ++o) sorted_bins[o * 256 + threadIdx.x] = sb[o];
+  // entries are collected four at a time and stored as one group (both
+  // layouts): one store per four entries instead of one per entry
+  const int capG = 4 * list_groups(capR);  // entries the groups can hold
+  uint4 grp = make_uint4(0u, 0u, 0u, 0u);
+  uint4* colG = reinterpret_cast<uint4*>(nbrR) + p;  // column-major groups
+  uint4* rowG = reinterpret_cast<uint4*>(nbrT + p * rowT);  // the same, row-major
   int kR = 0, kA = 0;
   for (int z = 0; z < n_species; ++z) {
     for (int o = 0; o < 27; ++o) {
@@ -329,16 +335,25 @@ __global__ __launch_bounds__(256) void k_build_lists(int64_t n_slots, int n_spec
           const float d2 = pair_d2(rx, ry, rz);
           if (d2 < rclR2) {
             const uint32_t e = (uint32_t)q | (code << kNbrShift);
-            if (kR < capR) {
-              nbrR[(int64_t)kR * n_slots + p] = e;
-              nbrT[p * rowT + kR] = e;
-            }
+            const uint32_t u = (uint32_t)kR & 3u;
+            grp.x = u == 0 ? e : grp.x;
+            grp.y = u == 1 ? e : grp.y;
+            grp.z = u == 2 ? e : grp.z;
+            grp.w = u == 3 ? e : grp.w;
             ++kR;
+            if (u == 3 && kR <= capG) {
+              colG[(int64_t)((kR >> 2) - 1) * n_slots] = grp;
+              rowG[(kR >> 2) - 1] = grp;
+            }
             if (d2 < rclA2) ++kA;
           }
         }
       }
     }
+  }
+  if ((kR & 3) && kR < capG) {  // the last, partly filled group
+    colG[(int64_t)(kR >> 2) * n_slots] = grp;
+    rowG[kR >> 2] = grp;
   }
   cntR[p] = kR < capR ? kR : capR;
   // the angular pairs within rc_angular at any step between rebuilds are among
@@ -353,13 +368,14 @@ __global__ __launch_bounds__(256) void k_build_lists(int64_t n_slots, int n_spec
 // entry with i's slot and the opposite image code), else 0xFFFFFFFF.  The
 // pair-force buffer is indexed by these positions, so that each step's gather
 // reads without searching.  A pair found from one side only raises the
-// asymmetry flag.  Grid (slot tiles, rows): row y takes the entries
-// k = y, y + rows, ... of each list, so the searches of one atom run side by
-// side.  The x extent is a multiple of the XCD count, so that every row maps
-// a slot tile to the same XCD.  Small batches take kRevSplit rows; from
-// kRevOneRow tiles on, the slot tiles alone fill the chip and one row is used
-// (more rows there only add blocks, which cost time even when the rebuild
-// gate sends them home at once).
+// asymmetry flag.  The results of a group of four entries are stored
+// together.  Grid (slot tiles, rows): row y takes the groups g = y, y + rows,
+// ... of each list, so the searches of one atom run side by side.  The x
+// extent is a multiple of the XCD count, so that every row maps a slot tile to
+// the same XCD.  Small batches take kRevSplit rows; from kRevOneRow tiles on,
+// the slot tiles alone fill the chip and one row is used (more rows there only
+// add blocks, which cost time even when the rebuild gate sends them home at
+// once).
 constexpr int kRevSplit = 4;
 constexpr unsigned kRevOneRow = 2048;
 __global__ __launch_bounds__(256) void k_reverse(int64_t n_slots, const CfgDev* __restrict__ cfgs,
@@ -378,24 +394,32 @@ __global__ __launch_bounds__(256) void k_reverse(int64_t n_slots, const CfgDev* 
   for (int x = 0; x < 9; ++x) H[x] = cfgs[c].H[x];
   const float4 xi = pos4[p];
   const int n = cntR[p];
+  const int ng = list_groups(n);
+  const uint4* grp = reinterpret_cast<const uint4*>(nbrR) + p;
+  uint4* out = reinterpret_cast<uint4*>(vrev) + p;
   bool missing = false;
-  for (int k = (int)blockIdx.y; k < n; k += (int)gridDim.y) {
-    const uint32_t e = nbrR[(int64_t)k * n_slots + p];
-    const int q = (int)(e & kNbrMask);
-    const uint32_t code = e >> kNbrShift;
-    float sx, sy, sz;
-    image_shift(H, code, sx, sy, sz);
-    const float4 xq = pos4[q];
-    const float rx = (xq.x - xi.x) + sx, ry = (xq.y - xi.y) + sy, rz = (xq.z - xi.z) + sz;
-    uint32_t res = 0xFFFFFFFFu;
-    if (pair_d2(rx, ry, rz) < rclA2) {
+  for (int g = (int)blockIdx.y; g < ng; g += (int)gridDim.y) {
+    const uint4 eg = grp[(int64_t)g * n_slots];
+    uint32_t res[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (4 * g + u >= n) break;
+      const uint32_t e = comp4(eg, u);
+      const int q = (int)(e & kNbrMask);
+      const uint32_t code = e >> kNbrShift;
+      float sx, sy, sz;
+      image_shift(H, code, sx, sy, sz);
+      const float4 xq = pos4[q];
+      const float rx = (xq.x - xi.x) + sx, ry = (xq.y - xi.y) + sy, rz = (xq.z - xi.z) + sz;
+      if (!(pair_d2(rx, ry, rz) < rclA2)) continue;
       const uint32_t want = (uint32_t)p | ((26u - code) << kNbrShift);
       // q's list, row-major: rows are padded to a multiple of 4 entries, so
       // the 16-byte reads stay inside the row.  Up to 64 entries are read at
       // once (one memory latency per search); entries at or past nq are ignored.
       const int nq = cntR[q];
       const uint4* row = reinterpret_cast<const uint4*>(nbrT + (int64_t)q * rowT);
-      for (int j0 = 0; j0 < nq && res == 0xFFFFFFFFu; j0 += 64) {
+      uint32_t r = 0xFFFFFFFFu;
+      for (int j0 = 0; j0 < nq && r == 0xFFFFFFFFu; j0 += 64) {
         uint4 w[16];
 #pragma unroll
         for (int t = 0; t < 16; ++t)
@@ -403,15 +427,16 @@ __global__ __launch_bounds__(256) void k_reverse(int64_t n_slots, const CfgDev* 
 #pragma unroll
         for (int t = 15; t >= 0; --t) {
           const int j = j0 + 4 * t;
-          if (w[t].w == want && j + 3 < nq) res = (uint32_t)(j + 3);
-          if (w[t].z == want && j + 2 < nq) res = (uint32_t)(j + 2);
-          if (w[t].y == want && j + 1 < nq) res = (uint32_t)(j + 1);
-          if (w[t].x == want && j < nq) res = (uint32_t)j;
+          if (w[t].w == want && j + 3 < nq) r = (uint32_t)(j + 3);
+          if (w[t].z == want && j + 2 < nq) r = (uint32_t)(j + 2);
+          if (w[t].y == want && j + 1 < nq) r = (uint32_t)(j + 1);
+          if (w[t].x == want && j < nq) r = (uint32_t)j;
         }
       }
-      missing |= res == 0xFFFFFFFFu;
+      missing |= r == 0xFFFFFFFFu;
+      res[u] = r;
     }
-    vrev[(int64_t)k * n_slots + p] = res;
+    out[(int64_t)g * n_slots] = make_uint4(res[0], res[1], res[2], res[3]);
   }
   if (missing) atomicOr(&flags[kFlagAsym], 1);
 }
@@ -613,9 +638,10 @@ int NbrPipeline::ensure_lists(int capR_, int capA_) {
   int rc;
   const size_t ns = (size_t)n_slots;
   rowT = (capR + 3) / 4 * 4;
-  // the compact lists are stored in groups of four entries (see list_groups)
-  if ((rc = nbrR.ensure(4 * (size_t)capR * ns)) || (rc = nbrT.ensure(4 * (size_t)rowT * ns)) ||
-      (rc = vrev.ensure(4 * (size_t)capR * ns)) ||
+  // the Verlet list, its reverse index and the compact lists are stored in
+  // groups of four entries (see list_groups); rowT = 4 * list_groups(capR)
+  if ((rc = nbrR.ensure(16 * (size_t)list_groups(capR) * ns)) || (rc = nbrT.ensure(4 * (size_t)rowT * ns)) ||
+      (rc = vrev.ensure(16 * (size_t)list_groups(capR) * ns)) ||
       (rc = cnbrR.ensure(16 * (size_t)list_groups(capR) * ns)) ||
       (rc = cnbrA.ensure(16 * (size_t)list_groups(capA) * ns)) ||
       (rc = cposA.ensure(16 * (size_t)list_groups(capA) * ns)))

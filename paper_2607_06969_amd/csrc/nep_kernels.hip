@@ -56,10 +56,6 @@ __device__ __forceinline__ float tanh_fast(float x) {
   return fmaf(-2.0f, __builtin_amdgcn_rcpf(1.0f + e), 1.0f);
 }
 
-// Prefetch distances, measured at 900k atoms: entries 4 and positions 2
-// pairs ahead; deeper rings (6/2, 6/3, 8/2, 8/4) are no faster.
-constexpr int kWalkDE = 4;
-constexpr int kWalkDX = 2;
 
 __device__ __forceinline__ void load_cell(const CfgDev* __restrict__ cfgs, int c, float (&H)[9]) {
   if (c >= 0) {
@@ -221,8 +217,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
     uint4 gr = make_uint4(0u, 0u, 0u, 0u), ga = gr, gp = gr;
     uint64_t* mw = amask + p;
     uint64_t mword = 0;  // bit k % 64: entry k of the Verlet list is in the compact angular list
-    walk_pairs<kWalkDE, kWalkDX, true>(nbrR, vrev, n_slots, p, n, pos4, NoPre{},
-                                       [&](int k, uint32_t e, float4 xq, uint32_t rvk, int) {
+    walk_groups<true>(reinterpret_cast<const uint4*>(nbrR), n_slots, p, n, pos4, NoPre{},
+                      [&](int k, uint32_t e, float4 xq, uint32_t rvk, int) {
       const PairVec v = pair_vec(e, xq, xi, Hc);
       if (v.d2 < cut.rcR2) {
         put4(gr, nR & 3, e);
@@ -263,7 +259,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
         mw += n_slots;
         mword = 0;
       }
-    });
+    }, reinterpret_cast<const uint4*>(vrev));
     // the last, partly filled groups
     if (nR & 3) *wr = gr;
     if (nA & 3) {

@@ -36,9 +36,9 @@ struct NepIO {
   const int* cfg_of;
   const int* orig;
   const CfgDev* cfgs;
-  const uint32_t* nbrR;  // Verlet list (rc_radial + skin)
+  const uint32_t* nbrR;  // Verlet list (rc_radial + skin), in groups of four entries
   const int* cntR;
-  const uint32_t* vrev;  // [capR][n_slots] row of i in j's Verlet list (pairs within rc_angular + skin)
+  const uint32_t* vrev;  // row of i in j's Verlet list (pairs within rc_angular + skin), grouped as nbrR
   uint32_t* cnR;         // compact list: pairs within rc_radial (written by k_desc)
   int* ccR;
   uint32_t* cnA;         // compact list: pairs within rc_angular (written by k_desc)

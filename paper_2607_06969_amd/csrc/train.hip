@@ -106,13 +106,8 @@ __device__ __forceinline__ PV<R> pvec(const Vec4<R>* __restrict__ pos4, uint32_t
   return pvec_at(e, pos4[e & kNbrMask], xi, H);
 }
 
-// Pair-walker ring sizes of the training kernels (entries, positions ahead).
-constexpr int kTWalkDE = 4;
-constexpr int kTWalkDX = 2;
-// The float32 kernels walk the compact lists of the forward (groups of four
-// entries); the float64 variant walks the Verlet list (one entry per row).
-template <class R>
-constexpr bool kGroupedLists = std::is_same<R, float>::value;
+// The pair lists walked here (compact lists of the forward in float32, the
+// Verlet list in float64) are stored in groups of four entries (walk_groups).
 
 // ---------------------------------------------------------------- seeds
 
@@ -259,7 +254,7 @@ __global__ __launch_bounds__(kTB) void k_train_atom(TrainIOT<R> io, CutoffsT<R> 
 #pragma unroll
       for (int k = 0; k < BR; ++k) P[b][k] = Pd[b][k] = R(0);
     const int n = io.cntR[p];
-    walk_list<kGroupedLists<R>, kTWalkDE, kTWalkDX>(io.nbrR, ns, p, n, io.pos4, lam_of,
+    walk_groups(reinterpret_cast<const uint4*>(io.nbrR), ns, p, n, io.pos4, lam_of,
                                           [&](int, uint32_t e, Vec4<R> xq, uint32_t, Vec4<R> lj) {
       const PV<R> v = pvec_at(e, xq, xi, Hc);
       if (v.d2 < cut.rcR2) {
@@ -313,7 +308,7 @@ __global__ __launch_bounds__(kTB) void k_train_atom(TrainIOT<R> io, CutoffsT<R> 
     for (int nn = 0; nn < NC; ++nn)
 #pragma unroll
       for (int lm = 0; lm < K; ++lm) Sg[nn][lm] = Sd[nn][lm] = R(0);
-    walk_list<kGroupedLists<R>, kTWalkDE, kTWalkDX>(io.nbrA, ns, p, nA, io.pos4, lam_of,
+    walk_groups(reinterpret_cast<const uint4*>(io.nbrA), ns, p, nA, io.pos4, lam_of,
                                           [&](int, uint32_t e, Vec4<R> xq, uint32_t, Vec4<R> lj) {
       const PV<R> v = pvec_at(e, xq, xi, Hc);
       if (v.d2 < cut.rcA2) {
@@ -551,7 +546,7 @@ __global__ __launch_bounds__(kTB) void k_train_coefA(TrainIOT<R> io, CutoffsT<R>
     for (int b = 0; b < T; ++b)
 #pragma unroll
       for (int k = 0; k < BA; ++k) G[b][k] = R(0);
-    walk_list<kGroupedLists<R>, kTWalkDE, kTWalkDX>(io.nbrA, ns, p, nA, io.pos4, lam_of,
+    walk_groups(reinterpret_cast<const uint4*>(io.nbrA), ns, p, nA, io.pos4, lam_of,
                                           [&](int, uint32_t e, Vec4<R> xq, uint32_t, Vec4<R> lj) {
       const PV<R> v = pvec_at(e, xq, xi, Hc);
       if (v.d2 < cut.rcA2) {
@@ -986,7 +981,7 @@ __global__ __launch_bounds__(kTB) void k_pair_force64(TrainIOT<double> io, Cutof
   const double* cA = params + S::PCR;
   const int n = io.cntR[p];
   for (int k = 0; k < n; ++k) {
-    const PV<double> v = pvec(io.pos4, io.nbrR[(int64_t)k * ns + p], xi, Hc);
+    const PV<double> v = pvec(io.pos4, io.nbrR[group_index(ns, p, k)], xi, Hc);
     if (!(v.d2 < cut.rcR2)) continue;
     const double d = sqrt(v.d2);
     const double ux = v.rx / d, uy = v.ry / d, uz = v.rz / d;
