@@ -79,7 +79,7 @@ int prepare_eval(EvalWork& w, const Ops* ops, const nepmi_hparams& hp, int n_cfg
   const size_t ns = (size_t)nb.n_slots, N = (size_t)(nb.N > 0 ? nb.N : 1);
   if ((rc = w.fp.ensure(4 * ns * (size_t)ops->NANG)) || (rc = w.aR.ensure(4 * ns * (size_t)(ops->T * ops->BR))) ||
       (rc = w.Ei.ensure(4 * N)) || (rc = w.frad.ensure(16 * ns)) ||
-      (rc = w.amask.ensure(8 * ns * (size_t)((nb.capR + 63) / 64))) || (rc = w.fA.ensure(16 * ns * (size_t)nb.capA)) ||
+      (rc = w.amask.ensure(8 * ns * (size_t)((nb.capA + 63) / 64))) || (rc = w.fA.ensure(16 * ns * (size_t)nb.capA)) ||
       (rc = w.Wi.ensure(36 * N)) || (rc = w.Eproc.ensure(4 * ns)))
     return rc;
   return NEPMI_OK;

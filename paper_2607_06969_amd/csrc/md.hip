@@ -439,7 +439,7 @@ int nepmi_md_create(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, cons
     set_error("angular neighbour list is not symmetric");
     return fail(NEPMI_INVALID_ARG);
   }
-  if ((rc = md->amask.ensure(8 * (size_t)ns * ((nb.capR + 63) / 64))) || (rc = md->fA.ensure(16 * (size_t)ns * nb.capA)))
+  if ((rc = md->amask.ensure(8 * (size_t)ns * ((nb.capA + 63) / 64))) || (rc = md->fA.ensure(16 * (size_t)ns * nb.capA)))
     return fail(rc);
   fill_int(st, nb.flags.ptr<int>(), kFlagCount, 0, nullptr);
   // kernel variants timed on this state, then the forces of the initial state

@@ -256,8 +256,9 @@ __global__ __launch_bounds__(256) void k_build_lists(int64_t n_slots, int n_spec
                                                      const float4* __restrict__ pos4, const int* __restrict__ cfg_of,
                                                      const int* __restrict__ bin_of, const int* __restrict__ start,
                                                      const int* __restrict__ base, float rclR2, float rclA2, int capR,
-                                                     int capA, int rowT, uint32_t* __restrict__ nbrR,
-                                                     uint32_t* __restrict__ nbrT, int* __restrict__ cntR,
+                                                     int capA, int rowTA, uint32_t* __restrict__ nbrR,
+                                                     uint32_t* __restrict__ nbrTA, int* __restrict__ cntR,
+                                                     int* __restrict__ cntAV,
                                                      int* __restrict__ flags, const int* __restrict__ gate) {
   if (gate && *gate == 0) return;
   const int64_t p = xcd_tile() * blockDim.x + threadIdx.x;
@@ -265,6 +266,7 @@ __global__ __launch_bounds__(256) void k_build_lists(int64_t n_slots, int n_spec
   const int c = cfg_of[p];
   if (c < 0) {
     cntR[p] = 0;
+    cntAV[p] = 0;
     return;
   }
   const CfgDev& C = cfgs[c];
@@ -304,12 +306,15 @@ __global__ __launch_bounds__(256) void k_build_lists(int64_t n_slots, int n_spec
     }
 #pragma unroll
   for (int o = 0; o < 27; ++o) sorted_bins[o * 256 + threadIdx.x] = sb[o];
-  // entries are collected four at a time and stored as one group (both
-  // layouts): one store per four entries instead of one per entry
-  const int capG = 4 * list_groups(capR);  // entries the groups can hold
-  uint4 grp = make_uint4(0u, 0u, 0u, 0u);
-  uint4* colG = reinterpret_cast<uint4*>(nbrR) + p;  // column-major groups
-  uint4* rowG = reinterpret_cast<uint4*>(nbrT + p * rowT);  // the same, row-major
+  // Entries are collected four at a time and stored as one group: one store
+  // per four entries instead of one per entry.  The entries within
+  // rc_angular + skin (the angular part of the list, which the reverse index
+  // searches) are also kept in their own row-major list.
+  const int capG = 4 * list_groups(capR);   // entries the groups can hold
+  const int capGA = 4 * list_groups(capA);
+  uint4 grp = make_uint4(0u, 0u, 0u, 0u), gra = grp;
+  uint4* colG = reinterpret_cast<uint4*>(nbrR) + p;         // column-major groups
+  uint4* rowA = reinterpret_cast<uint4*>(nbrTA + p * rowTA);  // angular part, row-major
   int kR = 0, kA = 0;
   for (int z = 0; z < n_species; ++z) {
     for (int o = 0; o < 27; ++o) {
@@ -341,21 +346,26 @@ __global__ __launch_bounds__(256) void k_build_lists(int64_t n_slots, int n_spec
             grp.z = u == 2 ? e : grp.z;
             grp.w = u == 3 ? e : grp.w;
             ++kR;
-            if (u == 3 && kR <= capG) {
-              colG[(int64_t)((kR >> 2) - 1) * n_slots] = grp;
-              rowG[(kR >> 2) - 1] = grp;
+            if (u == 3 && kR <= capG) colG[(int64_t)((kR >> 2) - 1) * n_slots] = grp;
+            if (d2 < rclA2) {
+              const uint32_t ua = (uint32_t)kA & 3u;
+              gra.x = ua == 0 ? e : gra.x;
+              gra.y = ua == 1 ? e : gra.y;
+              gra.z = ua == 2 ? e : gra.z;
+              gra.w = ua == 3 ? e : gra.w;
+              ++kA;
+              if (ua == 3 && kA <= capGA) rowA[(kA >> 2) - 1] = gra;
             }
-            if (d2 < rclA2) ++kA;
           }
         }
       }
     }
   }
-  if ((kR & 3) && kR < capG) {  // the last, partly filled group
-    colG[(int64_t)(kR >> 2) * n_slots] = grp;
-    rowG[kR >> 2] = grp;
-  }
+  // the last, partly filled groups
+  if ((kR & 3) && kR < capG) colG[(int64_t)(kR >> 2) * n_slots] = grp;
+  if ((kA & 3) && kA < capGA) rowA[kA >> 2] = gra;
   cntR[p] = kR < capR ? kR : capR;
+  cntAV[p] = kA < capA ? kA : capA;
   // the angular pairs within rc_angular at any step between rebuilds are among
   // those within rc_angular + skin now, so kA bounds the per-step angular list
   if (kR > capR || kA > capA) atomicOr(&flags[kFlagOverflow], 1);
@@ -364,24 +374,27 @@ __global__ __launch_bounds__(256) void k_build_lists(int64_t n_slots, int n_spec
 }
 
 // Reverse index: for every entry k of i's Verlet list whose pair is within
-// rc_angular + skin, the position of i in the list of the neighbour j (the
-// entry with i's slot and the opposite image code), else 0xFFFFFFFF.  The
-// pair-force buffer is indexed by these positions, so that each step's gather
-// reads without searching.  A pair found from one side only raises the
-// asymmetry flag.  The results of a group of four entries are stored
-// together.  Grid (slot tiles, rows): row y takes the groups g = y, y + rows,
-// ... of each list, so the searches of one atom run side by side.  The x
-// extent is a multiple of the XCD count, so that every row maps a slot tile to
-// the same XCD.  Small batches take kRevSplit rows; from kRevOneRow tiles on,
-// the slot tiles alone fill the chip and one row is used (more rows there only
-// add blocks, which cost time even when the rebuild gate sends them home at
-// once).
+// rc_angular + skin (the angular part of the list), the position of i in the
+// angular part of the list of the neighbour j (the entry with i's slot and the
+// opposite image code), else 0xFFFFFFFF; 0xFFFFFFFE marks an angular entry
+// whose partner was not found, which also raises the asymmetry flag.  The
+// pair-force buffer is indexed through these positions, so that each step's
+// gather reads without searching.  The search reads the angular part of j's
+// list only (about a third of the list).  The results of a group of four
+// entries are stored together.  Grid (slot tiles, rows): row y takes the
+// groups g = y, y + rows, ... of each list, so the searches of one atom run
+// side by side.  The x extent is a multiple of the XCD count, so that every
+// row maps a slot tile to the same XCD.  Small batches take kRevSplit rows;
+// from kRevOneRow tiles on, the slot tiles alone fill the chip and one row is
+// used (more rows there only add blocks, which cost time even when the
+// rebuild gate sends them home at once).
 constexpr int kRevSplit = 4;
 constexpr unsigned kRevOneRow = 2048;
 __global__ __launch_bounds__(256) void k_reverse(int64_t n_slots, const CfgDev* __restrict__ cfgs,
                                                  const float4* __restrict__ pos4, const int* __restrict__ cfg_of,
-                                                 const uint32_t* __restrict__ nbrR, const uint32_t* __restrict__ nbrT,
-                                                 int rowT, const int* __restrict__ cntR, float rclA2,
+                                                 const uint32_t* __restrict__ nbrR, const uint32_t* __restrict__ nbrTA,
+                                                 int rowTA, const int* __restrict__ cntR,
+                                                 const int* __restrict__ cntAV, float rclA2,
                                                  uint32_t* __restrict__ vrev, int* __restrict__ flags,
                                                  const int* __restrict__ gate) {
   if (gate && *gate == 0) return;
@@ -413,13 +426,14 @@ __global__ __launch_bounds__(256) void k_reverse(int64_t n_slots, const CfgDev* 
       const float rx = (xq.x - xi.x) + sx, ry = (xq.y - xi.y) + sy, rz = (xq.z - xi.z) + sz;
       if (!(pair_d2(rx, ry, rz) < rclA2)) continue;
       const uint32_t want = (uint32_t)p | ((26u - code) << kNbrShift);
-      // q's list, row-major: rows are padded to a multiple of 4 entries, so
-      // the 16-byte reads stay inside the row.  Up to 64 entries are read at
-      // once (one memory latency per search); entries at or past nq are ignored.
-      const int nq = cntR[q];
-      const uint4* row = reinterpret_cast<const uint4*>(nbrT + (int64_t)q * rowT);
-      uint32_t r = 0xFFFFFFFFu;
-      for (int j0 = 0; j0 < nq && r == 0xFFFFFFFFu; j0 += 64) {
+      // the angular part of q's list, row-major, rows padded to a multiple of
+      // 4 entries so that the 16-byte reads stay inside the row; up to 64
+      // entries are read at once (one memory latency per search); entries at
+      // or past nq are ignored
+      const int nq = cntAV[q];
+      const uint4* row = reinterpret_cast<const uint4*>(nbrTA + (int64_t)q * rowTA);
+      uint32_t r = 0xFFFFFFFEu;
+      for (int j0 = 0; j0 < nq && r == 0xFFFFFFFEu; j0 += 64) {
         uint4 w[16];
 #pragma unroll
         for (int t = 0; t < 16; ++t)
@@ -433,7 +447,7 @@ __global__ __launch_bounds__(256) void k_reverse(int64_t n_slots, const CfgDev* 
           if (w[t].x == want && j < nq) r = (uint32_t)j;
         }
       }
-      missing |= r == 0xFFFFFFFFu;
+      missing |= r == 0xFFFFFFFEu;
       res[u] = r;
     }
     out[(int64_t)g * n_slots] = make_uint4(res[0], res[1], res[2], res[3]);
@@ -593,7 +607,8 @@ int NbrPipeline::setup(int n_cfg_, const int64_t* atom_off, const double* cells,
       (rc = pos_tmp.ensure(16 * Na)) || (rc = cfg_tmp.ensure(4 * Na)) || (rc = crd_tmp.ensure(4 * Na)) || (rc = pos4.ensure(16 * (size_t)n_slots)) ||
       (rc = cfg_of.ensure(4 * (size_t)n_slots)) || (rc = orig.ensure(4 * (size_t)n_slots)) ||
       (rc = bin_of.ensure(4 * (size_t)n_slots)) || (rc = slot_of.ensure(4 * Na)) ||
-      (rc = cntR.ensure(4 * (size_t)n_slots)) || (rc = ccntR.ensure(4 * (size_t)n_slots)) ||
+      (rc = cntR.ensure(4 * (size_t)n_slots)) || (rc = cntAV.ensure(4 * (size_t)n_slots)) ||
+      (rc = ccntR.ensure(4 * (size_t)n_slots)) ||
       (rc = ccntA.ensure(4 * (size_t)n_slots)) ||
       (rc = flags.ensure(4 * kFlagCount)))
     return rc;
@@ -618,7 +633,7 @@ int NbrPipeline::setup(int n_cfg_, const int64_t* atom_off, const double* cells,
 
 void NbrPipeline::use_arena(Arena* a) {
   DevBuf* all[] = {&cfgs, &atom_off_dev, &key, &cnt, &start, &cursor, &tile_sums, &base, &perm, &pos_tmp,
-                   &cfg_tmp, &crd_tmp, &pos4, &cfg_of, &orig, &bin_of, &slot_of, &nbrR, &cntR, &nbrT, &vrev,
+                   &cfg_tmp, &crd_tmp, &pos4, &cfg_of, &orig, &bin_of, &slot_of, &nbrR, &cntR, &cntAV, &nbrTA, &vrev,
                    &cnbrR, &ccntR, &cnbrA, &ccntA, &cposA, &flags};
   for (DevBuf* b : all) {
     b->release();
@@ -637,10 +652,11 @@ int NbrPipeline::ensure_lists(int capR_, int capA_) {
   capA = capA_;
   int rc;
   const size_t ns = (size_t)n_slots;
-  rowT = (capR + 3) / 4 * 4;
+  rowTA = 4 * list_groups(capA_);
   // the Verlet list, its reverse index and the compact lists are stored in
-  // groups of four entries (see list_groups); rowT = 4 * list_groups(capR)
-  if ((rc = nbrR.ensure(16 * (size_t)list_groups(capR) * ns)) || (rc = nbrT.ensure(4 * (size_t)rowT * ns)) ||
+  // groups of four entries (see list_groups); the angular part of the Verlet
+  // list, row-major, in rows of rowTA entries
+  if ((rc = nbrR.ensure(16 * (size_t)list_groups(capR) * ns)) || (rc = nbrTA.ensure(4 * (size_t)rowTA * ns)) ||
       (rc = vrev.ensure(16 * (size_t)list_groups(capR) * ns)) ||
       (rc = cnbrR.ensure(16 * (size_t)list_groups(capR) * ns)) ||
       (rc = cnbrA.ensure(16 * (size_t)list_groups(capA) * ns)) ||
@@ -721,13 +737,13 @@ int NbrPipeline::launch_sort(hipStream_t st, const float* pos, int pos_stride, c
 int NbrPipeline::launch_lists(hipStream_t st, int n_species, const int* gate) {
   hipLaunchKernelGGL(k_build_lists, dim3(nblk(n_slots, 256)), dim3(256), 0, st, n_slots, n_species, total_bins,
                      cfgs.ptr<CfgDev>(), pos4.ptr<float4>(), cfg_of.ptr<int>(), bin_of.ptr<int>(), start.ptr<int>(),
-                     base.ptr<int>(), rclR2, rclA2, capR, capA, rowT, nbrR.ptr<uint32_t>(), nbrT.ptr<uint32_t>(),
-                     cntR.ptr<int>(), flags.ptr<int>(), gate);
+                     base.ptr<int>(), rclR2, rclA2, capR, capA, rowTA, nbrR.ptr<uint32_t>(), nbrTA.ptr<uint32_t>(),
+                     cntR.ptr<int>(), cntAV.ptr<int>(), flags.ptr<int>(), gate);
   const unsigned rev_tiles = (nblk(n_slots, 256) + kXcds - 1) / kXcds * kXcds;
   const unsigned rev_rows = rev_tiles >= kRevOneRow ? 1u : (unsigned)kRevSplit;
   hipLaunchKernelGGL(k_reverse, dim3(rev_tiles, rev_rows), dim3(256), 0, st, n_slots, cfgs.ptr<CfgDev>(),
-                     pos4.ptr<float4>(), cfg_of.ptr<int>(), nbrR.ptr<uint32_t>(), nbrT.ptr<uint32_t>(), rowT,
-                     cntR.ptr<int>(), rclA2, vrev.ptr<uint32_t>(), flags.ptr<int>(), gate);
+                     pos4.ptr<float4>(), cfg_of.ptr<int>(), nbrR.ptr<uint32_t>(), nbrTA.ptr<uint32_t>(), rowTA,
+                     cntR.ptr<int>(), cntAV.ptr<int>(), rclA2, vrev.ptr<uint32_t>(), flags.ptr<int>(), gate);
   NEPMI_HIP(hipGetLastError());
   return NEPMI_OK;
 }

@@ -67,8 +67,9 @@ struct NbrPipeline {
   DevBuf key, cnt, start, cursor, tile_sums, base, perm, pos_tmp, cfg_tmp, crd_tmp;
   DevBuf pos4, cfg_of, orig, bin_of, slot_of;
   DevBuf nbrR, cntR;             // Verlet list (rc_radial + skin)
-  DevBuf nbrT;                   // the same list row-major, rows of rowT entries (reverse search)
-  int rowT = 0;
+  DevBuf cntAV;                  // entries within rc_angular + skin (the angular part of the list)
+  DevBuf nbrTA;                  // the angular part of each list, row-major, rows of rowTA entries (reverse search)
+  int rowTA = 0;
   DevBuf vrev;                   // reverse index of the Verlet list (see k_reverse)
   DevBuf cnbrR, ccntR, cnbrA, ccntA, cposA;  // per-evaluation compact lists (rc_radial, rc_angular),
                                              // in groups of four entries (see list_groups)

@@ -216,10 +216,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
     uint4* wp = reinterpret_cast<uint4*>(cpA) + p;   // ... and of its row pairs
     uint4 gr = make_uint4(0u, 0u, 0u, 0u), ga = gr, gp = gr;
     uint64_t* mw = amask + p;
-    uint64_t mword = 0;  // bit k % 64: entry k of the Verlet list is in the compact angular list
+    // bit a % 64: entry a of the angular part of the Verlet list (the entries
+    // with a reverse position) is in the compact angular list
+    uint64_t mword = 0;
+    int ka = 0;  // position in the angular part of the list
     walk_groups<true>(reinterpret_cast<const uint4*>(nbrR), n_slots, p, n, pos4, NoPre{},
-                      [&](int k, uint32_t e, float4 xq, uint32_t rvk, int) {
+                      [&](int, uint32_t e, float4 xq, uint32_t rvk, int) {
       const PairVec v = pair_vec(e, xq, xi, Hc);
+      const bool in_ang_part = rvk != 0xFFFFFFFFu;
       if (v.d2 < cut.rcR2) {
         put4(gr, nR & 3, e);
         if ((++nR & 3) == 0) {
@@ -231,14 +235,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
           // last build, so nA stays below capA and the reverse row exists
           if (rvk <= 0xFFFFu && nA < capA) {
             put4(ga, nA & 3, e);
-            put4(gp, nA & 3, (uint32_t)k | (rvk << 16));
+            put4(gp, nA & 3, (uint32_t)ka | (rvk << 16));
             if ((++nA & 3) == 0) {
               *wa = ga;
               *wp = gp;
               wa += n_slots;
               wp += n_slots;
             }
-            mword |= 1ull << (k & 63);
+            mword |= 1ull << (ka & 63);
           } else {
             bad = true;
           }
@@ -254,13 +258,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
           for (int kk = 0; kk < BR; ++kk) PT[b][kk] = fmaf(m, Tk[kk], PT[b][kk]);
         }
       }
-      if ((k & 63) == 63 || k == n - 1) {
+      if (in_ang_part && (++ka & 63) == 0) {
         *mw = mword;
         mw += n_slots;
         mword = 0;
       }
     }, reinterpret_cast<const uint4*>(vrev));
-    // the last, partly filled groups
+    // the last, partly filled mask word and groups
+    if (ka & 63) *mw = mword;
     if (nR & 3) *wr = gr;
     if (nA & 3) {
       *wa = ga;
@@ -654,8 +659,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
 
 // F_i = (radial part + sum_j f_ij) - sum_j f_ji (Eq. 3).  The own part was
 // summed by k_force.  f_ji = dE_j/dr_ji sits in j's compact angular slot of
-// i, whose index is the number of j's Verlet entries before i's that are in
-// j's compact angular list: a popcount of j's entry mask.
+// i, whose index is the number of entries of the angular part of j's Verlet
+// list before i's that are in j's compact angular list: a popcount of j's
+// entry mask below i's reverse position.
 //
 // Each pair needs three dependent loads: its entry and row pair (from the
 // grouped compact lists, four pairs per load), j's mask word, then j's pair

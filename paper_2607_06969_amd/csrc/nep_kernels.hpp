@@ -38,11 +38,12 @@ struct NepIO {
   const CfgDev* cfgs;
   const uint32_t* nbrR;  // Verlet list (rc_radial + skin), in groups of four entries
   const int* cntR;
-  const uint32_t* vrev;  // row of i in j's Verlet list (pairs within rc_angular + skin), grouped as nbrR
+  const uint32_t* vrev;  // position of i in the angular part (rc_angular + skin) of j's Verlet list,
+                         // 0xFFFFFFFF outside that part; grouped as nbrR
   uint32_t* cnR;         // compact list: pairs within rc_radial (written by k_desc)
   int* ccR;
   uint32_t* cnA;         // compact list: pairs within rc_angular (written by k_desc)
-  uint32_t* cpA;         // [capA][n_slots] own Verlet row | reverse Verlet row << 16
+  uint32_t* cpA;         // own angular-part position | reverse position << 16, grouped as cnA
   int* ccA;
   int* flags;
   Cutoffs cut;
@@ -52,7 +53,8 @@ struct NepIO {
   float* qout;   // [N][D] caller order, optional
   float4* frad;  // [n_slots] own force part (radial pairs both ways, angular dE_i/dr_ij)
   float4* fA;    // [capA][n_slots] angular pair forces dE_i/dr_ij in i's compact slots
-  uint64_t* amask; // [ceil(capR/64)][n_slots] Verlet entries of i in its compact angular list
+  uint64_t* amask; // [ceil(capA/64)][n_slots] entries of the angular part of i's Verlet list that are
+                   // in its compact angular list
   float* Wi;     // [N][9] caller order, per-atom virial
   float* Fuser;  // [N][3] caller order, optional
   float4* Fproc; // [n_slots], optional
