@@ -380,8 +380,8 @@ __global__ __launch_bounds__(256) void k_build_lists(int64_t n_slots, int n_spec
 // whose partner was not found, which also raises the asymmetry flag.  The
 // pair-force buffer is indexed through these positions, so that each step's
 // gather reads without searching.  The search reads the angular part of j's
-// list only (about a third of the list).  The results of a group of four
-// entries are stored together.  Grid (slot tiles, rows): row y takes the
+// list only (about a third of the list).  The four entries of a group are
+// searched together and their results stored together.  Grid (slot tiles, rows): row y takes the
 // groups g = y, y + rows, ... of each list, so the searches of one atom run
 // side by side.  The x extent is a multiple of the XCD count, so that every
 // row maps a slot tile to the same XCD.  Small batches take kRevSplit rows;
@@ -411,44 +411,65 @@ __global__ __launch_bounds__(256) void k_reverse(int64_t n_slots, const CfgDev* 
   const uint4* grp = reinterpret_cast<const uint4*>(nbrR) + p;
   uint4* out = reinterpret_cast<uint4*>(vrev) + p;
   bool missing = false;
+  // The four entries of a group are searched side by side: their neighbours'
+  // positions and list lengths are loaded together, then the first kRevWin
+  // entries of every row that needs a search (one memory latency for the
+  // group); longer rows are finished one at a time.
+  constexpr int kRevWin = 8;  // uint4 per row read at once (32 entries)
   for (int g = (int)blockIdx.y; g < ng; g += (int)gridDim.y) {
     const uint4 eg = grp[(int64_t)g * n_slots];
-    uint32_t res[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
+    float4 xq[4];
+    int nq[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      if (4 * g + u >= n) break;
+      const int q = (int)(comp4(eg, 4 * g + u < n ? u : 0) & kNbrMask);  // past the end: the group's first entry
+      xq[u] = pos4[q];
+      nq[u] = cntAV[q];
+    }
+    bool ang[4];
+    uint32_t want[4];
+    const uint4* row[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
       const uint32_t e = comp4(eg, u);
-      const int q = (int)(e & kNbrMask);
       const uint32_t code = e >> kNbrShift;
       float sx, sy, sz;
       image_shift(H, code, sx, sy, sz);
-      const float4 xq = pos4[q];
-      const float rx = (xq.x - xi.x) + sx, ry = (xq.y - xi.y) + sy, rz = (xq.z - xi.z) + sz;
-      if (!(pair_d2(rx, ry, rz) < rclA2)) continue;
-      const uint32_t want = (uint32_t)p | ((26u - code) << kNbrShift);
-      // the angular part of q's list, row-major, rows padded to a multiple of
-      // 4 entries so that the 16-byte reads stay inside the row; up to 64
-      // entries are read at once (one memory latency per search); entries at
-      // or past nq are ignored
-      const int nq = cntAV[q];
-      const uint4* row = reinterpret_cast<const uint4*>(nbrTA + (int64_t)q * rowTA);
+      const float rx = (xq[u].x - xi.x) + sx, ry = (xq[u].y - xi.y) + sy, rz = (xq[u].z - xi.z) + sz;
+      ang[u] = 4 * g + u < n && pair_d2(rx, ry, rz) < rclA2;
+      want[u] = (uint32_t)p | ((26u - code) << kNbrShift);
+      row[u] = reinterpret_cast<const uint4*>(nbrTA + (int64_t)(e & kNbrMask) * rowTA);
+      if (!ang[u]) nq[u] = 0;
+    }
+    // the angular part of each neighbour's list, row-major, rows padded to a
+    // multiple of 4 entries so that the 16-byte reads stay inside the row;
+    // entries at or past nq are ignored
+    uint4 w[4][kRevWin];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int t = 0; t < kRevWin; ++t) w[u][t] = 4 * t < nq[u] ? row[u][t] : make_uint4(~0u, ~0u, ~0u, ~0u);
+    uint32_t res[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
       uint32_t r = 0xFFFFFFFEu;
-      for (int j0 = 0; j0 < nq && r == 0xFFFFFFFEu; j0 += 64) {
-        uint4 w[16];
 #pragma unroll
-        for (int t = 0; t < 16; ++t)
-          w[t] = j0 + 4 * t < nq ? row[(j0 >> 2) + t] : make_uint4(~0u, ~0u, ~0u, ~0u);
-#pragma unroll
-        for (int t = 15; t >= 0; --t) {
-          const int j = j0 + 4 * t;
-          if (w[t].w == want && j + 3 < nq) r = (uint32_t)(j + 3);
-          if (w[t].z == want && j + 2 < nq) r = (uint32_t)(j + 2);
-          if (w[t].y == want && j + 1 < nq) r = (uint32_t)(j + 1);
-          if (w[t].x == want && j < nq) r = (uint32_t)j;
-        }
+      for (int t = kRevWin - 1; t >= 0; --t) {
+        const int j = 4 * t;
+        if (w[u][t].w == want[u] && j + 3 < nq[u]) r = (uint32_t)(j + 3);
+        if (w[u][t].z == want[u] && j + 2 < nq[u]) r = (uint32_t)(j + 2);
+        if (w[u][t].y == want[u] && j + 1 < nq[u]) r = (uint32_t)(j + 1);
+        if (w[u][t].x == want[u] && j < nq[u]) r = (uint32_t)j;
       }
-      missing |= r == 0xFFFFFFFEu;
-      res[u] = r;
+      for (int j0 = 4 * kRevWin; j0 < nq[u] && r == 0xFFFFFFFEu; j0 += 4) {
+        const uint4 x = row[u][j0 >> 2];
+        if (x.w == want[u] && j0 + 3 < nq[u]) r = (uint32_t)(j0 + 3);
+        if (x.z == want[u] && j0 + 2 < nq[u]) r = (uint32_t)(j0 + 2);
+        if (x.y == want[u] && j0 + 1 < nq[u]) r = (uint32_t)(j0 + 1);
+        if (x.x == want[u]) r = (uint32_t)j0;
+      }
+      if (ang[u]) missing |= r == 0xFFFFFFFEu;
+      res[u] = ang[u] ? r : 0xFFFFFFFFu;
     }
     out[(int64_t)g * n_slots] = make_uint4(res[0], res[1], res[2], res[3]);
   }
