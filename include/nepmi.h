@@ -202,10 +202,25 @@ int nepmi_md_create(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, cons
                     const float *dev_pos, const float *dev_vel, const int32_t *dev_species, const double *masses,
                     double dt_fs, double skin, nepmi_md **out, void *stream);
 
-/* Advance n_steps time steps (graph replays) on `stream`.  Synchronises
- * `stream` at the end to check the neighbour capacity and returns
- * NEPMI_NEIGHBOR_OVERFLOW if it was exceeded (results are then invalid). */
+/* Advance n_steps time steps (graph replays) on `stream`.  The replays run in
+ * chunks of 32 steps; after each chunk the call synchronises `stream` and
+ * reads the device flags.  Before each chunk the state (positions, velocities,
+ * step counters) is checkpointed on the device.  If a list build inside a
+ * chunk needed more entries than the lists hold, the chunk is undone: the
+ * checkpoint is restored, the lists are regrown to 1.25x the longest list seen
+ * plus 16, rebuilt, the step graph re-captured and the chunk run again (the
+ * trajectory is the same up to float32 summation order).  Returns
+ * NEPMI_NEIGHBOR_OVERFLOW only if three regrows within one call do not
+ * suffice, or if a list would exceed 65535 entries; the state is then the
+ * last checkpoint.  Returns when the n_steps are done (stream synchronised). */
 int nepmi_md_step(nepmi_md *md, int32_t n_steps, void *stream);
+
+/* List capacities of the run.  capR, capA > 0 set the radial / angular list
+ * capacity (entries per atom; raised to the longest list built so far, and 0
+ * keeps the current value); the lists are rebuilt from the current state and
+ * the step graph re-captured.  cur_capR, cur_capA (host, may be NULL) receive
+ * the capacities in force.  Synchronises the null stream. */
+int nepmi_md_capacity(nepmi_md *md, int32_t capR, int32_t capA, int32_t *cur_capR, int32_t *cur_capA);
 
 /* Copy the current state out (any pointer may be NULL): positions and
  * velocities float[N*3] and forces float[N*3] in the caller's atom order;
@@ -214,8 +229,9 @@ int nepmi_md_step(nepmi_md *md, int32_t n_steps, void *stream);
 int nepmi_md_get(nepmi_md *md, float *dev_pos, float *dev_vel, float *dev_forces, double *dev_epot,
                  double *dev_ekin, double *dev_virial, void *stream);
 
-/* Host counters: steps taken and neighbour-list builds (including the first). */
-int nepmi_md_stats(nepmi_md *md, int64_t *steps, int64_t *rebuilds);
+/* Host counters (any pointer may be NULL): steps taken, neighbour-list
+ * builds (including the first) and list regrows after an overflow. */
+int nepmi_md_stats(nepmi_md *md, int64_t *steps, int64_t *rebuilds, int64_t *regrows);
 
 void nepmi_md_destroy(nepmi_md *md);
 
@@ -224,7 +240,8 @@ void nepmi_md_destroy(nepmi_md *md);
  * k_force and k_gather and after k_gather, each step into its own events.
  * ms_per_launch: host double[3] = average duration (ms) of descriptors +
  * network, pair forces + virial, force gather over the n_steps replays.
- * Synchronises `stream` once at the end.  Errors as nepmi_md_step, and
+ * Chunks, checkpoints and overflow recovery as nepmi_md_step (a chunk run
+ * again records its steps again).  Errors as nepmi_md_step, and
  * NEPMI_UNSUPPORTED if the graph could not be built with timing nodes. */
 int nepmi_md_step_timed(nepmi_md *md, int32_t n_steps, double *ms_per_launch, void *stream);
 

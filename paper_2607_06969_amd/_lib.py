@@ -70,7 +70,8 @@ SIGNATURES = [
     ("nepmi_md_step", C.c_int, [_vp, _i32, _vp]),
     ("nepmi_md_step_timed", C.c_int, [_vp, _i32, _dp, _vp]),
     ("nepmi_md_get", C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
-    ("nepmi_md_stats", C.c_int, [_vp, _i64p, _i64p]),
+    ("nepmi_md_stats", C.c_int, [_vp, _i64p, _i64p, _i64p]),
+    ("nepmi_md_capacity", C.c_int, [_vp, _i32, _i32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     ("nepmi_md_destroy", None, [_vp]),
     ("nepmi_md_time_kernels", C.c_int, [_vp, _i32, _dp, _vp]),
 ]

@@ -225,10 +225,14 @@ struct nepmi_md {
   DevBuf species_user, xd_user, x_user, v_user, xd, vel4, ref4, F4;
   DevBuf fp, aR, Ei, frad, fA, amask, Wi, Ki, Eproc;
   DevBuf epot, ekin, vir, counters;
+  // checkpoint of the last checked step (caller order, wrapped positions), its
+  // device counters, and a device word holding 1 (an always-open gate)
+  DevBuf snap_xd, snap_x, snap_v, snap_cnt, one;
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int64_t host_steps = 0;
+  int64_t regrows = 0;
   // timing: events recorded before k_desc, k_force, k_gather and after
   // k_gather in every replay; their graph nodes; a pool of per-step events
   hipEvent_t tev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -352,6 +356,82 @@ struct nepmi_md {
     return NEPMI_OK;
   }
 
+  // Capture one step into the graph (replacing any earlier one).
+  int capture() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    for (hipGraphNode_t& n : tnode) n = nullptr;
+    mark_failed = false;
+    NEPMI_HIP(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = step_launch(cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(cap_stream, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    graph = g;
+    NEPMI_HIP(hipGraphInstantiate(&exec, g, nullptr, nullptr, 0));
+    timing = !mark_failed && tnode[0] && tnode[1] && tnode[2] && tnode[3];
+    return NEPMI_OK;
+  }
+
+  // Checkpoint the current state (caller order) and the step counters.
+  int snapshot(hipStream_t st) {
+    const int64_t ns = nbr.n_slots;
+    hipLaunchKernelGGL(k_md_unpermute, dim3(nb256(ns)), dim3(256), 0, st, ns, nbr.cfg_of.ptr<int>(),
+                       nbr.orig.ptr<int>(), nbr.cfgs.ptr<CfgDev>(), xd.ptr<Dbl3>(), vel4.ptr<float4>(),
+                       snap_xd.ptr<Dbl3>(), snap_x.ptr<float4>(), snap_v.ptr<float4>(), one.ptr<int>());
+    NEPMI_HIP(hipGetLastError());
+    NEPMI_HIP(hipMemcpyAsync(snap_cnt.p, counters.p, 16, hipMemcpyDeviceToDevice, st));
+    return NEPMI_OK;
+  }
+
+  // Back to the checkpoint with lists of capR x capA entries: the lists are
+  // rebuilt from the checkpoint's positions, the forces and sums recomputed,
+  // and the step re-captured (the list buffers may have moved).
+  int restore(hipStream_t st, int capR, int capA) {
+    int rc;
+    const int64_t N = nbr.N, ns = nbr.n_slots;
+    const size_t Na = (size_t)(N > 0 ? N : 1);
+    int* flags = nbr.flags.ptr<int>();
+    for (int attempt = 0;; ++attempt) {
+      if ((rc = nbr.ensure_lists(capR, capA)) || (rc = amask.ensure(8 * (size_t)ns * ((nbr.capA + 63) / 64))) ||
+          (rc = fA.ensure(16 * (size_t)ns * nbr.capA)))
+        return rc;
+      NEPMI_HIP(hipMemcpyAsync(xd_user.p, snap_xd.p, 24 * Na, hipMemcpyDeviceToDevice, st));
+      NEPMI_HIP(hipMemcpyAsync(x_user.p, snap_x.p, 16 * Na, hipMemcpyDeviceToDevice, st));
+      NEPMI_HIP(hipMemcpyAsync(v_user.p, snap_v.p, 16 * Na, hipMemcpyDeviceToDevice, st));
+      NEPMI_HIP(hipMemcpyAsync(counters.p, snap_cnt.p, 16, hipMemcpyDeviceToDevice, st));
+      fill_int(st, flags, kFlagCount, 0, nullptr);
+      hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, flags + kFlagRebuild, 1);
+      if ((rc = after_unpermute(st, flags + kFlagRebuild))) return rc;
+      int hf[kFlagCount];
+      if ((rc = nbr.check_flags(st, hf))) return rc;
+      if (!hf[kFlagOverflow]) break;
+      // the checkpoint itself needs longer lists than asked for
+      if (attempt == 1) {
+        set_error("neighbour capacity overflow after regrowing the lists");
+        return NEPMI_NEIGHBOR_OVERFLOW;
+      }
+      capR = hf[kFlagMaxR] + hf[kFlagMaxR] / 4 + 16;
+      capA = hf[kFlagMaxA] + hf[kFlagMaxA] / 4 + 16;
+    }
+    // the longest lists seen stay in the flags; the rebuild request is spent
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, flags + kFlagRebuild, 0);
+    if ((rc = forces(st))) return rc;
+    hipLaunchKernelGGL(k_md_kin, dim3(nb256(ns)), dim3(256), 0, st, ns, mc, nbr.orig.ptr<int>(),
+                       nbr.pos4.ptr<float4>(), vel4.ptr<float4>(), Ki.ptr<float>());
+    if ((rc = red.run(st, Ei.ptr<float>(), Wi.ptr<float>(), Ki.ptr<float>(), epot.ptr<double>(), vir.ptr<double>(),
+                      ekin.ptr<double>())))
+      return rc;
+    NEPMI_HIP(hipStreamSynchronize(st));
+    return capture();
+  }
+
   ~nepmi_md() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -409,8 +489,11 @@ int nepmi_md_create(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, cons
       (rc = md->aR.ensure(4 * (size_t)ns * m->ops->T * m->ops->BR)) || (rc = md->Ei.ensure(4 * Na)) ||
       (rc = md->frad.ensure(16 * (size_t)ns)) || (rc = md->Wi.ensure(36 * Na)) || (rc = md->Ki.ensure(4 * Na)) ||
       (rc = md->epot.ensure(8 * (size_t)n_cfg)) || (rc = md->ekin.ensure(8 * (size_t)n_cfg)) ||
-      (rc = md->vir.ensure(72 * (size_t)n_cfg)) || (rc = md->counters.ensure(16)))
+      (rc = md->vir.ensure(72 * (size_t)n_cfg)) || (rc = md->counters.ensure(16)) ||
+      (rc = md->snap_xd.ensure(24 * Na)) || (rc = md->snap_x.ensure(16 * Na)) || (rc = md->snap_v.ensure(16 * Na)) ||
+      (rc = md->snap_cnt.ensure(16)) || (rc = md->one.ensure(4)))
     return fail(rc);
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, md->one.ptr<int>(), 1);
   if (hipMemcpyAsync(md->species_user.p, dev_species, 4 * (size_t)N, hipMemcpyDeviceToDevice, st) != hipSuccess)
     return fail(hip_fail(hipGetLastError(), "hipMemcpyAsync(species)"));
   hipLaunchKernelGGL(k_md_init, dim3(nb256(N > 0 ? N : 1)), dim3(256), 0, st, N, n_cfg, nb.atom_off_dev.ptr<int64_t>(),
@@ -441,7 +524,8 @@ int nepmi_md_create(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, cons
   }
   if ((rc = md->amask.ensure(8 * (size_t)ns * ((nb.capA + 63) / 64))) || (rc = md->fA.ensure(16 * (size_t)ns * nb.capA)))
     return fail(rc);
-  fill_int(st, nb.flags.ptr<int>(), kFlagCount, 0, nullptr);
+  // the longest lists seen stay in the flags; the rebuild request is spent
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, nb.flags.ptr<int>() + kFlagRebuild, 0);
   // kernel variants timed on this state, then the forces of the initial state
   if (!m->pinned && (rc = autotune_io(m, md->io(), st, 2))) return fail(rc);
   if ((rc = md->forces(st))) return fail(rc);
@@ -456,33 +540,87 @@ int nepmi_md_create(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, cons
     if (hipEventCreate(&md->tev[i]) != hipSuccess) return fail(hip_fail(hipGetLastError(), "hipEventCreate"));
   if (hipStreamCreateWithFlags(&md->cap_stream, hipStreamNonBlocking) != hipSuccess)
     return fail(hip_fail(hipGetLastError(), "hipStreamCreate"));
-  if (hipStreamBeginCapture(md->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
-    return fail(hip_fail(hipGetLastError(), "hipStreamBeginCapture"));
-  rc = md->step_launch(md->cap_stream);
-  hipGraph_t g = nullptr;
-  hipError_t e = hipStreamEndCapture(md->cap_stream, &g);
-  if (rc) return fail(rc);
-  if (e != hipSuccess) return fail(hip_fail(e, "hipStreamEndCapture"));
-  md->graph = g;
-  if ((e = hipGraphInstantiate(&md->exec, g, nullptr, nullptr, 0)) != hipSuccess)
-    return fail(hip_fail(e, "hipGraphInstantiate"));
-  md->timing = !md->mark_failed && md->tnode[0] && md->tnode[1] && md->tnode[2] && md->tnode[3];
+  if ((rc = md->capture())) return fail(rc);
   if (hipStreamSynchronize(st) != hipSuccess) return fail(hip_fail(hipGetLastError(), "hipStreamSynchronize"));
   *out = md;
   return NEPMI_OK;
 }
 
-static int md_check_flags(nepmi_md* md, hipStream_t st) {
-  int hf[kFlagCount];
-  int rc = md->nbr.check_flags(st, hf);
-  if (rc) return rc;
-  if (hf[kFlagOverflow]) {
-    set_error("neighbour capacity exceeded during MD (results are invalid)");
-    return NEPMI_NEIGHBOR_OVERFLOW;
+// Steps between overflow checks.  Every chunk of this many graph replays ends
+// with one stream synchronisation and a read of the device flags; a chunk in
+// which a list build overflowed its capacity is undone (back to the
+// checkpoint taken before it) and run again with larger lists.
+constexpr int kMdCheckEvery = 32;
+constexpr int kMdMaxRegrows = 3;
+
+// Advance n_steps replays with overflow recovery; with `ms`, the graph's event
+// nodes record into per-step events and ms[0..2] get the average durations.
+static int md_run(nepmi_md* md, int32_t n_steps, hipStream_t st, double* ms) {
+  if (ms) {
+    const size_t need = 4 * (size_t)n_steps;
+    while (md->tpool.size() < need) {
+      hipEvent_t e;
+      NEPMI_HIP(hipEventCreate(&e));
+      md->tpool.push_back(e);
+    }
   }
-  if (hf[kFlagAsym]) {
-    set_error("angular neighbour list is not symmetric");
-    return NEPMI_INVALID_ARG;
+  int rc;
+  if ((rc = md->snapshot(st))) return rc;
+  int done = 0, regrown = 0;
+  while (done < n_steps) {
+    const int k = n_steps - done < kMdCheckEvery ? n_steps - done : kMdCheckEvery;
+    if (ms && !md->timing) {
+      set_error("the step graph has no timing nodes");
+      return NEPMI_UNSUPPORTED;
+    }
+    for (int s = done; s < done + k; ++s) {
+      if (ms) {
+        // every launch is enqueued before the next change of its event nodes,
+        // so each step records into its own four events
+        for (int i = 0; i < 4; ++i)
+          NEPMI_HIP(hipGraphExecEventRecordNodeSetEvent(md->exec, md->tnode[i], md->tpool[4 * (size_t)s + i]));
+      }
+      NEPMI_HIP(hipGraphLaunch(md->exec, st));
+    }
+    int hf[kFlagCount];
+    if ((rc = md->nbr.check_flags(st, hf))) return rc;
+    if (hf[kFlagOverflow]) {
+      // a list build in this chunk truncated a list: undo the chunk, grow the
+      // lists to the longest seen plus a margin and run the chunk again
+      if (++regrown > kMdMaxRegrows) {
+        set_error("neighbour capacity exceeded during MD after regrowing the lists");
+        return NEPMI_NEIGHBOR_OVERFLOW;
+      }
+      const int wantR = hf[kFlagMaxR] + hf[kFlagMaxR] / 4 + 16, wantA = hf[kFlagMaxA] + hf[kFlagMaxA] / 4 + 16;
+      if ((rc = md->restore(st, wantR > md->nbr.capR ? wantR : md->nbr.capR,
+                            wantA > md->nbr.capA ? wantA : md->nbr.capA)))
+        return rc;
+      ++md->regrows;
+      continue;
+    }
+    if (hf[kFlagAsym]) {
+      set_error("angular neighbour list is not symmetric");
+      return NEPMI_INVALID_ARG;
+    }
+    done += k;
+    md->host_steps += k;
+    if (done < n_steps && (rc = md->snapshot(st))) return rc;
+  }
+  if (ms) {
+    double acc[3] = {0, 0, 0};
+    rc = NEPMI_OK;
+    for (int s = 0; s < n_steps && !rc; ++s)
+      for (int i = 0; i < 3; ++i) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, md->tpool[4 * (size_t)s + i], md->tpool[4 * (size_t)s + i + 1]) != hipSuccess) {
+          rc = hip_fail(hipGetLastError(), "hipEventElapsedTime");
+          break;
+        }
+        acc[i] += t;
+      }
+    for (int i = 0; i < 4; ++i) (void)hipGraphExecEventRecordNodeSetEvent(md->exec, md->tnode[i], md->tev[i]);
+    if (rc) return rc;
+    for (int i = 0; i < 3; ++i) ms[i] = acc[i] / n_steps;
   }
   return NEPMI_OK;
 }
@@ -492,42 +630,7 @@ int nepmi_md_step_timed(nepmi_md* md, int32_t n_steps, double* ms, void* stream)
     set_error("invalid argument");
     return NEPMI_INVALID_ARG;
   }
-  if (!md->timing) {
-    set_error("the step graph has no timing nodes");
-    return NEPMI_UNSUPPORTED;
-  }
-  hipStream_t st = (hipStream_t)stream;
-  const size_t need = 4 * (size_t)n_steps;
-  while (md->tpool.size() < need) {
-    hipEvent_t e;
-    NEPMI_HIP(hipEventCreate(&e));
-    md->tpool.push_back(e);
-  }
-  // every launch is enqueued before the next change of its event nodes, so
-  // each step records into its own four events
-  int rc = NEPMI_OK;
-  for (int s = 0; s < n_steps && !rc; ++s) {
-    for (int i = 0; i < 4 && !rc; ++i)
-      if (hipGraphExecEventRecordNodeSetEvent(md->exec, md->tnode[i], md->tpool[4 * (size_t)s + i]) != hipSuccess)
-        rc = hip_fail(hipGetLastError(), "hipGraphExecEventRecordNodeSetEvent");
-    if (!rc && hipGraphLaunch(md->exec, st) != hipSuccess) rc = hip_fail(hipGetLastError(), "hipGraphLaunch");
-  }
-  if (hipStreamSynchronize(st) != hipSuccess && !rc) rc = hip_fail(hipGetLastError(), "hipStreamSynchronize");
-  double acc[3] = {0, 0, 0};
-  for (int s = 0; s < n_steps && !rc; ++s)
-    for (int i = 0; i < 3; ++i) {
-      float t = 0.f;
-      if (hipEventElapsedTime(&t, md->tpool[4 * (size_t)s + i], md->tpool[4 * (size_t)s + i + 1]) != hipSuccess) {
-        rc = hip_fail(hipGetLastError(), "hipEventElapsedTime");
-        break;
-      }
-      acc[i] += t;
-    }
-  for (int i = 0; i < 4; ++i) (void)hipGraphExecEventRecordNodeSetEvent(md->exec, md->tnode[i], md->tev[i]);
-  if (rc) return rc;
-  md->host_steps += n_steps;
-  for (int i = 0; i < 3; ++i) ms[i] = acc[i] / n_steps;
-  return md_check_flags(md, st);
+  return md_run(md, n_steps, (hipStream_t)stream, ms);
 }
 
 int nepmi_md_step(nepmi_md* md, int32_t n_steps, void* stream) {
@@ -535,10 +638,28 @@ int nepmi_md_step(nepmi_md* md, int32_t n_steps, void* stream) {
     set_error("invalid argument");
     return NEPMI_INVALID_ARG;
   }
-  hipStream_t st = (hipStream_t)stream;
-  for (int s = 0; s < n_steps; ++s) NEPMI_HIP(hipGraphLaunch(md->exec, st));
-  md->host_steps += n_steps;
-  return md_check_flags(md, st);
+  return md_run(md, n_steps, (hipStream_t)stream, nullptr);
+}
+
+int nepmi_md_capacity(nepmi_md* md, int32_t capR, int32_t capA, int32_t* cur_capR, int32_t* cur_capA) {
+  if (!md || capR < 0 || capA < 0) {
+    set_error("invalid argument");
+    return NEPMI_INVALID_ARG;
+  }
+  if (capR > 0 || capA > 0) {
+    // never below the longest lists of the builds so far
+    int hf[kFlagCount];
+    int rc;
+    if ((rc = md->nbr.check_flags(0, hf))) return rc;
+    int r = capR > 0 ? capR : md->nbr.capR, a = capA > 0 ? capA : md->nbr.capA;
+    r = r > hf[kFlagMaxR] ? r : hf[kFlagMaxR];
+    a = a > hf[kFlagMaxA] ? a : hf[kFlagMaxA];
+    // the lists of the new shape are built from the current state
+    if ((rc = md->snapshot(0)) || (rc = md->restore(0, r, a))) return rc;
+  }
+  if (cur_capR) *cur_capR = md->nbr.capR;
+  if (cur_capA) *cur_capA = md->nbr.capA;
+  return NEPMI_OK;
 }
 
 int nepmi_md_get(nepmi_md* md, float* dev_pos, float* dev_vel, float* dev_forces, double* dev_epot, double* dev_ekin,
@@ -560,12 +681,13 @@ int nepmi_md_get(nepmi_md* md, float* dev_pos, float* dev_vel, float* dev_forces
   return NEPMI_OK;
 }
 
-int nepmi_md_stats(nepmi_md* md, int64_t* steps, int64_t* rebuilds) {
+int nepmi_md_stats(nepmi_md* md, int64_t* steps, int64_t* rebuilds, int64_t* regrows) {
   if (!md) return NEPMI_INVALID_ARG;
   long long c[2];
   NEPMI_HIP(hipMemcpy(c, md->counters.p, sizeof c, hipMemcpyDeviceToHost));
   if (steps) *steps = c[0];
   if (rebuilds) *rebuilds = c[1] + 1;  // plus the build at creation
+  if (regrows) *regrows = md->regrows;
   return NEPMI_OK;
 }
 

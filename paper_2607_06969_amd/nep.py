@@ -357,9 +357,16 @@ class NepMD:
         return {"pos": x, "vel": v, "F": f, "Epot": ep, "Ekin": ek, "V": vir.view(-1, 3, 3)}
 
     def stats(self):
-        s, r = C.c_int64(), C.c_int64()
-        check(load().nepmi_md_stats(self._h, C.byref(s), C.byref(r)))
-        return {"steps": s.value, "rebuilds": r.value}
+        s, r, g = C.c_int64(), C.c_int64(), C.c_int64()
+        check(load().nepmi_md_stats(self._h, C.byref(s), C.byref(r), C.byref(g)))
+        return {"steps": s.value, "rebuilds": r.value, "regrows": g.value}
+
+    def capacity(self, capR=0, capA=0):
+        """Set the radial / angular list capacity (0 keeps it; never below the
+        longest list built so far) and return the capacities in force."""
+        r, a = C.c_int32(), C.c_int32()
+        check(load().nepmi_md_capacity(self._h, int(capR), int(capA), C.byref(r), C.byref(a)))
+        return {"capR": r.value, "capA": a.value}
 
     def time_kernels(self, reps=10):
         ms = (C.c_double * 4)()
