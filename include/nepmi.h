@@ -12,10 +12,19 @@
  *
  * Conventions (every entry point):
  *   - Units: Angstrom, eV, eV/Angstrom, atomic mass units, femtoseconds.
- *   - Species are 0..n_species-1.  Periodic in all three directions; the
- *     cell's rows are its lattice vectors a, b, c (row-major double[9]).
- *     Every cell width must be at least 2 * (rc_radial + skin); the pair
- *     vectors use the cell rounded to float32.
+ *   - Species are 0..n_species-1.  The cell's rows are its lattice vectors
+ *     a, b, c (row-major double[9] per configuration); the pair vectors use
+ *     the cell rounded to float32.
+ *   - Periodicity: pbc is a host int32[3*n_cfg] (pbc[3c+a] = 1 if
+ *     configuration c is periodic along lattice vector a, 0 if not) or NULL
+ *     (periodic in all three directions).  Eq. 3-4 sum over the neighbours
+ *     inside the cutoff: along a periodic direction these include periodic
+ *     images, along a non-periodic one there are none (a cluster, a slab).
+ *     Every periodic direction must be at least 2 * (rc_radial + skin) wide
+ *     (NEPMI_CELL_TOO_SMALL); a non-periodic one may have any width, and an
+ *     atom may lie outside the cell along it (it is not wrapped; its list
+ *     search then starts from the nearest bin of the cell).  Entries other
+ *     than 0 and 1 give NEPMI_INVALID_ARG.
  *   - Positions and forces are float32, array-of-structs (N x 3, row-major),
  *     in the caller's atom order; configuration c owns atoms
  *     [atom_off[c], atom_off[c+1]).
@@ -26,7 +35,7 @@
  *   - Pointers named dev_* are device pointers the caller owns (for example
  *     torch tensors) and that stay valid for the duration of the call, which
  *     is asynchronous on `stream` (a hipStream_t; NULL = default stream) unless
- *     stated.  Host pointers (atom_off, cells, masses, weights) are read
+ *     stated.  Host pointers (atom_off, cells, pbc, masses, weights) are read
  *     before the call returns.  The library keeps no caller pointer past a
  *     call; handles own their workspace, which grows on demand.
  *   - Every call returns NEPMI_OK (0) or a negative code; nepmi_last_error()
@@ -45,7 +54,7 @@ extern "C" {
 enum {
   NEPMI_OK = 0,
   NEPMI_INVALID_ARG = -1,       /* bad size, pointer, species or hyper-parameter  */
-  NEPMI_CELL_TOO_SMALL = -2,    /* a cell width below 2 * (rc_radial + skin)      */
+  NEPMI_CELL_TOO_SMALL = -2,    /* a periodic width below 2 * (rc_radial + skin)  */
   NEPMI_NEIGHBOR_OVERFLOW = -3, /* neighbour capacity exceeded (MD only; compute
                                    calls grow the capacity and retry)            */
   NEPMI_HIP_ERROR = -4,         /* a HIP runtime call failed                      */
@@ -106,14 +115,16 @@ int nepmi_model_reuse_lists(nepmi_model *m, int32_t enable);
 
 void nepmi_model_destroy(nepmi_model *m);
 
-/* Energy, forces and virial of n_cfg periodic configurations (Eq. 1, 3, 4).
- *   atom_off: host int64[n_cfg+1]; cells: host double[9*n_cfg];
+/* Energy, forces and virial of n_cfg configurations (Eq. 1, 3, 4).
+ *   atom_off: host int64[n_cfg+1]; cells: host double[9*n_cfg]; pbc: host
+ *   int32[3*n_cfg] or NULL (see the conventions above);
  *   dev_pos: float[N*3]; dev_species: int32[N];
  *   dev_energy: double[n_cfg]; dev_forces: float[N*3]; dev_virial:
  *   double[9*n_cfg]; dev_atom_energy: float[N] or NULL; dev_atom_virial:
  *   float[N*9] or NULL (row-major 3x3 per atom, -sum_j dE_i/dr_ij (x) r_ij).
- * Synchronises `stream` once to check the neighbour capacity. */
-int nepmi_compute(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, const double *cells,
+ * Synchronises `stream` once to check the neighbour capacity (twice when the
+ * lists must grow); the rest of the call is asynchronous. */
+int nepmi_compute(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, const double *cells, const int32_t *pbc,
                   const float *dev_pos, const int32_t *dev_species, double *dev_energy, float *dev_forces,
                   double *dev_virial, float *dev_atom_energy, float *dev_atom_virial, void *stream);
 
@@ -130,14 +141,14 @@ int nepmi_compute(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, const 
  * All calls on one GPU share that array and it keeps the last call's
  * contents: calls that overlap on one GPU (from other streams or threads)
  * race and must not be made. */
-int nepmi_compute_noalloc(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, const double *cells,
+int nepmi_compute_noalloc(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, const double *cells, const int32_t *pbc,
                           const float *dev_pos, const int32_t *dev_species, double *dev_energy, float *dev_forces,
                           double *dev_virial, float *dev_atom_energy, float *dev_atom_virial, void *stream);
 
 /* Descriptors q_i (float[N*D], caller's atom order) of the same batch: the
  * radial q_n (Eq. 11), three-body q_nl (Eq. 17, l = 1..l_max, index
  * n_radial + (l-1) n_angular + n), then the 4-body and 5-body values. */
-int nepmi_descriptors(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, const double *cells,
+int nepmi_descriptors(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, const double *cells, const int32_t *pbc,
                       const float *dev_pos, const int32_t *dev_species, float *dev_q, void *stream);
 
 /* Neighbour lists of the same batch, for inspection and tests.  which = 0:
@@ -147,7 +158,7 @@ int nepmi_descriptors(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, co
  * dev_rvec[(i*cap + k)*3 + a] (float32, r_ij = r_j - r_i + image shift);
  * entries beyond cap are dropped (dev_count still reports the full length).
  * The list order is the library's evaluation order. */
-int nepmi_neighbors(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, const double *cells,
+int nepmi_neighbors(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, const double *cells, const int32_t *pbc,
                     const float *dev_pos, const int32_t *dev_species, int32_t which, int32_t cap,
                     int32_t *dev_count, int32_t *dev_nbr, float *dev_rvec, void *stream);
 
@@ -159,7 +170,7 @@ int nepmi_neighbors(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, cons
  * fastest in the model; chosen = host int32[2] (descriptor, force) or NULL.
  * Synchronises `stream`.  nepmi_set_variants pins a choice (0..3 each);
  * nepmi_md_create autotunes on its initial state unless a choice is pinned. */
-int nepmi_autotune(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, const double *cells,
+int nepmi_autotune(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, const double *cells, const int32_t *pbc,
                    const float *dev_pos, const int32_t *dev_species, int32_t *chosen, void *stream);
 int nepmi_set_variants(nepmi_model *m, int32_t desc_variant, int32_t force_variant);
 int nepmi_get_variants(nepmi_model *m, int32_t *desc_variant, int32_t *force_variant);
@@ -171,7 +182,7 @@ int nepmi_get_variants(nepmi_model *m, int32_t *desc_variant, int32_t *force_var
  * dev_grad float[param_count] is overwritten.  The neighbour lists and
  * forward state are rebuilt for the batch given; descriptors are recomputed,
  * no per-pair state is cached. */
-int nepmi_backward_params(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, const double *cells,
+int nepmi_backward_params(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, const double *cells, const int32_t *pbc,
                           const float *dev_pos, const int32_t *dev_species, const double *dev_ebar,
                           const float *dev_lambda, const double *dev_mu, float *dev_grad, void *stream);
 
@@ -185,7 +196,7 @@ int nepmi_backward_params(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off
  * dev_E_ref double[n_cfg], dev_F_ref float[N*3], dev_V_ref double[9*n_cfg];
  * dev_loss double[4] = (total, energy, force, virial); dev_grad float[P] or
  * NULL (loss only). */
-int nepmi_loss_grad(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, const double *cells,
+int nepmi_loss_grad(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, const double *cells, const int32_t *pbc,
                     const float *dev_pos, const int32_t *dev_species, const double *dev_E_ref,
                     const float *dev_F_ref, const double *dev_V_ref, const double *weights, int32_t loss_form,
                     double *dev_loss, float *dev_grad, void *stream);
@@ -195,10 +206,11 @@ int nepmi_loss_grad(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, cons
  * (float[N*3], Angstrom/fs) and species; masses: host double[n_species] (u);
  * dt_fs: time step; skin: Verlet-list skin in Angstrom (lists are rebuilt
  * when an atom has moved more than skin/2 since the last build).  Positions
- * are wrapped into the cell at each rebuild.  The step (half kick, drift,
+ * are wrapped into the cell along its periodic directions at each rebuild
+ * (pbc as for nepmi_compute).  The step (half kick, drift,
  * displacement check, conditional rebuild, forces, half kick, float64
  * energy/virial/kinetic sums) is captured once in a HIP graph and replayed. */
-int nepmi_md_create(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, const double *cells,
+int nepmi_md_create(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, const double *cells, const int32_t *pbc,
                     const float *dev_pos, const float *dev_vel, const int32_t *dev_species, const double *masses,
                     double dt_fs, double skin, nepmi_md **out, void *stream);
 
@@ -262,17 +274,18 @@ int nepmi_md_time_kernels(nepmi_md *md, int32_t reps, double *ms_per_launch, voi
  * them; the model handle supplies the shape, the cutoffs and the work space.
  * Neighbour lists come from the float32 rounding of the positions with a
  * 0.01 A skin; every pair is then tested against the cutoffs in float64.
- * Cell widths must be at least 2 (rc_radial + 0.01) (NEPMI_CELL_TOO_SMALL).
+ * Periodic widths must be at least 2 (rc_radial + 0.01) (NEPMI_CELL_TOO_SMALL).
  * Asynchronous on `stream`.
  * ------------------------------------------------------------------------- */
 
 /* Energy, forces and virial of a batch (Eq. 1-4) in float64.
- * atom_off host int64[n_cfg + 1], cells host double[9 * n_cfg] (rows a, b, c);
+ * atom_off host int64[n_cfg + 1], cells host double[9 * n_cfg] (rows a, b, c),
+ * pbc host int32[3 * n_cfg] or NULL;
  * dev_pos double[N*3], dev_species int32[N] (caller order);
  * outputs: dev_energy double[n_cfg], dev_forces double[N*3],
  * dev_virial double[9 * n_cfg] (row-major, sum over atoms of
  * -dE_i/dr_ij (x) r_ij), dev_atom_energy double[N] or NULL. */
-int nepmi_compute_f64(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, const double *cells,
+int nepmi_compute_f64(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, const double *cells, const int32_t *pbc,
                       const double *dev_pos, const int32_t *dev_species, const double *dev_params, double *dev_energy,
                       double *dev_forces, double *dev_virial, double *dev_atom_energy, void *stream);
 
@@ -282,7 +295,7 @@ int nepmi_compute_f64(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, co
  *               + sum_c mu_c : dV_c/dtheta_p
  * dev_ebar double[n_cfg], dev_lambda double[N*3], dev_mu double[9*n_cfg];
  * dev_grad double[param_count] is overwritten. */
-int nepmi_backward_params_f64(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, const double *cells,
+int nepmi_backward_params_f64(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, const double *cells, const int32_t *pbc,
                               const double *dev_pos, const int32_t *dev_species, const double *dev_params,
                               const double *dev_ebar, const double *dev_lambda, const double *dev_mu,
                               double *dev_grad, void *stream);

@@ -42,6 +42,7 @@ class HParams(C.Structure):
 _vp, _i32, _i64, _d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
 _hp = C.POINTER(HParams)
 _i64p, _dp = C.POINTER(C.c_int64), C.POINTER(C.c_double)
+_i32p = C.POINTER(C.c_int32)
 SIGNATURES = [
     ("nepmi_last_error", C.c_char_p, []),
     ("nepmi_param_count", C.c_int, [_hp, _i64p]),
@@ -51,18 +52,18 @@ SIGNATURES = [
     ("nepmi_model_set_params", C.c_int, [_vp, _vp, _vp]),
     ("nepmi_model_reuse_lists", C.c_int, [_vp, _i32]),
     ("nepmi_model_destroy", None, [_vp]),
-    ("nepmi_compute", C.c_int, [_vp, _i32, _i64p, _dp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
-    ("nepmi_compute_noalloc", C.c_int, [_vp, _i32, _i64p, _dp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
-    ("nepmi_descriptors", C.c_int, [_vp, _i32, _i64p, _dp, _vp, _vp, _vp, _vp]),
-    ("nepmi_neighbors", C.c_int, [_vp, _i32, _i64p, _dp, _vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp]),
-    ("nepmi_autotune", C.c_int, [_vp, _i32, _i64p, _dp, _vp, _vp, C.POINTER(C.c_int32), _vp]),
+    ("nepmi_compute", C.c_int, [_vp, _i32, _i64p, _dp, _i32p, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    ("nepmi_compute_noalloc", C.c_int, [_vp, _i32, _i64p, _dp, _i32p, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    ("nepmi_descriptors", C.c_int, [_vp, _i32, _i64p, _dp, _i32p, _vp, _vp, _vp, _vp]),
+    ("nepmi_neighbors", C.c_int, [_vp, _i32, _i64p, _dp, _i32p, _vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp]),
+    ("nepmi_autotune", C.c_int, [_vp, _i32, _i64p, _dp, _i32p, _vp, _vp, C.POINTER(C.c_int32), _vp]),
     ("nepmi_set_variants", C.c_int, [_vp, _i32, _i32]),
     ("nepmi_get_variants", C.c_int, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
-    ("nepmi_backward_params", C.c_int, [_vp, _i32, _i64p, _dp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
-    ("nepmi_loss_grad", C.c_int, [_vp, _i32, _i64p, _dp, _vp, _vp, _vp, _vp, _vp, _dp, _i32, _vp, _vp, _vp]),
-    ("nepmi_md_create", C.c_int, [_vp, _i32, _i64p, _dp, _vp, _vp, _vp, _dp, _d, _d, C.POINTER(_vp), _vp]),
-    ("nepmi_compute_f64", C.c_int, [_vp, _i32, _i64p, _dp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
-    ("nepmi_backward_params_f64", C.c_int, [_vp, _i32, _i64p, _dp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    ("nepmi_backward_params", C.c_int, [_vp, _i32, _i64p, _dp, _i32p, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    ("nepmi_loss_grad", C.c_int, [_vp, _i32, _i64p, _dp, _i32p, _vp, _vp, _vp, _vp, _vp, _dp, _i32, _vp, _vp, _vp]),
+    ("nepmi_md_create", C.c_int, [_vp, _i32, _i64p, _dp, _i32p, _vp, _vp, _vp, _dp, _d, _d, C.POINTER(_vp), _vp]),
+    ("nepmi_compute_f64", C.c_int, [_vp, _i32, _i64p, _dp, _i32p, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    ("nepmi_backward_params_f64", C.c_int, [_vp, _i32, _i64p, _dp, _i32p, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     ("nepmi_adam_step", C.c_int, [C.c_int64, _vp, _vp, _vp, _vp, C.c_int64, C.c_double, C.c_double, C.c_double,
                                   C.c_double, _vp]),
     ("nepmi_lr_schedule", C.c_int, [C.c_int64, C.c_int64, C.c_int64, C.c_double, C.c_double, C.c_double, _dp]),

@@ -70,11 +70,13 @@ using namespace nepmi;
 namespace nepmi {
 
 int prepare_eval(EvalWork& w, const Ops* ops, const nepmi_hparams& hp, int n_cfg, const int64_t* atom_off,
-                 const double* cells, const float* pos, const int32_t* species, hipStream_t st, double skin) {
+                 const double* cells, const int32_t* pbc, const float* pos, const int32_t* species, hipStream_t st, double skin) {
   int rc;
-  if ((rc = w.nbr.setup(n_cfg, atom_off, cells, ops->T, hp.rc_radial, hp.rc_angular, skin, st))) return rc;
-  if ((rc = w.nbr.build(st, pos, species))) return rc;
-  if ((rc = w.red.setup(n_cfg, atom_off, st))) return rc;
+  // the list build's capacity check synchronises the stream once, which also
+  // completes the uploads of both setups
+  if ((rc = w.nbr.setup(n_cfg, atom_off, cells, pbc, ops->T, hp.rc_radial, hp.rc_angular, skin, st)) ||
+      (rc = w.red.setup(n_cfg, atom_off, st)) || (rc = w.nbr.build(st, pos, species)))
+    return rc;
   const NbrPipeline& nb = w.nbr;
   const size_t ns = (size_t)nb.n_slots, N = (size_t)(nb.N > 0 ? nb.N : 1);
   if ((rc = w.fp.ensure(4 * ns * (size_t)ops->NANG)) || (rc = w.aR.ensure(4 * ns * (size_t)(ops->T * ops->BR))) ||
@@ -144,16 +146,19 @@ int run_eval(EvalWork& w, const nepmi_model* m, float* dev_forces, double* dev_e
 
 }  // namespace nepmi
 
-int nepmi_model::prepare(int n_cfg, const int64_t* atom_off, const double* cells, const float* pos,
+int nepmi_model::prepare(int n_cfg, const int64_t* atom_off, const double* cells, const int32_t* pbc, const float* pos,
                          const int32_t* species, hipStream_t st, double skin, bool may_reuse) {
+  // periodicity flags as given (null: every direction periodic)
+  std::vector<int32_t> per(3 * (size_t)(n_cfg > 0 ? n_cfg : 0), 1);
+  if (pbc) per.assign(pbc, pbc + per.size());
   if (n_cfg >= 1 && atom_off && cells && reuse_lists && may_reuse && last.valid && last.pos == pos &&
       last.species == species && last.skin == skin && last.off.size() == (size_t)n_cfg + 1 &&
       std::equal(last.off.begin(), last.off.end(), atom_off) &&
-      std::equal(last.cells.begin(), last.cells.end(), cells))
+      std::equal(last.cells.begin(), last.cells.end(), cells) && last.pbc == per)
     return NEPMI_OK;
   last.valid = false;
   int rc;
-  if ((rc = prepare_eval(*this, ops, hp, n_cfg, atom_off, cells, pos, species, st, skin))) return rc;
+  if ((rc = prepare_eval(*this, ops, hp, n_cfg, atom_off, cells, pbc, pos, species, st, skin))) return rc;
   if (may_reuse) {
     last.valid = true;
     last.pos = pos;
@@ -161,6 +166,7 @@ int nepmi_model::prepare(int n_cfg, const int64_t* atom_off, const double* cells
     last.skin = skin;
     last.off.assign(atom_off, atom_off + n_cfg + 1);
     last.cells.assign(cells, cells + 9 * (size_t)n_cfg);
+    last.pbc = per;
   }
   return NEPMI_OK;
 }
@@ -236,7 +242,7 @@ int nepmi_model_reuse_lists(nepmi_model* m, int32_t enable) {
 
 void nepmi_model_destroy(nepmi_model* m) { delete m; }
 
-int nepmi_compute(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, const double* cells, const float* dev_pos,
+int nepmi_compute(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, const double* cells, const int32_t* pbc, const float* dev_pos,
                   const int32_t* dev_species, double* dev_energy, float* dev_forces, double* dev_virial,
                   float* dev_atom_energy, float* dev_atom_virial, void* stream) {
   if (!m || !dev_pos || !dev_species) {
@@ -244,19 +250,19 @@ int nepmi_compute(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, const 
     return NEPMI_INVALID_ARG;
   }
   hipStream_t st = (hipStream_t)stream;
-  int rc = m->prepare(n_cfg, atom_off, cells, dev_pos, dev_species, st);
+  int rc = m->prepare(n_cfg, atom_off, cells, pbc, dev_pos, dev_species, st);
   if (rc) return rc;
   return run_eval(*m, m, dev_forces, dev_energy, dev_virial, dev_atom_energy, dev_atom_virial, st);
 }
 
-int nepmi_descriptors(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, const double* cells,
+int nepmi_descriptors(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, const double* cells, const int32_t* pbc,
                       const float* dev_pos, const int32_t* dev_species, float* dev_q, void* stream) {
   if (!m || !dev_pos || !dev_species || !dev_q) {
     set_error("null argument");
     return NEPMI_INVALID_ARG;
   }
   hipStream_t st = (hipStream_t)stream;
-  int rc = m->prepare(n_cfg, atom_off, cells, dev_pos, dev_species, st);
+  int rc = m->prepare(n_cfg, atom_off, cells, pbc, dev_pos, dev_species, st);
   if (rc) return rc;
   NepIO io = m->io(nullptr, nullptr, dev_q);
   return m->ops->desc(st, io, m->params.ptr<float>(), false, m->vdesc);
@@ -301,7 +307,7 @@ __global__ void k_export_lists(int64_t n_slots, const float4* __restrict__ pos4,
 }
 }  // namespace nepmi
 
-extern "C" int nepmi_neighbors(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, const double* cells,
+extern "C" int nepmi_neighbors(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, const double* cells, const int32_t* pbc,
                                const float* dev_pos, const int32_t* dev_species, int32_t which, int32_t cap,
                                int32_t* dev_count, int32_t* dev_nbr, float* dev_rvec, void* stream) {
   if (!m || !dev_pos || !dev_species || !dev_count || !dev_nbr || !dev_rvec || cap < 0 || (which != 0 && which != 1)) {
@@ -309,7 +315,7 @@ extern "C" int nepmi_neighbors(nepmi_model* m, int32_t n_cfg, const int64_t* ato
     return NEPMI_INVALID_ARG;
   }
   hipStream_t st = (hipStream_t)stream;
-  int rc = m->prepare(n_cfg, atom_off, cells, dev_pos, dev_species, st);
+  int rc = m->prepare(n_cfg, atom_off, cells, pbc, dev_pos, dev_species, st);
   if (rc) return rc;
   const float rc1 = (float)(which ? m->hp.rc_angular : m->hp.rc_radial);
   const int64_t ns = m->nbr.n_slots;

@@ -216,7 +216,7 @@ struct CfgDev {
   int bin_off;      // first global bin of this configuration
   int64_t atom_off; // first atom (caller's order)
   int n_atoms;
-  int pad;
+  int periodic;     // bit a set: periodic along lattice vector a
 };
 
 // Runtime (non-shape) parameters of a launch.

@@ -56,6 +56,29 @@ __global__ void k_md_kick_drift(int64_t n_slots, MdConst mc, const int* __restri
   if (dx * dx + dy * dy + dz * dz > mc.half_skin2) atomicOr(&flags[kFlagRebuild], 1);
 }
 
+// Wrap r into the cell along its periodic directions in float64, and round it
+// to f; if the rounding lands outside the cell (a last-ulp case at a face),
+// wrap the rounded value once more.  Non-periodic directions are left alone.
+__device__ void wrap_periodic(const CfgDev& C, double r[3], float f[3]) {
+  for (int pass = 0; pass < 2; ++pass) {
+    double m[3];
+    for (int a = 0; a < 3; ++a) {
+      const double s = r[0] * C.Hinv[a] + r[1] * C.Hinv[3 + a] + r[2] * C.Hinv[6 + a];
+      m[a] = (C.periodic >> a) & 1 ? floor(s) : 0.0;
+    }
+    for (int a = 0; a < 3; ++a) r[a] -= m[0] * C.Hd[a] + m[1] * C.Hd[3 + a] + m[2] * C.Hd[6 + a];
+    for (int a = 0; a < 3; ++a) f[a] = (float)r[a];
+    // the float32 copy must also lie in the cell (as the staging kernel sees it)
+    bool inside = true;
+    for (int a = 0; a < 3; ++a) {
+      const double s = (double)f[0] * C.Hinv[a] + (double)f[1] * C.Hinv[3 + a] + (double)f[2] * C.Hinv[6 + a];
+      if ((C.periodic >> a) & 1 && floor(s) != 0.0) inside = false;
+    }
+    if (inside) break;
+    for (int a = 0; a < 3; ++a) r[a] = (double)f[a];
+  }
+}
+
 // Before a rebuild: state back to caller order, positions wrapped into the
 // cell in float64 so that the float32 copy needs no further wrapping.
 __global__ void k_md_unpermute(int64_t n_slots, const int* __restrict__ cfg_of, const int* __restrict__ orig,
@@ -68,26 +91,9 @@ __global__ void k_md_unpermute(int64_t n_slots, const int* __restrict__ cfg_of, 
   if (p >= n_slots) return;
   const int c = cfg_of[p];
   if (c < 0) return;
-  const CfgDev& C = cfgs[c];
   double r[3] = {xd[p].x, xd[p].y, xd[p].z};
   float f[3];
-  for (int pass = 0; pass < 2; ++pass) {
-    double m[3];
-    for (int a = 0; a < 3; ++a) {
-      const double s = r[0] * C.Hinv[a] + r[1] * C.Hinv[3 + a] + r[2] * C.Hinv[6 + a];
-      m[a] = floor(s);
-    }
-    for (int a = 0; a < 3; ++a) r[a] -= m[0] * C.Hd[a] + m[1] * C.Hd[3 + a] + m[2] * C.Hd[6 + a];
-    for (int a = 0; a < 3; ++a) f[a] = (float)r[a];
-    // the float32 copy must also lie in the cell (as the staging kernel sees it)
-    bool inside = true;
-    for (int a = 0; a < 3; ++a) {
-      const double s = (double)f[0] * C.Hinv[a] + (double)f[1] * C.Hinv[3 + a] + (double)f[2] * C.Hinv[6 + a];
-      if (floor(s) != 0.0) inside = false;
-    }
-    if (inside) break;
-    for (int a = 0; a < 3; ++a) r[a] = (double)f[a];
-  }
+  wrap_periodic(cfgs[c], r, f);
   const int i = orig[p];
   xd_user[i] = Dbl3{r[0], r[1], r[2]};
   x_user[i] = make_float4(f[0], f[1], f[2], 0.f);
@@ -186,21 +192,9 @@ __global__ void k_md_init(int64_t N, int n_cfg, const int64_t* __restrict__ atom
     const int mid = (lo + hi) >> 1;
     if (atom_off[mid] <= i) lo = mid; else hi = mid;
   }
-  const CfgDev& C = cfgs[lo];
   double r[3] = {(double)pos[3 * i], (double)pos[3 * i + 1], (double)pos[3 * i + 2]};
   float f[3];
-  for (int pass = 0; pass < 2; ++pass) {
-    double m[3];
-    for (int a = 0; a < 3; ++a) m[a] = floor(r[0] * C.Hinv[a] + r[1] * C.Hinv[3 + a] + r[2] * C.Hinv[6 + a]);
-    for (int a = 0; a < 3; ++a) r[a] -= m[0] * C.Hd[a] + m[1] * C.Hd[3 + a] + m[2] * C.Hd[6 + a];
-    for (int a = 0; a < 3; ++a) f[a] = (float)r[a];
-    bool inside = true;
-    for (int a = 0; a < 3; ++a)
-      if (floor((double)f[0] * C.Hinv[a] + (double)f[1] * C.Hinv[3 + a] + (double)f[2] * C.Hinv[6 + a]) != 0.0)
-        inside = false;
-    if (inside) break;
-    for (int a = 0; a < 3; ++a) r[a] = (double)f[a];
-  }
+  wrap_periodic(cfgs[lo], r, f);
   xd_user[i] = Dbl3{r[0], r[1], r[2]};
   x_user[i] = make_float4(f[0], f[1], f[2], 0.f);
   v_user[i] = make_float4(vel[3 * i], vel[3 * i + 1], vel[3 * i + 2], 0.f);
@@ -445,7 +439,7 @@ struct nepmi_md {
 
 extern "C" {
 
-int nepmi_md_create(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, const double* cells, const float* dev_pos,
+int nepmi_md_create(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, const double* cells, const int32_t* pbc, const float* dev_pos,
                     const float* dev_vel, const int32_t* dev_species, const double* masses, double dt_fs, double skin,
                     nepmi_md** out, void* stream) {
   if (!m || !dev_pos || !dev_vel || !dev_species || !masses || !out || !(dt_fs > 0) || !(skin >= 0)) {
@@ -477,7 +471,7 @@ int nepmi_md_create(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, cons
   md->mc.dt = (float)dt_fs;
   md->mc.half_skin2 = (float)(0.25 * skin * skin);
   NbrPipeline& nb = md->nbr;
-  if ((rc = nb.setup(n_cfg, atom_off, cells, md->n_species, m->hp.rc_radial, m->hp.rc_angular, skin, st)))
+  if ((rc = nb.setup(n_cfg, atom_off, cells, pbc, md->n_species, m->hp.rc_radial, m->hp.rc_angular, skin, st)))
     return fail(rc);
   if ((rc = md->red.setup(n_cfg, atom_off, st))) return fail(rc);
   const int64_t N = nb.N, ns = nb.n_slots;

@@ -60,7 +60,7 @@ struct EvalWork {
 // Neighbour lists (pairs within the cutoffs + skin), work buffers and
 // reduction plan of a batch in `w`.
 int prepare_eval(EvalWork& w, const Ops* ops, const nepmi_hparams& hp, int n_cfg, const int64_t* atom_off,
-                 const double* cells, const float* pos, const int32_t* species, hipStream_t st, double skin);
+                 const double* cells, const int32_t* pbc, const float* pos, const int32_t* species, hipStream_t st, double skin);
 // Kernel arguments of an evaluation on `w` (optional caller-order forces,
 // slot-order forces and descriptors).
 NepIO eval_io(EvalWork& w, const nepmi_hparams& hp, float* Fuser, float4* Fproc, float* qout);
@@ -80,7 +80,7 @@ struct nepmi_model : nepmi::EvalWork {
   // work buffers and reduction plan.  With reuse_lists set and may_reuse, a
   // batch identical to the previous one (same sizes, cells and device
   // pointers) keeps what the previous call prepared.
-  int prepare(int n_cfg, const int64_t* atom_off, const double* cells, const float* pos, const int32_t* species,
+  int prepare(int n_cfg, const int64_t* atom_off, const double* cells, const int32_t* pbc, const float* pos, const int32_t* species,
               hipStream_t st, double skin = 0.0, bool may_reuse = true);
   bool reuse_lists = false;
   struct {
@@ -90,6 +90,7 @@ struct nepmi_model : nepmi::EvalWork {
     double skin = 0.0;
     std::vector<int64_t> off;
     std::vector<double> cells;
+    std::vector<int32_t> pbc;
   } last;
   nepmi::NepIO io(float* Fuser, float4* Fproc, float* qout);
 };

@@ -69,9 +69,13 @@ __global__ void k_stage(int64_t N, int n_cfg, const int64_t* __restrict__ atom_o
   double m[3];
   for (int a = 0; a < 3; ++a) {
     const double s = (double)x * C.Hinv[a] + (double)y * C.Hinv[3 + a] + (double)w * C.Hinv[6 + a];
-    m[a] = floor(s);
-    int bb = (int)floor((s - m[a]) * C.nb[a]);
-    b[a] = bb < 0 ? 0 : (bb >= C.nb[a] ? C.nb[a] - 1 : bb);
+    // along a non-periodic direction the atom is not wrapped, and one outside
+    // the cell goes to the nearest bin: its neighbours within the list cutoff
+    // lie in that bin or beyond the face as well (bins are wider than the
+    // cutoff), so the stencil still finds every pair
+    m[a] = (C.periodic >> a) & 1 ? floor(s) : 0.0;
+    const double t = (s - m[a]) * C.nb[a];
+    b[a] = t < 0.0 ? 0 : (t >= (double)C.nb[a] ? C.nb[a] - 1 : (int)t);
   }
   float o[3] = {x, y, w};
   if (m[0] != 0.0 || m[1] != 0.0 || m[2] != 0.0) {
@@ -250,7 +254,9 @@ __global__ void k_fill_slots(int64_t n_slots, const int* __restrict__ base, cons
 // --------------------------------------------------------- Verlet lists
 
 // For every active slot, scan the 27 stencil bins (with periodic images) and
-// keep neighbours within the radial and angular list cutoffs.
+// keep neighbours within the radial and angular list cutoffs.  Along a
+// non-periodic direction a stencil bin beyond the cell has no atoms (no
+// images): it is skipped.
 __global__ __launch_bounds__(256) void k_build_lists(int64_t n_slots, int n_species, int total_bins,
                                                      const CfgDev* __restrict__ cfgs,
                                                      const float4* __restrict__ pos4, const int* __restrict__ cfg_of,
@@ -281,19 +287,23 @@ __global__ __launch_bounds__(256) void k_build_lists(int64_t n_slots, int n_spec
   // (bin key << 5 | code: unique, so the order is total; bin keys are below
   // 2^27) and sorted by a compare-exchange network with fixed indices, which
   // stays in registers; the sorted bins wait in this thread's LDS column.
+  // Skipped bins are kNoBin, which sorts last.
+  constexpr uint32_t kNoBin = 0xFFFFFFFFu;
   __shared__ uint32_t sorted_bins[27 * 256];
   uint32_t sb[27];
+  const int per = C.periodic;
 #pragma unroll
   for (int o = 0; o < 27; ++o) {
     int t0 = b0 + o / 9 - 1, t1 = b1 + (o / 3) % 3 - 1, t2 = b2 + o % 3 - 1;
     const int w0 = t0 < 0 ? -1 : (t0 >= C.nb[0] ? 1 : 0);
     const int w1 = t1 < 0 ? -1 : (t1 >= C.nb[1] ? 1 : 0);
     const int w2 = t2 < 0 ? -1 : (t2 >= C.nb[2] ? 1 : 0);
+    const bool skip = (w0 && !(per & 1)) || (w1 && !(per & 2)) || (w2 && !(per & 4));
     t0 -= w0 * C.nb[0];
     t1 -= w1 * C.nb[1];
     t2 -= w2 * C.nb[2];
     const uint32_t code = (uint32_t)((w0 + 1) * 9 + (w1 + 1) * 3 + (w2 + 1));
-    sb[o] = ((uint32_t)bin_key(C, t0, t1, t2) << 5) | code;
+    sb[o] = skip ? kNoBin : (((uint32_t)bin_key(C, t0, t1, t2) << 5) | code);
   }
 #pragma unroll
   for (int i = 1; i < 27; ++i)
@@ -319,6 +329,7 @@ __global__ __launch_bounds__(256) void k_build_lists(int64_t n_slots, int n_spec
   for (int z = 0; z < n_species; ++z) {
     for (int o = 0; o < 27; ++o) {
       const uint32_t sbo = sorted_bins[o * 256 + threadIdx.x];
+      if (sbo == kNoBin) break;
       const int tb = (int)(sbo >> 5);
       const uint32_t code = sbo & 31u;
       float sx, sy, sz;
@@ -543,8 +554,8 @@ static void cell_geometry(const double* H, double w[3], double Hi[9], double& de
   }
 }
 
-int NbrPipeline::setup(int n_cfg_, const int64_t* atom_off, const double* cells, int n_species_, double rcR,
-                       double rcA, double skin_, hipStream_t st) {
+int NbrPipeline::setup(int n_cfg_, const int64_t* atom_off, const double* cells, const int32_t* pbc, int n_species_,
+                       double rcR, double rcA, double skin_, hipStream_t st) {
   if (n_cfg_ < 1 || !atom_off || !cells) {
     set_error("n_cfg must be >= 1 and atom_off, cells non-null");
     return NEPMI_INVALID_ARG;
@@ -575,8 +586,17 @@ int NbrPipeline::setup(int n_cfg_, const int64_t* atom_off, const double* cells,
       set_error("singular or non-finite cell");
       return NEPMI_INVALID_ARG;
     }
+    C.periodic = 0;
     for (int a = 0; a < 3; ++a) {
-      if (w[a] < 2.0 * rcl) {
+      const int32_t pa = pbc ? pbc[3 * (size_t)c + a] : 1;
+      if (pa != 0 && pa != 1) {
+        set_error("pbc entries must be 0 or 1");
+        return NEPMI_INVALID_ARG;
+      }
+      C.periodic |= pa << a;
+      // only a periodic direction needs the width: no pair may meet two
+      // images of one atom
+      if (pa && w[a] < 2.0 * rcl) {
         set_error("cell width " + std::to_string(w[a]) + " of configuration " + std::to_string(c) +
                   " is below 2 * (rc_radial + skin) = " + std::to_string(2.0 * rcl));
         return NEPMI_CELL_TOO_SMALL;
@@ -593,7 +613,6 @@ int NbrPipeline::setup(int n_cfg_, const int64_t* atom_off, const double* cells,
     C.bin_off = (int)bins;
     C.atom_off = atom_off[c];
     C.n_atoms = (int)(atom_off[c + 1] - atom_off[c]);
-    C.pad = 0;
     bins += (int64_t)((C.nb[0] + 3) / 4) * ((C.nb[1] + 3) / 4) * ((C.nb[2] + 3) / 4) * 64;
   }
   // bin keys below 2^27: the list build packs a key and a 5-bit image code
@@ -633,8 +652,10 @@ int NbrPipeline::setup(int n_cfg_, const int64_t* atom_off, const double* cells,
       (rc = ccntA.ensure(4 * (size_t)n_slots)) ||
       (rc = flags.ensure(4 * kFlagCount)))
     return rc;
-  NEPMI_HIP(hipMemcpyAsync(cfgs.p, hc.data(), sizeof(CfgDev) * (size_t)n_cfg_, hipMemcpyHostToDevice, st));
-  NEPMI_HIP(hipMemcpyAsync(atom_off_dev.p, atom_off, 8 * (size_t)(n_cfg_ + 1), hipMemcpyHostToDevice, st));
+  // uploaded from the members, which outlive the asynchronous copies (the
+  // caller synchronises the stream before the next setup)
+  NEPMI_HIP(hipMemcpyAsync(cfgs.p, host_cfgs.data(), sizeof(CfgDev) * (size_t)n_cfg_, hipMemcpyHostToDevice, st));
+  NEPMI_HIP(hipMemcpyAsync(atom_off_dev.p, host_off.data(), 8 * (size_t)(n_cfg_ + 1), hipMemcpyHostToDevice, st));
   if (capR == 0) {
     // initial capacity from the densest configuration
     double dmax = 0.0;

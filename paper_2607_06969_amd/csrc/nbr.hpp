@@ -76,9 +76,11 @@ struct NbrPipeline {
   DevBuf flags;
 
   // Host-side setup of a batch: validates the cells, computes bins, sizes
-  // buffers and uploads the configuration table.  Returns NEPMI_* codes.
-  int setup(int n_cfg, const int64_t* atom_off, const double* cells, int n_species, double rcR, double rcA,
-            double skin, hipStream_t st);
+  // buffers and uploads the configuration table.  pbc: host int32[3 n_cfg]
+  // (1 periodic, 0 not, per lattice vector) or null (all periodic).  Returns
+  // NEPMI_* codes.
+  int setup(int n_cfg, const int64_t* atom_off, const double* cells, const int32_t* pbc, int n_species, double rcR,
+            double rcA, double skin, hipStream_t st);
   // Sizes the lists for capR x capA entries per slot.
   int ensure_lists(int capR_, int capA_);
   // Take every buffer from `a` from now on (releases what is held; the next

@@ -57,7 +57,7 @@ static int noalloc_device(NoAllocDevice** out) {
 
 using namespace nepmi;
 
-extern "C" int nepmi_compute_noalloc(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, const double* cells,
+extern "C" int nepmi_compute_noalloc(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, const double* cells, const int32_t* pbc,
                                      const float* dev_pos, const int32_t* dev_species, double* dev_energy,
                                      float* dev_forces, double* dev_virial, float* dev_atom_energy,
                                      float* dev_atom_virial, void* stream) {
@@ -72,7 +72,7 @@ extern "C" int nepmi_compute_noalloc(nepmi_model* m, int32_t n_cfg, const int64_
   // every call lays the workspace out afresh from the start of the array
   d->arena.used = 0;
   d->work.use_arena(&d->arena);
-  if ((rc = prepare_eval(d->work, m->ops, m->hp, n_cfg, atom_off, cells, dev_pos, dev_species, st, 0.0)))
+  if ((rc = prepare_eval(d->work, m->ops, m->hp, n_cfg, atom_off, cells, pbc, dev_pos, dev_species, st, 0.0)))
     return rc;
   return run_eval(d->work, m, dev_forces, dev_energy, dev_virial, dev_atom_energy, dev_atom_virial, st);
 }

@@ -77,8 +77,10 @@ __global__ __launch_bounds__(kRedBlock) void k_reduce_final(int n_cfg, const int
 }
 
 int Reducer::setup(int n_cfg_, const int64_t* atom_off, hipStream_t st) {
-  std::vector<RedItem> items;
-  std::vector<int> start((size_t)n_cfg_ + 1);
+  std::vector<RedItem>& items = host_items;
+  std::vector<int>& start = host_start;
+  items.clear();
+  start.assign((size_t)n_cfg_ + 1, 0);
   for (int c = 0; c < n_cfg_; ++c) {
     start[(size_t)c] = (int)items.size();
     int64_t a = atom_off[c];
@@ -101,7 +103,6 @@ int Reducer::setup(int n_cfg_, const int64_t* atom_off, hipStream_t st) {
     return rc;
   NEPMI_HIP(hipMemcpyAsync(items_dev.p, items.data(), sizeof(RedItem) * items.size(), hipMemcpyHostToDevice, st));
   NEPMI_HIP(hipMemcpyAsync(start_dev.p, start.data(), 4 * start.size(), hipMemcpyHostToDevice, st));
-  NEPMI_HIP(hipStreamSynchronize(st));
   return NEPMI_OK;
 }
 

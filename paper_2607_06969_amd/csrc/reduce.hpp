@@ -19,6 +19,12 @@ struct RedItem {
 struct Reducer {
   int n_cfg = 0, n_items = 0;
   DevBuf items_dev, start_dev, part;
+  // host copies of the plan, the sources of setup's asynchronous uploads:
+  // they stay alive until the next setup, and the caller synchronises the
+  // stream before that
+  std::vector<RedItem> host_items;
+  std::vector<int> host_start;
+  // Plan the sums of a batch and upload it on `st` (does not synchronise).
   int setup(int n_cfg, const int64_t* atom_off, hipStream_t st);
   void use_arena(Arena* a) {
     for (DevBuf* b : {&items_dev, &start_dev, &part}) {

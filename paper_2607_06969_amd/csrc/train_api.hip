@@ -150,7 +150,7 @@ CutoffsT<double> f64_cut(const nepmi_model* m) {
 constexpr double kSkin64 = 0.01;
 
 // lists from the float32 rounding of the positions, then the float64 staging
-int prepare64(nepmi_model* m, int n_cfg, const int64_t* atom_off, const double* cells, const double* dev_pos,
+int prepare64(nepmi_model* m, int n_cfg, const int64_t* atom_off, const double* cells, const int32_t* pbc, const double* dev_pos,
               const int32_t* dev_species, const double* dev_params, hipStream_t st, F64Args& a) {
   if (n_cfg < 1 || !atom_off || atom_off[0] != 0 || atom_off[n_cfg] < 0) {
     set_error("invalid batch");
@@ -160,7 +160,7 @@ int prepare64(nepmi_model* m, int n_cfg, const int64_t* atom_off, const double* 
   int rc;
   if ((rc = m->f64.posf.ensure(12 * (size_t)(N > 0 ? N : 1))) ||
       (rc = launch_round_pos(st, 3 * N, dev_pos, m->f64.posf.ptr<float>())) ||
-      (rc = m->prepare(n_cfg, atom_off, cells, m->f64.posf.ptr<float>(), dev_species, st, kSkin64, false)) ||
+      (rc = m->prepare(n_cfg, atom_off, cells, pbc, m->f64.posf.ptr<float>(), dev_species, st, kSkin64, false)) ||
       (rc = ensure_f64(m)))
     return rc;
   a.atom_off = m->nbr.atom_off_dev.ptr<int64_t>();
@@ -176,7 +176,7 @@ int prepare64(nepmi_model* m, int n_cfg, const int64_t* atom_off, const double* 
 
 extern "C" {
 
-int nepmi_compute_f64(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, const double* cells,
+int nepmi_compute_f64(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, const double* cells, const int32_t* pbc,
                       const double* dev_pos, const int32_t* dev_species, const double* dev_params, double* dev_energy,
                       double* dev_forces, double* dev_virial, double* dev_atom_energy, void* stream) {
   if (!m || !cells || !dev_pos || !dev_species || !dev_params || !dev_energy || !dev_forces || !dev_virial) {
@@ -186,7 +186,7 @@ int nepmi_compute_f64(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, co
   hipStream_t st = (hipStream_t)stream;
   F64Args a;
   int rc;
-  if ((rc = prepare64(m, n_cfg, atom_off, cells, dev_pos, dev_species, dev_params, st, a))) return rc;
+  if ((rc = prepare64(m, n_cfg, atom_off, cells, pbc, dev_pos, dev_species, dev_params, st, a))) return rc;
   F64Bufs& f = m->f64;
   if ((rc = launch_fill64(st, n_cfg, 1.0, f.ebar1.ptr<double>())) ||
       (rc = launch_fill64(st, 9 * (int64_t)n_cfg, 0.0, f.mu0.ptr<double>())))
@@ -198,7 +198,7 @@ int nepmi_compute_f64(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, co
   return m->red.run64(st, Ei, a.Wi, dev_energy, dev_virial);
 }
 
-int nepmi_backward_params_f64(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, const double* cells,
+int nepmi_backward_params_f64(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, const double* cells, const int32_t* pbc,
                               const double* dev_pos, const int32_t* dev_species, const double* dev_params,
                               const double* dev_ebar, const double* dev_lambda, const double* dev_mu,
                               double* dev_grad, void* stream) {
@@ -209,14 +209,14 @@ int nepmi_backward_params_f64(nepmi_model* m, int32_t n_cfg, const int64_t* atom
   hipStream_t st = (hipStream_t)stream;
   F64Args a;
   int rc;
-  if ((rc = prepare64(m, n_cfg, atom_off, cells, dev_pos, dev_species, dev_params, st, a))) return rc;
+  if ((rc = prepare64(m, n_cfg, atom_off, cells, pbc, dev_pos, dev_species, dev_params, st, a))) return rc;
   TrainIOT<double> io = f64_io(m, dev_mu, dev_ebar, nullptr);
   return m->ops->backward64(st, io, f64_cut(m), a, dev_lambda, m->nbr.base.ptr<int>(), m->f64.part.ptr<double>(),
                             dev_grad);
 }
 
 
-int nepmi_backward_params(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, const double* cells,
+int nepmi_backward_params(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, const double* cells, const int32_t* pbc,
                           const float* dev_pos, const int32_t* dev_species, const double* dev_ebar,
                           const float* dev_lambda, const double* dev_mu, float* dev_grad, void* stream) {
   if (!m || !dev_pos || !dev_species || !dev_ebar || !dev_lambda || !dev_mu || !dev_grad) {
@@ -225,13 +225,13 @@ int nepmi_backward_params(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off
   }
   hipStream_t st = (hipStream_t)stream;
   int rc;
-  if ((rc = m->prepare(n_cfg, atom_off, cells, dev_pos, dev_species, st)) || (rc = ensure_train(m))) return rc;
+  if ((rc = m->prepare(n_cfg, atom_off, cells, pbc, dev_pos, dev_species, st)) || (rc = ensure_train(m))) return rc;
   // the descriptor kernel writes the per-evaluation compact pair lists
   if ((rc = m->ops->desc(st, m->io(nullptr, nullptr, nullptr), m->params.ptr<float>(), false, m->vdesc))) return rc;
   return run_backward(m, st, dev_ebar, dev_lambda, dev_mu, dev_grad);
 }
 
-int nepmi_loss_grad(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, const double* cells,
+int nepmi_loss_grad(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, const double* cells, const int32_t* pbc,
                     const float* dev_pos, const int32_t* dev_species, const double* dev_E_ref, const float* dev_F_ref,
                     const double* dev_V_ref, const double* weights, int32_t loss_form, double* dev_loss,
                     float* dev_grad, void* stream) {
@@ -242,7 +242,7 @@ int nepmi_loss_grad(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, cons
   }
   hipStream_t st = (hipStream_t)stream;
   int rc;
-  if ((rc = m->prepare(n_cfg, atom_off, cells, dev_pos, dev_species, st)) || (rc = ensure_train(m))) return rc;
+  if ((rc = m->prepare(n_cfg, atom_off, cells, pbc, dev_pos, dev_species, st)) || (rc = ensure_train(m))) return rc;
   TrainBufs& t = m->tr;
   // forward: E, F, V
   NepIO io = m->io(t.F.ptr<float>(), nullptr, nullptr);

@@ -70,14 +70,14 @@ using namespace nepmi;
 
 extern "C" {
 
-int nepmi_autotune(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, const double* cells, const float* dev_pos,
+int nepmi_autotune(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, const double* cells, const int32_t* pbc, const float* dev_pos,
                    const int32_t* dev_species, int32_t* chosen, void* stream) {
   if (!m || !dev_pos || !dev_species) {
     set_error("null argument");
     return NEPMI_INVALID_ARG;
   }
   hipStream_t st = (hipStream_t)stream;
-  int rc = m->prepare(n_cfg, atom_off, cells, dev_pos, dev_species, st);
+  int rc = m->prepare(n_cfg, atom_off, cells, pbc, dev_pos, dev_species, st);
   if (rc) return rc;
   if ((rc = autotune_io(m, m->io(nullptr, nullptr, nullptr), st, 2))) return rc;
   if (chosen) {

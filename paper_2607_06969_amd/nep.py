@@ -24,29 +24,39 @@ def _dev(t, dtype):
 
 
 class Batch:
-    """A batch of periodic configurations resident on the GPU.
+    """A batch of configurations resident on the GPU.
 
     pos: (N, 3) float32 CUDA tensor; species: (N,) int32 CUDA tensor;
-    atom_off: host int64 (n_cfg + 1); cells: host float64 (n_cfg, 3, 3)."""
+    atom_off: host int64 (n_cfg + 1); cells: host float64 (n_cfg, 3, 3);
+    pbc: host int (n_cfg, 3) of 0/1 per lattice vector, or None (periodic
+    in every direction)."""
 
-    def __init__(self, pos, species, atom_off, cells):
+    def __init__(self, pos, species, atom_off, cells, pbc=None):
         self.pos = _dev(pos, torch.float32)
         self.species = _dev(species, torch.int32)
         self.atom_off = np.ascontiguousarray(np.asarray(atom_off, dtype=np.int64))
         self.cells = np.ascontiguousarray(np.asarray(cells, dtype=np.float64).reshape(-1, 9))
         self.n_cfg = len(self.atom_off) - 1
         self.n_atoms = int(self.atom_off[-1])
+        self.pbc = None
+        if pbc is not None:
+            self.pbc = np.ascontiguousarray(np.asarray(pbc, dtype=np.int32).reshape(-1, 3))
+            if self.pbc.shape[0] != self.n_cfg:
+                raise ValueError("pbc must have one row of three flags per configuration")
 
     @classmethod
     def from_system(cls, system, device="cuda"):
         return cls(torch.as_tensor(system.pos, dtype=torch.float32, device=device).contiguous(),
                    torch.as_tensor(system.species, dtype=torch.int32, device=device).contiguous(),
-                   system.atom_off, system.cells)
+                   system.atom_off, system.cells, getattr(system, "pbc", None))
 
     def _meta(self):
+        """Host arrays to keep alive for the call, and the pointers to pass
+        (pbc: NULL when every direction is periodic)."""
         off, poff = _host_i64(self.atom_off)
         cel, pcel = _host_f64(self.cells)
-        return (off, cel), poff, pcel
+        ppbc = None if self.pbc is None else self.pbc.ctypes.data_as(C.POINTER(C.c_int32))
+        return (off, cel, self.pbc), poff, pcel, ppbc
 
 
 class NepModel:
@@ -94,9 +104,9 @@ class NepModel:
         V = torch.empty(batch.n_cfg, 9, dtype=torch.float64, device=dev)
         Ea = torch.empty(batch.n_atoms, dtype=torch.float32, device=dev) if atom_energy else None
         Wa = torch.empty(batch.n_atoms, 9, dtype=torch.float32, device=dev) if atom_virial else None
-        keep, poff, pcel = batch._meta()
+        keep, poff, pcel, ppbc = batch._meta()
         fn = load().nepmi_compute_noalloc if noalloc else load().nepmi_compute
-        check(fn(self._h, batch.n_cfg, poff, pcel, _ptr(batch.pos), _ptr(batch.species),
+        check(fn(self._h, batch.n_cfg, poff, pcel, ppbc, _ptr(batch.pos), _ptr(batch.species),
                  _ptr(E), _ptr(F), _ptr(V), _ptr(Ea), _ptr(Wa), _stream()))
         out = {"E": E, "F": F, "V": V.view(-1, 3, 3)}
         if atom_energy:
@@ -107,8 +117,8 @@ class NepModel:
 
     def descriptors(self, batch: Batch):
         q = torch.empty(batch.n_atoms, self.dim, dtype=torch.float32, device=batch.pos.device)
-        keep, poff, pcel = batch._meta()
-        check(load().nepmi_descriptors(self._h, batch.n_cfg, poff, pcel, _ptr(batch.pos), _ptr(batch.species),
+        keep, poff, pcel, ppbc = batch._meta()
+        check(load().nepmi_descriptors(self._h, batch.n_cfg, poff, pcel, ppbc, _ptr(batch.pos), _ptr(batch.species),
                                        _ptr(q), _stream()))
         return q
 
@@ -118,16 +128,16 @@ class NepModel:
         cnt = torch.empty(batch.n_atoms, dtype=torch.int32, device=dev)
         nb = torch.full((batch.n_atoms, cap), -1, dtype=torch.int32, device=dev)
         rv = torch.zeros(batch.n_atoms, cap, 3, dtype=torch.float32, device=dev)
-        keep, poff, pcel = batch._meta()
-        check(load().nepmi_neighbors(self._h, batch.n_cfg, poff, pcel, _ptr(batch.pos), _ptr(batch.species),
+        keep, poff, pcel, ppbc = batch._meta()
+        check(load().nepmi_neighbors(self._h, batch.n_cfg, poff, pcel, ppbc, _ptr(batch.pos), _ptr(batch.species),
                                      int(which), int(cap), _ptr(cnt), _ptr(nb), _ptr(rv), _stream()))
         return cnt, nb, rv
 
     def autotune(self, batch: Batch):
         """Time every kernel variant on this batch and keep the fastest; returns (desc, force)."""
         ch = (C.c_int32 * 2)()
-        keep, poff, pcel = batch._meta()
-        check(load().nepmi_autotune(self._h, batch.n_cfg, poff, pcel, _ptr(batch.pos), _ptr(batch.species), ch,
+        keep, poff, pcel, ppbc = batch._meta()
+        check(load().nepmi_autotune(self._h, batch.n_cfg, poff, pcel, ppbc, _ptr(batch.pos), _ptr(batch.species), ch,
                                     _stream()))
         return int(ch[0]), int(ch[1])
 
@@ -143,9 +153,9 @@ class NepModel:
         """sum_c ebar_c dE_c/dtheta + sum_i lam_i.dF_i/dtheta + sum_c mu_c:dV_c/dtheta (float32, P).
         Needs a preceding compute() on the same batch."""
         g = torch.empty(self.n_params, dtype=torch.float32, device=batch.pos.device)
-        keep, poff, pcel = batch._meta()
+        keep, poff, pcel, ppbc = batch._meta()
         check(load().nepmi_backward_params(
-            self._h, batch.n_cfg, poff, pcel, _ptr(batch.pos), _ptr(batch.species),
+            self._h, batch.n_cfg, poff, pcel, ppbc, _ptr(batch.pos), _ptr(batch.species),
             _ptr(_dev(ebar.contiguous(), torch.float64)), _ptr(_dev(lam.contiguous(), torch.float32)),
             _ptr(_dev(mu.reshape(-1, 9).contiguous(), torch.float64)), _ptr(g), _stream()))
         return g
@@ -167,8 +177,8 @@ class NepModel:
         F = torch.empty(batch.n_atoms, 3, dtype=torch.float64, device=dev)
         V = torch.empty(batch.n_cfg, 9, dtype=torch.float64, device=dev)
         Ea = torch.empty(batch.n_atoms, dtype=torch.float64, device=dev) if atom_energy else None
-        keep, poff, pcel = batch._meta()
-        check(load().nepmi_compute_f64(self._h, batch.n_cfg, poff, pcel, _ptr(X), _ptr(batch.species), _ptr(P),
+        keep, poff, pcel, ppbc = batch._meta()
+        check(load().nepmi_compute_f64(self._h, batch.n_cfg, poff, pcel, ppbc, _ptr(X), _ptr(batch.species), _ptr(P),
                                        _ptr(E), _ptr(F), _ptr(V), _ptr(Ea), _stream()))
         out = {"E": E, "F": F, "V": V.view(-1, 3, 3)}
         if atom_energy:
@@ -179,9 +189,9 @@ class NepModel:
         """Float64 twin of backward_params, at the float64 parameter vector `params`."""
         P, X = self._f64_inputs(batch, params, pos)
         g = torch.empty(self.n_params, dtype=torch.float64, device=batch.pos.device)
-        keep, poff, pcel = batch._meta()
+        keep, poff, pcel, ppbc = batch._meta()
         check(load().nepmi_backward_params_f64(
-            self._h, batch.n_cfg, poff, pcel, _ptr(X), _ptr(batch.species), _ptr(P),
+            self._h, batch.n_cfg, poff, pcel, ppbc, _ptr(X), _ptr(batch.species), _ptr(P),
             _ptr(_dev(ebar.contiguous(), torch.float64)), _ptr(_dev(lam.reshape(-1, 3).contiguous(), torch.float64)),
             _ptr(_dev(mu.reshape(-1, 9).contiguous(), torch.float64)), _ptr(g), _stream()))
         return g
@@ -191,10 +201,10 @@ class NepModel:
         dev = batch.pos.device
         loss = torch.empty(4, dtype=torch.float64, device=dev)
         g = torch.empty(self.n_params, dtype=torch.float32, device=dev) if grad else None
-        keep, poff, pcel = batch._meta()
+        keep, poff, pcel, ppbc = batch._meta()
         w, pw = _host_f64(weights)
         check(load().nepmi_loss_grad(
-            self._h, batch.n_cfg, poff, pcel, _ptr(batch.pos), _ptr(batch.species),
+            self._h, batch.n_cfg, poff, pcel, ppbc, _ptr(batch.pos), _ptr(batch.species),
             _ptr(_dev(E_ref, torch.float64)), _ptr(_dev(F_ref, torch.float32)),
             _ptr(_dev(V_ref.reshape(-1, 9).contiguous(), torch.float64)), pw, int(loss_form), _ptr(loss), _ptr(g),
             _stream()))
@@ -317,10 +327,10 @@ class NepMD:
     def __init__(self, model: NepModel, batch: Batch, vel, masses, dt_fs=1.0, skin=1.0):
         self.model, self.batch = model, batch
         vel = _dev(vel, torch.float32)
-        keep, poff, pcel = batch._meta()
+        keep, poff, pcel, ppbc = batch._meta()
         m, pm = _host_f64(masses)
         h = C.c_void_p()
-        check(load().nepmi_md_create(model._h, batch.n_cfg, poff, pcel, _ptr(batch.pos), _ptr(vel),
+        check(load().nepmi_md_create(model._h, batch.n_cfg, poff, pcel, ppbc, _ptr(batch.pos), _ptr(vel),
                                      _ptr(batch.species), pm, float(dt_fs), float(skin), C.byref(h), _stream()))
         self._h = h
 
