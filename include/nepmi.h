@@ -163,12 +163,16 @@ int nepmi_neighbors(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, cons
                     int32_t *dev_count, int32_t *dev_nbr, float *dev_rvec, void *stream);
 
 /* Kernel variants.  The descriptor and pair-force kernels are compiled in
- * several variants (angular functions handled per pass over the pairs, and
- * the register budget they keep to); all compute the same result (descriptor
- * variants bitwise, force variants up to float32 summation order).
- * nepmi_autotune times every variant on the given batch and keeps the
- * fastest in the model; chosen = host int32[2] (descriptor, force) or NULL.
- * Synchronises `stream`.  nepmi_set_variants pins a choice (0..3 each);
+ * several variants (angular functions handled per pass over the pairs, the
+ * register budget they keep to, and for the descriptors whether the network
+ * runs in the same kernel (0..3) or in one of its own on dense 16x16x4
+ * matrix products (4..7)); all compute the same result (descriptors bitwise
+ * across descriptor variants, energies bitwise within each network form and
+ * up to float32 summation order across them; force variants up to float32
+ * summation order).  nepmi_autotune times every variant on the given batch
+ * and keeps the fastest in the model; chosen = host int32[2] (descriptor,
+ * force) or NULL.  Synchronises `stream`.  nepmi_set_variants pins a choice
+ * (descriptor 0..7, force 0..3);
  * nepmi_md_create autotunes on its initial state unless a choice is pinned. */
 int nepmi_autotune(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, const double *cells, const int32_t *pbc,
                    const float *dev_pos, const int32_t *dev_species, int32_t *chosen, void *stream);

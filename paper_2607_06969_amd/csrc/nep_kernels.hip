@@ -141,9 +141,160 @@ __device__ __forceinline__ void angular_sums(const float4* __restrict__ pos4, co
   (void)T;
 }
 
+// ------------------------------------------------------- network (Sec. 2.3)
+
+// First-layer weights of the species this block's wavefronts hold (each
+// wavefront is uniform) into LDS, zero padded, as [Z][h][d] and transposed
+// [Z][d][h].  Every thread of the block must call it (it ends with a barrier).
+template <class S>
+__device__ __forceinline__ void load_weights(const float* __restrict__ params, const float4* __restrict__ pos4,
+                                             int64_t n_slots, int64_t p, float* W0s, float* W0Ts) {
+  constexpr int T = S::T, D = S::D, H = S::H;
+  constexpr int HP = MlpPad<S>::HP, DP = MlpPad<S>::DP;
+  const int64_t b0 = p - threadIdx.x;
+  unsigned need = 0;
+#pragma unroll
+  for (int w = 0; w < kBlock / kWave; ++w) {
+    const int64_t s0 = b0 + w * kWave;
+    need |= 1u << __float_as_int(pos4[s0 < n_slots ? s0 : n_slots - 1].w);
+  }
+  for (int z = 0; z < T; ++z) {
+    if (!(need >> z & 1u)) continue;
+    const float* W0g = params + S::PCR + S::PCA + (int64_t)z * S::PMLP;
+    for (int t = threadIdx.x; t < HP * DP; t += kBlock) {
+      const int h = t / DP, d = t % DP;
+      const float w = (h < H && d < D) ? W0g[h * D + d] : 0.0f;
+      W0s[(z * HP + h) * DP + d] = w;
+      W0Ts[(z * DP + d) * HP + h] = w;
+    }
+  }
+  __syncthreads();
+}
+
+// The network of species Zs on the matrix cores, and what follows from it:
+// site energy E_i, dE_i/dq for the angular descriptors (fp), the radial
+// adjoint atil_i[b][k] = sum_n dE_i/dq_n ctil[Z_i][b][n][k] (aR), and the
+// optional descriptor copy.  With the 16-block 4x4x1 fp32 MFMA, block b
+// (lanes 4b..4b+3) forms C[i][j] += A[i] B[j] with A[i] from lane 4b+i and
+// B[j] from lane 4b+j, and lane 4b+j keeps column j.  Every lane supplies its
+// own atom's value as B and a weight row selected by lane % 4 as A, so each
+// lane accumulates four entries of its own atom: no data moves between
+// lanes.  Every lane of the wavefront must call it (inactive atoms included).
+template <class S>
+__device__ __forceinline__ void network(const float (&q)[MlpPad<S>::DP], int Zs, bool active, int64_t n_slots,
+                                        int64_t p, const int* __restrict__ orig, const float* __restrict__ params,
+                                        const float* W0s, const float* W0Ts, float* __restrict__ fp,
+                                        float* __restrict__ aR, float* __restrict__ Ei, float* __restrict__ qout,
+                                        float* __restrict__ Eproc, int want_adjoint) {
+  constexpr int T = S::T, NR = S::NR, BR = S::BR, D = S::D, H = S::H;
+  constexpr int HP = MlpPad<S>::HP, DP = MlpPad<S>::DP;
+  const float* __restrict__ dco = params + S::P;
+  const int lq = threadIdx.x & 3;
+  const float* b0g = params + S::PCR + S::PCA + (int64_t)Zs * S::PMLP + H * D;
+  const float* w1g = b0g + H;
+  //  forward: a_h = b0_h + sum_d W0[h][d] q_d, four hidden units per group
+  floatx4 acc[HP / 4];
+#pragma unroll
+  for (int hg = 0; hg < HP / 4; ++hg)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[hg][r] = (4 * hg + r < H) ? b0g[4 * hg + r] : 0.f;
+  {
+    const float* Wz = W0s + (Zs * HP + lq) * DP;
+#pragma unroll
+    for (int dg = 0; dg < DP / 4; ++dg) {
+#pragma unroll
+      for (int hg = 0; hg < HP / 4; ++hg) {
+        const float4 w = *reinterpret_cast<const float4*>(Wz + 4 * hg * DP + 4 * dg);
+        acc[hg] = __builtin_amdgcn_mfma_f32_4x4x1f32(w.x, q[4 * dg + 0], acc[hg], 0, 0, 0);
+        acc[hg] = __builtin_amdgcn_mfma_f32_4x4x1f32(w.y, q[4 * dg + 1], acc[hg], 0, 0, 0);
+        acc[hg] = __builtin_amdgcn_mfma_f32_4x4x1f32(w.z, q[4 * dg + 2], acc[hg], 0, 0, 0);
+        acc[hg] = __builtin_amdgcn_mfma_f32_4x4x1f32(w.w, q[4 * dg + 3], acc[hg], 0, 0, 0);
+      }
+    }
+  }
+  if (active && qout) {
+    const int i = orig[p];
+#pragma unroll
+    for (int d = 0; d < D; ++d) qout[(int64_t)i * D + d] = q[d];
+  }
+  //  E = b1 + sum_h w1_h tanh(a_h);  z_h = dE/da_h = w1_h (1 - tanh^2)
+  float E = w1g[H];
+  float zt[HP];
+#pragma unroll
+  for (int hg = 0; hg < HP / 4; ++hg)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int h = 4 * hg + r;
+      if (h < H) {
+        const float t = tanh_fast(acc[hg][r]);
+        E = fmaf(w1g[h], t, E);
+        zt[h] = w1g[h] * fmaf(-t, t, 1.0f);
+      } else {
+        zt[h] = 0.f;
+      }
+    }
+  //  backward: dE/dq_d = sum_h z_h W0[h][d], four descriptors per group
+  floatx4 fpa[DP / 4];
+#pragma unroll
+  for (int dg = 0; dg < DP / 4; ++dg) fpa[dg] = floatx4{0.f, 0.f, 0.f, 0.f};
+  {
+    const float* WzT = W0Ts + (Zs * DP + lq) * HP;
+#pragma unroll
+    for (int hg = 0; hg < HP / 4; ++hg) {
+#pragma unroll
+      for (int dg = 0; dg < DP / 4; ++dg) {
+        const float4 w = *reinterpret_cast<const float4*>(WzT + 4 * dg * HP + 4 * hg);
+        fpa[dg] = __builtin_amdgcn_mfma_f32_4x4x1f32(w.x, zt[4 * hg + 0], fpa[dg], 0, 0, 0);
+        fpa[dg] = __builtin_amdgcn_mfma_f32_4x4x1f32(w.y, zt[4 * hg + 1], fpa[dg], 0, 0, 0);
+        fpa[dg] = __builtin_amdgcn_mfma_f32_4x4x1f32(w.z, zt[4 * hg + 2], fpa[dg], 0, 0, 0);
+        fpa[dg] = __builtin_amdgcn_mfma_f32_4x4x1f32(w.w, zt[4 * hg + 3], fpa[dg], 0, 0, 0);
+      }
+    }
+  }
+  float Fp[DP];
+#pragma unroll
+  for (int dg = 0; dg < DP / 4; ++dg)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Fp[4 * dg + r] = fpa[dg][r];
+  if (!active) return;
+  const int i = orig[p];
+  Ei[i] = E;
+  if (Eproc) Eproc[p] = E;
+  if (!want_adjoint) return;
+#pragma unroll
+  for (int d = NR; d < D; ++d) fp[(int64_t)(d - NR) * n_slots + p] = Fp[d];
+  // radial adjoint atil[b][k] = sum_n dE/dq_n ctil[Z_i][b][n][k], one row
+  // of B_R floats per part, written as float4
+  static_assert(BR % 4 == 0, "adjoint rows are written as float4");
+  const float* cR = dco + (int64_t)Zs * (T * NR * BR);
+#pragma unroll
+  for (int b = 0; b < T; ++b) {
+    float4* row = reinterpret_cast<float4*>(aR + ((int64_t)b * n_slots + p) * BR);
+#pragma unroll
+    for (int k4 = 0; k4 < BR / 4; ++k4) {
+      float v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        float acc = 0.f;
+#pragma unroll
+        for (int nn = 0; nn < NR; ++nn) acc = fmaf(Fp[nn], cR[(b * NR + nn) * BR + 4 * k4 + u], acc);
+        v[u] = acc;
+      }
+      row[k4] = make_float4(v[0], v[1], v[2], v[3]);
+    }
+  }
+}
+
 // ------------------------------------------------------------------ k_desc
 
-template <class S, int NSPLIT, int WPE>
+// NET: the network runs in this kernel (4x4x1 matrix instructions, one atom
+// per lane); otherwise the descriptors are left for k_net in the buffers the
+// network's outputs later take: radial q_n in the atom's aR rows (entry
+// n % B_R of part n / B_R), the angular ones in fp.  The unfused form needs no
+// network weights in LDS and fewer registers, so more wavefronts share a
+// compute unit during the pair walks, and k_net runs the network as dense
+// products; it pays one extra write and read of the descriptors.
+template <class S, int NSPLIT, int WPE, bool NET>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) void k_desc(
     int64_t n_slots, int capA, const float4* __restrict__ pos4, const int* __restrict__ cfg_of,
     const int* __restrict__ orig, const CfgDev* __restrict__ cfgs, const uint32_t* __restrict__ nbrR,
@@ -158,8 +309,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
   constexpr int HP = MlpPad<S>::HP, DP = MlpPad<S>::DP;
   const float* __restrict__ dco = params + S::P;  // derived coefficients: radial, then angular
   __shared__ float cA_s[T * T * NA * BA];
-  __shared__ float W0s[T * HP * DP];   // [Z][h][d] network weights, zero padded
-  __shared__ float W0Ts[T * DP * HP];  // [Z][d][h] the same, transposed
+  __shared__ float W0s[NET ? T * HP * DP : 1];   // [Z][h][d] network weights, zero padded
+  __shared__ float W0Ts[NET ? T * DP * HP : 1];  // [Z][d][h] the same, transposed
 
   // Every lane of a wavefront takes part in the matrix instructions of the
   // network, so lanes past the last slot stay alive as inactive atoms.
@@ -168,28 +319,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
   const int64_t pc = in_range ? p : n_slots - 1;
   const float4 xi = pos4[pc];
   const int Zs = __builtin_amdgcn_readfirstlane(__float_as_int(xi.w));
-  {
-    // weights of the species of this block's wavefronts (each is uniform)
-    const int64_t b0 = p - threadIdx.x;
-    unsigned need = 0;
-#pragma unroll
-    for (int w = 0; w < kBlock / kWave; ++w) {
-      const int64_t s0 = b0 + w * kWave;
-      need |= 1u << __float_as_int(pos4[s0 < n_slots ? s0 : n_slots - 1].w);
-    }
-    for (int t = threadIdx.x; t < T * T * NA * BA; t += kBlock) cA_s[t] = dco[S::PCR + t];
-    for (int z = 0; z < T; ++z) {
-      if (!(need >> z & 1u)) continue;
-      const float* W0g = params + S::PCR + S::PCA + (int64_t)z * S::PMLP;
-      for (int t = threadIdx.x; t < HP * DP; t += kBlock) {
-        const int h = t / DP, d = t % DP;
-        const float w = (h < H && d < D) ? W0g[h * D + d] : 0.0f;
-        W0s[(z * HP + h) * DP + d] = w;
-        W0Ts[(z * DP + d) * HP + h] = w;
-      }
-    }
+  for (int t = threadIdx.x; t < T * T * NA * BA; t += kBlock) cA_s[t] = dco[S::PCR + t];
+  if constexpr (NET) {
+    load_weights<S>(params, pos4, n_slots, p, W0s, W0Ts);
+  } else {
+    __syncthreads();
   }
-  __syncthreads();
 
   const int c = in_range ? cfg_of[p] : -1;
   const bool active = c >= 0;
@@ -281,6 +416,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
   float q[DP];
 #pragma unroll
   for (int d = D; d < DP; ++d) q[d] = 0.f;
+  // descriptor d: kept for the fused network, else stored at once for k_net
+  // (so that no register holds it through the angular passes)
+  auto put_q = [&](int d, float v) {
+    if constexpr (NET) {
+      q[d] = v;
+    } else if (active) {
+      if (d < NR)
+        aR[((int64_t)(d / BR) * n_slots + p) * BR + d % BR] = v;
+      else
+        fp[(int64_t)(d - NR) * n_slots + p] = v;
+    }
+  };
   // ---- radial descriptors, Eq. 11: q_n = sum_b sum_k ctil[Z_i][b][n][k] PT_b[k]
   {
     const float* cR = dco + (int64_t)Zs * (T * NR * BR);
@@ -291,7 +438,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
       for (int b = 0; b < T; ++b)
 #pragma unroll
         for (int kk = 0; kk < BR; ++kk) acc = fmaf(cR[(b * NR + nn) * BR + kk], PT[b][kk], acc);
-      q[nn] = acc;
+      put_q(nn, acc);
     }
   }
 
@@ -304,113 +451,215 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
 #pragma unroll
     for (int nn = 0; nn < NH; ++nn) {
       const int n = h * NH + nn;
+      float s1 = 0.f;
 #pragma unroll
       for (int l = 1; l <= L; ++l) {
         float s = 0.f;
 #pragma unroll
         for (int lm = l * l - 1; lm < (l + 1) * (l + 1) - 1; ++lm) s = fmaf(Sg[nn][lm], Sg[nn][lm], s);
-        q[NR + (l - 1) * NA + n] = s;
+        put_q(NR + (l - 1) * NA + n, s);
+        if (l == 1) s1 = s;
       }
       if constexpr (S::F4) {
         float A[6];
         a_from_s2(&Sg[nn][3], A);
-        q[S::OFF4 + n] = tr_cube(A);
+        put_q(S::OFF4 + n, tr_cube(A));
       }
-      if constexpr (S::F5) q[S::OFF5 + n] = q[NR + n] * q[NR + n];
+      if constexpr (S::F5) put_q(S::OFF5 + n, s1 * s1);
     }
   }
 
-  // ---- network of Sec. 2.3 on the matrix cores.  With the 16-block 4x4x1
-  //      fp32 MFMA, block b (lanes 4b..4b+3) forms C[i][j] += A[i] B[j] with
-  //      A[i] from lane 4b+i and B[j] from lane 4b+j, and lane 4b+j keeps
-  //      column j.  Every lane supplies its own atom's value as B and a weight
-  //      row selected by lane % 4 as A, so each lane accumulates four entries
-  //      of its own atom: no data moves between lanes.
-  const int lq = threadIdx.x & 3;
-  const float* b0g = params + S::PCR + S::PCA + (int64_t)Zs * S::PMLP + H * D;
-  const float* w1g = b0g + H;
-  //  forward: a_h = b0_h + sum_d W0[h][d] q_d, four hidden units per group
-  floatx4 acc[HP / 4];
+  if constexpr (NET) network<S>(q, Zs, active, n_slots, p, orig, params, W0s, W0Ts, fp, aR, Ei, qout, Eproc, want_adjoint);
+  (void)H;
+}
+
+// ------------------------------------------------------------------- k_net
+
+// The network for descriptors left by the unfused k_desc, as dense products
+// on the 16x16x4 fp32 matrix instructions.  A wavefront's 64 atoms are the
+// columns (four tiles of 16).  Forward, a[h][atom] = b0_h + sum_d W0[h][d]
+// q[d][atom]: rows are hidden units, the reduction runs over descriptors.
+// Backward, dE/dq[d][atom] = sum_h W0[h][d] z[h][atom] with
+// z_h = w1_h (1 - tanh^2 a_h): rows are descriptors, the reduction runs over
+// hidden units, and z is consumed in the register layout the forward product
+// left it in (lane group g of a tile holds rows 4g..4g+3, so the reduction
+// index h = 16 m + 4 g + r is taken in that order, for A and B alike).
+// Operand layouts of v_mfma_f32_16x16x4f32: lane l holds A[l % 16][l / 16],
+// B[l / 16][l % 16], and D[4 (l / 16) + r][l % 16] in its r-th register.
+// First-layer weights sit in LDS once, [h][d] with a row stride of 68 floats
+// (4 mod 64), which keeps both read patterns free of bank conflicts.  Each
+// wavefront reads the descriptors of its own 64 atoms and overwrites them
+// with the adjoints only after its products are done.
+template <class S>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_net(int64_t n_slots, const float4* __restrict__ pos4,
+                                                const int* __restrict__ cfg_of, const int* __restrict__ orig,
+                                                const float* __restrict__ params, float* __restrict__ fp,
+                                                float* __restrict__ aR, float* __restrict__ Ei,
+                                                float* __restrict__ qout, float* __restrict__ Eproc,
+                                                int want_adjoint) {
+  constexpr int T = S::T, NR = S::NR, BR = S::BR, D = S::D, H = S::H;
+  constexpr int MT = (H + 15) / 16;   // tiles of hidden units
+  constexpr int KS = (D + 3) / 4;     // reduction steps of the forward product
+  constexpr int MD = (D + 15) / 16;   // tiles of descriptors
+  constexpr int HR = 16 * MT;         // rows of the weight table (zero beyond H)
+  constexpr int WSR = ((16 * MD > 4 * KS ? 16 * MD : 4 * KS) + 63) / 64 * 64 + 4;  // row stride
+  static_assert(NR <= T * BR, "the radial descriptors must fit the radial adjoint rows");
+  static_assert(NR <= 16, "the radial adjoints come from the first descriptor tile");
+  static_assert(BR % 4 == 0, "adjoint rows are written as float4");
+  __shared__ float W0s[T * HR * WSR];
+  __shared__ float b0s[T * HR];
+  __shared__ float w1s[T * HR];
+  __shared__ float fr_s[kBlock / kWave][NR][kWave + 1];  // radial dE/dq, transposed to one atom per lane
+  // The grid is at most two blocks per compute unit, each looping over tiles
+  // of kBlock slots: the weights of every species enter LDS once per block.
+  for (int t = threadIdx.x; t < T * HR * WSR; t += kBlock) {
+    const int z = t / (HR * WSR), h = (t / WSR) % HR, d = t % WSR;
+    W0s[t] = (h < H && d < D) ? params[S::PCR + S::PCA + (int64_t)z * S::PMLP + h * D + d] : 0.0f;
+  }
+  for (int t = threadIdx.x; t < T * HR; t += kBlock) {
+    const int z = t / HR, h = t % HR;
+    const float* b0g = params + S::PCR + S::PCA + (int64_t)z * S::PMLP + H * D;
+    b0s[t] = h < H ? b0g[h] : 0.0f;
+    w1s[t] = h < H ? b0g[H + h] : 0.0f;
+  }
+  const int lane = threadIdx.x & (kWave - 1), g = lane >> 4, c = lane & 15, wv = threadIdx.x / kWave;
+  const int64_t n_tiles = (n_slots + kBlock - 1) / kBlock;
+#pragma unroll 1
+  for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    __syncthreads();  // weights loaded; the previous tile's transposition read
+    // the slot count as an opaque per-tile value: otherwise the compiler keeps
+    // every row offset (d - n_R) n_slots live across the loop in registers
+    int64_t ns = n_slots;
+    __asm__ volatile("" : "+s"(ns));
+    const int64_t p = tile * kBlock + threadIdx.x;
+    const int64_t base = p - lane;
+    const bool in_range = p < ns;
+    const int64_t pc = in_range ? p : ns - 1;
+    const int Zs = __builtin_amdgcn_readfirstlane(__float_as_int(pos4[pc].w));
+    const bool active = in_range && cfg_of[p] >= 0;
+    auto q_at = [&](int d, int64_t a) {
+      return d < NR ? aR[((int64_t)(d / BR) * ns + a) * BR + d % BR] : fp[(int64_t)(d - NR) * ns + a];
+    };
+    if (active && qout) {
+      const int i = orig[p];
 #pragma unroll
-  for (int hg = 0; hg < HP / 4; ++hg)
+      for (int d = 0; d < D; ++d) qout[(int64_t)i * D + d] = q_at(d, p);
+    }
+    // B operands of the forward product: q[4 ks + g][atom 16 nt + c] (zero
+    // past the last descriptor; columns past the last slot read the last slot)
+    float qb[KS][4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) acc[hg][r] = (4 * hg + r < H) ? b0g[4 * hg + r] : 0.f;
-  {
-    const float* Wz = W0s + (Zs * HP + lq) * DP;
+    for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-    for (int dg = 0; dg < DP / 4; ++dg) {
+      for (int nt = 0; nt < 4; ++nt) {
+        const int d = 4 * ks + g;
+        const int64_t a = base + 16 * nt + c;
+        qb[ks][nt] = d < D ? q_at(d, a < ns ? a : ns - 1) : 0.0f;
+      }
+    const float* Wz = W0s + Zs * HR * WSR;
+    floatx4 C[MT][4];
 #pragma unroll
-      for (int hg = 0; hg < HP / 4; ++hg) {
-        const float4 w = *reinterpret_cast<const float4*>(Wz + 4 * hg * DP + 4 * dg);
-        acc[hg] = __builtin_amdgcn_mfma_f32_4x4x1f32(w.x, q[4 * dg + 0], acc[hg], 0, 0, 0);
-        acc[hg] = __builtin_amdgcn_mfma_f32_4x4x1f32(w.y, q[4 * dg + 1], acc[hg], 0, 0, 0);
-        acc[hg] = __builtin_amdgcn_mfma_f32_4x4x1f32(w.z, q[4 * dg + 2], acc[hg], 0, 0, 0);
-        acc[hg] = __builtin_amdgcn_mfma_f32_4x4x1f32(w.w, q[4 * dg + 3], acc[hg], 0, 0, 0);
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float bb = b0s[Zs * HR + 16 * mt + 4 * g + r];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) C[mt][nt][r] = bb;
+      }
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const float a = Wz[(16 * mt + c) * WSR + 4 * ks + g];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+          C[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, qb[ks][nt], C[mt][nt], 0, 0, 0);
+      }
+    //  E = b1 + sum_h w1_h tanh(a_h): per lane over its rows, then over the
+    //  four lane groups of each column; z_h = w1_h (1 - tanh^2) replaces a_h
+    float Ep[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float w = w1s[Zs * HR + 16 * mt + 4 * g + r];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+          const float t = tanh_fast(C[mt][nt][r]);
+          Ep[nt] = fmaf(w, t, Ep[nt]);
+          C[mt][nt][r] = w * fmaf(-t, t, 1.0f);
+        }
+      }
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      Ep[nt] += __shfl_xor(Ep[nt], 16);
+      Ep[nt] += __shfl_xor(Ep[nt], 32);
+    }
+    // lane 16 g + c is atom 16 g + c of the wavefront: column c of tile g
+    const float Es = g == 0 ? Ep[0] : (g == 1 ? Ep[1] : (g == 2 ? Ep[2] : Ep[3]));
+    const float E = params[S::PCR + S::PCA + (int64_t)Zs * S::PMLP + H * D + 2 * H] + Es;
+    if (active) {
+      const int i = orig[p];
+      Ei[i] = E;
+      if (Eproc) Eproc[p] = E;
+    }
+    if (!want_adjoint) continue;
+    floatx4 C2[MD][4];
+#pragma unroll
+    for (int md = 0; md < MD; ++md)
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) C2[md][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int md = 0; md < MD; ++md) {
+          const float a = Wz[(16 * mt + 4 * g + r) * WSR + 16 * md + c];
+#pragma unroll
+          for (int nt = 0; nt < 4; ++nt)
+            C2[md][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, C[mt][nt][r], C2[md][nt], 0, 0, 0);
+        }
+    // dE/dq of the angular descriptors straight from the product's layout (16
+    // consecutive atoms per lane group); the radial ones through LDS
+#pragma unroll
+    for (int md = 0; md < MD; ++md)
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int d = 16 * md + 4 * g + r;
+          const int64_t a = base + 16 * nt + c;
+          if (d < NR)
+            fr_s[wv][d][16 * nt + c] = C2[md][nt][r];
+          else if (d < D && a < ns)
+            fp[(int64_t)(d - NR) * ns + a] = C2[md][nt][r];
+        }
+    __syncthreads();
+    if (active) {
+      float Fr[NR];
+#pragma unroll
+      for (int nn = 0; nn < NR; ++nn) Fr[nn] = fr_s[wv][nn][lane];
+      // radial adjoint atil[b][k] = sum_n dE/dq_n ctil[Z_i][b][n][k]
+      const float* cR = params + S::P + (int64_t)Zs * (T * NR * BR);
+#pragma unroll
+      for (int b = 0; b < T; ++b) {
+        float4* row = reinterpret_cast<float4*>(aR + ((int64_t)b * ns + p) * BR);
+#pragma unroll
+        for (int k4 = 0; k4 < BR / 4; ++k4) {
+          float v[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            float acc = 0.f;
+#pragma unroll
+            for (int nn = 0; nn < NR; ++nn) acc = fmaf(Fr[nn], cR[(b * NR + nn) * BR + 4 * k4 + u], acc);
+            v[u] = acc;
+          }
+          row[k4] = make_float4(v[0], v[1], v[2], v[3]);
+        }
       }
     }
   }
-  if (active && qout) {
-    const int i = orig[p];
-#pragma unroll
-    for (int d = 0; d < D; ++d) qout[(int64_t)i * D + d] = q[d];
-  }
-  //  E = b1 + sum_h w1_h tanh(a_h);  z_h = dE/da_h = w1_h (1 - tanh^2)
-  float E = w1g[H];
-  float zt[HP];
-#pragma unroll
-  for (int hg = 0; hg < HP / 4; ++hg)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int h = 4 * hg + r;
-      if (h < H) {
-        const float t = tanh_fast(acc[hg][r]);
-        E = fmaf(w1g[h], t, E);
-        zt[h] = w1g[h] * fmaf(-t, t, 1.0f);
-      } else {
-        zt[h] = 0.f;
-      }
-    }
-  //  backward: dE/dq_d = sum_h z_h W0[h][d], four descriptors per group
-  floatx4 fpa[DP / 4];
-#pragma unroll
-  for (int dg = 0; dg < DP / 4; ++dg) fpa[dg] = floatx4{0.f, 0.f, 0.f, 0.f};
-  {
-    const float* WzT = W0Ts + (Zs * DP + lq) * HP;
-#pragma unroll
-    for (int hg = 0; hg < HP / 4; ++hg) {
-#pragma unroll
-      for (int dg = 0; dg < DP / 4; ++dg) {
-        const float4 w = *reinterpret_cast<const float4*>(WzT + 4 * dg * HP + 4 * hg);
-        fpa[dg] = __builtin_amdgcn_mfma_f32_4x4x1f32(w.x, zt[4 * hg + 0], fpa[dg], 0, 0, 0);
-        fpa[dg] = __builtin_amdgcn_mfma_f32_4x4x1f32(w.y, zt[4 * hg + 1], fpa[dg], 0, 0, 0);
-        fpa[dg] = __builtin_amdgcn_mfma_f32_4x4x1f32(w.z, zt[4 * hg + 2], fpa[dg], 0, 0, 0);
-        fpa[dg] = __builtin_amdgcn_mfma_f32_4x4x1f32(w.w, zt[4 * hg + 3], fpa[dg], 0, 0, 0);
-      }
-    }
-  }
-  float Fp[DP];
-#pragma unroll
-  for (int dg = 0; dg < DP / 4; ++dg)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) Fp[4 * dg + r] = fpa[dg][r];
-  if (!active) return;
-  const int i = orig[p];
-  Ei[i] = E;
-  if (Eproc) Eproc[p] = E;
-  if (!want_adjoint) return;
-#pragma unroll
-  for (int d = NR; d < D; ++d) fp[(int64_t)(d - NR) * n_slots + p] = Fp[d];
-  // radial adjoint atil[b][k] = sum_n dE/dq_n ctil[Z_i][b][n][k]
-  const float* cR = dco + (int64_t)Zs * (T * NR * BR);
-#pragma unroll
-  for (int b = 0; b < T; ++b)
-#pragma unroll
-    for (int kk = 0; kk < BR; ++kk) {
-      float acc = 0.f;
-#pragma unroll
-      for (int nn = 0; nn < NR; ++nn) acc = fmaf(Fp[nn], cR[(b * NR + nn) * BR + kk], acc);
-      aR[((int64_t)b * n_slots + p) * BR + kk] = acc;
-    }
 }
 
 // ----------------------------------------------------------------- k_force
@@ -778,21 +1027,32 @@ __global__ void k_derive(const float* __restrict__ params, float* __restrict__ o
 // ------------------------------------------------------------- launchers
 
 // Kernel variants: (passes over the angular pairs, each for n_A / passes of the
-// angular functions; waves per SIMD the register allocation must allow).
-// Every variant computes the same result;
-// descriptor variants are bitwise identical, force variants differ only in
-// the order the per-group pair forces are added.
+// angular functions; waves per SIMD the register allocation must allow; for
+// the descriptors, network in k_desc or in k_net).  Every variant computes
+// the same result: descriptors are bitwise identical across descriptor
+// variants, site energies within each network form (the two forms sum the
+// network in different orders); force variants differ only in the order the
+// per-group pair forces are added.
+// Blocks of k_net: two per compute unit (its LDS holds two).
+constexpr unsigned kNetBlocks = 2 * 256;
+
 template <class S, int NS>
 constexpr int groups() {
   return NS <= S::NA ? NS : S::NA;
 }
 
-template <class S, int NS, int W>
+template <class S, int NS, int W, bool NET>
 static int launch_desc(hipStream_t st, const NepIO& io, const float* params, bool want_adjoint) {
   const unsigned g = (unsigned)((io.n_slots + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL((k_desc<S, groups<S, NS>(), W>), dim3(g), dim3(kBlock), 0, st, io.n_slots, io.capA, io.pos4,
-                     io.cfg_of, io.orig, io.cfgs, io.nbrR, io.cntR, io.vrev, io.cnR, io.ccR, io.cnA, io.cpA, io.ccA, io.amask, io.flags,
-                     io.cut, params, io.fp, io.aR, io.Ei, io.qout, io.Eproc, want_adjoint ? 1 : 0);
+  hipLaunchKernelGGL((k_desc<S, groups<S, NS>(), W, NET>), dim3(g), dim3(kBlock), 0, st, io.n_slots, io.capA,
+                     io.pos4, io.cfg_of, io.orig, io.cfgs, io.nbrR, io.cntR, io.vrev, io.cnR, io.ccR, io.cnA, io.cpA,
+                     io.ccA, io.amask, io.flags, io.cut, params, io.fp, io.aR, io.Ei, io.qout, io.Eproc,
+                     want_adjoint ? 1 : 0);
+  if constexpr (!NET) {
+    const unsigned gn = g < kNetBlocks ? g : kNetBlocks;
+    hipLaunchKernelGGL(k_net<S>, dim3(gn), dim3(kBlock), 0, st, io.n_slots, io.pos4, io.cfg_of, io.orig, params,
+                       io.fp, io.aR, io.Ei, io.qout, io.Eproc, want_adjoint ? 1 : 0);
+  }
   NEPMI_HIP(hipGetLastError());
   return NEPMI_OK;
 }
@@ -810,10 +1070,14 @@ static int launch_force(hipStream_t st, const NepIO& io, const float* params) {
 template <class S>
 int Launch<S>::desc(hipStream_t st, const NepIO& io, const float* params, bool want_adjoint, int variant) {
   switch (variant) {
-    case 1: return launch_desc<S, 4, 3>(st, io, params, want_adjoint);
-    case 2: return launch_desc<S, 4, 2>(st, io, params, want_adjoint);
-    case 3: return launch_desc<S, 1, 1>(st, io, params, want_adjoint);
-    default: return launch_desc<S, 2, 2>(st, io, params, want_adjoint);
+    case 1: return launch_desc<S, 4, 3, true>(st, io, params, want_adjoint);
+    case 2: return launch_desc<S, 4, 2, true>(st, io, params, want_adjoint);
+    case 3: return launch_desc<S, 1, 1, true>(st, io, params, want_adjoint);
+    case 4: return launch_desc<S, 4, 4, false>(st, io, params, want_adjoint);
+    case 5: return launch_desc<S, 1, 2, false>(st, io, params, want_adjoint);
+    case 6: return launch_desc<S, 2, 2, false>(st, io, params, want_adjoint);
+    case 7: return launch_desc<S, 2, 3, false>(st, io, params, want_adjoint);
+    default: return launch_desc<S, 2, 2, true>(st, io, params, want_adjoint);
   }
 }
 

@@ -61,7 +61,8 @@ struct NepIO {
   float* Eproc;  // [n_slots] site energies in slot order, optional
 };
 
-constexpr int kVariants = 4;  // compiled variants of k_desc and of k_force
+constexpr int kDescVariants = 8;   // compiled variants of k_desc (4..7: network in its own kernel)
+constexpr int kForceVariants = 4;  // compiled variants of k_force
 
 template <class S>
 struct Launch {

@@ -2,7 +2,8 @@
 //
 // k_desc and k_force are compiled in several variants (how many angular
 // functions one pass over the pairs handles, and how many waves per SIMD the
-// register allocation must leave room for).  The best one depends on the
+// register allocation must leave room for; for k_desc also whether the
+// network runs in it or in a kernel of its own).  The best one depends on the
 // model shape and on the pair counts of the workload, so it is measured:
 // every variant runs on the caller's batch (or MD state) with HIP events
 // around it, and the fastest is kept in the model handle.
@@ -18,7 +19,7 @@ int autotune_io(nepmi_model* m, const NepIO& io, hipStream_t st, int reps) {
   int rc = NEPMI_OK;
   double best = 1e300;
   int bd = m->vdesc, bf = m->vforce;
-  for (int v = 0; v < kVariants && !rc; ++v) {
+  for (int v = 0; v < kDescVariants && !rc; ++v) {
     rc = m->ops->desc(st, io, P, true, v);  // warm-up (also code-object load)
     double t = 0.0;
     for (int r = 0; r < reps && !rc; ++r) {
@@ -37,7 +38,7 @@ int autotune_io(nepmi_model* m, const NepIO& io, hipStream_t st, int reps) {
   }
   if (!rc) rc = m->ops->desc(st, io, P, true, bd);
   best = 1e300;
-  for (int v = 0; v < kVariants && !rc; ++v) {
+  for (int v = 0; v < kForceVariants && !rc; ++v) {
     rc = m->ops->force(st, io, P, v);
     double t = 0.0;
     for (int r = 0; r < reps && !rc; ++r) {
@@ -88,7 +89,8 @@ int nepmi_autotune(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, const
 }
 
 int nepmi_set_variants(nepmi_model* m, int32_t desc_variant, int32_t force_variant) {
-  if (!m || desc_variant < 0 || desc_variant >= kVariants || force_variant < 0 || force_variant >= kVariants) {
+  if (!m || desc_variant < 0 || desc_variant >= kDescVariants || force_variant < 0 ||
+      force_variant >= kForceVariants) {
     set_error("variant out of range");
     return NEPMI_INVALID_ARG;
   }

@@ -176,9 +176,11 @@ def test_run_to_run_bitwise(oracle_lib):
 
 @pytest.mark.parametrize("name", ["cubic64_single", "gst_rocksalt_8", "table2_rocksalt_8", "gst_amorphous_batch"])
 def test_every_kernel_variant(evaluated, name):
-    """Each compiled (groups of angular functions, occupancy) variant of the
-    descriptor and force kernels meets the same bar; descriptor variants give
-    bitwise identical descriptors and energies."""
+    """Each compiled (groups of angular functions, occupancy, fused or
+    separate network) variant of the descriptor and force kernels meets the
+    same bar; descriptor variants give bitwise identical descriptors, and
+    bitwise identical energies within each network form (in the kernel,
+    variants 0-3, or in its own kernel, 4-7: the two sum in different orders)."""
     nep = _nep()
     from paper_2607_06969_amd._lib import load
     hpf, sysf, seed = CASES[name]
@@ -186,11 +188,12 @@ def test_every_kernel_variant(evaluated, name):
     _, ref, _, _ = evaluated[name]
     m = nep.NepModel(hp, W.random_params(hp, seed))
     b = nep.Batch.from_system(s)
-    n_var = 4
-    base_q = base_E = None
+    base_q = None
+    base_E = {}
     n_c = np.diff(s.atom_off)
-    for dv in range(n_var):
-        for fv in range(n_var):
+    for dv in range(8):  # 4..7: the network in a kernel of its own
+        form = dv // 4
+        for fv in range(4):
             print(f"[variants] {name} desc={dv} force={fv}", flush=True)
             m.set_variants(dv, fv)
             got = m.compute(b)
@@ -199,10 +202,10 @@ def test_every_kernel_variant(evaluated, name):
             assert rel(got["F"].cpu().numpy(), ref["F"]) <= 1e-5, (dv, fv)
             for c in range(s.n_cfg):
                 assert rel(got["V"][c].cpu().numpy(), ref["V"][c]) <= 1e-5, (dv, fv, c)
-            if base_E is None:
-                base_E = got["E"].clone()
+            if form not in base_E:
+                base_E[form] = got["E"].clone()
             else:
-                assert torch.equal(got["E"], base_E), (dv, fv)
+                assert torch.equal(got["E"], base_E[form]), (dv, fv)
         q = m.descriptors(b)
         if base_q is None:
             base_q = q.clone()
