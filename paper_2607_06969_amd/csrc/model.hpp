@@ -36,7 +36,7 @@ struct TrainBufs {
 
 // Buffers of the float64 variant (see train.hip).
 struct F64Bufs {
-  DevBuf posf, pos4, lam4, ebar1, mu0, Ei, Wi;
+  DevBuf posf, pos4, lam4, ebar1, mu0, Ei, Wi, fA, aR;
   DevBuf Sst, Sdt, q, qd, Pb, Pdn, abar, zneg, gw1, eat, qbR, FpR, GA, part, FpA, qbA;
 };
 

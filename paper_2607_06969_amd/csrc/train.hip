@@ -203,7 +203,9 @@ __global__ void k_lam_slots(int64_t ns, const int* __restrict__ orig, const R* _
 // disjoint outputs, and running them side by side rather than one after
 // another keeps a batch of a few ten thousand atoms from leaving SIMDs idle.
 // PHASE 3 runs on a grid (slot blocks, NA), one angular function per row.
-template <class S, int NC, class R, int PHASE>
+// FWD: forward quantities only (q, S, E_i, dE/dq, sigma), for the float64
+// evaluation: the tangent parts and the second-order adjoint are skipped.
+template <class S, int NC, class R, int PHASE, bool FWD = false>
 __global__ __launch_bounds__(kTB) void k_train_atom(TrainIOT<R> io, CutoffsT<R> cut, const R* __restrict__ params) {
   constexpr int T = S::T, NR = S::NR, NA = S::NA, BR = S::BR, BA = S::BA, L = S::L, K = S::K, D = S::D, H = S::H;
   static_assert(NA % NC == 0, "chunk must divide n_angular");
@@ -253,6 +255,7 @@ __global__ __launch_bounds__(kTB) void k_train_atom(TrainIOT<R> io, CutoffsT<R> 
     for (int b = 0; b < T; ++b)
 #pragma unroll
       for (int k = 0; k < BR; ++k) P[b][k] = Pd[b][k] = R(0);
+    (void)Pd;
     const int n = io.cntR[p];
     walk_groups(reinterpret_cast<const uint4*>(io.nbrR), ns, p, n, io.pos4, lam_of,
                                           [&](int, uint32_t e, Vec4<R> xq, uint32_t, Vec4<R> lj) {
@@ -261,18 +264,27 @@ __global__ __launch_bounds__(kTB) void k_train_atom(TrainIOT<R> io, CutoffsT<R> 
         const R d = sqrt_(v.d2), inv = R(1.0) / d;
         R Q[BR], dQ[BR];
         cheb_basis_d<BR>(d, rcR_inv, Q, dQ);
-        const R tx = lj.x - li.x + mu[0] * v.rx + mu[1] * v.ry + mu[2] * v.rz;
-        const R ty = lj.y - li.y + mu[3] * v.rx + mu[4] * v.ry + mu[5] * v.rz;
-        const R tz = lj.z - li.z + mu[6] * v.rx + mu[7] * v.ry + mu[8] * v.rz;
-        const R ut = (v.rx * tx + v.ry * ty + v.rz * tz) * inv;
+        if constexpr (FWD) {
 #pragma unroll
-        for (int b = 0; b < T; ++b) {
-          const R m = (T == 1 || v.zj == b) ? R(1.0) : R(0.0);
-          const R mut = m * ut;
+          for (int b = 0; b < T; ++b) {
+            const R m = (T == 1 || v.zj == b) ? R(1.0) : R(0.0);
 #pragma unroll
-          for (int kk = 0; kk < BR; ++kk) {
-            P[b][kk] = fma_(m, Q[kk], P[b][kk]);
-            Pd[b][kk] = fma_(mut, dQ[kk], Pd[b][kk]);
+            for (int kk = 0; kk < BR; ++kk) P[b][kk] = fma_(m, Q[kk], P[b][kk]);
+          }
+        } else {
+          const R tx = lj.x - li.x + mu[0] * v.rx + mu[1] * v.ry + mu[2] * v.rz;
+          const R ty = lj.y - li.y + mu[3] * v.rx + mu[4] * v.ry + mu[5] * v.rz;
+          const R tz = lj.z - li.z + mu[6] * v.rx + mu[7] * v.ry + mu[8] * v.rz;
+          const R ut = (v.rx * tx + v.ry * ty + v.rz * tz) * inv;
+#pragma unroll
+          for (int b = 0; b < T; ++b) {
+            const R m = (T == 1 || v.zj == b) ? R(1.0) : R(0.0);
+            const R mut = m * ut;
+#pragma unroll
+            for (int kk = 0; kk < BR; ++kk) {
+              P[b][kk] = fma_(m, Q[kk], P[b][kk]);
+              Pd[b][kk] = fma_(mut, dQ[kk], Pd[b][kk]);
+            }
           }
         }
       }
@@ -289,15 +301,17 @@ __global__ __launch_bounds__(kTB) void k_train_atom(TrainIOT<R> io, CutoffsT<R> 
           ad = fma_(cR[(b * NR + nn) * BR + kk], Pd[b][kk], ad);
         }
       io.q[(int64_t)nn * ns + p] = a;
-      io.qd[(int64_t)nn * ns + p] = ad;
+      if constexpr (!FWD) io.qd[(int64_t)nn * ns + p] = ad;
     }
+    if constexpr (!FWD) {
 #pragma unroll
-    for (int b = 0; b < T; ++b)
+      for (int b = 0; b < T; ++b)
 #pragma unroll
-      for (int kk = 0; kk < BR; ++kk) {
-        io.Pb[(b * BR + kk) * ns + p] = P[b][kk];
-        io.Pdn[(b * BR + kk) * ns + p] = -Pd[b][kk];
-      }
+        for (int kk = 0; kk < BR; ++kk) {
+          io.Pb[(b * BR + kk) * ns + p] = P[b][kk];
+          io.Pdn[(b * BR + kk) * ns + p] = -Pd[b][kk];
+        }
+    }
   }
   // ---- angular: S and Sdot in chunks of NC functions (stored for the adjoint)
   if (blockIdx.y > 0) {
@@ -316,15 +330,28 @@ __global__ __launch_bounds__(kTB) void k_train_atom(TrainIOT<R> io, CutoffsT<R> 
         const R ux = v.rx * inv, uy = v.ry * inv, uz = v.rz * inv;
         R Q[BA], dQ[BA];
         cheb_basis_d<BA>(d, rcA_inv, Q, dQ);
+        R Y[K], Dl[K];
+        real_sph<L>(ux, uy, uz, Y);
+        const R* cl = cA_s + ((Zs * T + v.zj) * NA + h * NC) * BA;
+        if constexpr (FWD) {
+#pragma unroll
+          for (int nn = 0; nn < NC; ++nn) {
+            R g = R(0);
+#pragma unroll
+            for (int kk = 0; kk < BA; ++kk) g = fma_(cl[nn * BA + kk], Q[kk], g);
+#pragma unroll
+            for (int lm = 0; lm < K; ++lm) Sg[nn][lm] = fma_(g, Y[lm], Sg[nn][lm]);
+          }
+          (void)Dl;
+          (void)dQ;
+          return;
+        }
         const R tx = lj.x - li.x + mu[0] * v.rx + mu[1] * v.ry + mu[2] * v.rz;
         const R ty = lj.y - li.y + mu[3] * v.rx + mu[4] * v.ry + mu[5] * v.rz;
         const R tz = lj.z - li.z + mu[6] * v.rx + mu[7] * v.ry + mu[8] * v.rz;
         const R ut = ux * tx + uy * ty + uz * tz;
-        R Y[K], Dl[K];
-        real_sph<L>(ux, uy, uz, Y);
         // grad_r Y_lm . t = grad P_lm . (t - (u.t) u) / d
         real_sph_dir<L>(ux, uy, uz, (tx - ut * ux) * inv, (ty - ut * uy) * inv, (tz - ut * uz) * inv, Dl);
-        const R* cl = cA_s + ((Zs * T + v.zj) * NA + h * NC) * BA;
 #pragma unroll
         for (int nn = 0; nn < NC; ++nn) {
           R g = R(0), gp = R(0);
@@ -348,7 +375,7 @@ __global__ __launch_bounds__(kTB) void k_train_atom(TrainIOT<R> io, CutoffsT<R> 
 #pragma unroll
       for (int lm = 0; lm < K; ++lm) {
         io.Sst[(int64_t)(n * K + lm) * ns + p] = Sg[nn][lm];
-        io.Sdt[(int64_t)(n * K + lm) * ns + p] = Sd[nn][lm];
+        if constexpr (!FWD) io.Sdt[(int64_t)(n * K + lm) * ns + p] = Sd[nn][lm];
       }
       R q1 = R(0), qd1 = R(0);
 #pragma unroll
@@ -360,7 +387,7 @@ __global__ __launch_bounds__(kTB) void k_train_atom(TrainIOT<R> io, CutoffsT<R> 
           sd = fma_(Sg[nn][lm], Sd[nn][lm], sd);
         }
         io.q[(int64_t)(NR + (l - 1) * NA + n) * ns + p] = s;
-        io.qd[(int64_t)(NR + (l - 1) * NA + n) * ns + p] = R(2.0) * sd;
+        if constexpr (!FWD) io.qd[(int64_t)(NR + (l - 1) * NA + n) * ns + p] = R(2.0) * sd;
         if (l == 1) {
           q1 = s;
           qd1 = R(2.0) * sd;
@@ -372,11 +399,11 @@ __global__ __launch_bounds__(kTB) void k_train_atom(TrainIOT<R> io, CutoffsT<R> 
         sym_from_s2(&Sd[nn][3], Ad);
         sym_sq6(A, A2);
         io.q[(int64_t)(S::OFF4 + n) * ns + p] = sym_dot(A2, A);
-        io.qd[(int64_t)(S::OFF4 + n) * ns + p] = R(3.0) * sym_dot(A2, Ad);
+        if constexpr (!FWD) io.qd[(int64_t)(S::OFF4 + n) * ns + p] = R(3.0) * sym_dot(A2, Ad);
       }
       if constexpr (S::F5) {
         io.q[(int64_t)(S::OFF5 + n) * ns + p] = q1 * q1;
-        io.qd[(int64_t)(S::OFF5 + n) * ns + p] = R(2.0) * q1 * qd1;
+        if constexpr (!FWD) io.qd[(int64_t)(S::OFF5 + n) * ns + p] = R(2.0) * q1 * qd1;
       }
     }
   }
@@ -391,7 +418,7 @@ __global__ __launch_bounds__(kTB) void k_train_atom(TrainIOT<R> io, CutoffsT<R> 
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       q[d] = io.q[(int64_t)d * ns + p];
-      qd[d] = io.qd[(int64_t)d * ns + p];
+      qd[d] = FWD ? R(0) : io.qd[(int64_t)d * ns + p];
     }
     R Esite = w1[H];  // E_i = b1 + sum_h w1_h h_h (written by the float64 variant)
     for (int hh = 0; hh < H; ++hh) {
@@ -399,41 +426,44 @@ __global__ __launch_bounds__(kTB) void k_train_atom(TrainIOT<R> io, CutoffsT<R> 
 #pragma unroll
       for (int d = 0; d < D; ++d) {
         a = fma_(W0[hh * D + d], q[d], a);
-        ad = fma_(W0[hh * D + d], qd[d], ad);
+        if constexpr (!FWD) ad = fma_(W0[hh * D + d], qd[d], ad);
       }
       const R t = tanh_(a);
       Esite = fma_(w1[hh], t, Esite);
       const R s2 = R(1.0) - t * t;
       const R z = w1[hh] * s2;
-      io.abar[(int64_t)hh * ns + p] = z * (eb + R(2.0) * t * ad);
+      if constexpr (!FWD) {
+        io.abar[(int64_t)hh * ns + p] = z * (eb + R(2.0) * t * ad);
+        io.gw1[(int64_t)hh * ns + p] = eb * t - s2 * ad;
+      }
       io.zneg[(int64_t)hh * ns + p] = -z;
-      io.gw1[(int64_t)hh * ns + p] = eb * t - s2 * ad;
     }
     if constexpr (sizeof(R) == 8) {
       if (io.Ei) io.Ei[io.orig[p]] = Esite;
     }
   }
-  io.eat[p] = eb;
+  if constexpr (!FWD) io.eat[p] = eb;
   // pass 2: qbar = W0^T abar, Fp = W0^T z
   R qb[D], Fp[D];
 #pragma unroll
   for (int d = 0; d < D; ++d) qb[d] = Fp[d] = R(0);
   for (int hh = 0; hh < H; ++hh) {
-    const R ab = io.abar[(int64_t)hh * ns + p], z = -io.zneg[(int64_t)hh * ns + p];
+    const R z = -io.zneg[(int64_t)hh * ns + p];
+    const R ab = FWD ? R(0) : io.abar[(int64_t)hh * ns + p];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-      qb[d] = fma_(ab, W0[hh * D + d], qb[d]);
+      if constexpr (!FWD) qb[d] = fma_(ab, W0[hh * D + d], qb[d]);
       Fp[d] = fma_(z, W0[hh * D + d], Fp[d]);
     }
   }
 #pragma unroll
   for (int nn = 0; nn < NR; ++nn) {
-    io.qbR[(int64_t)nn * ns + p] = qb[nn];
+    if constexpr (!FWD) io.qbR[(int64_t)nn * ns + p] = qb[nn];
     io.FpR[(int64_t)nn * ns + p] = Fp[nn];
   }
 #pragma unroll
   for (int d = NR; d < D; ++d) {
-    io.qbA[(int64_t)d * ns + p] = qb[d];
+    if constexpr (!FWD) io.qbA[(int64_t)d * ns + p] = qb[d];
     io.FpA[(int64_t)d * ns + p] = Fp[d];
   }
   }  // network
@@ -448,7 +478,7 @@ __global__ __launch_bounds__(kTB) void k_train_atom(TrainIOT<R> io, CutoffsT<R> 
 #pragma unroll
     for (int lm = 0; lm < K; ++lm) {
       Sg[lm] = io.Sst[(int64_t)(n * K + lm) * ns + p];
-      Sd[lm] = io.Sdt[(int64_t)(n * K + lm) * ns + p];
+      Sd[lm] = FWD ? R(0) : io.Sdt[(int64_t)(n * K + lm) * ns + p];
     }
     R g4s[5] = {0, 0, 0, 0, 0}, g4b[5] = {0, 0, 0, 0, 0};
     if constexpr (S::F4) {
@@ -459,7 +489,7 @@ __global__ __launch_bounds__(kTB) void k_train_atom(TrainIOT<R> io, CutoffsT<R> 
       R AAd[9], AdA[9];
       sym_mul_sym(A, Ad, AAd);
       sym_mul_sym(Ad, A, AdA);
-      const R fp4 = Fp_at(S::OFF4 + n), qb4 = qb_at(S::OFF4 + n);
+      const R fp4 = Fp_at(S::OFF4 + n), qb4 = FWD ? R(0) : qb_at(S::OFF4 + n);
       const int ix[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
 #pragma unroll
       for (int x = 0; x < 6; ++x) {
@@ -472,17 +502,17 @@ __global__ __launch_bounds__(kTB) void k_train_atom(TrainIOT<R> io, CutoffsT<R> 
     }
 #pragma unroll
     for (int l = 1; l <= L; ++l) {
-      const R fp3 = Fp_at(NR + (l - 1) * NA + n), qb3 = qb_at(NR + (l - 1) * NA + n);
+      const R fp3 = Fp_at(NR + (l - 1) * NA + n), qb3 = FWD ? R(0) : qb_at(NR + (l - 1) * NA + n);
       R fp5 = R(0), qb5 = R(0);
       if constexpr (S::F5) {
         fp5 = Fp_at(S::OFF5 + n);
-        qb5 = qb_at(S::OFF5 + n);
+        qb5 = FWD ? R(0) : qb_at(S::OFF5 + n);
       }
       R cs = R(2.0) * fp3;   // sigma = cs S
       R cbS = R(2.0) * qb3;  // Sbar = cbS S + cbD Sdot
       R cbD = -R(2.0) * fp3;
       if (S::F5 && l == 1) {
-        const R q1 = io.q[(int64_t)(NR + n) * ns + p], qd1 = io.qd[(int64_t)(NR + n) * ns + p];
+        const R q1 = io.q[(int64_t)(NR + n) * ns + p], qd1 = FWD ? R(0) : io.qd[(int64_t)(NR + n) * ns + p];
         cs += R(4.0) * fp5 * q1;
         cbS += R(4.0) * qb5 * q1 - R(4.0) * fp5 * qd1;
         cbD += -R(4.0) * fp5 * q1;
@@ -496,7 +526,7 @@ __global__ __launch_bounds__(kTB) void k_train_atom(TrainIOT<R> io, CutoffsT<R> 
           sb += g4b[lm - 3];
         }
         io.Sst[(int64_t)(n * K + lm) * ns + p] = sg;
-        io.Sdt[(int64_t)(n * K + lm) * ns + p] = sb;
+        if constexpr (!FWD) io.Sdt[(int64_t)(n * K + lm) * ns + p] = sb;
       }
     }
   }
@@ -951,16 +981,51 @@ __global__ __launch_bounds__(kTT * 8) void k_slot_major64(int64_t ns, int R, con
   }
 }
 
+// Radial adjoint in float64, atil_i[b][k] = sum_n dE_i/dq_n c[Z_i][b][n][k],
+// stored [T][slot][B_R] (the pair kernel reads i's part Z_j and j's part Z_i,
+// 12 contiguous values each, instead of two 8 x 12 coefficient blocks per pair).
+template <class S>
+__global__ __launch_bounds__(kTB) void k_radial_adj64(int64_t ns, const int* __restrict__ cfg_of,
+                                                      const double4* __restrict__ pos4,
+                                                      const double* __restrict__ FpR,
+                                                      const double* __restrict__ params, double* __restrict__ aR) {
+  constexpr int T = S::T, NR = S::NR, BR = S::BR;
+  const int64_t p = (int64_t)blockIdx.x * kTB + threadIdx.x;
+  if (p >= ns || cfg_of[p] < 0) return;
+  const int Zi = species_of(pos4[p]);
+  double fp[NR];
+#pragma unroll
+  for (int n = 0; n < NR; ++n) fp[n] = FpR[(int64_t)n * ns + p];
+#pragma unroll
+  for (int b = 0; b < T; ++b) {
+    const double* c = params + ((int64_t)(Zi * T + b) * NR) * BR;
+#pragma unroll
+    for (int k = 0; k < BR; ++k) {
+      double acc = 0.0;
+#pragma unroll
+      for (int n = 0; n < NR; ++n) acc = fma(fp[n], c[n * BR + k], acc);
+      aR[((int64_t)b * ns + p) * BR + k] = acc;
+    }
+  }
+}
+
 // F_i = sum_j (dE_i/dr_ij - dE_j/dr_ji) (Eq. 3) and the per-atom virial
 // W_i = - sum_j dE_i/dr_ij (x) r_ij, from the per-atom adjoints that the atom
-// pass leaves with zero tangent seeds: FpR = dE/dq (radial) and sigma =
-// dE/dS (sigmaT: its slot-major copy).  Caller order for F and W.
+// pass leaves with zero tangent seeds: the radial adjoint aR (k_radial_adj64)
+// and sigma = dE/dS (sigmaT: its slot-major copy).  Caller order for F and W.
+// Radial pairs take both directions here: dE_i/dd = sum_k atil_i[Z_j][k] dQ_k
+// and dE_j/dd = sum_k atil_j[Z_i][k] dQ_k.  For an angular pair only i's own derivative dE_i/dr_ij is formed
+// (from i's sigma row) and kept at the pair's position in the angular part of
+// i's list; k_gather_force64 then subtracts the partners' own derivatives,
+// found through the reverse index, so no pair reads a neighbour's sigma row.
 template <class S>
 __global__ __launch_bounds__(kTB) void k_pair_force64(TrainIOT<double> io, CutoffsT<double> cut,
                                                       const double* __restrict__ params,
-                                                      const double* __restrict__ sigmaT, double* __restrict__ F,
-                                                      double* __restrict__ W) {
-  constexpr int T = S::T, NR = S::NR, BR = S::BR;
+                                                      const double* __restrict__ sigmaT,
+                                                      const double* __restrict__ aR,
+                                                      const uint32_t* __restrict__ vrev, double4* __restrict__ fA,
+                                                      double* __restrict__ F, double* __restrict__ W) {
+  constexpr int BR = S::BR;
   const int64_t ns = io.ns;
   const int64_t p = (int64_t)blockIdx.x * kTB + threadIdx.x;
   if (p >= ns) return;
@@ -972,67 +1037,77 @@ __global__ __launch_bounds__(kTB) void k_pair_force64(TrainIOT<double> io, Cutof
   double Hc[9];
   load_cell9(io.cfgs, c, Hc);
   const double rcR_inv = 1.0 / cut.rcR, rcA_inv = 1.0 / cut.rcA;
-  double fpi[NR];
-#pragma unroll
-  for (int n = 0; n < NR; ++n) fpi[n] = io.FpR[(int64_t)n * ns + p];
   double Fx = 0.0, Fy = 0.0, Fz = 0.0, Wm[9];
 #pragma unroll
   for (int x = 0; x < 9; ++x) Wm[x] = 0.0;
   const double* cA = params + S::PCR;
   const int n = io.cntR[p];
+  int ka = 0;  // position in the angular part of the list
   for (int k = 0; k < n; ++k) {
-    const PV<double> v = pvec(io.pos4, io.nbrR[group_index(ns, p, k)], xi, Hc);
-    if (!(v.d2 < cut.rcR2)) continue;
-    const double d = sqrt(v.d2);
-    const double ux = v.rx / d, uy = v.ry / d, uz = v.rz / d;
-    // radial: dE_i/dd and dE_j/dd through q_n = sum_j sum_k c[Zi][Zj][n][k] Q_k
-    double Q[BR], dQ[BR];
-    cheb_basis_d<BR>(d, rcR_inv, Q, dQ);
-    const double* ci = params + ((int64_t)(Zi * T + v.zj) * NR) * BR;
-    const double* cj = params + ((int64_t)(v.zj * T + Zi) * NR) * BR;
-    // the neighbour's dE/dq_R, all rows loaded together (one memory latency)
-    double fpj[NR];
-#pragma unroll
-    for (int nn = 0; nn < NR; ++nn) fpj[nn] = io.FpR[(int64_t)nn * ns + v.q];
-    double own = 0.0, rev = 0.0;
-#pragma unroll
-    for (int nn = 0; nn < NR; ++nn) {
-      double gi = 0.0, gj = 0.0;
+    const int64_t gk = group_index(ns, p, k);
+    const bool in_ang_part = vrev[gk] != 0xFFFFFFFFu;
+    const PV<double> v = pvec(io.pos4, io.nbrR[gk], xi, Hc);
+    double ax = 0.0, ay = 0.0, az = 0.0;  // dE_i/dr_ij of the angular descriptors
+    if (v.d2 < cut.rcR2) {
+      const double d = sqrt(v.d2);
+      const double ux = v.rx / d, uy = v.ry / d, uz = v.rz / d;
+      // radial: dE_i/dd and dE_j/dd through the two adjoint rows
+      double Q[BR], dQ[BR];
+      cheb_basis_d<BR>(d, rcR_inv, Q, dQ);
+      const double* ai = aR + ((int64_t)v.zj * ns + p) * BR;
+      const double* aj = aR + ((int64_t)Zi * ns + v.q) * BR;
+      double own = 0.0, rev = 0.0;
 #pragma unroll
       for (int kk = 0; kk < BR; ++kk) {
-        gi = fma(ci[nn * BR + kk], dQ[kk], gi);
-        gj = fma(cj[nn * BR + kk], dQ[kk], gj);
+        own = fma(ai[kk], dQ[kk], own);
+        rev = fma(aj[kk], dQ[kk], rev);
       }
-      own = fma(fpi[nn], gi, own);
-      rev = fma(fpj[nn], gj, rev);
-    }
-    double fx = own * ux, fy = own * uy, fz = own * uz;  // dE_i/dr_ij
-    double bx = -rev * ux, by = -rev * uy, bz = -rev * uz;  // dE_j/dr_ji (r_ji = -r_ij)
-    if (v.d2 < cut.rcA2) {
-      double ax, ay, az, cx, cy, cz;
-      angular_pair_grad<S>(sigmaT, p, cA, Zi, v.zj, ux, uy, uz, d, rcA_inv, ax, ay, az);
-      angular_pair_grad<S>(sigmaT, v.q, cA, v.zj, Zi, -ux, -uy, -uz, d, rcA_inv, cx, cy, cz);
-      fx += ax;
-      fy += ay;
-      fz += az;
-      bx += cx;
-      by += cy;
-      bz += cz;
-    }
-    Fx += fx - bx;
-    Fy += fy - by;
-    Fz += fz - bz;
-    const double f[3] = {fx, fy, fz}, r[3] = {v.rx, v.ry, v.rz};
+      if (v.d2 < cut.rcA2) angular_pair_grad<S>(sigmaT, p, cA, Zi, v.zj, ux, uy, uz, d, rcA_inv, ax, ay, az);
+      const double fx = own * ux + ax, fy = own * uy + ay, fz = own * uz + az;  // dE_i/dr_ij
+      // minus dE_j/dr_ji of the radial descriptors (r_ji = -r_ij)
+      Fx += fx + rev * ux;
+      Fy += fy + rev * uy;
+      Fz += fz + rev * uz;
+      const double f[3] = {fx, fy, fz}, r[3] = {v.rx, v.ry, v.rz};
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
+      for (int a = 0; a < 3; ++a)
 #pragma unroll
-      for (int b = 0; b < 3; ++b) Wm[3 * a + b] -= f[a] * r[b];
+        for (int b = 0; b < 3; ++b) Wm[3 * a + b] -= f[a] * r[b];
+    }
+    if (in_ang_part) fA[(int64_t)ka++ * ns + p] = make_double4(ax, ay, az, 0.0);
   }
   F[3 * (int64_t)i] = Fx;
   F[3 * (int64_t)i + 1] = Fy;
   F[3 * (int64_t)i + 2] = Fz;
 #pragma unroll
   for (int x = 0; x < 9; ++x) W[9 * (int64_t)i + x] = Wm[x];
+}
+
+// F_i -= sum_j dE_j/dr_ji over the angular part of i's list: the partner's
+// own derivative sits at i's position in the angular part of j's list.
+__global__ __launch_bounds__(kTB) void k_gather_force64(int64_t ns, const int* __restrict__ cfg_of,
+                                                        const int* __restrict__ orig,
+                                                        const uint32_t* __restrict__ nbrR,
+                                                        const int* __restrict__ cntR,
+                                                        const uint32_t* __restrict__ vrev,
+                                                        const double4* __restrict__ fA, double* __restrict__ F) {
+  const int64_t p = (int64_t)blockIdx.x * kTB + threadIdx.x;
+  if (p >= ns || cfg_of[p] < 0) return;
+  const int i = orig[p];
+  double Fx = 0.0, Fy = 0.0, Fz = 0.0;
+  const int n = cntR[p];
+  for (int k = 0; k < n; ++k) {
+    const int64_t gk = group_index(ns, p, k);
+    const uint32_t r = vrev[gk];
+    if (r == 0xFFFFFFFFu) continue;
+    const double4 b = fA[(int64_t)r * ns + (nbrR[gk] & kNbrMask)];
+    Fx -= b.x;
+    Fy -= b.y;
+    Fz -= b.z;
+  }
+  F[3 * (int64_t)i] += Fx;
+  F[3 * (int64_t)i + 1] += Fy;
+  F[3 * (int64_t)i + 2] += Fz;
 }
 
 // ------------------------------------------------------------ launchers
@@ -1102,15 +1177,23 @@ int TrainLaunch<S>::forward64(hipStream_t st, TrainIOT<double> io, const Cutoffs
   hipLaunchKernelGGL(k_fill64, dim3(blocks(4 * ns, 256)), dim3(256), 0, st, 4 * ns, 0.0,
                      reinterpret_cast<double*>(io.lam4));
   constexpr int NC = S::NA >= 4 ? 2 : 1;
-  hipLaunchKernelGGL((k_train_atom<S, NC, double, 1>), dim3(blocks(ns, kTB), 1 + S::NA / NC), dim3(kTB), 0, st, io, cut, a.params);
-  hipLaunchKernelGGL((k_train_atom<S, NC, double, 2>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params);
-  hipLaunchKernelGGL((k_train_atom<S, NC, double, 3>), dim3(blocks(ns, kTB), S::NA), dim3(kTB), 0, st, io, cut, a.params);
+  hipLaunchKernelGGL((k_train_atom<S, NC, double, 1, true>), dim3(blocks(ns, kTB), 1 + S::NA / NC), dim3(kTB), 0, st,
+                     io, cut, a.params);
+  hipLaunchKernelGGL((k_train_atom<S, NC, double, 2, true>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut,
+                     a.params);
+  hipLaunchKernelGGL((k_train_atom<S, NC, double, 3, true>), dim3(blocks(ns, kTB), S::NA), dim3(kTB), 0, st, io, cut,
+                     a.params);
   // sigma, slot-major, into the Sdot buffer (free once the dE/dS pass is done;
   // the backward recomputes it)
   hipLaunchKernelGGL(k_slot_major64, dim3(blocks(ns, kTT), (S::NA * S::K + kTT - 1) / kTT), dim3(kTT * 8), 0, st, ns,
                      S::NA * S::K, io.Sst, io.Sdt);
-  hipLaunchKernelGGL((k_pair_force64<S>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params, io.Sdt, forces,
-                     a.Wi);
+  // the radial adjoint rows of every atom
+  hipLaunchKernelGGL((k_radial_adj64<S>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, ns, io.cfg_of, io.pos4, io.FpR,
+                     a.params, a.aR);
+  hipLaunchKernelGGL((k_pair_force64<S>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params, io.Sdt, a.aR,
+                     a.vrev, a.fA, forces, a.Wi);
+  hipLaunchKernelGGL(k_gather_force64, dim3(blocks(ns, kTB)), dim3(kTB), 0, st, ns, io.cfg_of, io.orig, io.nbrR,
+                     io.cntR, a.vrev, a.fA, forces);
   NEPMI_HIP(hipGetLastError());
   return NEPMI_OK;
 }

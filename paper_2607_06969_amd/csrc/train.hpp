@@ -79,6 +79,9 @@ struct F64Args {
   const double* params;     // device [P], the parameter layout of the model
   double4* pos4;            // work: [ns] positions in slot order
   double* Wi;               // work: [N][9] per-atom virial, caller order
+  const uint32_t* vrev;     // reverse index of the Verlet list (grouped as the list)
+  double4* fA;              // work: [capA][ns] dE_i/dr_ij of the angular part of i's list, by position
+  double* aR;               // work: [T][ns][BR] radial adjoint rows
 };
 
 template <class S>

@@ -93,7 +93,9 @@ int ensure_f64(nepmi_model* m) {
       (rc = f.abar.ensure(8 * ns * o->H)) || (rc = f.zneg.ensure(8 * ns * o->H)) || (rc = f.gw1.ensure(8 * ns * o->H)) ||
       (rc = f.eat.ensure(8 * ns)) || (rc = f.qbR.ensure(8 * ns * o->NR)) || (rc = f.FpR.ensure(8 * ns * o->NR)) ||
       (rc = f.GA.ensure(8 * ns * o->T * o->NA * o->BA)) || (rc = f.part.ensure(8 * (size_t)o->T * kRBlocks * sumE)) ||
-      (rc = f.FpA.ensure(8 * ns * o->D)) || (rc = f.qbA.ensure(8 * ns * o->D)))
+      (rc = f.FpA.ensure(8 * ns * o->D)) || (rc = f.qbA.ensure(8 * ns * o->D)) ||
+      (rc = f.fA.ensure(32 * ns * (size_t)(m->nbr.capA > 0 ? m->nbr.capA : 1))) ||
+      (rc = f.aR.ensure(8 * ns * o->T * o->BR)))
     return rc;
   return NEPMI_OK;
 }
@@ -169,6 +171,9 @@ int prepare64(nepmi_model* m, int n_cfg, const int64_t* atom_off, const double* 
   a.params = dev_params;
   a.pos4 = m->f64.pos4.ptr<double4>();
   a.Wi = m->f64.Wi.ptr<double>();
+  a.vrev = m->nbr.vrev.ptr<uint32_t>();
+  a.fA = m->f64.fA.ptr<double4>();
+  a.aR = m->f64.aR.ptr<double>();
   return launch_stage64(st, f64_io(m, nullptr, nullptr, nullptr), a, m->nbr.pos4.ptr<float4>());
 }
 
