@@ -13,11 +13,28 @@ struct PairVec {
   int q, zj;
 };
 
-__device__ __forceinline__ PairVec pair_vec(uint32_t e, float4 xq, float4 xi, const float (&H)[9]) {
+// Lattice-vector multiples (w0, w1, w2) of the 27 image codes (see
+// image_shift), in LDS: one read per pair instead of the integer decode.
+struct ImageTable {
+  float4 w[32];
+  __device__ void fill() {
+    if (threadIdx.x < 27) {
+      const int c = threadIdx.x;
+      w[c] = make_float4((float)(c / 9 - 1), (float)((c / 3) % 3 - 1), (float)(c % 3 - 1), 0.f);
+    }
+  }
+};
+
+__device__ __forceinline__ PairVec pair_vec(uint32_t e, float4 xq, float4 xi, const float (&H)[9],
+                                            const ImageTable& it) {
   PairVec v;
   v.q = (int)(e & kNbrMask);
-  float sx, sy, sz;
-  image_shift(H, e >> kNbrShift, sx, sy, sz);
+  // the same expression as image_shift, so the shift of code 26 - c is again
+  // exactly the negative of the shift of c
+  const float4 w = it.w[e >> kNbrShift];
+  const float sx = w.x * H[0] + w.y * H[3] + w.z * H[6];
+  const float sy = w.x * H[1] + w.y * H[4] + w.z * H[7];
+  const float sz = w.x * H[2] + w.y * H[5] + w.z * H[8];
   v.rx = (xq.x - xi.x) + sx;
   v.ry = (xq.y - xi.y) + sy;
   v.rz = (xq.z - xi.z) + sz;
@@ -104,7 +121,8 @@ __device__ __forceinline__ float tr_cube(const float (&A)[6]) {
 template <class S, int NH>
 __device__ __forceinline__ void angular_sums(const float4* __restrict__ pos4, const uint32_t* __restrict__ cnA,
                                              int64_t n_slots, int64_t p, int nA, float4 xi, const float (&Hc)[9],
-                                             const float* cl0, float rcA_inv, float (&Sg)[NH][S::K]) {
+                                             const ImageTable& it, const float* cl0, float rcA_inv,
+                                             float (&Sg)[NH][S::K]) {
   constexpr int T = S::T, NA = S::NA, BA = S::BA, L = S::L, K = S::K;
 #pragma unroll
   for (int nn = 0; nn < NH; ++nn)
@@ -112,7 +130,7 @@ __device__ __forceinline__ void angular_sums(const float4* __restrict__ pos4, co
     for (int lm = 0; lm < K; ++lm) Sg[nn][lm] = 0.f;
   walk_groups(reinterpret_cast<const uint4*>(cnA), n_slots, p, nA, pos4, NoPre{},
               [&](int, uint32_t e, float4 xq, uint32_t, int) {
-    const PairVec v = pair_vec(e, xq, xi, Hc);
+    const PairVec v = pair_vec(e, xq, xi, Hc, it);
     const float inv = rsqrt_hw(v.d2);
     const RadialF f = radial_f(v.d2 * inv * rcA_inv);
     float Tk[BA];
@@ -309,6 +327,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
   constexpr int HP = MlpPad<S>::HP, DP = MlpPad<S>::DP;
   const float* __restrict__ dco = params + S::P;  // derived coefficients: radial, then angular
   __shared__ float cA_s[T * T * NA * BA];
+  __shared__ ImageTable itab;
   __shared__ float W0s[NET ? T * HP * DP : 1];   // [Z][h][d] network weights, zero padded
   __shared__ float W0Ts[NET ? T * DP * HP : 1];  // [Z][d][h] the same, transposed
 
@@ -320,6 +339,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
   const float4 xi = pos4[pc];
   const int Zs = __builtin_amdgcn_readfirstlane(__float_as_int(xi.w));
   for (int t = threadIdx.x; t < T * T * NA * BA; t += kBlock) cA_s[t] = dco[S::PCR + t];
+  itab.fill();
   if constexpr (NET) {
     load_weights<S>(params, pos4, n_slots, p, W0s, W0Ts);
   } else {
@@ -357,7 +377,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
     int ka = 0;  // position in the angular part of the list
     walk_groups<true>(reinterpret_cast<const uint4*>(nbrR), n_slots, p, n, pos4, NoPre{},
                       [&](int, uint32_t e, float4 xq, uint32_t rvk, int) {
-      const PairVec v = pair_vec(e, xq, xi, Hc);
+      const PairVec v = pair_vec(e, xq, xi, Hc, itab);
       const bool in_ang_part = rvk != 0xFFFFFFFFu;
       if (v.d2 < cut.rcR2) {
         put4(gr, nR & 3, e);
@@ -446,7 +466,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
 #pragma unroll
   for (int h = 0; h < NSPLIT; ++h) {
     float Sg[NH][K];
-    angular_sums<S, NH>(pos4, cnA, n_slots, p, nA, xi, Hc, cA_s + (Zs * T * NA + h * NH) * BA, rcA_inv, Sg);
+    angular_sums<S, NH>(pos4, cnA, n_slots, p, nA, xi, Hc, itab, cA_s + (Zs * T * NA + h * NH) * BA, rcA_inv, Sg);
     // invariants of this group
 #pragma unroll
     for (int nn = 0; nn < NH; ++nn) {
@@ -687,7 +707,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
   const float* __restrict__ dco = params + S::P;
   __shared__ float cA_s[T * T * NA * BA];
   __shared__ float aown_s[T > 1 ? kBlock * RW : 1];
+  __shared__ ImageTable itab;
   for (int t = threadIdx.x; t < T * T * NA * BA; t += kBlock) cA_s[t] = dco[S::PCR + t];
+  itab.fill();
   __syncthreads();
 
   const int64_t p = xcd_tile() * kBlock + threadIdx.x;
@@ -735,7 +757,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
     };
     walk_groups(reinterpret_cast<const uint4*>(cnR), n_slots, p, n, pos4, row,
                 [&](int, uint32_t e, float4 xq, uint32_t, const AdjRow<BR>& arow) {
-      const PairVec v = pair_vec(e, xq, xi, Hc);
+      const PairVec v = pair_vec(e, xq, xi, Hc, itab);
       const float* ar = reinterpret_cast<const float*>(arow.v);
       const float inv = rsqrt_hw(v.d2);
       const RadialFD f = radial_fd(v.d2 * inv * rcR_inv, rcR_inv);
@@ -785,7 +807,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
     const float* cl0 = cA_s + (Zs * T * NA + h * NH) * BA;
     // recompute S for this group
     float Sg[NH][K];
-    angular_sums<S, NH>(pos4, cnA, n_slots, p, nA, xi, Hc, cl0, rcA_inv, Sg);
+    angular_sums<S, NH>(pos4, cnA, n_slots, p, nA, xi, Hc, itab, cl0, rcA_inv, Sg);
     // sigma = dE_i/dS for this group (in place), then scaled by kappa so that
     // the pair loop works with the unnormalised polynomials
 #pragma unroll
@@ -840,7 +862,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
     };
     walk_groups(reinterpret_cast<const uint4*>(cnA), n_slots, p, nA, pos4, prev,
                 [&](int, uint32_t e, float4 xq, uint32_t, float4 o) {
-      const PairVec v = pair_vec(e, xq, xi, Hc);
+      const PairVec v = pair_vec(e, xq, xi, Hc, itab);
       const float inv = rsqrt_hw(v.d2);
       const float ux = v.rx * inv, uy = v.ry * inv, uz = v.rz * inv;
       const RadialFD f = radial_fd(v.d2 * inv * rcA_inv, rcA_inv);
