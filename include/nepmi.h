@@ -163,21 +163,28 @@ int nepmi_neighbors(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, cons
                     int32_t *dev_count, int32_t *dev_nbr, float *dev_rvec, void *stream);
 
 /* Kernel variants.  The descriptor and pair-force kernels are compiled in
- * several variants (angular functions handled per pass over the pairs, the
- * register budget they keep to, and for the descriptors whether the network
- * runs in the same kernel (0..3) or in one of its own on dense 16x16x4
- * matrix products (4..7)); all compute the same result (descriptors bitwise
- * across descriptor variants, energies bitwise within each network form and
- * up to float32 summation order across them; force variants up to float32
- * summation order).  nepmi_autotune times every variant on the given batch
+ * several variants: angular functions handled per pass over the pairs, the
+ * register budget they keep to, the block size (256 threads unless stated),
+ * and for the descriptors whether the network runs in the same kernel or in
+ * one of its own on dense 16x16x4 matrix products.  Descriptor variants:
+ * 0..3 network in the kernel, 4..7 network apart, 8 and 9 variant 0 in
+ * blocks of 128 and 512 threads.  Force variants: 0..3, and 4 and 5 variant 0
+ * in blocks of 128 and 512.  The gather runs in blocks of 256, 128, 512 or
+ * 1024 threads (gather variants 0..3).  All compute the same result:
+ * descriptors bitwise across descriptor variants, energies bitwise within
+ * each network form and up to float32 summation order across them, forces
+ * up to float32 summation order across force variants and bitwise across
+ * gather variants.  nepmi_autotune times every variant on the given batch
  * and keeps the fastest in the model; chosen = host int32[2] (descriptor,
- * force) or NULL.  Synchronises `stream`.  nepmi_set_variants pins a choice
- * (descriptor 0..7, force 0..3);
- * nepmi_md_create autotunes on its initial state unless a choice is pinned. */
+ * force) or NULL.  Synchronises `stream`.  nepmi_set_variants and
+ * nepmi_set_gather_variant pin a choice; nepmi_md_create autotunes on its
+ * initial state unless a choice is pinned. */
 int nepmi_autotune(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, const double *cells, const int32_t *pbc,
                    const float *dev_pos, const int32_t *dev_species, int32_t *chosen, void *stream);
 int nepmi_set_variants(nepmi_model *m, int32_t desc_variant, int32_t force_variant);
 int nepmi_get_variants(nepmi_model *m, int32_t *desc_variant, int32_t *force_variant);
+int nepmi_set_gather_variant(nepmi_model *m, int32_t gather_variant);
+int nepmi_get_gather_variant(nepmi_model *m, int32_t *gather_variant);
 
 /* Vector-Jacobian product of (E, F, V) with respect to the parameters:
  *   dev_grad[p] = sum_c ebar_c dE_c/dtheta_p + sum_i lambda_i . dF_i/dtheta_p

@@ -59,6 +59,8 @@ SIGNATURES = [
     ("nepmi_autotune", C.c_int, [_vp, _i32, _i64p, _dp, _i32p, _vp, _vp, C.POINTER(C.c_int32), _vp]),
     ("nepmi_set_variants", C.c_int, [_vp, _i32, _i32]),
     ("nepmi_get_variants", C.c_int, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    ("nepmi_set_gather_variant", C.c_int, [_vp, _i32]),
+    ("nepmi_get_gather_variant", C.c_int, [_vp, C.POINTER(C.c_int32)]),
     ("nepmi_backward_params", C.c_int, [_vp, _i32, _i64p, _dp, _i32p, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     ("nepmi_loss_grad", C.c_int, [_vp, _i32, _i64p, _dp, _i32p, _vp, _vp, _vp, _vp, _vp, _dp, _i32, _vp, _vp, _vp]),
     ("nepmi_md_create", C.c_int, [_vp, _i32, _i64p, _dp, _i32p, _vp, _vp, _vp, _dp, _d, _d, C.POINTER(_vp), _vp]),

@@ -135,7 +135,7 @@ int run_eval(EvalWork& w, const nepmi_model* m, float* dev_forces, double* dev_e
   const float* P = m->params.ptr<float>();
   int rc;
   if ((rc = m->ops->desc(st, io, P, true, m->vdesc)) || (rc = m->ops->force(st, io, P, m->vforce)) ||
-      (rc = m->ops->gather(st, io)))
+      (rc = m->ops->gather(st, io, m->vgather)))
     return rc;
   if ((rc = w.red.run(st, io.Ei, io.Wi, nullptr, dev_energy, dev_virial, nullptr))) return rc;
   const size_t N = (size_t)w.nbr.N;

@@ -305,7 +305,7 @@ struct nepmi_md {
     if (timed) mark(1, st);
     if ((rc = m->ops->force(st, o, P, m->vforce))) return rc;
     if (timed) mark(2, st);
-    if ((rc = m->ops->gather(st, o))) return rc;
+    if ((rc = m->ops->gather(st, o, m->vgather))) return rc;
     if (timed) mark(3, st);
     return NEPMI_OK;
   }
@@ -705,7 +705,7 @@ int nepmi_md_time_kernels(nepmi_md* md, int32_t reps, double* ms, void* stream) 
     NEPMI_HIP(hipEventRecord(ev[1], st));
     if (!rc) rc = md->m->ops->force(st, o, P, md->m->vforce);
     NEPMI_HIP(hipEventRecord(ev[2], st));
-    if (!rc) rc = md->m->ops->gather(st, o);
+    if (!rc) rc = md->m->ops->gather(st, o, md->m->vgather);
     NEPMI_HIP(hipEventRecord(ev[3], st));
     // a full list rebuild on the current state (sort + lists)
     hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, md->nbr.flags.ptr<int>() + kFlagRebuild, 1);

@@ -13,7 +13,7 @@ namespace nepmi {
 struct Ops {
   int (*desc)(hipStream_t, const NepIO&, const float*, bool, int);
   int (*force)(hipStream_t, const NepIO&, const float*, int);
-  int (*gather)(hipStream_t, const NepIO&);
+  int (*gather)(hipStream_t, const NepIO&, int);
   int (*derive)(hipStream_t, float*);
   int (*seeds)(hipStream_t, const TrainSeedArgs&);
   int (*backward)(hipStream_t, TrainIO, const Cutoffs&, const float*, const float*, const int*, double*, double*,
@@ -75,6 +75,7 @@ struct nepmi_model : nepmi::EvalWork {
   nepmi::F64Bufs f64;
   int device = 0;
   int vdesc = 0, vforce = 0;  // kernel variants in use (see nepmi_autotune)
+  int vgather = 0;            // block size of the gather (see kGatherVariants)
   bool pinned = false;        // variants chosen by nepmi_set_variants: MD creation keeps them
   // Prepare the batch: neighbour lists (pairs within the cutoffs + skin),
   // work buffers and reduction plan.  With reuse_lists set and may_reuse, a

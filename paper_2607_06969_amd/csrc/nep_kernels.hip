@@ -164,7 +164,7 @@ __device__ __forceinline__ void angular_sums(const float4* __restrict__ pos4, co
 // First-layer weights of the species this block's wavefronts hold (each
 // wavefront is uniform) into LDS, zero padded, as [Z][h][d] and transposed
 // [Z][d][h].  Every thread of the block must call it (it ends with a barrier).
-template <class S>
+template <class S, int BS>
 __device__ __forceinline__ void load_weights(const float* __restrict__ params, const float4* __restrict__ pos4,
                                              int64_t n_slots, int64_t p, float* W0s, float* W0Ts) {
   constexpr int T = S::T, D = S::D, H = S::H;
@@ -172,14 +172,14 @@ __device__ __forceinline__ void load_weights(const float* __restrict__ params, c
   const int64_t b0 = p - threadIdx.x;
   unsigned need = 0;
 #pragma unroll
-  for (int w = 0; w < kBlock / kWave; ++w) {
+  for (int w = 0; w < BS / kWave; ++w) {
     const int64_t s0 = b0 + w * kWave;
     need |= 1u << __float_as_int(pos4[s0 < n_slots ? s0 : n_slots - 1].w);
   }
   for (int z = 0; z < T; ++z) {
     if (!(need >> z & 1u)) continue;
     const float* W0g = params + S::PCR + S::PCA + (int64_t)z * S::PMLP;
-    for (int t = threadIdx.x; t < HP * DP; t += kBlock) {
+    for (int t = threadIdx.x; t < HP * DP; t += BS) {
       const int h = t / DP, d = t % DP;
       const float w = (h < H && d < D) ? W0g[h * D + d] : 0.0f;
       W0s[(z * HP + h) * DP + d] = w;
@@ -312,8 +312,8 @@ __device__ __forceinline__ void network(const float (&q)[MlpPad<S>::DP], int Zs,
 // network weights in LDS and fewer registers, so more wavefronts share a
 // compute unit during the pair walks, and k_net runs the network as dense
 // products; it pays one extra write and read of the descriptors.
-template <class S, int NSPLIT, int WPE, bool NET>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) void k_desc(
+template <class S, int NSPLIT, int WPE, bool NET, int BS = kBlock>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(WPE))) void k_desc(
     int64_t n_slots, int capA, const float4* __restrict__ pos4, const int* __restrict__ cfg_of,
     const int* __restrict__ orig, const CfgDev* __restrict__ cfgs, const uint32_t* __restrict__ nbrR,
     const int* __restrict__ cntR, const uint32_t* __restrict__ vrev, uint32_t* __restrict__ cnR, int* __restrict__ ccR,
@@ -333,15 +333,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
 
   // Every lane of a wavefront takes part in the matrix instructions of the
   // network, so lanes past the last slot stay alive as inactive atoms.
-  const int64_t p = xcd_tile() * kBlock + threadIdx.x;
+  const int64_t p = xcd_tile() * BS + threadIdx.x;
   const bool in_range = p < n_slots;
   const int64_t pc = in_range ? p : n_slots - 1;
   const float4 xi = pos4[pc];
   const int Zs = __builtin_amdgcn_readfirstlane(__float_as_int(xi.w));
-  for (int t = threadIdx.x; t < T * T * NA * BA; t += kBlock) cA_s[t] = dco[S::PCR + t];
+  for (int t = threadIdx.x; t < T * T * NA * BA; t += BS) cA_s[t] = dco[S::PCR + t];
   itab.fill();
   if constexpr (NET) {
-    load_weights<S>(params, pos4, n_slots, p, W0s, W0Ts);
+    load_weights<S, BS>(params, pos4, n_slots, p, W0s, W0Ts);
   } else {
     __syncthreads();
   }
@@ -692,8 +692,8 @@ constexpr int lds_row() {
   return ((W + 3) / 4) % 2 ? ((W + 3) / 4) * 4 : ((W + 3) / 4 + 1) * 4;
 }
 
-template <class S, int NSPLIT, int WPE>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) void k_force(
+template <class S, int NSPLIT, int WPE, int BS = kBlock>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(WPE))) void k_force(
     int64_t n_slots, const float4* __restrict__ pos4, const int* __restrict__ cfg_of,
     const int* __restrict__ orig, const CfgDev* __restrict__ cfgs, const uint32_t* __restrict__ cnR,
     const int* __restrict__ ccR, const uint32_t* __restrict__ cnA, const int* __restrict__ ccA, Cutoffs cut, const float* __restrict__ params, const float* __restrict__ fp,
@@ -706,13 +706,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
   constexpr int RW = lds_row<T * BR>();
   const float* __restrict__ dco = params + S::P;
   __shared__ float cA_s[T * T * NA * BA];
-  __shared__ float aown_s[T > 1 ? kBlock * RW : 1];
+  __shared__ float aown_s[T > 1 ? BS * RW : 1];
   __shared__ ImageTable itab;
-  for (int t = threadIdx.x; t < T * T * NA * BA; t += kBlock) cA_s[t] = dco[S::PCR + t];
+  for (int t = threadIdx.x; t < T * T * NA * BA; t += BS) cA_s[t] = dco[S::PCR + t];
   itab.fill();
   __syncthreads();
 
-  const int64_t p = xcd_tile() * kBlock + threadIdx.x;
+  const int64_t p = xcd_tile() * BS + threadIdx.x;
   if (p >= n_slots) return;
   const float4 xi = pos4[p];
   const int Zs = __builtin_amdgcn_readfirstlane(__float_as_int(xi.w));
@@ -960,12 +960,13 @@ __device__ __forceinline__ void gather_masks(GatherStage& st, const uint64_t* __
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_gather(int64_t n_slots, const int* __restrict__ orig,
+template <int BS>
+__global__ __launch_bounds__(BS) void k_gather(int64_t n_slots, const int* __restrict__ orig,
                                                    const uint32_t* __restrict__ cnA, const uint32_t* __restrict__ cpA,
                                                    const int* __restrict__ ccA, const uint64_t* __restrict__ amask,
                                                    const float4* __restrict__ frad, const float4* __restrict__ fA,
                                                    float* __restrict__ Fuser, float4* __restrict__ Fproc) {
-  const int64_t p = xcd_tile() * kBlock + threadIdx.x;
+  const int64_t p = xcd_tile() * BS + threadIdx.x;
   if (p >= n_slots) return;
   const int i = orig[p];
   if (i < 0) {
@@ -1050,7 +1051,8 @@ __global__ void k_derive(const float* __restrict__ params, float* __restrict__ o
 
 // Kernel variants: (passes over the angular pairs, each for n_A / passes of the
 // angular functions; waves per SIMD the register allocation must allow; for
-// the descriptors, network in k_desc or in k_net).  Every variant computes
+// the descriptors, network in k_desc or in k_net; block size, 256 threads
+// unless stated).  Every variant computes
 // the same result: descriptors are bitwise identical across descriptor
 // variants, site energies within each network form (the two forms sum the
 // network in different orders); force variants differ only in the order the
@@ -1063,15 +1065,16 @@ constexpr int groups() {
   return NS <= S::NA ? NS : S::NA;
 }
 
-template <class S, int NS, int W, bool NET>
+template <class S, int NS, int W, bool NET, int BS = kBlock>
 static int launch_desc(hipStream_t st, const NepIO& io, const float* params, bool want_adjoint) {
-  const unsigned g = (unsigned)((io.n_slots + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL((k_desc<S, groups<S, NS>(), W, NET>), dim3(g), dim3(kBlock), 0, st, io.n_slots, io.capA,
+  const unsigned g = (unsigned)((io.n_slots + BS - 1) / BS);
+  hipLaunchKernelGGL((k_desc<S, groups<S, NS>(), W, NET, BS>), dim3(g), dim3(BS), 0, st, io.n_slots, io.capA,
                      io.pos4, io.cfg_of, io.orig, io.cfgs, io.nbrR, io.cntR, io.vrev, io.cnR, io.ccR, io.cnA, io.cpA,
                      io.ccA, io.amask, io.flags, io.cut, params, io.fp, io.aR, io.Ei, io.qout, io.Eproc,
                      want_adjoint ? 1 : 0);
   if constexpr (!NET) {
-    const unsigned gn = g < kNetBlocks ? g : kNetBlocks;
+    const unsigned gk = (unsigned)((io.n_slots + kBlock - 1) / kBlock);
+    const unsigned gn = gk < kNetBlocks ? gk : kNetBlocks;
     hipLaunchKernelGGL(k_net<S>, dim3(gn), dim3(kBlock), 0, st, io.n_slots, io.pos4, io.cfg_of, io.orig, params,
                        io.fp, io.aR, io.Ei, io.qout, io.Eproc, want_adjoint ? 1 : 0);
   }
@@ -1079,10 +1082,10 @@ static int launch_desc(hipStream_t st, const NepIO& io, const float* params, boo
   return NEPMI_OK;
 }
 
-template <class S, int NS, int W>
+template <class S, int NS, int W, int BS = kBlock>
 static int launch_force(hipStream_t st, const NepIO& io, const float* params) {
-  const unsigned g = (unsigned)((io.n_slots + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL((k_force<S, groups<S, NS>(), W>), dim3(g), dim3(kBlock), 0, st, io.n_slots, io.pos4,
+  const unsigned g = (unsigned)((io.n_slots + BS - 1) / BS);
+  hipLaunchKernelGGL((k_force<S, groups<S, NS>(), W, BS>), dim3(g), dim3(BS), 0, st, io.n_slots, io.pos4,
                      io.cfg_of, io.orig, io.cfgs, io.cnR, io.ccR, io.cnA, io.ccA, io.cut, params, io.fp, io.aR,
                      io.frad, io.fA, io.Wi);
   NEPMI_HIP(hipGetLastError());
@@ -1099,6 +1102,8 @@ int Launch<S>::desc(hipStream_t st, const NepIO& io, const float* params, bool w
     case 5: return launch_desc<S, 1, 2, false>(st, io, params, want_adjoint);
     case 6: return launch_desc<S, 2, 2, false>(st, io, params, want_adjoint);
     case 7: return launch_desc<S, 2, 3, false>(st, io, params, want_adjoint);
+    case 8: return launch_desc<S, 2, 2, true, 128>(st, io, params, want_adjoint);
+    case 9: return launch_desc<S, 2, 2, true, 512>(st, io, params, want_adjoint);
     default: return launch_desc<S, 2, 2, true>(st, io, params, want_adjoint);
   }
 }
@@ -1109,17 +1114,29 @@ int Launch<S>::force(hipStream_t st, const NepIO& io, const float* params, int v
     case 1: return launch_force<S, 4, 2>(st, io, params);
     case 2: return launch_force<S, 4, 3>(st, io, params);
     case 3: return launch_force<S, 1, 1>(st, io, params);
+    case 4: return launch_force<S, 2, 2, 128>(st, io, params);
+    case 5: return launch_force<S, 2, 2, 512>(st, io, params);
     default: return launch_force<S, 2, 2>(st, io, params);
   }
 }
 
-template <class S>
-int Launch<S>::gather(hipStream_t st, const NepIO& io) {
-  const unsigned g = (unsigned)((io.n_slots + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_gather, dim3(g), dim3(kBlock), 0, st, io.n_slots, io.orig, io.cnA, io.cpA, io.ccA, io.amask,
+template <int BS>
+static int launch_gather(hipStream_t st, const NepIO& io) {
+  const unsigned g = (unsigned)((io.n_slots + BS - 1) / BS);
+  hipLaunchKernelGGL(k_gather<BS>, dim3(g), dim3(BS), 0, st, io.n_slots, io.orig, io.cnA, io.cpA, io.ccA, io.amask,
                      io.frad, io.fA, io.Fuser, io.Fproc);
   NEPMI_HIP(hipGetLastError());
   return NEPMI_OK;
+}
+
+template <class S>
+int Launch<S>::gather(hipStream_t st, const NepIO& io, int variant) {
+  switch (variant) {
+    case 1: return launch_gather<128>(st, io);
+    case 2: return launch_gather<512>(st, io);
+    case 3: return launch_gather<1024>(st, io);
+    default: return launch_gather<256>(st, io);
+  }
 }
 
 template <class S>

@@ -61,14 +61,16 @@ struct NepIO {
   float* Eproc;  // [n_slots] site energies in slot order, optional
 };
 
-constexpr int kDescVariants = 8;   // compiled variants of k_desc (4..7: network in its own kernel)
-constexpr int kForceVariants = 4;  // compiled variants of k_force
+constexpr int kDescVariants = 10;  // compiled variants of k_desc (4..7: network in its own kernel;
+                                   // 8, 9: variant 0 in blocks of 128 and 512 threads)
+constexpr int kForceVariants = 6;  // compiled variants of k_force (4, 5: variant 0 in blocks of 128, 512)
+constexpr int kGatherVariants = 4; // k_gather in blocks of 256, 128, 512, 1024 threads
 
 template <class S>
 struct Launch {
   static int desc(hipStream_t st, const NepIO& io, const float* params, bool want_adjoint, int variant);
   static int force(hipStream_t st, const NepIO& io, const float* params, int variant);
-  static int gather(hipStream_t st, const NepIO& io);
+  static int gather(hipStream_t st, const NepIO& io, int variant);
   // Writes the derived coefficient table after the P parameters (the
   // parameter buffer holds P + PCR + PCA floats).
   static int derive(hipStream_t st, float* params);

@@ -252,7 +252,7 @@ int nepmi_loss_grad(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, cons
   // forward: E, F, V
   NepIO io = m->io(t.F.ptr<float>(), nullptr, nullptr);
   const float* P = m->params.ptr<float>();
-  if ((rc = m->ops->desc(st, io, P, true, m->vdesc)) || (rc = m->ops->force(st, io, P, m->vforce)) || (rc = m->ops->gather(st, io)) ||
+  if ((rc = m->ops->desc(st, io, P, true, m->vdesc)) || (rc = m->ops->force(st, io, P, m->vforce)) || (rc = m->ops->gather(st, io, m->vgather)) ||
       (rc = m->red.run(st, io.Ei, io.Wi, nullptr, t.E.ptr<double>(), t.V.ptr<double>(), nullptr)))
     return rc;
   // loss and seeds

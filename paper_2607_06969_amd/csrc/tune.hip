@@ -55,13 +55,35 @@ int autotune_io(nepmi_model* m, const NepIO& io, hipStream_t st, int reps) {
       bf = v;
     }
   }
+  // gather block sizes, after the chosen force variant
+  if (!rc) rc = m->ops->force(st, io, P, bf);
+  int bg = m->vgather;
+  best = 1e300;
+  for (int v = 0; v < kGatherVariants && !rc; ++v) {
+    rc = m->ops->gather(st, io, v);
+    double t = 0.0;
+    for (int r = 0; r < reps && !rc; ++r) {
+      NEPMI_HIP(hipEventRecord(e0, st));
+      rc = m->ops->gather(st, io, v);
+      NEPMI_HIP(hipEventRecord(e1, st));
+      NEPMI_HIP(hipEventSynchronize(e1));
+      float ms;
+      NEPMI_HIP(hipEventElapsedTime(&ms, e0, e1));
+      t += ms;
+    }
+    if (t < best) {
+      best = t;
+      bg = v;
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) return rc;
   m->vdesc = bd;
   m->vforce = bf;
+  m->vgather = bg;
   // leave the outputs of the chosen variants behind
-  if ((rc = m->ops->force(st, io, P, bf)) || (rc = m->ops->gather(st, io))) return rc;
+  if ((rc = m->ops->gather(st, io, bg))) return rc;
   return NEPMI_OK;
 }
 
@@ -85,6 +107,22 @@ int nepmi_autotune(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, const
     chosen[0] = m->vdesc;
     chosen[1] = m->vforce;
   }
+  return NEPMI_OK;
+}
+
+int nepmi_set_gather_variant(nepmi_model* m, int32_t variant) {
+  if (!m || variant < 0 || variant >= kGatherVariants) {
+    set_error("variant out of range");
+    return NEPMI_INVALID_ARG;
+  }
+  m->vgather = variant;
+  m->pinned = true;
+  return NEPMI_OK;
+}
+
+int nepmi_get_gather_variant(nepmi_model* m, int32_t* variant) {
+  if (!m) return NEPMI_INVALID_ARG;
+  if (variant) *variant = m->vgather;
   return NEPMI_OK;
 }
 

@@ -149,6 +149,15 @@ class NepModel:
         check(load().nepmi_get_variants(self._h, C.byref(d), C.byref(f)))
         return d.value, f.value
 
+    def set_gather_variant(self, v: int):
+        """Pin the block size of the force gather (0..3: 256, 128, 512, 1024 threads)."""
+        check(load().nepmi_set_gather_variant(self._h, int(v)))
+
+    def gather_variant(self):
+        g = C.c_int32()
+        check(load().nepmi_get_gather_variant(self._h, C.byref(g)))
+        return g.value
+
     def backward_params(self, batch: Batch, ebar, lam, mu):
         """sum_c ebar_c dE_c/dtheta + sum_i lam_i.dF_i/dtheta + sum_c mu_c:dV_c/dtheta (float32, P).
         Needs a preceding compute() on the same batch."""

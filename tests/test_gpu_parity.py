@@ -177,7 +177,7 @@ def test_run_to_run_bitwise(oracle_lib):
 @pytest.mark.parametrize("name", ["cubic64_single", "gst_rocksalt_8", "table2_rocksalt_8", "gst_amorphous_batch"])
 def test_every_kernel_variant(evaluated, name):
     """Each compiled (groups of angular functions, occupancy, fused or
-    separate network) variant of the descriptor and force kernels meets the
+    separate network, block size) variant of the descriptor and force kernels meets the
     same bar; descriptor variants give bitwise identical descriptors, and
     bitwise identical energies within each network form (in the kernel,
     variants 0-3, or in its own kernel, 4-7: the two sum in different orders)."""
@@ -191,9 +191,9 @@ def test_every_kernel_variant(evaluated, name):
     base_q = None
     base_E = {}
     n_c = np.diff(s.atom_off)
-    for dv in range(8):  # 4..7: the network in a kernel of its own
-        form = dv // 4
-        for fv in range(4):
+    for dv in range(10):  # 4..7: the network in a kernel of its own; 8, 9: other block sizes
+        form = 1 if 4 <= dv < 8 else 0
+        for fv in range(6):
             print(f"[variants] {name} desc={dv} force={fv}", flush=True)
             m.set_variants(dv, fv)
             got = m.compute(b)
@@ -211,3 +211,13 @@ def test_every_kernel_variant(evaluated, name):
             base_q = q.clone()
         else:
             assert torch.equal(q, base_q), dv
+    # the gather's block size changes nothing
+    m.set_variants(0, 0)
+    base_F = None
+    for gv in range(4):
+        m.set_gather_variant(gv)
+        got = m.compute(b)
+        if base_F is None:
+            base_F = got["F"].clone()
+        else:
+            assert torch.equal(got["F"], base_F), gv
