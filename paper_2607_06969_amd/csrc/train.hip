@@ -915,70 +915,296 @@ __global__ void k_stage64(int64_t ns, const int* __restrict__ orig, const int* _
   pos4[p] = make_double4(w[0], w[1], w[2], (double)species_of(wf));
 }
 
-// dE_a/dr_ab for centre a (species Za) and neighbour b (species Zb) at
-// r_ab = d u, from a's sigma = dE_a/dS_a (slot-major: the NA K values of slot
-// sa are contiguous, so a lane reads whole cache lines of its neighbour's
-// row): with g_n = sum_k c[Za][Zb][n][k] Q_k (Eq. 11-15, 16),
-//   dE_a/dr_ab = u sum_n g'_n Z_n + (I - u u^T) grad_u(sum_lm G_lm Y_lm) / d,
-//   Z_n = sum_lm sigma_nlm Y_lm(u),  G_lm = sum_n sigma_nlm g_n.
-template <class S>
-__device__ void angular_pair_grad(const double* __restrict__ sigmaT, int64_t sa, const double* cA, int Za,
-                                  int Zb, double ux, double uy, double uz, double d, double rcA_inv, double& fx,
-                                  double& fy, double& fz) {
-  constexpr int T = S::T, NA = S::NA, BA = S::BA, L = S::L, K = S::K;
-  const double* sigma = sigmaT + sa * (int64_t)(NA * K);
-  double Q[BA], dQ[BA], Y[K], G[K];
-  cheb_basis_d<BA>(d, rcA_inv, Q, dQ);
-  real_sph<L>(ux, uy, uz, Y);
-#pragma unroll
-  for (int lm = 0; lm < K; ++lm) G[lm] = 0.0;
-  double s = 0.0;
-  const double* cl = cA + ((int64_t)(Za * T + Zb) * NA) * BA;
-#pragma unroll 1
-  for (int n = 0; n < NA; ++n) {
-    double g = 0.0, gp = 0.0;
-#pragma unroll
-    for (int k = 0; k < BA; ++k) {
-      g = fma(cl[n * BA + k], Q[k], g);
-      gp = fma(cl[n * BA + k], dQ[k], gp);
-    }
-    double zn = 0.0;
-#pragma unroll
-    for (int lm = 0; lm < K; ++lm) {
-      const double sg = sigma[n * K + lm];
-      zn = fma(sg, Y[lm], zn);
-      G[lm] = fma(sg, g, G[lm]);
-    }
-    s = fma(gp, zn, s);
+// Constants of the float64 force kernels.  Float64 instructions take no
+// 64-bit literal operands, so every constant of the pair arithmetic that the
+// compiler hoists out of a pair loop holds two registers for the whole loop
+// (about a hundred of them here, which spills).  The kernels read them instead
+// through a pointer made opaque once per pair: they are then loaded with scalar
+// loads where they are used.
+struct K64 {
+  double sc[12];  // sin(pi w) = w sum_k sc[k] w^(2k),  sc[k] = (-1)^k pi^(2k+1) / (2k+1)!
+  double cc[12];  // cos(pi w) = sum_k cc[k] w^(2k),    cc[k] = (-1)^k pi^(2k) / (2k)!
+  double pi;
+  double c1, k20, k21, k22, k30, k31, k32, k32s, k33, k40, k41, k42, k42s, k43, k44, k44s;
+  double n3, n5, n6, n7, n10, n14, n15, n21, n30, n35, n60, n140;
+};
+
+constexpr K64 make_k64() {
+  using C = ShC<double>;
+  K64 k{};
+  // Taylor series of sin and cos at 0; on |w| <= 1/2 the first omitted terms,
+  // (pi/2)^25 / 25! and (pi/2)^24 / 24!, are below 2e-20.
+  double s = C::pi, c = 1.0;
+  for (int j = 0; j < 12; ++j) {
+    k.sc[j] = s;
+    k.cc[j] = c;
+    s = -s * C::pi * C::pi / ((2.0 * j + 2.0) * (2.0 * j + 3.0));
+    c = -c * C::pi * C::pi / ((2.0 * j + 1.0) * (2.0 * j + 2.0));
   }
-  double gx, gy, gz;
-  real_sph_grad_dot<L>(ux, uy, uz, G, gx, gy, gz);
-  const double ug = ux * gx + uy * gy + uz * gz;
-  fx = s * ux + (gx - ug * ux) / d;
-  fy = s * uy + (gy - ug * uy) / d;
-  fz = s * uz + (gz - ug * uz) / d;
+  k.pi = C::pi;
+  k.c1 = C::c1;
+  k.k20 = C::k20;
+  k.k21 = C::k21;
+  k.k22 = C::k22;
+  k.k30 = C::k30;
+  k.k31 = C::k31;
+  k.k32 = C::k32;
+  k.k32s = C::k32s;
+  k.k33 = C::k33;
+  k.k40 = C::k40;
+  k.k41 = C::k41;
+  k.k42 = C::k42;
+  k.k42s = C::k42s;
+  k.k43 = C::k43;
+  k.k44 = C::k44;
+  k.k44s = C::k44s;
+  k.n3 = 3.0;
+  k.n5 = 5.0;
+  k.n6 = 6.0;
+  k.n7 = 7.0;
+  k.n10 = 10.0;
+  k.n14 = 14.0;
+  k.n15 = 15.0;
+  k.n21 = 21.0;
+  k.n30 = 30.0;
+  k.n35 = 35.0;
+  k.n60 = 60.0;
+  k.n140 = 140.0;
+  return k;
+}
+__device__ const K64 kK64 = make_k64();
+
+// The table through an address the compiler cannot see as loop-invariant, in
+// the constant address space (scalar loads).
+using K64c = const __attribute__((address_space(4))) K64;
+__device__ __forceinline__ K64c& k64_opaque() {
+  uint64_t a = reinterpret_cast<uint64_t>(&kK64);
+  __asm__ volatile("" : "+s"(a));
+  return *reinterpret_cast<K64c*>(a);
 }
 
-// dst[p][r] = src[r][p] for r < R rows of stride ns (slot-minor to slot-major),
-// through a 32 x 32 LDS tile so that both the reads and the writes coalesce.
-constexpr int kTT = 32;
-__global__ __launch_bounds__(kTT * 8) void k_slot_major64(int64_t ns, int R, const double* __restrict__ src,
-                                                          double* __restrict__ dst) {
-  __shared__ double tile[kTT][kTT + 1];
-  const int64_t p0 = (int64_t)blockIdx.x * kTT;
-  const int r0 = blockIdx.y * kTT;
-  const int tx = threadIdx.x % kTT, ty = threadIdx.x / kTT;  // 32 x 8 threads
-  for (int y = ty; y < kTT; y += 8) {
-    const int r = r0 + y;
-    const int64_t p = p0 + tx;
-    tile[y][tx] = (r < R && p < ns) ? src[(int64_t)r * ns + p] : 0.0;
+// sin(pi t) and cos(pi t) for t in [0, 1]: with w = t - 1/2,
+// sin(pi t) = cos(pi w) and cos(pi t) = -sin(pi w), |w| <= 1/2.
+__device__ __forceinline__ void sincospi64(K64c& K, double t, double& sn, double& cs) {
+  const double w = t - 0.5, w2 = w * w;
+  double s = K.sc[11], c = K.cc[11];
+#pragma unroll
+  for (int j = 10; j >= 0; --j) {
+    s = fma(s, w2, K.sc[j]);
+    c = fma(c, w2, K.cc[j]);
   }
-  __syncthreads();
-  for (int y = ty; y < kTT; y += 8) {
-    const int64_t p = p0 + y;
-    const int r = r0 + tx;
-    if (p < ns && r < R) dst[p * R + r] = tile[tx][y];
+  sn = c;
+  cs = -(w * s);
+}
+
+// The Chebyshev basis of Eq. 12-15 with its radial derivative, as
+// cheb_basis_d, for d < rc, on the float64 force kernels' constants.
+template <int B>
+__device__ __forceinline__ void cheb_basis64(K64c& K, double d, double rc_inv, double (&Q)[B], double (&dQ)[B]) {
+  const double t = d * rc_inv;
+  const double y = t - 1.0;
+  const double x = 2.0 * y * y - 1.0;
+  const double dx = 4.0 * y * rc_inv;
+  double sn, cs;
+  sincospi64(K, t, sn, cs);
+  const double fc = 0.5 * (1.0 + cs);
+  const double dfc = -0.5 * K.pi * rc_inv * sn;
+  double tm = 1.0, tk = x, dtm = 0.0, dtk = 1.0;
+  Q[0] = fc;
+  dQ[0] = dfc;
+  if (B > 1) {
+    Q[1] = 0.5 * (x + 1.0) * fc;
+    dQ[1] = 0.5 * (dx * fc + (x + 1.0) * dfc);
   }
+#pragma unroll
+  for (int k = 2; k < B; ++k) {
+    const double tn = 2.0 * x * tk - tm;
+    const double dtn = 2.0 * tk + 2.0 * x * dtk - dtm;
+    tm = tk;
+    tk = tn;
+    dtm = dtk;
+    dtk = dtn;
+    Q[k] = 0.5 * (tn + 1.0) * fc;
+    dQ[k] = 0.5 * (dtn * dx * fc + (tn + 1.0) * dfc);
+  }
+}
+
+// Real harmonics and their gradient one degree l at a time (the polynomials
+// of real_sph / real_sph_grad_dot, split by l), so that a float64 pair keeps
+// at most 2l + 1 harmonics and weights live.  Yl[m] = P_{l,m}(x, y, z) for
+// m = 0..2l, in the order of real_sph.
+template <int l>
+__device__ __forceinline__ void real_sph_l(K64c& K, double x, double y, double z, double (&Yl)[2 * l + 1]) {
+  if constexpr (l == 1) {
+    Yl[0] = K.c1 * z;
+    Yl[1] = K.c1 * x;
+    Yl[2] = K.c1 * y;
+  } else if constexpr (l == 2) {
+    const double z2 = z * z;
+    Yl[0] = K.k20 * (K.n3 * z2 - 1.0);
+    Yl[1] = K.k21 * x * z;
+    Yl[2] = K.k21 * y * z;
+    Yl[3] = K.k22 * (x * x - y * y);
+    Yl[4] = K.k21 * x * y;
+  } else if constexpr (l == 3) {
+    const double z2 = z * z;
+    const double x2my2 = x * x - y * y;
+    const double p = K.n5 * z2 - 1.0;
+    Yl[0] = K.k30 * z * (K.n5 * z2 - K.n3);
+    Yl[1] = K.k31 * x * p;
+    Yl[2] = K.k31 * y * p;
+    Yl[3] = K.k32 * z * x2my2;
+    Yl[4] = K.k32s * x * y * z;
+    Yl[5] = K.k33 * x * (x * x - K.n3 * y * y);
+    Yl[6] = K.k33 * y * (K.n3 * x * x - y * y);
+  } else {
+    static_assert(l == 4, "l_max <= 4");
+    const double z2 = z * z;
+    const double x2my2 = x * x - y * y;
+    const double q = K.n7 * z2 - K.n3;
+    const double r = K.n7 * z2 - 1.0;
+    Yl[0] = K.k40 * (K.n35 * z2 * z2 - K.n30 * z2 + K.n3);
+    Yl[1] = K.k41 * x * z * q;
+    Yl[2] = K.k41 * y * z * q;
+    Yl[3] = K.k42 * x2my2 * r;
+    Yl[4] = K.k42s * x * y * r;
+    Yl[5] = K.k43 * x * z * (x * x - K.n3 * y * y);
+    Yl[6] = K.k43 * y * z * (K.n3 * x * x - y * y);
+    Yl[7] = K.k44 * (x2my2 * x2my2 - 4.0 * x * x * y * y);
+    Yl[8] = K.k44s * x * y * x2my2;
+  }
+}
+
+// (gx, gy, gz) += sum_m Gl[m] grad_u P_{l,m}(u), degree l only.
+template <int l>
+__device__ __forceinline__ void real_sph_grad_acc_l(K64c& K, double x, double y, double z,
+                                                    const double (&G)[2 * l + 1], double& gx, double& gy,
+                                                    double& gz) {
+  if constexpr (l == 1) {
+    gx += K.c1 * G[1];
+    gy += K.c1 * G[2];
+    gz += K.c1 * G[0];
+  } else if constexpr (l == 2) {
+    gz += K.n6 * K.k20 * z * G[0];
+    gx += K.k21 * z * G[1];
+    gz += K.k21 * x * G[1];
+    gy += K.k21 * z * G[2];
+    gz += K.k21 * y * G[2];
+    gx += 2.0 * K.k22 * x * G[3];
+    gy -= 2.0 * K.k22 * y * G[3];
+    gx += K.k21 * y * G[4];
+    gy += K.k21 * x * G[4];
+  } else if constexpr (l == 3) {
+    const double z2 = z * z, x2 = x * x, y2 = y * y;
+    const double p = K.n5 * z2 - 1.0;
+    gz += K.k30 * (K.n15 * z2 - K.n3) * G[0];
+    gx += K.k31 * p * G[1];
+    gz += K.n10 * K.k31 * x * z * G[1];
+    gy += K.k31 * p * G[2];
+    gz += K.n10 * K.k31 * y * z * G[2];
+    gx += 2.0 * K.k32 * x * z * G[3];
+    gy -= 2.0 * K.k32 * y * z * G[3];
+    gz += K.k32 * (x2 - y2) * G[3];
+    gx += K.k32s * y * z * G[4];
+    gy += K.k32s * x * z * G[4];
+    gz += K.k32s * x * y * G[4];
+    gx += K.n3 * K.k33 * (x2 - y2) * G[5];
+    gy -= K.n6 * K.k33 * x * y * G[5];
+    gx += K.n6 * K.k33 * x * y * G[6];
+    gy += K.n3 * K.k33 * (x2 - y2) * G[6];
+  } else {
+    static_assert(l == 4, "l_max <= 4");
+    const double z2 = z * z, x2 = x * x, y2 = y * y;
+    const double q = K.n7 * z2 - K.n3;
+    const double r = K.n7 * z2 - 1.0;
+    gz += K.k40 * (K.n140 * z2 * z - K.n60 * z) * G[0];
+    gx += K.k41 * z * q * G[1];
+    gz += K.k41 * x * (K.n21 * z2 - K.n3) * G[1];
+    gy += K.k41 * z * q * G[2];
+    gz += K.k41 * y * (K.n21 * z2 - K.n3) * G[2];
+    gx += 2.0 * K.k42 * x * r * G[3];
+    gy -= 2.0 * K.k42 * y * r * G[3];
+    gz += K.n14 * K.k42 * z * (x2 - y2) * G[3];
+    gx += K.k42s * y * r * G[4];
+    gy += K.k42s * x * r * G[4];
+    gz += K.n14 * K.k42s * x * y * z * G[4];
+    gx += K.n3 * K.k43 * z * (x2 - y2) * G[5];
+    gy -= K.n6 * K.k43 * x * y * z * G[5];
+    gz += K.k43 * x * (x2 - K.n3 * y2) * G[5];
+    gx += K.n6 * K.k43 * x * y * z * G[6];
+    gy += K.n3 * K.k43 * z * (x2 - y2) * G[6];
+    gz += K.k43 * y * (K.n3 * x2 - y2) * G[6];
+    gx += 4.0 * K.k44 * x * (x2 - K.n3 * y2) * G[7];
+    gy += 4.0 * K.k44 * y * (y2 - K.n3 * x2) * G[7];
+    gx += K.k44s * y * (K.n3 * x2 - y2) * G[8];
+    gy += K.k44s * x * (x2 - K.n3 * y2) * G[8];
+  }
+}
+
+// One degree l of an angular pair, for the NP functions n of one pass:
+// Z_j += sum_m sigma_{j,lm} Y_lm and grad += sum_m G_lm grad P_lm with
+// G_lm = sum_j sigma_{j,lm} g_j.
+template <int l, int NP, int K>
+__device__ __forceinline__ void ang_degree64(K64c& KC, const double (&sg)[NP][K], double ux, double uy, double uz,
+                                             const double (&g)[NP], double (&Z)[NP], double& gx, double& gy,
+                                             double& gz) {
+  constexpr int base = l * l - 1;  // index of (l, m = 0) in real_sph's order
+  double Y[2 * l + 1], G[2 * l + 1];
+  real_sph_l<l>(KC, ux, uy, uz, Y);
+#pragma unroll
+  for (int m = 0; m < 2 * l + 1; ++m) G[m] = 0.0;
+#pragma unroll
+  for (int j = 0; j < NP; ++j)
+#pragma unroll
+    for (int m = 0; m < 2 * l + 1; ++m) {
+      Z[j] = fma(sg[j][base + m], Y[m], Z[j]);
+      G[m] = fma(sg[j][base + m], g[j], G[m]);
+    }
+  real_sph_grad_acc_l<l>(KC, ux, uy, uz, G, gx, gy, gz);
+}
+
+// The part of dE_a/dr_ab of the angular descriptors (Eq. 11-17) that the NP
+// functions n of one pass contribute, for centre a and neighbour b at
+// r_ab = d u:  with g_n = sum_k c[Za][Zb][n][k] Q_k(d),
+//   u sum_n g'_n Z_n + (I - u u^T) grad_u(sum_lm G_lm P_lm) / d,
+//   Z_n = sum_lm sigma_nlm Y_lm(u),  G_lm = sum_n sigma_nlm g_n,
+// sigma = dE_a/dS_a.  cl: the NP x BA rows of c[Za][Zb] of the pass.
+template <class S, int NP>
+__device__ __forceinline__ void ang_pair_grad64(K64c& KC, const double (&sg)[NP][S::K], const double* cl, double ux,
+                                                double uy, double uz, double d, double d_inv, double rcA_inv,
+                                                double& fx, double& fy, double& fz) {
+  constexpr int BA = S::BA, L = S::L, K = S::K;
+  double g[NP], gp[NP];
+  {
+    double Q[BA], dQ[BA];
+    cheb_basis64<BA>(KC, d, rcA_inv, Q, dQ);
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      double a = 0.0, b = 0.0;
+#pragma unroll
+      for (int k = 0; k < BA; ++k) {
+        a = fma(cl[j * BA + k], Q[k], a);
+        b = fma(cl[j * BA + k], dQ[k], b);
+      }
+      g[j] = a;
+      gp[j] = b;
+    }
+  }
+  double Z[NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) Z[j] = 0.0;
+  double gx = 0.0, gy = 0.0, gz = 0.0;
+  ang_degree64<1, NP, K>(KC, sg, ux, uy, uz, g, Z, gx, gy, gz);
+  if constexpr (L >= 2) ang_degree64<2, NP, K>(KC, sg, ux, uy, uz, g, Z, gx, gy, gz);
+  if constexpr (L >= 3) ang_degree64<3, NP, K>(KC, sg, ux, uy, uz, g, Z, gx, gy, gz);
+  if constexpr (L >= 4) ang_degree64<4, NP, K>(KC, sg, ux, uy, uz, g, Z, gx, gy, gz);
+  double s = 0.0;
+#pragma unroll
+  for (int j = 0; j < NP; ++j) s = fma(gp[j], Z[j], s);
+  const double ug = ux * gx + uy * gy + uz * gz;
+  fx = s * ux + (gx - ug * ux) * d_inv;
+  fy = s * uy + (gy - ug * uy) * d_inv;
+  fz = s * uz + (gz - ug * uz) * d_inv;
 }
 
 // Radial adjoint in float64, atil_i[b][k] = sum_n dE_i/dq_n c[Z_i][b][n][k],
@@ -1009,22 +1235,82 @@ __global__ __launch_bounds__(kTB) void k_radial_adj64(int64_t ns, const int* __r
   }
 }
 
-// F_i = sum_j (dE_i/dr_ij - dE_j/dr_ji) (Eq. 3) and the per-atom virial
-// W_i = - sum_j dE_i/dr_ij (x) r_ij, from the per-atom adjoints that the atom
-// pass leaves with zero tangent seeds: the radial adjoint aR (k_radial_adj64)
-// and sigma = dE/dS (sigmaT: its slot-major copy).  Caller order for F and W.
-// Radial pairs take both directions here: dE_i/dd = sum_k atil_i[Z_j][k] dQ_k
-// and dE_j/dd = sum_k atil_j[Z_i][k] dQ_k.  For an angular pair only i's own derivative dE_i/dr_ij is formed
-// (from i's sigma row) and kept at the pair's position in the angular part of
-// i's list; k_gather_force64 then subtracts the partners' own derivatives,
-// found through the reverse index, so no pair reads a neighbour's sigma row.
+
+// Forces and per-atom virials in float64 (Eq. 3, Eq. 4), from the adjoints
+// that the atom pass leaves with zero tangent seeds:
+// F_i = sum_j (dE_i/dr_ij - dE_j/dr_ji), W_i = - sum_j dE_i/dr_ij (x) r_ij,
+// caller order for F and W.
+//
+// k_ang_force64: for every entry of the angular part of i's list (rc_angular
+// + skin), dE_i/dr_ij of the angular descriptors, from i's own sigma, goes to
+// fA at the entry's position (zero beyond rc_angular).  The functions n are
+// taken NP at a time: their sigma rows (NP K values) are read once into
+// registers and every entry of the atom is visited per pass, its partial
+// derivative added to fA.  The coefficient blocks c[Z_i][Z_j] sit in LDS.
+template <class S, int NP>
+__global__ __launch_bounds__(kTB) void k_ang_force64(TrainIOT<double> io, CutoffsT<double> cut,
+                                                     const double* __restrict__ params,
+                                                     const uint32_t* __restrict__ nbrTA, int rowTA,
+                                                     const int* __restrict__ cntAV, double4* __restrict__ fA) {
+  constexpr int NA = S::NA, BA = S::BA, K = S::K;
+  static_assert(NA % NP == 0, "passes of NP functions");
+  constexpr int NCA = S::T * S::T * NA * BA;
+  __shared__ double cAs[NCA];
+  for (int x = threadIdx.x; x < NCA; x += kTB) cAs[x] = params[S::PCR + x];
+  __syncthreads();
+  const int64_t ns = io.ns;
+  const int64_t p = (int64_t)blockIdx.x * kTB + threadIdx.x;
+  if (p >= ns) return;
+  const int c = io.cfg_of[p];
+  if (c < 0) return;
+  const double4 xi = io.pos4[p];
+  const int Zi = species_of(xi);
+  double Hc[9];
+  load_cell9(io.cfgs, c, Hc);
+  const double rcA_inv = 1.0 / cut.rcA;
+  const uint32_t* row = nbrTA + p * rowTA;
+  const int n = cntAV[p];
+#pragma unroll 1
+  for (int h = 0; h < NA; h += NP) {
+    double sg[NP][K];
+#pragma unroll
+    for (int j = 0; j < NP; ++j)
+#pragma unroll
+      for (int lm = 0; lm < K; ++lm) sg[j][lm] = io.Sst[(int64_t)((h + j) * K + lm) * ns + p];
+    for (int ka = 0; ka < n; ++ka) {
+      const PV<double> v = pvec(io.pos4, row[ka], xi, Hc);
+      double ax = 0.0, ay = 0.0, az = 0.0;
+      if (v.d2 < cut.rcA2) {
+        const double d = sqrt(v.d2);
+        const double d_inv = 1.0 / d;
+        const double* cl = cAs + ((Zi * S::T + v.zj) * NA + h) * BA;
+        ang_pair_grad64<S, NP>(k64_opaque(), sg, cl, v.rx * d_inv, v.ry * d_inv, v.rz * d_inv, d, d_inv, rcA_inv,
+                               ax, ay, az);
+      }
+      double4* o = fA + (int64_t)ka * ns + p;
+      if (h > 0) {
+        const double4 prev = *o;
+        ax += prev.x;
+        ay += prev.y;
+        az += prev.z;
+      }
+      *o = make_double4(ax, ay, az, 0.0);
+    }
+  }
+}
+
+// k_force64 walks i's whole list once.  A radial pair takes both directions
+// at once through the two adjoint rows of k_radial_adj64:
+// dE_i/dd = sum_k atil_i[Z_j][k] dQ_k and dE_j/dd = sum_k atil_j[Z_i][k] dQ_k.
+// An entry of the angular part adds i's own angular dE_i/dr_ij (fA at its
+// position in i's angular part, also into W_i) and subtracts the partner's
+// dE_j/dr_ji, which sits at i's position in the angular part of j's list
+// (the reverse index).
 template <class S>
-__global__ __launch_bounds__(kTB) void k_pair_force64(TrainIOT<double> io, CutoffsT<double> cut,
-                                                      const double* __restrict__ params,
-                                                      const double* __restrict__ sigmaT,
-                                                      const double* __restrict__ aR,
-                                                      const uint32_t* __restrict__ vrev, double4* __restrict__ fA,
-                                                      double* __restrict__ F, double* __restrict__ W) {
+__global__ __launch_bounds__(kTB) void k_force64(TrainIOT<double> io, CutoffsT<double> cut,
+                                                 const double* __restrict__ aR, const uint32_t* __restrict__ vrev,
+                                                 const double4* __restrict__ fA, double* __restrict__ F,
+                                                 double* __restrict__ W) {
   constexpr int BR = S::BR;
   const int64_t ns = io.ns;
   const int64_t p = (int64_t)blockIdx.x * kTB + threadIdx.x;
@@ -1036,78 +1322,73 @@ __global__ __launch_bounds__(kTB) void k_pair_force64(TrainIOT<double> io, Cutof
   const int Zi = species_of(xi);
   double Hc[9];
   load_cell9(io.cfgs, c, Hc);
-  const double rcR_inv = 1.0 / cut.rcR, rcA_inv = 1.0 / cut.rcA;
+  const double rcR_inv = 1.0 / cut.rcR;
+  // i's own adjoint rows atil_i[b][.] for every neighbour species b, held for
+  // the whole walk (read once instead of once per pair)
+  double Ai[S::T][BR];
+#pragma unroll
+  for (int b = 0; b < S::T; ++b)
+#pragma unroll
+    for (int kk = 0; kk < BR; ++kk) Ai[b][kk] = aR[((int64_t)b * ns + p) * BR + kk];
   double Fx = 0.0, Fy = 0.0, Fz = 0.0, Wm[9];
 #pragma unroll
   for (int x = 0; x < 9; ++x) Wm[x] = 0.0;
-  const double* cA = params + S::PCR;
   const int n = io.cntR[p];
-  int ka = 0;  // position in the angular part of the list
+  int ka = 0;  // position in the angular part of i's list
   for (int k = 0; k < n; ++k) {
     const int64_t gk = group_index(ns, p, k);
-    const bool in_ang_part = vrev[gk] != 0xFFFFFFFFu;
+    const uint32_t rv = vrev[gk];
     const PV<double> v = pvec(io.pos4, io.nbrR[gk], xi, Hc);
-    double ax = 0.0, ay = 0.0, az = 0.0;  // dE_i/dr_ij of the angular descriptors
+    double fx = 0.0, fy = 0.0, fz = 0.0;  // dE_i/dr_ij
     if (v.d2 < cut.rcR2) {
       const double d = sqrt(v.d2);
-      const double ux = v.rx / d, uy = v.ry / d, uz = v.rz / d;
-      // radial: dE_i/dd and dE_j/dd through the two adjoint rows
+      const double d_inv = 1.0 / d;
+      const double ux = v.rx * d_inv, uy = v.ry * d_inv, uz = v.rz * d_inv;
       double Q[BR], dQ[BR];
-      cheb_basis_d<BR>(d, rcR_inv, Q, dQ);
-      const double* ai = aR + ((int64_t)v.zj * ns + p) * BR;
+      cheb_basis64<BR>(k64_opaque(), d, rcR_inv, Q, dQ);
       const double* aj = aR + ((int64_t)Zi * ns + v.q) * BR;
       double own = 0.0, rev = 0.0;
 #pragma unroll
-      for (int kk = 0; kk < BR; ++kk) {
-        own = fma(ai[kk], dQ[kk], own);
-        rev = fma(aj[kk], dQ[kk], rev);
+      for (int b = 0; b < S::T; ++b) {
+        double t = 0.0;
+#pragma unroll
+        for (int kk = 0; kk < BR; ++kk) t = fma(Ai[b][kk], dQ[kk], t);
+        own = v.zj == b ? t : own;
       }
-      if (v.d2 < cut.rcA2) angular_pair_grad<S>(sigmaT, p, cA, Zi, v.zj, ux, uy, uz, d, rcA_inv, ax, ay, az);
-      const double fx = own * ux + ax, fy = own * uy + ay, fz = own * uz + az;  // dE_i/dr_ij
+#pragma unroll
+      for (int kk = 0; kk < BR; ++kk) rev = fma(aj[kk], dQ[kk], rev);
+      fx = own * ux;
+      fy = own * uy;
+      fz = own * uz;
       // minus dE_j/dr_ji of the radial descriptors (r_ji = -r_ij)
-      Fx += fx + rev * ux;
-      Fy += fy + rev * uy;
-      Fz += fz + rev * uz;
-      const double f[3] = {fx, fy, fz}, r[3] = {v.rx, v.ry, v.rz};
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) Wm[3 * a + b] -= f[a] * r[b];
+      Fx += rev * ux;
+      Fy += rev * uy;
+      Fz += rev * uz;
     }
-    if (in_ang_part) fA[(int64_t)ka++ * ns + p] = make_double4(ax, ay, az, 0.0);
+    if (rv != 0xFFFFFFFFu) {
+      const double4 a = fA[(int64_t)ka++ * ns + p];
+      const double4 b = fA[(int64_t)rv * ns + v.q];
+      fx += a.x;
+      fy += a.y;
+      fz += a.z;
+      Fx -= b.x;
+      Fy -= b.y;
+      Fz -= b.z;
+    }
+    Fx += fx;
+    Fy += fy;
+    Fz += fz;
+    const double f[3] = {fx, fy, fz}, r[3] = {v.rx, v.ry, v.rz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) Wm[3 * a + b] -= f[a] * r[b];
   }
   F[3 * (int64_t)i] = Fx;
   F[3 * (int64_t)i + 1] = Fy;
   F[3 * (int64_t)i + 2] = Fz;
 #pragma unroll
   for (int x = 0; x < 9; ++x) W[9 * (int64_t)i + x] = Wm[x];
-}
-
-// F_i -= sum_j dE_j/dr_ji over the angular part of i's list: the partner's
-// own derivative sits at i's position in the angular part of j's list.
-__global__ __launch_bounds__(kTB) void k_gather_force64(int64_t ns, const int* __restrict__ cfg_of,
-                                                        const int* __restrict__ orig,
-                                                        const uint32_t* __restrict__ nbrR,
-                                                        const int* __restrict__ cntR,
-                                                        const uint32_t* __restrict__ vrev,
-                                                        const double4* __restrict__ fA, double* __restrict__ F) {
-  const int64_t p = (int64_t)blockIdx.x * kTB + threadIdx.x;
-  if (p >= ns || cfg_of[p] < 0) return;
-  const int i = orig[p];
-  double Fx = 0.0, Fy = 0.0, Fz = 0.0;
-  const int n = cntR[p];
-  for (int k = 0; k < n; ++k) {
-    const int64_t gk = group_index(ns, p, k);
-    const uint32_t r = vrev[gk];
-    if (r == 0xFFFFFFFFu) continue;
-    const double4 b = fA[(int64_t)r * ns + (nbrR[gk] & kNbrMask)];
-    Fx -= b.x;
-    Fy -= b.y;
-    Fz -= b.z;
-  }
-  F[3 * (int64_t)i] += Fx;
-  F[3 * (int64_t)i + 1] += Fy;
-  F[3 * (int64_t)i + 2] += Fz;
 }
 
 // ------------------------------------------------------------ launchers
@@ -1183,17 +1464,15 @@ int TrainLaunch<S>::forward64(hipStream_t st, TrainIOT<double> io, const Cutoffs
                      a.params);
   hipLaunchKernelGGL((k_train_atom<S, NC, double, 3, true>), dim3(blocks(ns, kTB), S::NA), dim3(kTB), 0, st, io, cut,
                      a.params);
-  // sigma, slot-major, into the Sdot buffer (free once the dE/dS pass is done;
-  // the backward recomputes it)
-  hipLaunchKernelGGL(k_slot_major64, dim3(blocks(ns, kTT), (S::NA * S::K + kTT - 1) / kTT), dim3(kTT * 8), 0, st, ns,
-                     S::NA * S::K, io.Sst, io.Sdt);
   // the radial adjoint rows of every atom
   hipLaunchKernelGGL((k_radial_adj64<S>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, ns, io.cfg_of, io.pos4, io.FpR,
                      a.params, a.aR);
-  hipLaunchKernelGGL((k_pair_force64<S>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params, io.Sdt, a.aR,
-                     a.vrev, a.fA, forces, a.Wi);
-  hipLaunchKernelGGL(k_gather_force64, dim3(blocks(ns, kTB)), dim3(kTB), 0, st, ns, io.cfg_of, io.orig, io.nbrR,
-                     io.cntR, a.vrev, a.fA, forces);
+  // the angular part of every list, then each list once
+  constexpr int NP = S::NA % 2 == 0 ? 2 : 1;
+  hipLaunchKernelGGL((k_ang_force64<S, NP>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.params, a.nbrTA,
+                     a.rowTA, a.cntAV, a.fA);
+  hipLaunchKernelGGL((k_force64<S>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, a.aR, a.vrev, a.fA, forces,
+                     a.Wi);
   NEPMI_HIP(hipGetLastError());
   return NEPMI_OK;
 }

@@ -80,6 +80,9 @@ struct F64Args {
   double4* pos4;            // work: [ns] positions in slot order
   double* Wi;               // work: [N][9] per-atom virial, caller order
   const uint32_t* vrev;     // reverse index of the Verlet list (grouped as the list)
+  const uint32_t* nbrTA;    // angular part (rc_angular + skin) of each list, row-major, rows of rowTA
+  int rowTA;
+  const int* cntAV;         // [ns] entries in that part
   double4* fA;              // work: [capA][ns] dE_i/dr_ij of the angular part of i's list, by position
   double* aR;               // work: [T][ns][BR] radial adjoint rows
 };

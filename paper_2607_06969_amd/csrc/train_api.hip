@@ -172,6 +172,9 @@ int prepare64(nepmi_model* m, int n_cfg, const int64_t* atom_off, const double* 
   a.pos4 = m->f64.pos4.ptr<double4>();
   a.Wi = m->f64.Wi.ptr<double>();
   a.vrev = m->nbr.vrev.ptr<uint32_t>();
+  a.nbrTA = m->nbr.nbrTA.ptr<uint32_t>();
+  a.rowTA = m->nbr.rowTA;
+  a.cntAV = m->nbr.cntAV.ptr<int>();
   a.fA = m->f64.fA.ptr<double4>();
   a.aR = m->f64.aR.ptr<double>();
   return launch_stage64(st, f64_io(m, nullptr, nullptr, nullptr), a, m->nbr.pos4.ptr<float4>());
