@@ -80,14 +80,17 @@ __device__ void wrap_periodic(const CfgDev& C, double r[3], float f[3]) {
 }
 
 // Before a rebuild: state back to caller order, positions wrapped into the
-// cell in float64 so that the float32 copy needs no further wrapping.
+// cell in float64 so that the float32 copy needs no further wrapping.  Also
+// clears the n_clear key counts of the sort that follows (cnt may be null).
 __global__ void k_md_unpermute(int64_t n_slots, const int* __restrict__ cfg_of, const int* __restrict__ orig,
                                const CfgDev* __restrict__ cfgs, const Dbl3* __restrict__ xd,
                                const float4* __restrict__ vel4, Dbl3* __restrict__ xd_user,
-                               float4* __restrict__ x_user, float4* __restrict__ v_user,
-                               const int* __restrict__ gate) {
+                               float4* __restrict__ x_user, float4* __restrict__ v_user, int* __restrict__ cnt,
+                               int64_t n_clear, const int* __restrict__ gate) {
   if (*gate == 0) return;
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cnt)
+    for (int64_t k = p; k < n_clear; k += (int64_t)gridDim.x * blockDim.x) cnt[k] = 0;
   if (p >= n_slots) return;
   const int c = cfg_of[p];
   if (c < 0) return;
@@ -98,28 +101,6 @@ __global__ void k_md_unpermute(int64_t n_slots, const int* __restrict__ cfg_of, 
   xd_user[i] = Dbl3{r[0], r[1], r[2]};
   x_user[i] = make_float4(f[0], f[1], f[2], 0.f);
   v_user[i] = vel4[p];
-}
-
-__global__ void k_md_repermute(int64_t n_slots, const int* __restrict__ orig, const Dbl3* __restrict__ xd_user,
-                               const float4* __restrict__ x_user, const float4* __restrict__ v_user,
-                               const float4* __restrict__ pos4, Dbl3* __restrict__ xd, float4* __restrict__ vel4,
-                               float4* __restrict__ ref4, const int* __restrict__ gate) {
-  if (*gate == 0) return;
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n_slots) return;
-  const int i = orig[p];
-  if (i < 0) {
-    vel4[p] = make_float4(0.f, 0.f, 0.f, 0.f);
-    return;
-  }
-  // the staging kernel wraps again only in a last-ulp case at a cell face;
-  // carry that shift (zero otherwise) into the float64 position
-  const float4 xs = pos4[p], xu = x_user[i];
-  const Dbl3 r = xd_user[i];
-  xd[p] = Dbl3{r.x + ((double)xs.x - (double)xu.x), r.y + ((double)xs.y - (double)xu.y),
-               r.z + ((double)xs.z - (double)xu.z)};
-  vel4[p] = v_user[i];
-  ref4[p] = pos4[p];
 }
 
 __global__ void k_md_kick2(int64_t n_slots, MdConst mc, const int* __restrict__ orig, const float4* __restrict__ pos4,
@@ -314,21 +295,26 @@ struct nepmi_md {
     const int64_t ns = nbr.n_slots;
     hipLaunchKernelGGL(k_md_unpermute, dim3(nb256(ns)), dim3(256), 0, st, ns, nbr.cfg_of.ptr<int>(),
                        nbr.orig.ptr<int>(), nbr.cfgs.ptr<CfgDev>(), xd.ptr<Dbl3>(), vel4.ptr<float4>(),
-                       xd_user.ptr<Dbl3>(), x_user.ptr<float4>(), v_user.ptr<float4>(), gate);
-    return after_unpermute(st, gate);
+                       xd_user.ptr<Dbl3>(), x_user.ptr<float4>(), v_user.ptr<float4>(), nbr.cnt.ptr<int>(),
+                       (int64_t)n_species * nbr.total_bins + 1, gate);
+    return after_unpermute(st, gate, true);
   }
 
-  int after_unpermute(hipStream_t st, const int* gate) {
+  // Sort and lists from the caller-order state; the sort moves the state into
+  // the new slot order.  cnt_zeroed: the key counts are already clear.
+  int after_unpermute(hipStream_t st, const int* gate, bool cnt_zeroed) {
+    SlotCarry carry;
+    carry.xd_user = reinterpret_cast<const double*>(xd_user.ptr<Dbl3>());
+    carry.x_user = x_user.ptr<float4>();
+    carry.v_user = v_user.ptr<float4>();
+    carry.xd = reinterpret_cast<double*>(xd.ptr<Dbl3>());
+    carry.vel4 = vel4.ptr<float4>();
+    carry.ref4 = ref4.ptr<float4>();
     int rc;
-    if ((rc = nbr.launch_sort(st, x_user.ptr<float>(), 4, species_user.ptr<int32_t>(), n_species, gate))) return rc;
-    if ((rc = nbr.launch_lists(st, n_species, gate))) return rc;
-    const int64_t ns = nbr.n_slots;
-    hipLaunchKernelGGL(k_md_repermute, dim3(nb256(ns)), dim3(256), 0, st, ns, nbr.orig.ptr<int>(),
-                       xd_user.ptr<Dbl3>(), x_user.ptr<float4>(), v_user.ptr<float4>(), nbr.pos4.ptr<float4>(),
-                       xd.ptr<Dbl3>(),
-                       vel4.ptr<float4>(), ref4.ptr<float4>(), gate);
-    NEPMI_HIP(hipGetLastError());
-    return NEPMI_OK;
+    if ((rc = nbr.launch_sort(st, x_user.ptr<float>(), 4, species_user.ptr<int32_t>(), n_species, gate, cnt_zeroed,
+                              &carry)))
+      return rc;
+    return nbr.launch_lists(st, n_species, gate);
   }
 
   int step_launch(hipStream_t st) {
@@ -378,7 +364,8 @@ struct nepmi_md {
     const int64_t ns = nbr.n_slots;
     hipLaunchKernelGGL(k_md_unpermute, dim3(nb256(ns)), dim3(256), 0, st, ns, nbr.cfg_of.ptr<int>(),
                        nbr.orig.ptr<int>(), nbr.cfgs.ptr<CfgDev>(), xd.ptr<Dbl3>(), vel4.ptr<float4>(),
-                       snap_xd.ptr<Dbl3>(), snap_x.ptr<float4>(), snap_v.ptr<float4>(), one.ptr<int>());
+                       snap_xd.ptr<Dbl3>(), snap_x.ptr<float4>(), snap_v.ptr<float4>(), nullptr, (int64_t)0,
+                       one.ptr<int>());
     NEPMI_HIP(hipGetLastError());
     NEPMI_HIP(hipMemcpyAsync(snap_cnt.p, counters.p, 16, hipMemcpyDeviceToDevice, st));
     return NEPMI_OK;
@@ -402,7 +389,7 @@ struct nepmi_md {
       NEPMI_HIP(hipMemcpyAsync(counters.p, snap_cnt.p, 16, hipMemcpyDeviceToDevice, st));
       fill_int(st, flags, kFlagCount, 0, nullptr);
       hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, flags + kFlagRebuild, 1);
-      if ((rc = after_unpermute(st, flags + kFlagRebuild))) return rc;
+      if ((rc = after_unpermute(st, flags + kFlagRebuild, false))) return rc;
       int hf[kFlagCount];
       if ((rc = nbr.check_flags(st, hf))) return rc;
       if (!hf[kFlagOverflow]) break;
@@ -498,7 +485,7 @@ int nepmi_md_create(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, cons
   // first build, with capacity growth and a margin for the density
   // fluctuations of the run
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, nb.flags.ptr<int>() + kFlagRebuild, 1);
-  if ((rc = md->after_unpermute(st, nb.flags.ptr<int>() + kFlagRebuild))) return fail(rc);
+  if ((rc = md->after_unpermute(st, nb.flags.ptr<int>() + kFlagRebuild, false))) return fail(rc);
   int hf[kFlagCount];
   if ((rc = nb.check_flags(st, hf))) return fail(rc);
   const int wantR = hf[kFlagMaxR] + hf[kFlagMaxR] / 4 + 16, wantA = hf[kFlagMaxA] + hf[kFlagMaxA] / 4 + 16;

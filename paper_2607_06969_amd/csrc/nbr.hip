@@ -134,49 +134,60 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_tiles(const int* __restrict
   if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
 }
 
-// Scan of the tile sums (one block; n_tiles <= kScanTile) and the final total.
+// Scan of the tile sums (one block; n_tiles <= kScanTile) and the final
+// total, then the processing order's species bases: base[z] = first slot of
+// species z, each species' group padded to the wavefront size.  out holds the
+// tile-local prefixes of k_scan_tiles; the global prefix of key k is
+// out[k] + (scanned tile sum of k's tile).
 __global__ __launch_bounds__(kScanBlock) void k_scan_sums(int* __restrict__ tile_sums, int n_tiles,
-                                                          int* __restrict__ out, int M,
+                                                          int* __restrict__ out, int M, int total_bins,
+                                                          int n_species, int* __restrict__ species_base,
                                                           const int* __restrict__ gate) {
   if (gate && *gate == 0) return;
   __shared__ int sh[kScanBlock];
-  const int base = threadIdx.x * kScanItems;
+  __shared__ int tile_ex[kScanTile];
+  const int b0 = threadIdx.x * kScanItems;
   int v[kScanItems], s = 0;
   for (int j = 0; j < kScanItems; ++j) {
-    v[j] = (base + j < n_tiles) ? tile_sums[base + j] : 0;
+    v[j] = (b0 + j < n_tiles) ? tile_sums[b0 + j] : 0;
     s += v[j];
   }
   int total;
   int ex = block_exclusive_scan(s, sh, total);
   for (int j = 0; j < kScanItems; ++j) {
-    if (base + j < n_tiles) tile_sums[base + j] = ex;
+    if (b0 + j < n_tiles) {
+      tile_sums[b0 + j] = ex;
+      tile_ex[b0 + j] = ex;
+    }
     ex += v[j];
   }
   if (threadIdx.x == 0) out[M] = total;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  int acc = 0, lo = 0;  // lo: global prefix at z * total_bins
+  for (int z = 0; z < n_species; ++z) {
+    const int k = (z + 1) * total_bins;
+    const int hi = k < M ? out[k] + tile_ex[k / kScanTile] : total;
+    species_base[z] = acc;
+    acc += (hi - lo + kWave - 1) / kWave * kWave;
+    lo = hi;
+  }
+  species_base[n_species] = acc;
 }
 
+// Global prefixes, also copied into the scatter cursors.
 __global__ void k_scan_add(int* __restrict__ out, int M, const int* __restrict__ tile_sums,
-                           const int* __restrict__ gate) {
+                           int* __restrict__ cursor, const int* __restrict__ gate) {
   if (gate && *gate == 0) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < M) out[i] += tile_sums[i / kScanTile];
+  if (i < M) {
+    const int v = out[i] + tile_sums[i / kScanTile];
+    out[i] = v;
+    cursor[i] = v;
+  }
 }
 
 // ------------------------------------------------------- processing order
-
-// base[z] = first slot of species z; groups are padded to the wavefront size.
-__global__ void k_species_base(const int* __restrict__ start, int total_bins, int n_species, int* __restrict__ base,
-                               const int* __restrict__ gate) {
-  if (gate && *gate == 0) return;
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  int acc = 0;
-  for (int z = 0; z < n_species; ++z) {
-    base[z] = acc;
-    const int c = start[(z + 1) * total_bins] - start[z * total_bins];
-    acc += (c + kWave - 1) / kWave * kWave;
-  }
-  base[n_species] = acc;
-}
 
 // Slot of every atom (order inside a key decided by an atomic; made
 // deterministic by k_sort_keys).
@@ -217,13 +228,16 @@ __global__ void k_sort_keys(int M, const int* __restrict__ start, const int* __r
 }
 
 // Fill the slot arrays.  Padding slots get orig = -1 and their group's species.
+// With carry.xd set, the carried state moves into the slot as well: the
+// staging wraps again only in a last-ulp case at a cell face, and that shift
+// (zero otherwise) is carried into the float64 position.
 __global__ void k_fill_slots(int64_t n_slots, const int* __restrict__ base, const int* __restrict__ start,
                              int total_bins, int n_species, const int* __restrict__ perm,
                              const float4* __restrict__ pos_tmp, const int* __restrict__ cfg_tmp,
                              const int* __restrict__ crd_tmp,
                              const int* __restrict__ key, float4* __restrict__ pos4, int* __restrict__ cfg_of,
                              int* __restrict__ orig, int* __restrict__ bin_of, int* __restrict__ slot_of,
-                             const int* __restrict__ gate) {
+                             SlotCarry carry, const int* __restrict__ gate) {
   if (gate && *gate == 0) return;
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n_slots) return;
@@ -235,16 +249,28 @@ __global__ void k_fill_slots(int64_t n_slots, const int* __restrict__ base, cons
     const int c = start[(z + 1) * total_bins] - start[z * total_bins];
     if (r < c) {
       const int i = perm[p];
-      pos4[p] = pos_tmp[i];
+      const float4 xs = pos_tmp[i];
+      pos4[p] = xs;
       cfg_of[p] = cfg_tmp[i];
       orig[p] = i;
       bin_of[p] = crd_tmp[i];  // packed bin coordinates
       if (slot_of) slot_of[i] = (int)p;
+      if (carry.xd) {
+        const float4 xu = carry.x_user[i];
+        const double* r = carry.xd_user + 3 * (int64_t)i;
+        double* o = carry.xd + 3 * p;
+        o[0] = r[0] + ((double)xs.x - (double)xu.x);
+        o[1] = r[1] + ((double)xs.y - (double)xu.y);
+        o[2] = r[2] + ((double)xs.z - (double)xu.z);
+        carry.vel4[p] = carry.v_user[i];
+        carry.ref4[p] = xs;
+      }
       return;
     }
   } else {
     z = 0;
   }
+  if (carry.xd) carry.vel4[p] = make_float4(0.f, 0.f, 0.f, 0.f);
   pos4[p] = make_float4(0.f, 0.f, 0.f, __int_as_float(z));
   cfg_of[p] = -1;
   orig[p] = -1;
@@ -497,13 +523,6 @@ __global__ void k_fill_int(int* __restrict__ p, int64_t n, int v, const int* __r
   if (i < n) p[i] = v;
 }
 
-__global__ void k_copy_int(int* __restrict__ dst, const int* __restrict__ src, int64_t n,
-                           const int* __restrict__ gate) {
-  if (gate && *gate == 0) return;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) dst[i] = src[i];
-}
-
 void fill_int(hipStream_t st, int* p, int64_t n, int v, const int* gate) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_fill_int, dim3(nblk(n, 256)), dim3(256), 0, st, p, n, v, gate);
@@ -745,9 +764,9 @@ int NbrPipeline::build(hipStream_t st, const float* pos, const int32_t* species)
 }
 
 int NbrPipeline::launch_sort(hipStream_t st, const float* pos, int pos_stride, const int32_t* species, int n_species,
-                             const int* gate) {
+                             const int* gate, bool cnt_zeroed, const SlotCarry* carry) {
   const int M = n_species * total_bins;
-  fill_int(st, cnt.ptr<int>(), M + 1, 0, gate);
+  if (!cnt_zeroed) fill_int(st, cnt.ptr<int>(), M + 1, 0, gate);
   if (N > 0)
   hipLaunchKernelGGL(k_stage, dim3(nblk(N, 256)), dim3(256), 0, st, N, n_cfg, atom_off_dev.ptr<int64_t>(),
                      cfgs.ptr<CfgDev>(), pos, pos_stride, species, n_species, total_bins, pos_tmp.ptr<float4>(),
@@ -756,13 +775,9 @@ int NbrPipeline::launch_sort(hipStream_t st, const float* pos, int pos_stride, c
   hipLaunchKernelGGL(k_scan_tiles, dim3(n_tiles), dim3(kScanBlock), 0, st, cnt.ptr<int>(), M, start.ptr<int>(),
                      tile_sums.ptr<int>(), gate);
   hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, st, tile_sums.ptr<int>(), n_tiles, start.ptr<int>(),
-                     M, gate);
+                     M, total_bins, n_species, base.ptr<int>(), gate);
   hipLaunchKernelGGL(k_scan_add, dim3(nblk(M, 256)), dim3(256), 0, st, start.ptr<int>(), M, tile_sums.ptr<int>(),
-                     gate);
-  hipLaunchKernelGGL(k_species_base, dim3(1), dim3(64), 0, st, start.ptr<int>(), total_bins, n_species,
-                     base.ptr<int>(), gate);
-  hipLaunchKernelGGL(k_copy_int, dim3(nblk(M, 256)), dim3(256), 0, st, cursor.ptr<int>(), start.ptr<int>(), (int64_t)M,
-                     gate);
+                     cursor.ptr<int>(), gate);
   if (N > 0)
   hipLaunchKernelGGL(k_scatter, dim3(nblk(N, 256)), dim3(256), 0, st, N, key.ptr<int>(), start.ptr<int>(),
                      cursor.ptr<int>(), base.ptr<int>(), total_bins, perm.ptr<int>(), gate);
@@ -771,7 +786,7 @@ int NbrPipeline::launch_sort(hipStream_t st, const float* pos, int pos_stride, c
   hipLaunchKernelGGL(k_fill_slots, dim3(nblk(n_slots, 256)), dim3(256), 0, st, n_slots, base.ptr<int>(),
                      start.ptr<int>(), total_bins, n_species, perm.ptr<int>(), pos_tmp.ptr<float4>(),
                      cfg_tmp.ptr<int>(), crd_tmp.ptr<int>(), key.ptr<int>(), pos4.ptr<float4>(), cfg_of.ptr<int>(), orig.ptr<int>(),
-                     bin_of.ptr<int>(), slot_of.ptr<int>(), gate);
+                     bin_of.ptr<int>(), slot_of.ptr<int>(), carry ? *carry : SlotCarry{}, gate);
   NEPMI_HIP(hipGetLastError());
   return NEPMI_OK;
 }

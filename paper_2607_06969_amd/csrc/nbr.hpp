@@ -50,6 +50,18 @@ struct DevBuf {
   DevBuf& operator=(const DevBuf&) = delete;
 };
 
+// State that a rebuild moves from caller order into the new slot order along
+// with the positions (MD: float64 positions, velocities, and the positions of
+// this build as the drift reference).  Used when xd is not null.
+struct SlotCarry {
+  const double* xd_user = nullptr;  // [N][3] float64 positions, caller order
+  const float4* x_user = nullptr;   // [N] the float32 positions the build staged
+  const float4* v_user = nullptr;   // [N] velocities
+  double* xd = nullptr;             // [n_slots][3]
+  float4* vel4 = nullptr;           // [n_slots] (zero in padding slots)
+  float4* ref4 = nullptr;           // [n_slots]
+};
+
 // Neighbour lists of one batch of configurations, in processing order.
 struct NbrPipeline {
   int64_t N = 0;        // atoms
@@ -87,9 +99,12 @@ struct NbrPipeline {
   // setup sizes the lists afresh).
   void use_arena(Arena* a);
   // Stage, bin and sort (pos: N x pos_stride floats).  gate: optional device
-  // flag; every kernel returns at once when *gate == 0.
+  // flag; every kernel returns at once when *gate == 0.  cnt_zeroed: the
+  // caller has already cleared the n_species * total_bins + 1 key counts
+  // (cnt) on the stream.  carry: state moved into slot order with the
+  // positions (optional).
   int launch_sort(hipStream_t st, const float* pos, int pos_stride, const int32_t* species, int n_species,
-                  const int* gate);
+                  const int* gate, bool cnt_zeroed = false, const SlotCarry* carry = nullptr);
   int launch_lists(hipStream_t st, int n_species, const int* gate);
   // Full build with capacity check and regrow (synchronises st once or twice).
   int build(hipStream_t st, const float* pos, const int32_t* species);
