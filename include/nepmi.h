@@ -259,13 +259,15 @@ int nepmi_md_stats(nepmi_md *md, int64_t *steps, int64_t *rebuilds, int64_t *reg
 void nepmi_md_destroy(nepmi_md *md);
 
 /* Advance n_steps (>= 1) like nepmi_md_step and time the hot kernels of
- * exactly these steps: the step graph records HIP events before k_desc,
- * k_force and k_gather and after k_gather, each step into its own events.
- * ms_per_launch: host double[3] = average duration (ms) of descriptors +
- * network, pair forces + virial, force gather over the n_steps replays.
- * Chunks, checkpoints and overflow recovery as nepmi_md_step (a chunk run
- * again records its steps again).  Errors as nepmi_md_step, and
- * NEPMI_UNSUPPORTED if the graph could not be built with timing nodes. */
+ * these steps: steps 0, 4, 8, ... of the call replay a copy of the step graph
+ * that records HIP events before k_desc, k_force and k_gather and after
+ * k_gather, each step into its own events; the other steps replay the plain
+ * graph (the event nodes cost a few microseconds each).  ms_per_launch: host
+ * double[3] = average duration (ms) of descriptors + network, pair forces +
+ * virial, force gather over the timed replays.  Chunks, checkpoints and
+ * overflow recovery as nepmi_md_step (a chunk run again records its steps
+ * again).  Errors as nepmi_md_step, and NEPMI_UNSUPPORTED if the graph could
+ * not be built with timing nodes. */
 int nepmi_md_step_timed(nepmi_md *md, int32_t n_steps, double *ms_per_launch, void *stream);
 
 /* Average duration of each hot kernel, measured with HIP events recorded on

@@ -204,12 +204,15 @@ struct nepmi_md {
   // device counters, and a device word holding 1 (an always-open gate)
   DevBuf snap_xd, snap_x, snap_v, snap_cnt, one;
   hipStream_t cap_stream = nullptr;
-  hipGraph_t graph = nullptr;
+  hipGraph_t graph = nullptr;     // the step
   hipGraphExec_t exec = nullptr;
+  hipGraph_t graph_t = nullptr;   // the same step with the timing nodes
+  hipGraphExec_t exec_t = nullptr;
   int64_t host_steps = 0;
   int64_t regrows = 0;
   // timing: events recorded before k_desc, k_force, k_gather and after
-  // k_gather in every replay; their graph nodes; a pool of per-step events
+  // k_gather in every replay of exec_t; their graph nodes; a pool of
+  // per-step events
   hipEvent_t tev[4] = {nullptr, nullptr, nullptr, nullptr};
   hipGraphNode_t tnode[4] = {nullptr, nullptr, nullptr, nullptr};
   bool timing = false, mark_failed = false;
@@ -317,7 +320,7 @@ struct nepmi_md {
     return nbr.launch_lists(st, n_species, gate);
   }
 
-  int step_launch(hipStream_t st) {
+  int step_launch(hipStream_t st, bool timed) {
     const int64_t ns = nbr.n_slots;
     int* flags = nbr.flags.ptr<int>();
     hipLaunchKernelGGL(k_md_kick_drift, dim3(nb256(ns)), dim3(256), 0, st, ns, mc, nbr.cfg_of.ptr<int>(),
@@ -325,7 +328,7 @@ struct nepmi_md {
                        ref4.ptr<float4>(), flags);
     int rc;
     if ((rc = rebuild(st, flags + kFlagRebuild))) return rc;
-    if ((rc = forces(st, true))) return rc;
+    if ((rc = forces(st, timed))) return rc;
     hipLaunchKernelGGL(k_md_kick2, dim3(nb256(ns)), dim3(256), 0, st, ns, mc, nbr.orig.ptr<int>(),
                        nbr.pos4.ptr<float4>(), F4.ptr<float4>(), vel4.ptr<float4>(), Ki.ptr<float>());
     if ((rc = red.run(st, Ei.ptr<float>(), Wi.ptr<float>(), Ki.ptr<float>(), epot.ptr<double>(), vir.ptr<double>(),
@@ -336,16 +339,18 @@ struct nepmi_md {
     return NEPMI_OK;
   }
 
-  // Capture one step into the graph (replacing any earlier one).
-  int capture() {
+  void drop_graphs() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
-    exec = nullptr;
-    graph = nullptr;
-    for (hipGraphNode_t& n : tnode) n = nullptr;
-    mark_failed = false;
+    if (exec_t) (void)hipGraphExecDestroy(exec_t);
+    if (graph_t) (void)hipGraphDestroy(graph_t);
+    exec = exec_t = nullptr;
+    graph = graph_t = nullptr;
+  }
+
+  int capture_one(bool timed, hipGraph_t& graph_out, hipGraphExec_t& exec_out) {
     NEPMI_HIP(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
-    int rc = step_launch(cap_stream);
+    int rc = step_launch(cap_stream, timed);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(cap_stream, &g);
     if (rc) {
@@ -353,8 +358,20 @@ struct nepmi_md {
       return rc;
     }
     if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-    graph = g;
-    NEPMI_HIP(hipGraphInstantiate(&exec, g, nullptr, nullptr, 0));
+    graph_out = g;
+    NEPMI_HIP(hipGraphInstantiate(&exec_out, g, nullptr, nullptr, 0));
+    return NEPMI_OK;
+  }
+
+  // Capture one step into the graphs (replacing any earlier ones): the plain
+  // step, and the step with event nodes around k_desc, k_force and k_gather
+  // that timed runs replay on a sample of their steps.
+  int capture() {
+    drop_graphs();
+    for (hipGraphNode_t& n : tnode) n = nullptr;
+    mark_failed = false;
+    int rc;
+    if ((rc = capture_one(false, graph, exec)) || (rc = capture_one(true, graph_t, exec_t))) return rc;
     timing = !mark_failed && tnode[0] && tnode[1] && tnode[2] && tnode[3];
     return NEPMI_OK;
   }
@@ -414,8 +431,7 @@ struct nepmi_md {
   }
 
   ~nepmi_md() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
+    drop_graphs();
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (hipEvent_t e : tev)
       if (e) (void)hipEventDestroy(e);
@@ -534,8 +550,15 @@ int nepmi_md_create(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, cons
 constexpr int kMdCheckEvery = 32;
 constexpr int kMdMaxRegrows = 3;
 
-// Advance n_steps replays with overflow recovery; with `ms`, the graph's event
-// nodes record into per-step events and ms[0..2] get the average durations.
+// Timed runs replay the graph with the event nodes on every kTimedEvery-th
+// step (the first of each group) and the plain graph on the others: the
+// kernel durations are averages over those steps, and the event nodes (a few
+// microseconds each) stay out of most of the steps that the run times.
+constexpr int kTimedEvery = 4;
+
+// Advance n_steps replays with overflow recovery; with `ms`, the timed graph's
+// event nodes record into per-step events and ms[0..2] get the average
+// durations over the steps that ran it.
 static int md_run(nepmi_md* md, int32_t n_steps, hipStream_t st, double* ms) {
   if (ms) {
     const size_t need = 4 * (size_t)n_steps;
@@ -555,13 +578,15 @@ static int md_run(nepmi_md* md, int32_t n_steps, hipStream_t st, double* ms) {
       return NEPMI_UNSUPPORTED;
     }
     for (int s = done; s < done + k; ++s) {
-      if (ms) {
+      if (ms && s % kTimedEvery == 0) {
         // every launch is enqueued before the next change of its event nodes,
-        // so each step records into its own four events
+        // so each timed step records into its own four events
         for (int i = 0; i < 4; ++i)
-          NEPMI_HIP(hipGraphExecEventRecordNodeSetEvent(md->exec, md->tnode[i], md->tpool[4 * (size_t)s + i]));
+          NEPMI_HIP(hipGraphExecEventRecordNodeSetEvent(md->exec_t, md->tnode[i], md->tpool[4 * (size_t)s + i]));
+        NEPMI_HIP(hipGraphLaunch(md->exec_t, st));
+      } else {
+        NEPMI_HIP(hipGraphLaunch(md->exec, st));
       }
-      NEPMI_HIP(hipGraphLaunch(md->exec, st));
     }
     int hf[kFlagCount];
     if ((rc = md->nbr.check_flags(st, hf))) return rc;
@@ -589,8 +614,9 @@ static int md_run(nepmi_md* md, int32_t n_steps, hipStream_t st, double* ms) {
   }
   if (ms) {
     double acc[3] = {0, 0, 0};
+    int n_timed = 0;
     rc = NEPMI_OK;
-    for (int s = 0; s < n_steps && !rc; ++s)
+    for (int s = 0; s < n_steps && !rc; s += kTimedEvery, ++n_timed)
       for (int i = 0; i < 3; ++i) {
         float t = 0.f;
         if (hipEventElapsedTime(&t, md->tpool[4 * (size_t)s + i], md->tpool[4 * (size_t)s + i + 1]) != hipSuccess) {
@@ -599,9 +625,9 @@ static int md_run(nepmi_md* md, int32_t n_steps, hipStream_t st, double* ms) {
         }
         acc[i] += t;
       }
-    for (int i = 0; i < 4; ++i) (void)hipGraphExecEventRecordNodeSetEvent(md->exec, md->tnode[i], md->tev[i]);
+    for (int i = 0; i < 4; ++i) (void)hipGraphExecEventRecordNodeSetEvent(md->exec_t, md->tnode[i], md->tev[i]);
     if (rc) return rc;
-    for (int i = 0; i < 3; ++i) ms[i] = acc[i] / n_steps;
+    for (int i = 0; i < 3; ++i) ms[i] = acc[i] / n_timed;
   }
   return NEPMI_OK;
 }

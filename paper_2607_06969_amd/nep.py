@@ -357,8 +357,9 @@ class NepMD:
 
     def step_timed(self, n):
         """Advance n steps; returns the average duration (ms) of the descriptor,
-        pair-force and gather kernels over exactly these steps (HIP events
-        recorded inside the step graph)."""
+        pair-force and gather kernels over steps 0, 4, 8, ... of these (HIP
+        events recorded inside a copy of the step graph that those steps
+        replay; the others replay the plain graph)."""
         ms = (C.c_double * 3)()
         check(load().nepmi_md_step_timed(self._h, int(n), ms, _stream()))
         return {"desc": ms[0], "force": ms[1], "gather": ms[2]}

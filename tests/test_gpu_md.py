@@ -92,8 +92,9 @@ def test_md_time_reversibility():
 
 
 def test_step_timed_advances_like_step():
-    """The timed replay (per-step events inside the graph) gives the same
-    trajectory bit for bit as the plain replay, and positive kernel times."""
+    """The timed replay (the graph with event nodes on every fourth step, the
+    plain graph on the others) gives the same trajectory bit for bit as the
+    plain replay, and positive kernel times."""
     _, _, _, m1, _, md1 = _make(seed=63, variants=(0, 0))
     _, _, _, m2, _, md2 = _make(seed=63, variants=(0, 0))
     assert m1.variants() == m2.variants() == (0, 0)  # pinned: MD creation keeps them
