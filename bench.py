@@ -394,11 +394,12 @@ def bench_serving(nep, W, hp, params, steps=20):
             "one_at_a_time_step_ms_p99": 1e3 * float(np.percentile(lat1, 99))}
 
 
-def amortised_window(md, min_rebuilds=2, min_steps=100, max_steps=2000, chunk=10):
-    """Steps in chunks of `chunk` until the window holds at least min_rebuilds
-    in-graph neighbour-list rebuilds and min_steps steps: the MD cost per step
-    with the rebuilds amortised.  Each chunk ends with the library's overflow
-    check (one stream synchronisation per chunk)."""
+def amortised_window(md, min_rebuilds=2, min_steps=128, max_steps=2048, chunk=64):
+    """Steps in calls of `chunk` steps until the window holds at least
+    min_rebuilds in-graph neighbour-list rebuilds and min_steps steps: the MD
+    cost per step with the rebuilds amortised.  Each call checkpoints the
+    state and checks for list overflow every 32 steps (one stream
+    synchronisation each), as any run of that length does."""
     import torch
     st0 = md.stats()
     torch.cuda.synchronize()
