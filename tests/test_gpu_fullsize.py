@@ -3,6 +3,7 @@ benchmark times:
   - the 900,000-atom rocksalt cell stepped as the timed MD graph (autotuned
     kernel variants, timed-step replay, in-graph list rebuild), every output
     against the FP64 oracle on the same positions;
+  - the float64 evaluation of the same cell (bar 1e-10);
   - the full 256-configuration training batch: loss and parameter gradient;
   - sampled cells (smallest, median, largest) of the 64-cell serving batch,
     evaluated inside the batched MD handle.
@@ -45,6 +46,26 @@ def test_md_900k_after_timed_steps_matches_oracle(oracle_lib):
     rF, rV = rel(st["F"].cpu().numpy(), ref["F"]), rel(st["V"][0].cpu().numpy(), ref["V"][0])
     print(f"[fullsize] MD dE/N {dE:.2e} F {rF:.2e} V {rV:.2e}", flush=True)
     assert dE < 1e-6 and rF < 1e-5 and rV < 1e-5
+
+
+def test_float64_900k_matches_oracle(oracle_lib):
+    """The float64 evaluation of the full 900,000-atom cell against the FP64
+    oracle on the same positions, at the float64 bar (1e-10)."""
+    from paper_2607_06969_amd import nep
+    hp = W.hp_gst()
+    p = W.random_params(hp, W.SEED_PARAM + 3)
+    s = W.rocksalt_gst(100, seed=W.SEED_POS + 3)
+    m = nep.NepModel(hp, p)
+    print(f"[fullsize] float64 {s.n_atoms} atoms", flush=True)
+    got = m.compute64(nep.Batch.from_system(s), torch.tensor(p, dtype=torch.float64, device="cuda"),
+                      pos=torch.tensor(s.pos, dtype=torch.float64, device="cuda"))
+    got = {k: v.cpu().numpy() for k, v in got.items()}
+    ref = oracle_lib.evaluate(hp, p, s, nbr_mode=1)
+    n = s.n_atoms
+    dE = abs(got["E"][0] - ref["E"][0]) / n
+    rF, rV = rel(got["F"], ref["F"]), rel(got["V"].reshape(-1), ref["V"].reshape(-1))
+    print(f"[fullsize] float64 dE/N {dE:.2e} F {rF:.2e} V {rV:.2e}", flush=True)
+    assert dE <= 1e-10 and rF <= 1e-10 and rV <= 1e-10
 
 
 def test_training_batch_256_matches_oracle(oracle_lib):
