@@ -289,8 +289,8 @@ __global__ __launch_bounds__(256) void k_build_lists(int64_t n_slots, int n_spec
                                                      const int* __restrict__ bin_of, const int* __restrict__ start,
                                                      const int* __restrict__ base, float rclR2, float rclA2, int capR,
                                                      int capA, int rowTA, uint32_t* __restrict__ nbrR,
-                                                     uint32_t* __restrict__ nbrTA, int* __restrict__ cntR,
-                                                     int* __restrict__ cntAV,
+                                                     uint32_t* __restrict__ nbrTA, uint64_t* __restrict__ angm,
+                                                     int* __restrict__ cntR, int* __restrict__ cntAV,
                                                      int* __restrict__ flags, const int* __restrict__ gate) {
   if (gate && *gate == 0) return;
   const int64_t p = xcd_tile() * blockDim.x + threadIdx.x;
@@ -345,12 +345,15 @@ __global__ __launch_bounds__(256) void k_build_lists(int64_t n_slots, int n_spec
   // Entries are collected four at a time and stored as one group: one store
   // per four entries instead of one per entry.  The entries within
   // rc_angular + skin (the angular part of the list, which the reverse index
-  // searches) are also kept in their own row-major list.
+  // searches) are also kept in their own row-major list, and marked in a bit
+  // mask over the list (bit k % 64 of word k / 64: entry k is in that part).
   const int capG = 4 * list_groups(capR);   // entries the groups can hold
   const int capGA = 4 * list_groups(capA);
   uint4 grp = make_uint4(0u, 0u, 0u, 0u), gra = grp;
+  uint64_t mword = 0;
   uint4* colG = reinterpret_cast<uint4*>(nbrR) + p;         // column-major groups
   uint4* rowA = reinterpret_cast<uint4*>(nbrTA + p * rowTA);  // angular part, row-major
+  uint64_t* colM = angm + p;                                // mask words, column-major
   int kR = 0, kA = 0;
   for (int z = 0; z < n_species; ++z) {
     for (int o = 0; o < 27; ++o) {
@@ -382,8 +385,13 @@ __global__ __launch_bounds__(256) void k_build_lists(int64_t n_slots, int n_spec
             grp.y = u == 1 ? e : grp.y;
             grp.z = u == 2 ? e : grp.z;
             grp.w = u == 3 ? e : grp.w;
+            if (d2 < rclA2) mword |= 1ull << (kR & 63);
             ++kR;
             if (u == 3 && kR <= capG) colG[(int64_t)((kR >> 2) - 1) * n_slots] = grp;
+            if ((kR & 63) == 0) {
+              if (kR <= capG) colM[(int64_t)((kR >> 6) - 1) * n_slots] = mword;
+              mword = 0;
+            }
             if (d2 < rclA2) {
               const uint32_t ua = (uint32_t)kA & 3u;
               gra.x = ua == 0 ? e : gra.x;
@@ -398,8 +406,9 @@ __global__ __launch_bounds__(256) void k_build_lists(int64_t n_slots, int n_spec
       }
     }
   }
-  // the last, partly filled groups
+  // the last, partly filled groups and mask word
   if ((kR & 3) && kR < capG) colG[(int64_t)(kR >> 2) * n_slots] = grp;
+  if ((kR & 63) && kR < capG) colM[(int64_t)(kR >> 6) * n_slots] = mword;
   if ((kA & 3) && kA < capGA) rowA[kA >> 2] = gra;
   cntR[p] = kR < capR ? kR : capR;
   cntAV[p] = kA < capA ? kA : capA;
@@ -416,7 +425,8 @@ __global__ __launch_bounds__(256) void k_build_lists(int64_t n_slots, int n_spec
 // opposite image code), else 0xFFFFFFFF; 0xFFFFFFFE marks an angular entry
 // whose partner was not found, which also raises the asymmetry flag.  The
 // pair-force buffer is indexed through these positions, so that each step's
-// gather reads without searching.  The search reads the angular part of j's
+// gather reads without searching.  The angular entries are known from the
+// bit mask k_build_lists leaves, and the search reads the angular part of j's
 // list only (about a third of the list).  The four entries of a group are
 // searched together and their results stored together.  Grid (slot tiles, rows): row y takes the
 // groups g = y, y + rows, ... of each list, so the searches of one atom run
@@ -427,11 +437,10 @@ __global__ __launch_bounds__(256) void k_build_lists(int64_t n_slots, int n_spec
 // rebuild gate sends them home at once).
 constexpr int kRevSplit = 4;
 constexpr unsigned kRevOneRow = 2048;
-__global__ __launch_bounds__(256) void k_reverse(int64_t n_slots, const CfgDev* __restrict__ cfgs,
-                                                 const float4* __restrict__ pos4, const int* __restrict__ cfg_of,
+__global__ __launch_bounds__(256) void k_reverse(int64_t n_slots, const int* __restrict__ cfg_of,
                                                  const uint32_t* __restrict__ nbrR, const uint32_t* __restrict__ nbrTA,
-                                                 int rowTA, const int* __restrict__ cntR,
-                                                 const int* __restrict__ cntAV, float rclA2,
+                                                 int rowTA, const uint64_t* __restrict__ angm,
+                                                 const int* __restrict__ cntR, const int* __restrict__ cntAV,
                                                  uint32_t* __restrict__ vrev, int* __restrict__ flags,
                                                  const int* __restrict__ gate) {
   if (gate && *gate == 0) return;
@@ -439,44 +448,30 @@ __global__ __launch_bounds__(256) void k_reverse(int64_t n_slots, const CfgDev* 
   if (p >= n_slots) return;
   const int c = cfg_of[p];
   if (c < 0) return;
-  float H[9];
-#pragma unroll
-  for (int x = 0; x < 9; ++x) H[x] = cfgs[c].H[x];
-  const float4 xi = pos4[p];
   const int n = cntR[p];
   const int ng = list_groups(n);
   const uint4* grp = reinterpret_cast<const uint4*>(nbrR) + p;
   uint4* out = reinterpret_cast<uint4*>(vrev) + p;
   bool missing = false;
-  // The four entries of a group are searched side by side: their neighbours'
-  // positions and list lengths are loaded together, then the first kRevWin
-  // entries of every row that needs a search (one memory latency for the
-  // group); longer rows are finished one at a time.
+  // The four entries of a group are searched side by side: the angular ones
+  // (marked by k_build_lists) have their neighbours' list lengths loaded
+  // together, then the first kRevWin entries of every row that needs a search
+  // (one memory latency for the group); longer rows are finished one at a time.
   constexpr int kRevWin = 8;  // uint4 per row read at once (32 entries)
   for (int g = (int)blockIdx.y; g < ng; g += (int)gridDim.y) {
     const uint4 eg = grp[(int64_t)g * n_slots];
-    float4 xq[4];
-    int nq[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int q = (int)(comp4(eg, 4 * g + u < n ? u : 0) & kNbrMask);  // past the end: the group's first entry
-      xq[u] = pos4[q];
-      nq[u] = cntAV[q];
-    }
+    const uint32_t bits = (uint32_t)(angm[(int64_t)(g >> 4) * n_slots + p] >> (4 * (g & 15))) & 15u;
     bool ang[4];
+    int nq[4];
     uint32_t want[4];
     const uint4* row[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const uint32_t e = comp4(eg, u);
-      const uint32_t code = e >> kNbrShift;
-      float sx, sy, sz;
-      image_shift(H, code, sx, sy, sz);
-      const float rx = (xq[u].x - xi.x) + sx, ry = (xq[u].y - xi.y) + sy, rz = (xq[u].z - xi.z) + sz;
-      ang[u] = 4 * g + u < n && pair_d2(rx, ry, rz) < rclA2;
-      want[u] = (uint32_t)p | ((26u - code) << kNbrShift);
+      ang[u] = 4 * g + u < n && ((bits >> u) & 1u);
+      const uint32_t e = comp4(eg, ang[u] ? u : 0);
+      nq[u] = ang[u] ? cntAV[e & kNbrMask] : 0;
+      want[u] = (uint32_t)p | ((26u - (e >> kNbrShift)) << kNbrShift);
       row[u] = reinterpret_cast<const uint4*>(nbrTA + (int64_t)(e & kNbrMask) * rowTA);
-      if (!ang[u]) nq[u] = 0;
     }
     // the angular part of each neighbour's list, row-major, rows padded to a
     // multiple of 4 entries so that the 16-byte reads stay inside the row;
@@ -694,7 +689,7 @@ int NbrPipeline::setup(int n_cfg_, const int64_t* atom_off, const double* cells,
 
 void NbrPipeline::use_arena(Arena* a) {
   DevBuf* all[] = {&cfgs, &atom_off_dev, &key, &cnt, &start, &cursor, &tile_sums, &base, &perm, &pos_tmp,
-                   &cfg_tmp, &crd_tmp, &pos4, &cfg_of, &orig, &bin_of, &slot_of, &nbrR, &cntR, &cntAV, &nbrTA, &vrev,
+                   &cfg_tmp, &crd_tmp, &pos4, &cfg_of, &orig, &bin_of, &slot_of, &nbrR, &cntR, &cntAV, &nbrTA, &angm, &vrev,
                    &cnbrR, &ccntR, &cnbrA, &ccntA, &cposA, &flags};
   for (DevBuf* b : all) {
     b->release();
@@ -718,6 +713,7 @@ int NbrPipeline::ensure_lists(int capR_, int capA_) {
   // groups of four entries (see list_groups); the angular part of the Verlet
   // list, row-major, in rows of rowTA entries
   if ((rc = nbrR.ensure(16 * (size_t)list_groups(capR) * ns)) || (rc = nbrTA.ensure(4 * (size_t)rowTA * ns)) ||
+      (rc = angm.ensure(8 * (size_t)((4 * list_groups(capR) + 63) / 64) * ns)) ||
       (rc = vrev.ensure(16 * (size_t)list_groups(capR) * ns)) ||
       (rc = cnbrR.ensure(16 * (size_t)list_groups(capR) * ns)) ||
       (rc = cnbrA.ensure(16 * (size_t)list_groups(capA) * ns)) ||
@@ -795,12 +791,12 @@ int NbrPipeline::launch_lists(hipStream_t st, int n_species, const int* gate) {
   hipLaunchKernelGGL(k_build_lists, dim3(nblk(n_slots, 256)), dim3(256), 0, st, n_slots, n_species, total_bins,
                      cfgs.ptr<CfgDev>(), pos4.ptr<float4>(), cfg_of.ptr<int>(), bin_of.ptr<int>(), start.ptr<int>(),
                      base.ptr<int>(), rclR2, rclA2, capR, capA, rowTA, nbrR.ptr<uint32_t>(), nbrTA.ptr<uint32_t>(),
-                     cntR.ptr<int>(), cntAV.ptr<int>(), flags.ptr<int>(), gate);
+                     angm.ptr<uint64_t>(), cntR.ptr<int>(), cntAV.ptr<int>(), flags.ptr<int>(), gate);
   const unsigned rev_tiles = (nblk(n_slots, 256) + kXcds - 1) / kXcds * kXcds;
   const unsigned rev_rows = rev_tiles >= kRevOneRow ? 1u : (unsigned)kRevSplit;
-  hipLaunchKernelGGL(k_reverse, dim3(rev_tiles, rev_rows), dim3(256), 0, st, n_slots, cfgs.ptr<CfgDev>(),
-                     pos4.ptr<float4>(), cfg_of.ptr<int>(), nbrR.ptr<uint32_t>(), nbrTA.ptr<uint32_t>(), rowTA,
-                     cntR.ptr<int>(), cntAV.ptr<int>(), rclA2, vrev.ptr<uint32_t>(), flags.ptr<int>(), gate);
+  hipLaunchKernelGGL(k_reverse, dim3(rev_tiles, rev_rows), dim3(256), 0, st, n_slots, cfg_of.ptr<int>(),
+                     nbrR.ptr<uint32_t>(), nbrTA.ptr<uint32_t>(), rowTA, angm.ptr<uint64_t>(), cntR.ptr<int>(),
+                     cntAV.ptr<int>(), vrev.ptr<uint32_t>(), flags.ptr<int>(), gate);
   NEPMI_HIP(hipGetLastError());
   return NEPMI_OK;
 }
