@@ -289,7 +289,7 @@ __global__ __launch_bounds__(256) void k_build_lists(int64_t n_slots, int n_spec
                                                      const int* __restrict__ bin_of, const int* __restrict__ start,
                                                      const int* __restrict__ base, float rclR2, float rclA2, int capR,
                                                      int capA, int rowTA, uint32_t* __restrict__ nbrR,
-                                                     uint32_t* __restrict__ nbrTA, uint64_t* __restrict__ angm,
+                                                     uint32_t* __restrict__ nbrTA, uint32_t* __restrict__ angm,
                                                      int* __restrict__ cntR, int* __restrict__ cntAV,
                                                      int* __restrict__ flags, const int* __restrict__ gate) {
   if (gate && *gate == 0) return;
@@ -346,14 +346,16 @@ __global__ __launch_bounds__(256) void k_build_lists(int64_t n_slots, int n_spec
   // per four entries instead of one per entry.  The entries within
   // rc_angular + skin (the angular part of the list, which the reverse index
   // searches) are also kept in their own row-major list, and marked in a bit
-  // mask over the list (bit k % 64 of word k / 64: entry k is in that part).
+  // mask over the list (bit k % 32 of word k / 32: entry k is in that part).
+  // Entries and mask bits shift in from the top, so a full group or word
+  // holds them in list order; the store pointers advance one column at a time.
   const int capG = 4 * list_groups(capR);   // entries the groups can hold
   const int capGA = 4 * list_groups(capA);
   uint4 grp = make_uint4(0u, 0u, 0u, 0u), gra = grp;
-  uint64_t mword = 0;
-  uint4* colG = reinterpret_cast<uint4*>(nbrR) + p;         // column-major groups
+  uint32_t mword = 0;
+  uint4* colG = reinterpret_cast<uint4*>(nbrR) + p;         // next group, column-major
   uint4* rowA = reinterpret_cast<uint4*>(nbrTA + p * rowTA);  // angular part, row-major
-  uint64_t* colM = angm + p;                                // mask words, column-major
+  uint32_t* colM = angm + p;                                // next mask word, column-major
   int kR = 0, kA = 0;
   for (int z = 0; z < n_species; ++z) {
     for (int o = 0; o < 27; ++o) {
@@ -379,37 +381,39 @@ __global__ __launch_bounds__(256) void k_build_lists(int64_t n_slots, int n_spec
           const float rx = (xs[u].x - xi.x) + sx, ry = (xs[u].y - xi.y) + sy, rz = (xs[u].z - xi.z) + sz;
           const float d2 = pair_d2(rx, ry, rz);
           if (d2 < rclR2) {
+            // entries shift into a group from the top (four register moves,
+            // no selects); a full group holds them in list order
             const uint32_t e = (uint32_t)q | (code << kNbrShift);
-            const uint32_t u = (uint32_t)kR & 3u;
-            grp.x = u == 0 ? e : grp.x;
-            grp.y = u == 1 ? e : grp.y;
-            grp.z = u == 2 ? e : grp.z;
-            grp.w = u == 3 ? e : grp.w;
-            if (d2 < rclA2) mword |= 1ull << (kR & 63);
+            grp = make_uint4(grp.y, grp.z, grp.w, e);
+            mword = (mword >> 1) | (d2 < rclA2 ? 0x80000000u : 0u);
             ++kR;
-            if (u == 3 && kR <= capG) colG[(int64_t)((kR >> 2) - 1) * n_slots] = grp;
-            if ((kR & 63) == 0) {
-              if (kR <= capG) colM[(int64_t)((kR >> 6) - 1) * n_slots] = mword;
-              mword = 0;
+            if ((kR & 3) == 0 && kR <= capG) {
+              *colG = grp;
+              colG += n_slots;
+            }
+            if ((kR & 31) == 0 && kR <= capG) {
+              *colM = mword;
+              colM += n_slots;
             }
             if (d2 < rclA2) {
-              const uint32_t ua = (uint32_t)kA & 3u;
-              gra.x = ua == 0 ? e : gra.x;
-              gra.y = ua == 1 ? e : gra.y;
-              gra.z = ua == 2 ? e : gra.z;
-              gra.w = ua == 3 ? e : gra.w;
+              gra = make_uint4(gra.y, gra.z, gra.w, e);
               ++kA;
-              if (ua == 3 && kA <= capGA) rowA[(kA >> 2) - 1] = gra;
+              if ((kA & 3) == 0 && kA <= capGA) rowA[(kA >> 2) - 1] = gra;
             }
           }
         }
       }
     }
   }
-  // the last, partly filled groups and mask word
-  if ((kR & 3) && kR < capG) colG[(int64_t)(kR >> 2) * n_slots] = grp;
-  if ((kR & 63) && kR < capG) colM[(int64_t)(kR >> 6) * n_slots] = mword;
-  if ((kA & 3) && kA < capGA) rowA[kA >> 2] = gra;
+  // the last, partly filled groups (their r entries sit in the top r
+  // components: moved down to the front) and mask word
+  auto front = [](uint4 g, int r) {
+    return r == 1 ? make_uint4(g.w, g.w, g.w, g.w) : r == 2 ? make_uint4(g.z, g.w, g.w, g.w)
+                                                           : make_uint4(g.y, g.z, g.w, g.w);
+  };
+  if ((kR & 3) && kR < capG) *colG = front(grp, kR & 3);
+  if ((kR & 31) && kR < capG) *colM = mword >> (32 - (kR & 31));
+  if ((kA & 3) && kA < capGA) rowA[kA >> 2] = front(gra, kA & 3);
   cntR[p] = kR < capR ? kR : capR;
   cntAV[p] = kA < capA ? kA : capA;
   // the angular pairs within rc_angular at any step between rebuilds are among
@@ -439,7 +443,7 @@ constexpr int kRevSplit = 4;
 constexpr unsigned kRevOneRow = 2048;
 __global__ __launch_bounds__(256) void k_reverse(int64_t n_slots, const int* __restrict__ cfg_of,
                                                  const uint32_t* __restrict__ nbrR, const uint32_t* __restrict__ nbrTA,
-                                                 int rowTA, const uint64_t* __restrict__ angm,
+                                                 int rowTA, const uint32_t* __restrict__ angm,
                                                  const int* __restrict__ cntR, const int* __restrict__ cntAV,
                                                  uint32_t* __restrict__ vrev, int* __restrict__ flags,
                                                  const int* __restrict__ gate) {
@@ -460,7 +464,7 @@ __global__ __launch_bounds__(256) void k_reverse(int64_t n_slots, const int* __r
   constexpr int kRevWin = 8;  // uint4 per row read at once (32 entries)
   for (int g = (int)blockIdx.y; g < ng; g += (int)gridDim.y) {
     const uint4 eg = grp[(int64_t)g * n_slots];
-    const uint32_t bits = (uint32_t)(angm[(int64_t)(g >> 4) * n_slots + p] >> (4 * (g & 15))) & 15u;
+    const uint32_t bits = (angm[(int64_t)(g >> 3) * n_slots + p] >> (4 * (g & 7))) & 15u;
     bool ang[4];
     int nq[4];
     uint32_t want[4];
@@ -713,7 +717,7 @@ int NbrPipeline::ensure_lists(int capR_, int capA_) {
   // groups of four entries (see list_groups); the angular part of the Verlet
   // list, row-major, in rows of rowTA entries
   if ((rc = nbrR.ensure(16 * (size_t)list_groups(capR) * ns)) || (rc = nbrTA.ensure(4 * (size_t)rowTA * ns)) ||
-      (rc = angm.ensure(8 * (size_t)((4 * list_groups(capR) + 63) / 64) * ns)) ||
+      (rc = angm.ensure(4 * (size_t)((4 * list_groups(capR) + 31) / 32) * ns)) ||
       (rc = vrev.ensure(16 * (size_t)list_groups(capR) * ns)) ||
       (rc = cnbrR.ensure(16 * (size_t)list_groups(capR) * ns)) ||
       (rc = cnbrA.ensure(16 * (size_t)list_groups(capA) * ns)) ||
@@ -791,11 +795,11 @@ int NbrPipeline::launch_lists(hipStream_t st, int n_species, const int* gate) {
   hipLaunchKernelGGL(k_build_lists, dim3(nblk(n_slots, 256)), dim3(256), 0, st, n_slots, n_species, total_bins,
                      cfgs.ptr<CfgDev>(), pos4.ptr<float4>(), cfg_of.ptr<int>(), bin_of.ptr<int>(), start.ptr<int>(),
                      base.ptr<int>(), rclR2, rclA2, capR, capA, rowTA, nbrR.ptr<uint32_t>(), nbrTA.ptr<uint32_t>(),
-                     angm.ptr<uint64_t>(), cntR.ptr<int>(), cntAV.ptr<int>(), flags.ptr<int>(), gate);
+                     angm.ptr<uint32_t>(), cntR.ptr<int>(), cntAV.ptr<int>(), flags.ptr<int>(), gate);
   const unsigned rev_tiles = (nblk(n_slots, 256) + kXcds - 1) / kXcds * kXcds;
   const unsigned rev_rows = rev_tiles >= kRevOneRow ? 1u : (unsigned)kRevSplit;
   hipLaunchKernelGGL(k_reverse, dim3(rev_tiles, rev_rows), dim3(256), 0, st, n_slots, cfg_of.ptr<int>(),
-                     nbrR.ptr<uint32_t>(), nbrTA.ptr<uint32_t>(), rowTA, angm.ptr<uint64_t>(), cntR.ptr<int>(),
+                     nbrR.ptr<uint32_t>(), nbrTA.ptr<uint32_t>(), rowTA, angm.ptr<uint32_t>(), cntR.ptr<int>(),
                      cntAV.ptr<int>(), vrev.ptr<uint32_t>(), flags.ptr<int>(), gate);
   NEPMI_HIP(hipGetLastError());
   return NEPMI_OK;

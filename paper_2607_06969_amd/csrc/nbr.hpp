@@ -81,7 +81,7 @@ struct NbrPipeline {
   DevBuf nbrR, cntR;             // Verlet list (rc_radial + skin)
   DevBuf cntAV;                  // entries within rc_angular + skin (the angular part of the list)
   DevBuf nbrTA;                  // the angular part of each list, row-major, rows of rowTA entries (reverse search)
-  DevBuf angm;                   // bit k % 64 of word k / 64 ([word][slot]): entry k is in the angular part
+  DevBuf angm;                   // uint32: bit k % 32 of word k / 32 ([word][slot]): entry k is in the angular part
   int rowTA = 0;
   DevBuf vrev;                   // reverse index of the Verlet list (see k_reverse)
   DevBuf cnbrR, ccntR, cnbrA, ccntA, cposA;  // per-evaluation compact lists (rc_radial, rc_angular),
