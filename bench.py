@@ -414,7 +414,8 @@ def amortised_window(md, min_rebuilds=2, min_steps=128, max_steps=2048, chunk=64
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     return {"amortised_ms_per_step": t / steps * 1e3, "window_steps": steps, "rebuilds_in_window": r,
-            "rebuild_interval_steps": steps / r if r else None}
+            "rebuild_interval_steps": steps / r if r else None,
+            "list_regrows_in_window": md.stats()["regrows"] - st0["regrows"]}
 
 
 def bench_table2_md(nep, W, sites, steps=20, warmup=5):
@@ -590,6 +591,7 @@ def main():
                                f"dt 1 fs, skin 1 A, 300 K",
                    "atoms": n, "pairs_radial_per_atom": pairs_r, "pairs_angular_per_atom": pairs_a,
                    "rebuilds_in_timed_steps": st1["rebuilds"] - st0["rebuilds"],
+                   "list_regrows_in_timed_steps": st1["regrows"] - st0["regrows"],
                    "epot_per_atom_eV": epot / n, "ekin_per_atom_eV": ekin / n},
         "roofline": roofline,
         "amortised": ({**amort, "atom_steps_per_s": n / (amort["amortised_ms_per_step"] * 1e-3)}
