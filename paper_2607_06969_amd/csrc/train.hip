@@ -1367,13 +1367,17 @@ __global__ __launch_bounds__(kTB) void k_force64(TrainIOT<double> io, CutoffsT<d
     }
     if (rv != 0xFFFFFFFFu) {
       const double4 a = fA[(int64_t)ka++ * ns + p];
-      const double4 b = fA[(int64_t)rv * ns + v.q];
       fx += a.x;
       fy += a.y;
       fz += a.z;
-      Fx -= b.x;
-      Fy -= b.y;
-      Fz -= b.z;
+      // a partner that was not found (0xFFFFFFFE) has made the list build fail
+      // already; the test only keeps the read in bounds
+      if (rv <= 0xFFFFu) {
+        const double4 b = fA[(int64_t)rv * ns + v.q];
+        Fx -= b.x;
+        Fy -= b.y;
+        Fz -= b.z;
+      }
     }
     Fx += fx;
     Fy += fy;
