@@ -45,12 +45,14 @@ __device__ __forceinline__ PairVec pair_vec(uint32_t e, float4 xq, float4 xi, co
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-// v[u] = e for a lane-varying u in 0..3 (a select per component).
-__device__ __forceinline__ void put4(uint4& v, int u, uint32_t e) {
-  v.x = u == 0 ? e : v.x;
-  v.y = u == 1 ? e : v.y;
-  v.z = u == 2 ? e : v.z;
-  v.w = u == 3 ? e : v.w;
+// Groups of four list entries fill by shifting entries in from the top
+// (register moves, no selects), so a full group holds them in order; a
+// partly filled one holds its r entries in the top r components, which
+// front4 moves to the front (the rest repeat the last entry, a real one).
+__device__ __forceinline__ void shift_in4(uint4& v, uint32_t e) { v = make_uint4(v.y, v.z, v.w, e); }
+__device__ __forceinline__ uint4 front4(uint4 g, int r) {
+  return r == 1 ? make_uint4(g.w, g.w, g.w, g.w) : r == 2 ? make_uint4(g.z, g.w, g.w, g.w)
+                                                           : make_uint4(g.y, g.z, g.w, g.w);
 }
 
 // One neighbour's radial adjoint row (B_R floats).
@@ -380,7 +382,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(WPE))) void 
       const PairVec v = pair_vec(e, xq, xi, Hc, itab);
       const bool in_ang_part = rvk != 0xFFFFFFFFu;
       if (v.d2 < cut.rcR2) {
-        put4(gr, nR & 3, e);
+        shift_in4(gr, e);
         if ((++nR & 3) == 0) {
           *wr = gr;
           wr += n_slots;
@@ -389,8 +391,8 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(WPE))) void 
           // within rc_angular now implies within rc_angular + skin at the
           // last build, so nA stays below capA and the reverse row exists
           if (rvk <= 0xFFFFu && nA < capA) {
-            put4(ga, nA & 3, e);
-            put4(gp, nA & 3, (uint32_t)ka | (rvk << 16));
+            shift_in4(ga, e);
+            shift_in4(gp, (uint32_t)ka | (rvk << 16));
             if ((++nA & 3) == 0) {
               *wa = ga;
               *wp = gp;
@@ -421,10 +423,10 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     }, reinterpret_cast<const uint4*>(vrev));
     // the last, partly filled mask word and groups
     if (ka & 63) *mw = mword;
-    if (nR & 3) *wr = gr;
+    if (nR & 3) *wr = front4(gr, nR & 3);
     if (nA & 3) {
-      *wa = ga;
-      *wp = gp;
+      *wa = front4(ga, nA & 3);
+      *wp = front4(gp, nA & 3);
     }
     if (bad) atomicOr(&flags[kFlagAsym], 1);
   }
