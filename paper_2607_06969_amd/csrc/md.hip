@@ -524,7 +524,7 @@ int nepmi_md_create(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, cons
   // the longest lists seen stay in the flags; the rebuild request is spent
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, nb.flags.ptr<int>() + kFlagRebuild, 0);
   // kernel variants timed on this state, then the forces of the initial state
-  if (!m->pinned && (rc = autotune_io(m, md->io(), st, 2))) return fail(rc);
+  if (!m->pinned && (rc = autotune_io(m, md->io(), st, 4))) return fail(rc);
   if ((rc = md->forces(st))) return fail(rc);
   hipLaunchKernelGGL(k_md_kin, dim3(nb256(ns)), dim3(256), 0, st, ns, md->mc, nb.orig.ptr<int>(), nb.pos4.ptr<float4>(),
                      md->vel4.ptr<float4>(), md->Ki.ptr<float>());

@@ -102,7 +102,7 @@ int nepmi_autotune(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, const
   hipStream_t st = (hipStream_t)stream;
   int rc = m->prepare(n_cfg, atom_off, cells, pbc, dev_pos, dev_species, st);
   if (rc) return rc;
-  if ((rc = autotune_io(m, m->io(nullptr, nullptr, nullptr), st, 2))) return rc;
+  if ((rc = autotune_io(m, m->io(nullptr, nullptr, nullptr), st, 4))) return rc;
   if (chosen) {
     chosen[0] = m->vdesc;
     chosen[1] = m->vforce;
