@@ -157,7 +157,13 @@ int nepmi_descriptors(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, co
  * dev_nbr[i*cap + k] (int32, caller index of the neighbour) and
  * dev_rvec[(i*cap + k)*3 + a] (float32, r_ij = r_j - r_i + image shift);
  * entries beyond cap are dropped (dev_count still reports the full length).
- * The list order is the library's evaluation order. */
+ * The list order is the library's evaluation order.  which = 2: the angular
+ * part of the library's own list (the entries within rc_angular, in the
+ * order the force gather indexes them), written the same way.  which = 3: for
+ * the same entries, dev_nbr receives the reverse index instead of the
+ * neighbour (the position of atom i in the angular part of its neighbour's
+ * list, or a negative value where no partner entry was found) and dev_rvec
+ * the pair vector of the entry. */
 int nepmi_neighbors(nepmi_model *m, int32_t n_cfg, const int64_t *atom_off, const double *cells, const int32_t *pbc,
                     const float *dev_pos, const int32_t *dev_species, int32_t which, int32_t cap,
                     int32_t *dev_count, int32_t *dev_nbr, float *dev_rvec, void *stream);

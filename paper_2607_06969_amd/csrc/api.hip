@@ -305,20 +305,77 @@ __global__ void k_export_lists(int64_t n_slots, const float4* __restrict__ pos4,
   }
   out_cnt[i] = n;
 }
+
+// Export the angular part of every atom's list (which = 2: neighbour caller
+// index and pair vector of each entry, in the order of that part) or, for the
+// same entries found through the mask over the whole list (which = 3), the
+// reverse index: the position of the atom in the angular part of its
+// neighbour's list, with the pair vector of the entry.
+__global__ void k_export_angular(int64_t n_slots, const float4* __restrict__ pos4, const int* __restrict__ cfg_of,
+                                 const int* __restrict__ orig, const CfgDev* __restrict__ cfgs,
+                                 const uint32_t* __restrict__ nbr, const int* __restrict__ cnt,
+                                 const uint32_t* __restrict__ nbrTA, int rowTA, const int* __restrict__ cntAV,
+                                 const uint32_t* __restrict__ angm, const uint32_t* __restrict__ vrev, int which,
+                                 int cap, int* __restrict__ out_cnt, int* __restrict__ out_nbr,
+                                 float* __restrict__ out_r) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_slots) return;
+  const int c = cfg_of[p];
+  if (c < 0) return;
+  const int i = orig[p];
+  const float4 xi = pos4[p];
+  float H[9];
+  for (int x = 0; x < 9; ++x) H[x] = cfgs[c].H[x];
+  auto put = [&](int a, uint32_t e, int v) {
+    if (a >= cap) return;
+    const float4 xq = pos4[e & kNbrMask];
+    float sx, sy, sz;
+    image_shift(H, e >> kNbrShift, sx, sy, sz);
+    out_nbr[(int64_t)i * cap + a] = v;
+    out_r[((int64_t)i * cap + a) * 3 + 0] = (xq.x - xi.x) + sx;
+    out_r[((int64_t)i * cap + a) * 3 + 1] = (xq.y - xi.y) + sy;
+    out_r[((int64_t)i * cap + a) * 3 + 2] = (xq.z - xi.z) + sz;
+  };
+  int n = 0;
+  if (which == 2) {
+    n = cntAV[p];
+    for (int a = 0; a < n; ++a) {
+      const uint32_t e = nbrTA[p * rowTA + a];
+      put(a, e, orig[e & kNbrMask]);
+    }
+  } else {
+    for (int k = 0; k < cnt[p]; ++k) {
+      if (!((angm[(int64_t)(k >> 5) * n_slots + p] >> (k & 31)) & 1u)) continue;
+      const int64_t gi = group_index(n_slots, p, k);
+      put(n++, nbr[gi], (int)vrev[gi]);
+    }
+  }
+  out_cnt[i] = n;
+}
 }  // namespace nepmi
 
 extern "C" int nepmi_neighbors(nepmi_model* m, int32_t n_cfg, const int64_t* atom_off, const double* cells, const int32_t* pbc,
                                const float* dev_pos, const int32_t* dev_species, int32_t which, int32_t cap,
                                int32_t* dev_count, int32_t* dev_nbr, float* dev_rvec, void* stream) {
-  if (!m || !dev_pos || !dev_species || !dev_count || !dev_nbr || !dev_rvec || cap < 0 || (which != 0 && which != 1)) {
+  if (!m || !dev_pos || !dev_species || !dev_count || !dev_nbr || !dev_rvec || cap < 0 || which < 0 || which > 3) {
     set_error("invalid argument");
     return NEPMI_INVALID_ARG;
   }
   hipStream_t st = (hipStream_t)stream;
   int rc = m->prepare(n_cfg, atom_off, cells, pbc, dev_pos, dev_species, st);
   if (rc) return rc;
-  const float rc1 = (float)(which ? m->hp.rc_angular : m->hp.rc_radial);
   const int64_t ns = m->nbr.n_slots;
+  if (which >= 2) {
+    hipLaunchKernelGGL(k_export_angular, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, ns,
+                       m->nbr.pos4.ptr<float4>(), m->nbr.cfg_of.ptr<int>(), m->nbr.orig.ptr<int>(),
+                       m->nbr.cfgs.ptr<CfgDev>(), m->nbr.nbrR.ptr<uint32_t>(), m->nbr.cntR.ptr<int>(),
+                       m->nbr.nbrTA.ptr<uint32_t>(), m->nbr.rowTA, m->nbr.cntAV.ptr<int>(),
+                       m->nbr.angm.ptr<uint32_t>(), m->nbr.vrev.ptr<uint32_t>(), which, cap, dev_count, dev_nbr,
+                       dev_rvec);
+    NEPMI_HIP(hipGetLastError());
+    return NEPMI_OK;
+  }
+  const float rc1 = (float)(which ? m->hp.rc_angular : m->hp.rc_radial);
   hipLaunchKernelGGL(k_export_lists, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, ns,
                      m->nbr.pos4.ptr<float4>(), m->nbr.cfg_of.ptr<int>(), m->nbr.orig.ptr<int>(),
                      m->nbr.cfgs.ptr<CfgDev>(), m->nbr.nbrR.ptr<uint32_t>(),

@@ -123,7 +123,8 @@ class NepModel:
         return q
 
     def neighbors(self, batch: Batch, which=0, cap=128):
-        """(count (N,), nbr (N, cap) caller indices, rvec (N, cap, 3)) of the radial (0) or angular (1) list."""
+        """(count (N,), nbr (N, cap) caller indices, rvec (N, cap, 3)) of the radial (0) or angular (1) list,
+        the angular part of the evaluation list (2), or its reverse index in place of the indices (3)."""
         dev = batch.pos.device
         cnt = torch.empty(batch.n_atoms, dtype=torch.int32, device=dev)
         nb = torch.full((batch.n_atoms, cap), -1, dtype=torch.int32, device=dev)

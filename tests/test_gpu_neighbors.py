@@ -67,6 +67,63 @@ def test_list_rows_in_processing_order():
                 assert np.all(np.diff(z) >= 0), (which, i, z)
 
 
+def _cluster(seed):
+    s = W.amorphous_batch(n_cfg=1, n_min=180, n_max=180, seed=seed)
+    s.pbc = np.array([[0, 0, 0]], dtype=np.int32)
+    return s
+
+
+@pytest.mark.parametrize("sysf", [lambda: W.rocksalt_gst(8, seed=86),
+                                  lambda: W.amorphous_batch(n_cfg=3, n_min=64, n_max=200, seed=87),
+                                  lambda: _cluster(88)])
+def test_reverse_index(oracle_lib, sysf):
+    """The angular part of the evaluation list and its reverse index.  The
+    force gather reads the pair force of the entry (j, i) at the position
+    that the reverse index gives for (i, j), so for every entry: the position
+    lies inside the angular part of j's list, the entry there is i with the
+    opposite pair vector (bitwise: the same expression, negated), and the map
+    is an involution.  The angular part is the set of pairs within
+    rc_angular (brute force of the oracle), in the order of the whole list."""
+    nep = _nep()
+    s = sysf()
+    hp = W.hp_gst()
+    m = nep.NepModel(hp, W.random_params(hp, 1))
+    b = nep.Batch.from_system(s)
+    cap = 96
+    c2, n2, r2 = (t.cpu().numpy() for t in m.neighbors(b, 2, cap=cap))
+    c3, v3, r3 = (t.cpu().numpy() for t in m.neighbors(b, 3, cap=cap))
+    assert np.array_equal(c2, c3) and c2.max() <= cap
+    for i in range(s.n_atoms):
+        k = c2[i]
+        # the mask over the whole list marks exactly the entries of the angular part, in order
+        assert np.array_equal(r2[i, :k], r3[i, :k])
+        assert np.all(v3[i, :k] >= 0), i
+        for a in range(k):
+            j, r = n2[i, a], v3[i, a]
+            assert r < c2[j], (i, a, j, r)
+            assert n2[j, r] == i, (i, a, j, r)
+            assert np.array_equal(r2[j, r], -r2[i, a]), (i, a, j, r)
+            assert v3[j, r] == a, (i, a, j, r)
+    # the angular part holds the pairs within rc_angular and no others
+    for c in range(s.n_cfg):
+        a0, a1 = s.atom_off[c], s.atom_off[c + 1]
+        sub = s.config(c)
+        if sub.pbc is None:
+            ij, r = oracle_lib.pairs(sub.pos, sub.cells[0], hp.rc_angular, 0)
+            ref = {(int(i) + a0, int(j) + a0): np.linalg.norm(v) for (i, j), v in zip(ij, r)}
+        else:  # a cluster: no images, every pair by brute force
+            assert not sub.pbc_array().any()
+            d = np.linalg.norm(sub.pos[None, :, :] - sub.pos[:, None, :], axis=2)
+            ref = {(i + a0, j + a0): d[i, j] for i in range(len(d)) for j in range(len(d))
+                   if i != j and d[i, j] < hp.rc_angular}
+        got = {(i, int(n2[i, a])): np.linalg.norm(r2[i, a]) for i in range(a0, a1) for a in range(c2[i])}
+        edge = {k for k, v in ref.items() if abs(v - hp.rc_angular) < 1e-4}
+        edge |= {k for k, v in got.items() if abs(v - hp.rc_angular) < 1e-4}
+        assert len(got) == sum(int(c2[i]) for i in range(a0, a1))  # one image per pair
+        assert set(ref) - edge == set(got) - edge
+    print(f"[reverse] {s.n_atoms} atoms, {int(c2.sum())} angular entries", flush=True)
+
+
 def test_triclinic_cell_and_unwrapped_positions(oracle_lib):
     nep = _nep()
     hp = W.hp_gst()
