@@ -103,9 +103,18 @@ __global__ void k_md_unpermute(int64_t n_slots, const int* __restrict__ cfg_of, 
   v_user[i] = vel4[p];
 }
 
+// Second half kick and per-atom kinetic energy.  The first thread also ends
+// the step's bookkeeping: it counts the step (and the rebuild, if one ran)
+// and clears the rebuild flag, which nothing later in the step reads.
 __global__ void k_md_kick2(int64_t n_slots, MdConst mc, const int* __restrict__ orig, const float4* __restrict__ pos4,
-                           const float4* __restrict__ F4, float4* __restrict__ vel4, float* __restrict__ Ki) {
+                           const float4* __restrict__ F4, float4* __restrict__ vel4, float* __restrict__ Ki,
+                           int* __restrict__ flags, long long* __restrict__ counters) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p == 0) {
+    if (flags[kFlagRebuild]) counters[1] += 1;
+    counters[0] += 1;
+    flags[kFlagRebuild] = 0;
+  }
   if (p >= n_slots) return;
   const int i = orig[p];
   if (i < 0) return;
@@ -127,14 +136,6 @@ __global__ void k_md_kin(int64_t n_slots, MdConst mc, const int* __restrict__ or
   if (i < 0) return;
   const float4 v = vel4[p];
   Ki[i] = mc.kin[__float_as_int(pos4[p].w)] * (v.x * v.x + v.y * v.y + v.z * v.z);
-}
-
-__global__ void k_md_finish(int* __restrict__ flags, long long* __restrict__ counters) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    if (flags[kFlagRebuild]) counters[1] += 1;
-    counters[0] += 1;
-    flags[kFlagRebuild] = 0;
-  }
 }
 
 __global__ void k_md_export(int64_t n_slots, const int* __restrict__ orig, const Dbl3* __restrict__ xd,
@@ -330,11 +331,11 @@ struct nepmi_md {
     if ((rc = rebuild(st, flags + kFlagRebuild))) return rc;
     if ((rc = forces(st, timed))) return rc;
     hipLaunchKernelGGL(k_md_kick2, dim3(nb256(ns)), dim3(256), 0, st, ns, mc, nbr.orig.ptr<int>(),
-                       nbr.pos4.ptr<float4>(), F4.ptr<float4>(), vel4.ptr<float4>(), Ki.ptr<float>());
+                       nbr.pos4.ptr<float4>(), F4.ptr<float4>(), vel4.ptr<float4>(), Ki.ptr<float>(), flags,
+                       counters.ptr<long long>());
     if ((rc = red.run(st, Ei.ptr<float>(), Wi.ptr<float>(), Ki.ptr<float>(), epot.ptr<double>(), vir.ptr<double>(),
                       ekin.ptr<double>())))
       return rc;
-    hipLaunchKernelGGL(k_md_finish, dim3(1), dim3(64), 0, st, flags, counters.ptr<long long>());
     NEPMI_HIP(hipGetLastError());
     return NEPMI_OK;
   }

@@ -3,27 +3,52 @@
 // E_c = sum_i E_i (Eq. 1) and V_c = sum_i W_i (Eq. 4), plus optional
 // kinetic energies, are summed in float64 in a fixed order: every
 // configuration's caller-order atom range is cut into chunks, one block sums
-// a chunk with a fixed-shape tree, and one block per configuration sums its
-// chunk sums the same way.  Results are bitwise reproducible run to run.
+// a chunk in a fixed shape (wavefront butterflies, then the wavefronts in
+// order), and one block per configuration sums its chunk sums the same way.
+// Results are bitwise reproducible run to run.
 #include "reduce.hpp"
 
 namespace nepmi {
 
-constexpr int kRedBlock = 256;
+constexpr int kRedBlock = 256;       // threads of a block of the final pass
+constexpr int kRedChunkBlock = 256;  // threads of a block of the first pass (1024 measured slower)
+
+// Sum of the block's acc[v] into thread v (v < NV), in a fixed shape: a
+// butterfly over the 64 lanes of each wavefront, then the wavefront sums in
+// order.
+template <int BS>
+__device__ __forceinline__ void block_sum(double (&acc)[kRedValues], double (&sh)[BS / 64][kRedValues]) {
+  constexpr int NV = kRedValues;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] += __shfl_xor(acc[v], o, 64);
+  const int w = (int)threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sh[w][v] = acc[v];
+  __syncthreads();
+  if ((int)threadIdx.x < NV) {
+    double t = sh[0][threadIdx.x];
+#pragma unroll
+    for (int u = 1; u < BS / 64; ++u) t += sh[u][threadIdx.x];
+    acc[0] = t;
+  }
+}
 
 template <class T>
-__global__ __launch_bounds__(kRedBlock) void k_reduce_chunks(const RedItem* __restrict__ items,
+__global__ __launch_bounds__(kRedChunkBlock) void k_reduce_chunks(const RedItem* __restrict__ items,
                                                              const T* __restrict__ Ei,
                                                              const T* __restrict__ Wi,
                                                              const T* __restrict__ Ki,
                                                              double* __restrict__ part) {
   constexpr int NV = kRedValues;
-  __shared__ double sh[NV][kRedBlock];
+  __shared__ double sh[kRedChunkBlock / 64][NV];
   const RedItem it = items[blockIdx.x];
   double acc[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-  for (int64_t a = it.a0 + threadIdx.x; a < it.a1; a += kRedBlock) {
+  for (int64_t a = it.a0 + threadIdx.x; a < it.a1; a += kRedChunkBlock) {
     if (Ei) acc[0] += (double)Ei[a];
     if (Wi) {
 #pragma unroll
@@ -31,26 +56,17 @@ __global__ __launch_bounds__(kRedBlock) void k_reduce_chunks(const RedItem* __re
     }
     if (Ki) acc[10] += (double)Ki[a];
   }
-#pragma unroll
-  for (int v = 0; v < NV; ++v) sh[v][threadIdx.x] = acc[v];
-  __syncthreads();
-  for (int s = kRedBlock / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) sh[v][threadIdx.x] += sh[v][threadIdx.x + s];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x < NV) part[(int64_t)blockIdx.x * NV + threadIdx.x] = sh[threadIdx.x][0];
+  block_sum<kRedChunkBlock>(acc, sh);
+  if (threadIdx.x < NV) part[(int64_t)blockIdx.x * NV + threadIdx.x] = acc[0];
 }
 
 // One block per configuration: its chunk sums in a fixed assignment to
-// threads, then the same fixed-shape tree.
+// threads, then the same fixed-shape sum.
 __global__ __launch_bounds__(kRedBlock) void k_reduce_final(int n_cfg, const int* __restrict__ item_start,
                                                             const double* __restrict__ part, double* __restrict__ E,
                                                             double* __restrict__ V, double* __restrict__ Kout) {
   constexpr int NV = kRedValues;
-  __shared__ double sh[NV][kRedBlock];
+  __shared__ double sh[kRedBlock / 64][NV];
   const int c = blockIdx.x;
   double acc[NV];
 #pragma unroll
@@ -58,22 +74,11 @@ __global__ __launch_bounds__(kRedBlock) void k_reduce_final(int n_cfg, const int
   for (int w = item_start[c] + (int)threadIdx.x; w < item_start[c + 1]; w += kRedBlock)
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] += part[(int64_t)w * NV + v];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) sh[v][threadIdx.x] = acc[v];
-  __syncthreads();
-  for (int s = kRedBlock / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) sh[v][threadIdx.x] += sh[v][threadIdx.x + s];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    if (E) E[c] = sh[0][0];
-    if (V)
-      for (int x = 0; x < 9; ++x) V[(int64_t)c * 9 + x] = sh[1 + x][0];
-    if (Kout) Kout[c] = sh[10][0];
-  }
+  block_sum<kRedBlock>(acc, sh);
+  const int v = (int)threadIdx.x;
+  if (v == 0 && E) E[c] = acc[0];
+  if (v >= 1 && v <= 9 && V) V[(int64_t)c * 9 + v - 1] = acc[0];
+  if (v == 10 && Kout) Kout[c] = acc[0];
 }
 
 int Reducer::setup(int n_cfg_, const int64_t* atom_off, hipStream_t st) {
@@ -108,7 +113,7 @@ int Reducer::setup(int n_cfg_, const int64_t* atom_off, hipStream_t st) {
 
 int Reducer::run(hipStream_t st, const float* Ei, const float* Wi, const float* Ki, double* E, double* V,
                  double* Kout) {
-  hipLaunchKernelGGL(k_reduce_chunks<float>, dim3(n_items), dim3(kRedBlock), 0, st, items_dev.ptr<RedItem>(), Ei, Wi,
+  hipLaunchKernelGGL(k_reduce_chunks<float>, dim3(n_items), dim3(kRedChunkBlock), 0, st, items_dev.ptr<RedItem>(), Ei, Wi,
                      Ki, part.ptr<double>());
   hipLaunchKernelGGL(k_reduce_final, dim3(n_cfg), dim3(kRedBlock), 0, st, n_cfg, start_dev.ptr<int>(),
                      part.ptr<double>(), E, V, Kout);
@@ -117,7 +122,7 @@ int Reducer::run(hipStream_t st, const float* Ei, const float* Wi, const float* 
 }
 
 int Reducer::run64(hipStream_t st, const double* Ei, const double* Wi, double* E, double* V) {
-  hipLaunchKernelGGL(k_reduce_chunks<double>, dim3(n_items), dim3(kRedBlock), 0, st, items_dev.ptr<RedItem>(), Ei,
+  hipLaunchKernelGGL(k_reduce_chunks<double>, dim3(n_items), dim3(kRedChunkBlock), 0, st, items_dev.ptr<RedItem>(), Ei,
                      Wi, static_cast<const double*>(nullptr), part.ptr<double>());
   hipLaunchKernelGGL(k_reduce_final, dim3(n_cfg), dim3(kRedBlock), 0, st, n_cfg, start_dev.ptr<int>(),
                      part.ptr<double>(), E, V, static_cast<double*>(nullptr));
