@@ -51,8 +51,8 @@ struct DevBuf {
 };
 
 // State that a rebuild moves from caller order into the new slot order along
-// with the positions (MD: float64 positions, velocities, and the positions of
-// this build as the drift reference).  Used when xd is not null.
+// with the positions (MD: float64 positions, velocities, and the positions the
+// new lists are built from, as the drift reference).  Used when xd is not null.
 struct SlotCarry {
   const double* xd_user = nullptr;  // [N][3] float64 positions, caller order
   const float4* x_user = nullptr;   // [N] the float32 positions the build staged

@@ -199,5 +199,9 @@ def test_error_paths_and_recovery():
     with pytest.raises(NepmiError) as e:
         m.compute(nep.Batch.from_system(W.System(s.pos, spc, s.cells, s.atom_off)))
     assert e.value.code == INVALID_ARG
+    for which in (-1, 4):  # list selectors outside 0..3
+        with pytest.raises(NepmiError) as e:
+            m.neighbors(nep.Batch.from_system(s), which, cap=8)
+        assert e.value.code == INVALID_ARG
     ok = m.compute(nep.Batch.from_system(s))
     assert torch.isfinite(ok["F"]).all()
