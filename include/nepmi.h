@@ -27,7 +27,8 @@
  *     than 0 and 1 give NEPMI_INVALID_ARG.
  *   - Positions and forces are float32, array-of-structs (N x 3, row-major),
  *     in the caller's atom order; configuration c owns atoms
- *     [atom_off[c], atom_off[c+1]).
+ *     [atom_off[c], atom_off[c+1]).  A configuration may be empty (its E and
+ *     V are 0); a batch with no atoms at all gives NEPMI_INVALID_ARG.
  *   - The virial is V_ab = - sum_i sum_j dE_i/dr_ij,a r_ij,b in eV (Eq. 4),
  *     not divided by the volume.
  *   - Arithmetic: float32 for descriptors, network and pair forces; float64

@@ -588,6 +588,10 @@ int NbrPipeline::setup(int n_cfg_, const int64_t* atom_off, const double* cells,
       return NEPMI_INVALID_ARG;
     }
   const int64_t N_ = atom_off[n_cfg_];
+  if (N_ < 1) {
+    set_error("the batch holds no atoms");
+    return NEPMI_INVALID_ARG;
+  }
   if (N_ > (int64_t)kMaxAtoms - 64 * n_species_) {
     set_error("too many atoms for 27-bit neighbour indices");
     return NEPMI_INVALID_ARG;

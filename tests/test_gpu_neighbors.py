@@ -199,6 +199,13 @@ def test_error_paths_and_recovery():
     with pytest.raises(NepmiError) as e:
         m.compute(nep.Batch.from_system(W.System(s.pos, spc, s.cells, s.atom_off)))
     assert e.value.code == INVALID_ARG
+    # a batch of empty configurations only: no atoms at all (non-null pointers,
+    # so the check of the batch itself answers)
+    nothing = nep.Batch(torch.zeros(1, 3, device="cuda"), torch.zeros(1, dtype=torch.int32, device="cuda"),
+                        [0, 0, 0], np.stack([np.eye(3) * 20.0] * 2))
+    with pytest.raises(NepmiError) as e:
+        m.compute(nothing)
+    assert e.value.code == INVALID_ARG and "no atoms" in str(e.value)
     for which in (-1, 4):  # list selectors outside 0..3
         with pytest.raises(NepmiError) as e:
             m.neighbors(nep.Batch.from_system(s), which, cap=8)
