@@ -3,6 +3,8 @@ benchmark times:
   - the 900,000-atom rocksalt cell stepped as the timed MD graph (autotuned
     kernel variants, timed-step replay, in-graph list rebuild), every output
     against the FP64 oracle on the same positions;
+  - the same cell over 600 steps with its list capacities clamped, so that a
+    rebuild overflows and the lists are regrown at full size;
   - the float64 evaluation of the same cell (bar 1e-10);
   - the full 256-configuration training batch: loss and parameter gradient;
   - sampled cells (smallest, median, largest) of the 64-cell serving batch,
@@ -46,6 +48,41 @@ def test_md_900k_after_timed_steps_matches_oracle(oracle_lib):
     rF, rV = rel(st["F"].cpu().numpy(), ref["F"]), rel(st["V"][0].cpu().numpy(), ref["V"][0])
     print(f"[fullsize] MD dE/N {dE:.2e} F {rF:.2e} V {rV:.2e}", flush=True)
     assert dE < 1e-6 and rF < 1e-5 and rV < 1e-5
+
+
+def test_md_900k_regrow_in_long_run_matches_oracle(oracle_lib):
+    """The 900,000-atom cell with its list capacities clamped to the longest
+    lists built so far: the random-parameter model heats the cell, the lists
+    grow, and a rebuild inside the step graph overflows.  The chunk is rolled
+    back, the lists regrown and the graph re-captured at full size; afterwards
+    the state still matches the FP64 oracle and the total energy is kept."""
+    from paper_2607_06969_amd import nep
+    hp = W.hp_gst()
+    p = W.random_params(hp, W.SEED_PARAM + 3)
+    s = W.rocksalt_gst(100, seed=W.SEED_POS + 3)
+    vel = W.maxwell_boltzmann(s.species, W.MASSES_GST, 300.0, seed=W.SEED_VEL)
+    m = nep.NepModel(hp, p)
+    v = torch.as_tensor(vel, dtype=torch.float32, device="cuda").contiguous()
+    md = nep.NepMD(m, nep.Batch.from_system(s), v, W.MASSES_GST, dt_fs=1.0, skin=1.0)
+    cap0 = md.capacity(1, 1)  # clamped up to the longest lists so far
+    st = md.state()
+    n = s.n_atoms
+    e0 = (float(st["Epot"][0]) + float(st["Ekin"][0])) / n
+    print(f"[fullsize] long MD {n} atoms, capacities {cap0}", flush=True)
+    md.step(600)
+    stats, cap1 = md.stats(), md.capacity()
+    print(f"[fullsize] long MD {stats} capacities {cap1}", flush=True)
+    assert stats["steps"] == 600 and stats["regrows"] >= 1, stats
+    assert cap1["capR"] > cap0["capR"] or cap1["capA"] > cap0["capA"]
+    st = md.state()
+    e1 = (float(st["Epot"][0]) + float(st["Ekin"][0])) / n
+    pos = st["pos"].cpu().numpy().astype(np.float64)
+    ref = oracle_lib.evaluate(hp, p, W.System(pos, s.species, s.cells, s.atom_off), nbr_mode=1)
+    dE = abs(float(st["Epot"][0]) - ref["E"][0]) / n
+    rF, rV = rel(st["F"].cpu().numpy(), ref["F"]), rel(st["V"][0].cpu().numpy(), ref["V"][0])
+    print(f"[fullsize] long MD dE/N {dE:.2e} F {rF:.2e} V {rV:.2e} drift {e1 - e0:.2e} eV/atom", flush=True)
+    assert dE < 1e-6 and rF < 1e-5 and rV < 1e-5
+    assert abs(e1 - e0) < 1e-5  # 1 fs steps: the total energy is kept (measured 3e-7 eV/atom)
 
 
 def test_float64_900k_matches_oracle(oracle_lib):
