@@ -1429,6 +1429,154 @@ static void species_sums(hipStream_t st, const TrainIOT<R>& io, const int* base,
   hipLaunchKernelGGL(k_part_final, dim3(blocks(pl.first[pl.n], 256)), dim3(256), 0, st, pl, part, grad);
 }
 
+// The network pass of the float training path on the fp32 matrix cores: the
+// same quantities as the network phase of k_train_atom (abar, -z and dj/dw1
+// per hidden unit; qbar = W0^T abar and dE/dq = W0^T z), from the four
+// products a = W0 q + b0, adot = W0 qdot, W0^T abar and W0^T z.  As in the
+// evaluation's network, the 16-block 4x4x1 instruction lets every lane supply
+// its own atom's vector as B and a weight row selected by lane % 4 as A, so
+// each lane accumulates four entries of its own atom; the weights of the
+// block's species sit in LDS as [Z][h][d] and [Z][d][h], zero padded.  Every
+// lane runs the matrix instructions (slots past the end and padding slots
+// with zero inputs); only real atoms store, and padding slots store zeros
+// where the species sums read them.
+typedef float tnetx4 __attribute__((ext_vector_type(4)));
+
+template <class S>
+__global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(2))) void k_train_net(TrainIO io,
+                                                                                         const float* __restrict__ params) {
+  constexpr int T = S::T, NR = S::NR, D = S::D, H = S::H;
+  constexpr int HP = (H + 3) / 4 * 4, DP = (D + 3) / 4 * 4;
+  __shared__ float W0s[T * HP * DP];
+  __shared__ float W0Ts[T * DP * HP];
+  const int64_t ns = io.ns;
+  const int64_t p = (int64_t)blockIdx.x * kTB + threadIdx.x;
+  const bool in = p < ns;
+  const int64_t pc = in ? p : ns - 1;
+  {
+    // the species of this block's wavefronts (each is uniform)
+    const int64_t b0 = (int64_t)blockIdx.x * kTB;
+    unsigned need = 0;
+#pragma unroll
+    for (int w = 0; w < kTB / kWave; ++w) {
+      const int64_t s0 = b0 + w * kWave;
+      need |= 1u << species_of(io.pos4[s0 < ns ? s0 : ns - 1]);
+    }
+    for (int z = 0; z < T; ++z) {
+      if (!(need >> z & 1u)) continue;
+      const float* W0g = params + S::PCR + S::PCA + (int64_t)z * S::PMLP;
+      for (int t = threadIdx.x; t < HP * DP; t += kTB) {
+        const int h = t / DP, d = t % DP;
+        const float w = (h < H && d < D) ? W0g[h * D + d] : 0.0f;
+        W0s[(z * HP + h) * DP + d] = w;
+        W0Ts[(z * DP + d) * HP + h] = w;
+      }
+    }
+    __syncthreads();
+  }
+  if (__builtin_amdgcn_readfirstlane((int)(p - threadIdx.x % kWave >= ns))) return;  // wavefront past the end
+  const int Zs = __builtin_amdgcn_readfirstlane(species_of(io.pos4[pc]));
+  const int c = io.cfg_of[pc];
+  const bool active = in && c >= 0;
+  const float eb = active ? (float)io.ebar[c] : 0.f;
+  const int lq = threadIdx.x & 3;
+  const float* b0g = params + S::PCR + S::PCA + (int64_t)Zs * S::PMLP + H * D;
+  const float* w1g = b0g + H;
+  // forward: a_h and adot_h, four hidden units per group
+  tnetx4 acc[HP / 4], accd[HP / 4];
+#pragma unroll
+  for (int hg = 0; hg < HP / 4; ++hg)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      acc[hg][r] = (4 * hg + r < H) ? b0g[4 * hg + r] : 0.f;
+      accd[hg][r] = 0.f;
+    }
+  {
+    float q[DP], qd[DP];
+#pragma unroll
+    for (int d = 0; d < DP; ++d) {
+      q[d] = (d < D && active) ? io.q[(int64_t)d * ns + p] : 0.f;
+      qd[d] = (d < D && active) ? io.qd[(int64_t)d * ns + p] : 0.f;
+    }
+    const float* Wz = W0s + (Zs * HP + lq) * DP;
+#pragma unroll
+    for (int dg = 0; dg < DP / 4; ++dg) {
+#pragma unroll
+      for (int hg = 0; hg < HP / 4; ++hg) {
+        const float4 w = *reinterpret_cast<const float4*>(Wz + 4 * hg * DP + 4 * dg);
+        acc[hg] = __builtin_amdgcn_mfma_f32_4x4x1f32(w.x, q[4 * dg + 0], acc[hg], 0, 0, 0);
+        acc[hg] = __builtin_amdgcn_mfma_f32_4x4x1f32(w.y, q[4 * dg + 1], acc[hg], 0, 0, 0);
+        acc[hg] = __builtin_amdgcn_mfma_f32_4x4x1f32(w.z, q[4 * dg + 2], acc[hg], 0, 0, 0);
+        acc[hg] = __builtin_amdgcn_mfma_f32_4x4x1f32(w.w, q[4 * dg + 3], acc[hg], 0, 0, 0);
+        accd[hg] = __builtin_amdgcn_mfma_f32_4x4x1f32(w.x, qd[4 * dg + 0], accd[hg], 0, 0, 0);
+        accd[hg] = __builtin_amdgcn_mfma_f32_4x4x1f32(w.y, qd[4 * dg + 1], accd[hg], 0, 0, 0);
+        accd[hg] = __builtin_amdgcn_mfma_f32_4x4x1f32(w.z, qd[4 * dg + 2], accd[hg], 0, 0, 0);
+        accd[hg] = __builtin_amdgcn_mfma_f32_4x4x1f32(w.w, qd[4 * dg + 3], accd[hg], 0, 0, 0);
+      }
+    }
+  }
+  // per hidden unit: abar = z (ebar + 2 h adot), z = w1 (1 - h^2), dj/dw1
+  float zt[HP], ab[HP];
+#pragma unroll
+  for (int hg = 0; hg < HP / 4; ++hg)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int h = 4 * hg + r;
+      zt[h] = ab[h] = 0.f;
+      if (h < H) {
+        const float t = tanh_(acc[hg][r]), ad = accd[hg][r];
+        const float s2 = 1.0f - t * t;
+        const float z = w1g[h] * s2;
+        if (active) {
+          zt[h] = z;
+          ab[h] = z * (eb + 2.0f * t * ad);
+        }
+        if (in) {
+          io.abar[(int64_t)h * ns + p] = ab[h];
+          io.gw1[(int64_t)h * ns + p] = active ? eb * t - s2 * ad : 0.f;
+          io.zneg[(int64_t)h * ns + p] = -zt[h];
+        }
+      }
+    }
+  if (in) io.eat[p] = eb;
+  // backward: qbar_d = sum_h abar_h W0[h][d], dE/dq_d = sum_h z_h W0[h][d]
+  tnetx4 qba[DP / 4], fpa[DP / 4];
+#pragma unroll
+  for (int dg = 0; dg < DP / 4; ++dg) qba[dg] = fpa[dg] = tnetx4{0.f, 0.f, 0.f, 0.f};
+  {
+    const float* WzT = W0Ts + (Zs * DP + lq) * HP;
+#pragma unroll
+    for (int hg = 0; hg < HP / 4; ++hg) {
+#pragma unroll
+      for (int dg = 0; dg < DP / 4; ++dg) {
+        const float4 w = *reinterpret_cast<const float4*>(WzT + 4 * dg * HP + 4 * hg);
+        qba[dg] = __builtin_amdgcn_mfma_f32_4x4x1f32(w.x, ab[4 * hg + 0], qba[dg], 0, 0, 0);
+        qba[dg] = __builtin_amdgcn_mfma_f32_4x4x1f32(w.y, ab[4 * hg + 1], qba[dg], 0, 0, 0);
+        qba[dg] = __builtin_amdgcn_mfma_f32_4x4x1f32(w.z, ab[4 * hg + 2], qba[dg], 0, 0, 0);
+        qba[dg] = __builtin_amdgcn_mfma_f32_4x4x1f32(w.w, ab[4 * hg + 3], qba[dg], 0, 0, 0);
+        fpa[dg] = __builtin_amdgcn_mfma_f32_4x4x1f32(w.x, zt[4 * hg + 0], fpa[dg], 0, 0, 0);
+        fpa[dg] = __builtin_amdgcn_mfma_f32_4x4x1f32(w.y, zt[4 * hg + 1], fpa[dg], 0, 0, 0);
+        fpa[dg] = __builtin_amdgcn_mfma_f32_4x4x1f32(w.z, zt[4 * hg + 2], fpa[dg], 0, 0, 0);
+        fpa[dg] = __builtin_amdgcn_mfma_f32_4x4x1f32(w.w, zt[4 * hg + 3], fpa[dg], 0, 0, 0);
+      }
+    }
+  }
+  if (!in) return;
+#pragma unroll
+  for (int dg = 0; dg < DP / 4; ++dg)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int d = 4 * dg + r;
+      if (d < NR) {
+        io.qbR[(int64_t)d * ns + p] = qba[dg][r];
+        io.FpR[(int64_t)d * ns + p] = fpa[dg][r];
+      } else if (d < D && active) {
+        io.qbA[(int64_t)d * ns + p] = qba[dg][r];
+        io.FpA[(int64_t)d * ns + p] = fpa[dg][r];
+      }
+    }
+}
+
 template <class S>
 int TrainLaunch<S>::backward(hipStream_t st, TrainIO io, const Cutoffs& cut, const float* params, const float* lam,
                              const int* base, double* part, double* grad64, float* grad) {
@@ -1437,7 +1585,7 @@ int TrainLaunch<S>::backward(hipStream_t st, TrainIO io, const Cutoffs& cut, con
                      const_cast<float4*>(io.lam4));
   constexpr int NC = S::NA >= 4 ? 2 : 1;
   hipLaunchKernelGGL((k_train_atom<S, NC, float, 1>), dim3(blocks(ns, kTB), 1 + S::NA / NC), dim3(kTB), 0, st, io, cut, params);
-  hipLaunchKernelGGL((k_train_atom<S, NC, float, 2>), dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, cut, params);
+  hipLaunchKernelGGL(k_train_net<S>, dim3(blocks(ns, kTB)), dim3(kTB), 0, st, io, params);
   hipLaunchKernelGGL((k_train_atom<S, NC, float, 3>), dim3(blocks(ns, kTB), S::NA), dim3(kTB), 0, st, io, cut, params);
   hipLaunchKernelGGL((k_train_coefA<S, float>), dim3(blocks(ns, kTB), S::NA), dim3(kTB), 0, st, io, cut, params);
   species_sums<S, float>(st, io, base, part, grad64);
